@@ -1,0 +1,213 @@
+"""O-method: IterNCGP (Algorithm 1), IterGP (Algorithm 2) and the virtual
+solver run with compression (Algorithm 3), FP64, matrix-free.
+
+Written from the paper's description of the algorithms, in its order and
+notation: actions s_j, products t_j = K s_j, buffers S and T, root Q of the
+approximate precision C_j = Q Q^T, search direction d_j, normaliser eta_j,
+observation alpha_j, representer weights v_j.
+
+Readings of points the paper leaves open (each also listed in the design doc):
+
+* The inner stopping test uses ||r_{j-1}|| right after it is formed, before
+  an action is chosen; the iteration cap is tested before the residual is
+  formed, so no product with K is spent on a residual that cannot be used.
+  Tolerances: ||r|| < max(tol_abs, tol_rel ||yhat - m||), both 1e-5 by
+  default (appendix on stopping criteria).
+* CG actions are stored normalised, s_j = r_{j-1} / ||r_{j-1}||.  All outputs
+  are invariant to the scale of an action (C_j depends only on span S); the
+  invariance is pinned by a test.
+* eta_j <= 0 ends the solve (appendix on stopping criteria); the action and
+  its product, already appended, are removed again so that the recycled M of
+  the next Newton step stays nonsingular.
+* Algorithm 3 takes M = S^T (T + W^+ S), symmetrised as (M + M^T)/2, and its
+  eigenpairs sorted by decreasing eigenvalue.  Eigenpairs with
+  lambda <= lambda_max * B * eps_64 are dropped before truncation to R
+  (the paper takes Lambda^{-1/2} without guarding against tiny eigenvalues).
+* The unit-vector policy restarts at e_1 in every Newton step and runs
+  without recycling (the paper's Cholesky runs are without recycling).
+
+Pins (tests/test_oracle_itergp.py): full-budget IterGP equals the dense
+Cholesky solve; C_j = S (S^T Khat S)^{-1} S^T equals Q Q^T; the unit policy
+equals exact GP regression on the leading coordinates; the residual policy
+equals textbook conjugate gradients (scipy.sparse.linalg.cg); S^T r_j = 0;
+after the virtual solver run S^T r_0 = 0 and the Khat-projected error is zero;
+R = 0 gives C_0 = 0; the marginal variance is non-increasing in j; the
+trace identity Tr K_{i,0} = Tr K - Tr M for eigenvector actions with
+W^{-1} = 0.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Callable, List, Optional
+
+import numpy as np
+
+from . import likelihood as lik
+from .newton import pseudo_target_offset
+
+Apply = Callable[[np.ndarray], np.ndarray]
+EPS64 = np.finfo(np.float64).eps
+
+
+@dataclasses.dataclass
+class VSRInfo:
+    eigvals: np.ndarray          # kept eigenvalues (descending)
+    n_dropped_floor: int = 0     # eigenpairs removed by the tiny-eigenvalue floor
+    n_dropped_rank: int = 0      # eigenpairs removed by compression to R
+
+
+@dataclasses.dataclass
+class SolveInfo:
+    iters: int = 0                       # new actions taken (j at exit)
+    res_norms: List[float] = dataclasses.field(default_factory=list)
+    etas: List[float] = dataclasses.field(default_factory=list)
+    alphas: List[float] = dataclasses.field(default_factory=list)
+    actions: List[np.ndarray] = dataclasses.field(default_factory=list)
+    breakdown: bool = False
+    converged: bool = False
+    rhs_norm: float = 0.0
+    vsr: Optional[VSRInfo] = None
+
+
+def virtual_solver_run(S: np.ndarray, T: np.ndarray, apply_Winv: Apply,
+                       rank_limit: Optional[int] = None):
+    """Algorithm 3.  Returns (Q0, S, T, info) with C_0 = Q0 Q0^T.
+
+    M = S^T (T + W^{-1} S) = S^T Khat S; M = U Lambda U^T with eigenvalues in
+    decreasing order; keep the R largest (compression); S <- S U, T <- T U;
+    Q0 = S Lambda^{-1/2}.
+    """
+    B = S.shape[1]
+    if B == 0:
+        return S.copy(), S.copy(), T.copy(), VSRInfo(np.zeros(0))
+    M = S.T @ (T + apply_Winv(S))
+    M = 0.5 * (M + M.T)
+    lam, U = np.linalg.eigh(M)
+    order = np.argsort(lam)[::-1]
+    lam, U = lam[order], U[:, order]
+    keep = lam > lam[0] * B * EPS64 if lam[0] > 0 else np.zeros(B, dtype=bool)
+    n_floor = int(B - keep.sum())
+    lam, U = lam[keep], U[:, keep]
+    n_rank = 0
+    if rank_limit is not None and rank_limit >= 0 and lam.size > rank_limit:
+        n_rank = int(lam.size - rank_limit)
+        lam, U = lam[:rank_limit], U[:, :rank_limit]
+    S = S @ U
+    T = T @ U
+    Q0 = S / np.sqrt(lam)[None, :]
+    return Q0, S, T, VSRInfo(lam, n_floor, n_rank)
+
+
+def itergp(apply_K: Apply, apply_Winv: Apply, rhs: np.ndarray,
+           S: np.ndarray, T: np.ndarray, policy: str = "cg", j_max: int = 100,
+           tol_abs: float = 1e-5, tol_rel: float = 1e-5,
+           rank_limit: Optional[int] = None, recycle: bool = True,
+           user_actions: Optional[np.ndarray] = None,
+           normalize_actions: bool = True):
+    """Algorithm 2 for the system Khat v = rhs (rhs = yhat - m).
+
+    Returns (v, Q, S, T, info).  ``policy`` is "cg" (s_j = r_{j-1}), "unit"
+    (s_j = e_j) or "user" (s_j = user_actions[:, j-1]).
+    """
+    n = rhs.shape[0]
+    if recycle:
+        Q, S, T, vinfo = virtual_solver_run(S, T, apply_Winv, rank_limit)
+    else:
+        Q, S, T, vinfo = np.zeros((n, 0)), np.zeros((n, 0)), np.zeros((n, 0)), None
+    info = SolveInfo(vsr=vinfo)
+    v = Q @ (Q.T @ rhs)                                  # v_0 = C_0 (yhat - m)
+    rhs_norm = float(np.linalg.norm(rhs))
+    info.rhs_norm = rhs_norm
+    thresh = max(tol_abs, tol_rel * rhs_norm)
+    j = 0
+    while j < j_max:
+        r = rhs - apply_K(v) - apply_Winv(v)             # r_{j-1}
+        rn = float(np.linalg.norm(r))
+        info.res_norms.append(rn)
+        if rn < thresh:
+            info.converged = True
+            break
+        j += 1
+        if policy == "cg":
+            s = r / rn if normalize_actions else r.copy()
+        elif policy == "unit":
+            s = np.zeros(n)
+            s[j - 1] = 1.0
+        elif policy == "user":
+            s = np.array(user_actions[:, j - 1], dtype=np.float64)
+        else:
+            raise ValueError(policy)
+        S = np.concatenate([S, s[:, None]], axis=1)      # append s_j to S
+        alpha = float(s @ r)                             # alpha_j = s_j^T r_{j-1}
+        t = apply_K(s)                                   # t_j = K s_j
+        T = np.concatenate([T, t[:, None]], axis=1)      # append t_j to T
+        z = t + apply_Winv(s)                            # z_j = Khat s_j
+        d = s - Q @ (Q.T @ z)                            # d_j = s_j - C_{j-1} z_j
+        eta = float(z @ d)                               # eta_j = z_j^T d_j
+        info.etas.append(eta)
+        info.alphas.append(alpha)
+        info.actions.append(s)
+        if eta <= 0.0:
+            info.breakdown = True
+            S, T = S[:, :-1], T[:, :-1]
+            info.actions.pop()
+            info.etas.pop()
+            info.alphas.pop()
+            j -= 1
+            break
+        Q = np.concatenate([Q, (d / np.sqrt(eta))[:, None]], axis=1)
+        v = v + (alpha / eta) * d
+    info.iters = j
+    return v, Q, S, T, info
+
+
+@dataclasses.dataclass
+class NewtonRecord:
+    F: np.ndarray          # iterate after the step, (N, C)
+    v: np.ndarray          # representer weights of the step
+    Q: np.ndarray          # root of C_j at the end of the step
+    rhs: np.ndarray        # yhat - m of the step
+    info: SolveInfo
+    rel_change: float
+
+
+def iterncgp(apply_K: Apply, y: np.ndarray, C: int, steps: int,
+             policy: str = "cg", j_max: int = 100, rank_limit: Optional[int] = None,
+             recycle: bool = True, tol_abs: float = 1e-5, tol_rel: float = 1e-5,
+             outer_tol: Optional[float] = None,
+             user_actions: Optional[List[np.ndarray]] = None,
+             F0: Optional[np.ndarray] = None):
+    """Algorithm 1 for the softmax likelihood with m = 0 and f_0 = m.
+
+    ``apply_K`` applies the NC x NC prior covariance to CN-ordered vectors or
+    (NC, b) matrices.  Returns the list of NewtonRecord, one per step.
+    """
+    N = len(y)
+    n = N * C
+    F = np.zeros((N, C)) if F0 is None else np.array(F0, dtype=np.float64)
+    S, T = np.zeros((n, 0)), np.zeros((n, 0))
+    recs = []
+    for i in range(steps):
+        Wp = lik.softmax_hessian_pinv_blocks(F)
+        apply_Winv = (lambda Wp_: (lambda V: lik.apply_blocks(Wp_, V)))(Wp)
+        rhs = pseudo_target_offset(F, y)                  # yhat(f_i) - m
+        ua = None if user_actions is None else user_actions[i]
+        v, Q, S, T, info = itergp(apply_K, apply_Winv, rhs, S, T, policy, j_max,
+                                  tol_abs, tol_rel, rank_limit,
+                                  recycle and policy != "unit", ua)
+        F_new = apply_K(v).reshape(N, C)                  # f_{i+1} = K v + m
+        g_old, g_new = F.reshape(-1), F_new.reshape(-1)
+        nn = float(np.linalg.norm(g_new))
+        rel = float(np.linalg.norm(g_new - g_old) / nn) if nn > 0 else float("inf")
+        recs.append(NewtonRecord(F_new, v, Q, rhs, info, rel))
+        F = F_new
+        if outer_tol is not None and rel <= outer_tol:
+            break
+    return recs
+
+
+def itergp_diag_noise(apply_K: Apply, winv_diag: np.ndarray, rhs: np.ndarray,
+                      S: np.ndarray, T: np.ndarray, **kw):
+    """Algorithm 2 for a diagonal observation noise W^{-1} (Poisson, Gaussian)."""
+    return itergp(apply_K, lambda V: (winv_diag[:, None] * V) if V.ndim == 2 else winv_diag * V,
+                  rhs, S, T, **kw)

@@ -1,0 +1,98 @@
+"""Kernel functions, FP64, plain definitions.
+
+The paper names the kernels (RBF for the toy and Poisson experiments,
+Matern-3/2 for the Gaussian-mixture and MNIST experiments; appendix on
+experimental details) with a lengthscale and an outputscale.  We read the
+outputscale as a multiplicative variance (GPyTorch's ScaleKernel) and use the
+textbook forms (Rasmussen & Williams 2006, Sec. 4.2) with r = ||x - x'|| / l:
+
+    RBF         os * exp(-r^2 / 2)
+    Matern-1/2  os * exp(-r)
+    Matern-3/2  os * (1 + sqrt(3) r) exp(-sqrt(3) r)
+    Matern-5/2  os * (1 + sqrt(5) r + 5 r^2 / 3) exp(-sqrt(5) r)
+
+Distances are formed from explicit coordinate differences (no norm
+expansion), so the diagonal of K(X, X) is exactly os.
+
+Pins (tests/test_oracle_kernels.py): the Matern forms against the general
+Bessel-function definition (scipy.special.kv); RBF against the Gaussian
+density (scipy.stats.norm); brute-force double loop; symmetry, PSD, diagonal.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+KINDS = ("rbf", "matern12", "matern32", "matern52")
+
+
+def scaled_sqdist(X1: np.ndarray, X2: np.ndarray, lengthscale: float) -> np.ndarray:
+    """r^2 = ||x1 - x2||^2 / l^2 from explicit differences, shape (N1, N2)."""
+    X1 = np.asarray(X1, dtype=np.float64)
+    X2 = np.asarray(X2, dtype=np.float64)
+    r2 = np.zeros((X1.shape[0], X2.shape[0]))
+    for d in range(X1.shape[1]):
+        diff = X1[:, d, None] - X2[None, :, d]
+        r2 += diff * diff
+    return r2 / (lengthscale * lengthscale)
+
+
+def kernel_of_r2(r2: np.ndarray, kind: str, outputscale: float) -> np.ndarray:
+    """Stationary kernel value as a function of the scaled squared distance."""
+    r2 = np.asarray(r2, dtype=np.float64)
+    if kind == "rbf":
+        return outputscale * np.exp(-0.5 * r2)
+    r = np.sqrt(r2)
+    if kind == "matern12":
+        return outputscale * np.exp(-r)
+    if kind == "matern32":
+        a = math.sqrt(3.0) * r
+        return outputscale * (1.0 + a) * np.exp(-a)
+    if kind == "matern52":
+        a = math.sqrt(5.0) * r
+        return outputscale * (1.0 + a + a * a / 3.0) * np.exp(-a)
+    raise ValueError(f"unknown kernel {kind!r}")
+
+
+def kernel_matrix(X1, X2, kind: str, lengthscale: float, outputscale: float,
+                  block: int = 2048) -> np.ndarray:
+    """K_X[n, m] = k(x1_n, x2_m), shape (N1, N2), FP64."""
+    X1 = np.asarray(X1, dtype=np.float64)
+    X2 = np.asarray(X2, dtype=np.float64)
+    out = np.empty((X1.shape[0], X2.shape[0]))
+    for i0 in range(0, X1.shape[0], block):
+        out[i0:i0 + block] = kernel_of_r2(
+            scaled_sqdist(X1[i0:i0 + block], X2, lengthscale), kind, outputscale)
+    return out
+
+
+def kernel_matvec(X1, X2, V, kind: str, lengthscale: float, outputscale: float,
+                  block: int = 1024) -> np.ndarray:
+    """Out = K_X(X1, X2) @ V for V of shape (N2, W), blockwise over rows of X1
+    so that K is never held whole (the paper's lazily evaluated product with K,
+    appendix on matrix-vector products)."""
+    X1 = np.asarray(X1, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    out = np.empty((X1.shape[0],) + V.shape[1:])
+    for i0 in range(0, X1.shape[0], block):
+        Kb = kernel_matrix(X1[i0:i0 + block], X2, kind, lengthscale, outputscale)
+        out[i0:i0 + block] = Kb @ V
+    return out
+
+
+def full_kernel_cn(KX: np.ndarray, C: int) -> np.ndarray:
+    """The NC x NC prior covariance in CN-ordering (index n*C + c) when the C
+    latent functions are independent GPs sharing one kernel: K = K_X (x) I_C.
+    (Appendix on orderings: K is block diagonal in NC-ordering; re-indexed to
+    CN-ordering it is the Kronecker product with the identity on the right.)"""
+    return np.kron(KX, np.eye(C))
+
+
+def apply_full_kernel_cn(KX: np.ndarray, v: np.ndarray, C: int) -> np.ndarray:
+    """(K_X (x) I_C) v for CN-ordered v of length N*C (or shape (N*C, b))."""
+    N = KX.shape[0]
+    if v.ndim == 1:
+        return (KX @ v.reshape(N, C)).reshape(-1)
+    b = v.shape[1]
+    return np.einsum("nm,mcb->ncb", KX, v.reshape(N, C, b)).reshape(N * C, b)
