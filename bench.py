@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""IterNCGP Newton steps per second on one MI355X.
+
+Workload (N=20000, D=16, C=5): X ~ N(0, I_16), labels from the softmax of a
+GP draw, Matern-5/2 prior (lengthscale 2, outputscale 1); IterNCGP-CG with
+residual actions, at most 200 new actions per Newton step, compression to
+R=100 eigenpairs at every virtual solver run, FP32 matrix-free K products and
+FP64 reductions / projected solves.  One timed step = one Newton step
+(Algorithms 1-3) followed by the prediction (mean, variance, probit) at the
+2000 test points.  Inputs are seeded and synthetic and resident in HBM before
+timing starts.
+
+Prints one JSON line.  ``--gpus`` above 1 is refused: this build measures one
+GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# VALU issue slots per kernel evaluation of the fused product at small D with
+# the distance and the W-contraction on MFMA ("ALU roofline"):
+# transcendentals (v_sqrt_f32, v_exp_f32) take 4 slots each.
+VALU_SLOTS_PER_EVAL = {"rbf": 9, "matern12": 14, "matern32": 14, "matern52": 15}
+VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes x clock
+
+
+def cpu_baseline(w, k_products_per_step: float):
+    """Time the oracle's FP64 K.v product on a bounded slice of the workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import kernels as ok
+    rows = 4000
+    rng = np.random.default_rng(0)
+    v = rng.standard_normal((w.N, w.C))
+    t0 = time.perf_counter()
+    ok.kernel_matvec(w.X[:rows], w.X, v, w.kernel, w.lengthscale, w.outputscale)
+    dt = time.perf_counter() - t0
+    per_product = dt * (w.N / rows)
+    per_step = per_product * k_products_per_step
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    return {"value": 1.0 / per_step, "unit": "Newton steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": (f"oracle.kernels.kernel_matvec (FP64 numpy) on {rows} of the {w.N} rows "
+                       f"of one K.v product ({dt:.1f} s), scaled to a full product "
+                       f"({per_product:.1f} s) and to {k_products_per_step:.0f} products per "
+                       f"Newton step as measured on the GPU; elementwise numpy runs on one "
+                       f"thread, its matrix products on the BLAS pool")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; multi-GPU runs are not part of this build",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_2310_20285_amd import api
+
+    dev = torch.device("cuda:0")
+    w = datagen.config2()
+    dt = torch.float64 if args.precision == "fp64" else torch.float32
+    X = torch.tensor(w.X, dtype=dt, device=dev)
+    y = torch.tensor(w.y, dtype=torch.int32, device=dev)
+    Xs = torch.tensor(w.Xs, dtype=dt, device=dev)
+    jmax, R = 200, 100
+    m = api.IterNCGP(X, y, w.C, w.kernel, w.lengthscale, w.outputscale, policy="cg",
+                     j_max=jmax, rank_limit=R, recycle=True, tol_abs=1e-5, tol_rel=1e-5,
+                     precision=args.precision, max_buffer=jmax + R)
+
+    def step():
+        info = m.newton_step()
+        m.predict(Xs)
+        return info
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    m.set_profiling(True)
+    infos = []
+    pred_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos.append(m.newton_step())
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        m.predict(Xs)
+        b.record()
+        b.synchronize()
+        pred_ms.append(a.elapsed_time(b))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = m.profile()
+
+    elapsed = t1 - t0
+    value = args.steps / elapsed
+    kv_avg_s = prof["kv_ms"] / max(prof["kv_launches"], 1) / 1e3
+    evals_per_launch = float(w.N) * w.N
+    achieved_evals = evals_per_launch / kv_avg_s
+    peak_evals = VALU_LANE_OPS_PER_S / VALU_SLOTS_PER_EVAL[w.kernel]
+    kv_tflops = prof["kv_flops"] / max(prof["kv_launches"], 1) / kv_avg_s / 1e12
+    k_per_step = prof["kv_launches"] / max(prof["steps"], 1)
+
+    out = {
+        "metric": "IterNCGP Newton steps/s",
+        "value": value,
+        "unit": "Newton steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "gpc N=20000 D=16 C=5 matern52 l=2; IterNCGP-CG j<=200 R=100; "
+                               "predict 2000 test points per step",
+                   "N": w.N, "D": w.D, "C": w.C, "j_max": jmax, "rank_limit": R,
+                   "precision": args.precision, "test_points": int(Xs.shape[0])},
+        "roofline": {"bound": "alu", "achieved": achieved_evals / 1e9,
+                     "peak": peak_evals / 1e9, "unit": "Geval/s",
+                     "frac": achieved_evals / peak_evals, "traffic": None,
+                     "kernel": "fused K.v (kernel evaluation + contraction)",
+                     "avg_launch_us": kv_avg_s * 1e6},
+        "kv": {"launches": prof["kv_launches"], "avg_us": kv_avg_s * 1e6,
+               "tflops_algorithmic": kv_tflops, "k_products_per_step": k_per_step,
+               "share_of_step": prof["kv_ms"] / max(prof["step_ms"], 1e-9)},
+        "predict_latency_ms": {"p50": float(np.percentile(pred_ms, 50)),
+                               "p99": float(np.percentile(pred_ms, 99))},
+        "newton": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in i.items()
+                    if k in ("iters", "buffer_cols", "converged", "res_norm", "rel_change", "psi")}
+                   for i in infos],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, k_per_step)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

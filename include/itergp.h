@@ -1,0 +1,255 @@
+/*
+ * itergp.h -- C ABI of the MI355X (gfx950) IterNCGP hot path.
+ *
+ * Method: Tatzel, Wenger, Schneider, Hennig, "Accelerating Non-Conjugate
+ * Gaussian Processes By Trading Off Computation For Uncertainty" (TMLR 2025).
+ * Multi-class GP classification with a softmax likelihood, Laplace
+ * approximation and Newton's method, each Newton step solved approximately by
+ * IterGP (Algorithm 2) with recycling and compression (Algorithm 3) inside
+ * the IterNCGP outer loop (Algorithm 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named X*, V, Out, F, mean, var, probs, y, arena and ws are DEVICE
+ *   pointers owned by the caller.  The library never allocates device memory:
+ *   calls that need scratch space take a caller-provided workspace whose size
+ *   is given by the matching *_ws_bytes / *_state_bytes query.
+ * - Vectors in R^{NC} use CN-ordering (the paper's appendix on orderings):
+ *   entry n*C + c belongs to point n and latent function c.  A set of nb such
+ *   vectors is stored column by column: vector b starts at element b*ld.
+ * - Inputs X are row-major N x D.  Floating-point arrays are double when the
+ *   precision argument is IGP_FP64 and float otherwise (IGP_FP32, IGP_BF16).
+ * - Calls are asynchronous on the caller's HIP stream unless stated.
+ * - Return value: IGP_OK (0) or a negative igp_status.  No C++ exception
+ *   crosses this boundary.  igp_last_error() returns a thread-local message
+ *   describing the last failure of the calling thread.
+ * - All latent functions share one kernel k with the same hyperparameters,
+ *   as in every experiment of the paper, so K = K_X (x) I_C in CN-ordering.
+ */
+#ifndef ITERGP_H
+#define ITERGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status ------------------------------------------------------------ */
+typedef enum igp_status {
+  IGP_OK = 0,
+  IGP_EINVAL = -1,       /* bad shape, NULL pointer, non-finite hyperparameter */
+  IGP_ENOMEM = -2,       /* workspace or arena smaller than the query says */
+  IGP_EDEVICE = -3,      /* a HIP runtime call failed */
+  IGP_EUNSUPPORTED = -4  /* valid but not implemented combination */
+} igp_status;
+
+/* ---- kernels (paper: RBF and Matern kernels with a lengthscale and an
+ * outputscale; the outputscale multiplies).  With r = ||x - x'|| / l:
+ *   RBF os*exp(-r^2/2); Matern-1/2 os*exp(-r);
+ *   Matern-3/2 os*(1+sqrt3 r)exp(-sqrt3 r); Matern-5/2 os*(1+sqrt5 r+5r^2/3)exp(-sqrt5 r) */
+typedef enum igp_kernel_kind {
+  IGP_RBF = 0, IGP_MATERN12 = 1, IGP_MATERN32 = 2, IGP_MATERN52 = 3
+} igp_kernel_kind;
+
+typedef struct igp_kernel_params {
+  int32_t kind;          /* igp_kernel_kind */
+  int32_t reserved;      /* must be 0 */
+  double lengthscale;    /* > 0 */
+  double outputscale;    /* > 0 */
+} igp_kernel_params;
+
+/* ---- arithmetic of the kernel-matrix product ----------------------------
+ * IGP_FP64: FP64 throughout.  IGP_FP32: FP32 storage and arithmetic, FP64
+ * reductions in the solver.  IGP_BF16: as FP32, but the distance product
+ * X1 X2^T runs on BF16 MFMA with FP32 accumulation (inputs rounded to BF16,
+ * squared norms taken of the rounded values). */
+typedef enum igp_precision { IGP_FP64 = 0, IGP_FP32 = 1, IGP_BF16 = 2 } igp_precision;
+
+/* ======================================================================
+ * glm_kernel_matmul -- the matrix-free product with the prior covariance.
+ *
+ * Computes, for b = 0..nb-1,
+ *     Out_b <- (K_X(X1, X2) (x) I_C) V_b + beta * Out_b
+ * i.e. Out[n*C + c + b*ldo] = sum_m k(x1_n, x2_m) V[m*C + c + b*ldv] (+ beta*Out).
+ * This is the product w -> K w that Algorithms 1 and 2 take as input (the
+ * paper's appendix on matrix-vector products: K is evaluated lazily and
+ * never formed; cost quadratic in N).
+ *   kp      kernel and hyperparameters.
+ *   X1      n1 x d row-major (device), X2 n2 x d row-major (device).
+ *   V       nb vectors of length n2*C, vector b at V + b*ldv (ldv >= n2*C).
+ *   Out     nb vectors of length n1*C, vector b at Out + b*ldo (ldo >= n1*C);
+ *           must not alias V, X1 or X2.
+ *   beta    0 overwrites Out (Out may hold NaN then); otherwise accumulates.
+ *   precision  igp_precision; selects the element type (see conventions).
+ *   ws      device workspace of at least glm_kernel_matmul_ws_bytes(...) bytes.
+ * n1 == 0 or nb == 0 is a no-op; n2 == 0 gives Out = beta*Out.
+ * Errors: IGP_EINVAL (NULL pointer with non-zero size, d < 1, C < 1,
+ * ld too small, non-positive hyperparameter), IGP_ENOMEM (ws too small),
+ * IGP_EDEVICE (launch failure).
+ * ====================================================================== */
+size_t glm_kernel_matmul_ws_bytes(int64_t n1, int64_t n2, int64_t d, int64_t C,
+                                  int64_t nb, int32_t precision);
+int glm_kernel_matmul(const igp_kernel_params* kp,
+                      const void* X1, int64_t n1, const void* X2, int64_t n2, int64_t d,
+                      const void* V, int64_t C, int64_t nb, int64_t ldv,
+                      void* Out, int64_t ldo, double beta, int32_t precision,
+                      void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ======================================================================
+ * glm_softmax_hessian_apply -- products with the per-point C x C blocks of
+ * the negative Hessian of the softmax log likelihood at logits F.
+ *   mode IGP_W:       Out_n = W_n V_n,  W_n = diag(pi_n) - pi_n pi_n^T
+ *   mode IGP_W_PINV:  Out_n = W_n^+ V_n, W_n^+ = P diag(1/pi_n) P,
+ *                     P = I - 11^T/C  (the paper's explicit pseudo-inverse,
+ *                     appendix lemma for multi-class classification)
+ * with pi_n = softmax(F_n) formed in-kernel by log-sum-exp.
+ *   F      N x C logits (CN-ordered vector of length N*C).
+ *   V/Out  nb CN-ordered vectors (strides ldv, ldo >= N*C); Out may equal V.
+ *   precision IGP_FP64 (double) or IGP_FP32 (float).
+ * Cost O(N C) per vector.  Errors: IGP_EINVAL, IGP_EDEVICE.
+ * ====================================================================== */
+typedef enum igp_hessian_mode { IGP_W = 0, IGP_W_PINV = 1 } igp_hessian_mode;
+int glm_softmax_hessian_apply(const void* F, int64_t N, int64_t C,
+                              const void* V, int64_t nb, int64_t ldv,
+                              void* Out, int64_t ldo, int32_t mode, int32_t precision,
+                              hipStream_t stream);
+
+/* ======================================================================
+ * IterNCGP model: Algorithm 1 with Algorithm 2 (IterGP) as inner solver and
+ * Algorithm 3 (virtual solver run + compression) at the start of each step.
+ * ====================================================================== */
+typedef enum igp_policy {
+  IGP_POLICY_CG = 0,    /* s_j = r_{j-1} / ||r_{j-1}||  (residual actions = CG) */
+  IGP_POLICY_UNIT = 1,  /* s_j = e_j (partial Cholesky / subset of data); no recycling */
+  IGP_POLICY_USER = 2   /* s_j = column j-1 of caller-supplied actions; the step
+                           ends when they are used up */
+} igp_policy;
+
+typedef enum igp_residual_mode {
+  IGP_RESIDUAL_EXPLICIT = 0,    /* r = (yhat - m) - K v - W^+ v with a fresh K product */
+  IGP_RESIDUAL_RECURRENCE = 1   /* K v kept up to date from K d_j (one K product per iteration) */
+} igp_residual_mode;
+
+typedef struct igp_solver_config {
+  int32_t policy;        /* igp_policy */
+  int32_t j_max;         /* maximum new actions per Newton step (>= 0) */
+  int32_t rank_limit;    /* R: eigenpairs kept by the virtual solver run; < 0 = no limit */
+  int32_t recycle;       /* 1: run Algorithm 3 at the start of every Newton step */
+  double tol_abs;        /* inner stop: ||r|| < max(tol_abs, tol_rel ||yhat - m||) */
+  double tol_rel;
+  int32_t precision;     /* igp_precision of K products and NC-vector storage */
+  int32_t residual_mode; /* igp_residual_mode */
+  int32_t max_buffer;    /* columns reserved for S, T, Q (>= j_max; >= R + j_max
+                            with recycling and a rank limit) */
+  int32_t reserved;      /* must be 0 */
+} igp_solver_config;
+
+typedef struct igp_step_info {
+  int32_t iters;          /* new actions taken in this step (j at exit) */
+  int32_t buffer_cols;    /* columns of S, T, Q at exit */
+  int32_t recycled_cols;  /* columns kept by the virtual solver run */
+  int32_t eig_dropped;    /* eigenpairs dropped by the tiny-eigenvalue floor */
+  int32_t converged;      /* inner tolerance reached */
+  int32_t breakdown;      /* eta_j <= 0 met (the offending action was removed) */
+  int32_t k_products;     /* products with K issued (incl. the Newton update) */
+  int32_t reserved;
+  double res_norm;        /* last residual norm formed */
+  double rhs_norm;        /* ||yhat - m|| */
+  double eta_min;         /* smallest accepted eta_j */
+  double rel_change;      /* ||g_{i+1} - g_i|| / ||g_{i+1}|| */
+  double psi;             /* log posterior at f_{i+1}: log p(y|f) - g^T v / 2 (FP64) */
+} igp_step_info;
+
+typedef struct igp_model igp_model;
+
+/* Device bytes needed for a model of N points, D features, C classes. */
+size_t itergp_state_bytes(int64_t N, int64_t D, int64_t C, const igp_solver_config* cfg);
+
+/* Create a model with f_0 = m = 0 and empty buffers (Algorithm 1, start).
+ *   X      N x D row-major (double for IGP_FP64, float otherwise); copied
+ *          into the arena, the caller may free it after the call returns.
+ *   y      N int32 labels in [0, C); read by every Newton step, so the
+ *          caller keeps it alive for the model's lifetime.
+ *   arena  device memory of >= itergp_state_bytes(...) bytes, 256-byte
+ *          aligned, owned by the caller, alive for the model's lifetime.
+ * Synchronises `stream`.  The model runs all its work on `stream`. */
+int itergp_init(igp_model** out, const igp_kernel_params* kp, const igp_solver_config* cfg,
+                const void* X, const int32_t* y, int64_t N, int64_t D, int64_t C,
+                void* arena, size_t arena_bytes, hipStream_t stream);
+
+/* Actions for IGP_POLICY_USER in the next Newton step: ncols CN-ordered
+ * vectors of length N*C (device, element type of the model), column j at
+ * actions + j*ld.  The pointer must stay valid until that step returns. */
+int itergp_set_user_actions(igp_model* m, const void* actions, int64_t ncols, int64_t ld);
+
+/* One Newton step (the body of Algorithm 1's loop):
+ *   pseudo-targets yhat - m = g + W(f)^+ (onehot(y) - pi);
+ *   C_0, S, T <- virtual solver run (Algorithm 3), if recycling;
+ *   v <- IterGP (Algorithm 2);  f <- K v + m.
+ * Host control flow; synchronises the model's stream.  info may be NULL. */
+int itergp_newton_step(igp_model* m, igp_step_info* info);
+
+/* Predictive mean, marginal variance and probit class probabilities at Xs
+ * (paper eqs. for m_{i,j} and k_{i,j}; probit as in its large-scale
+ * experiment), using the v and root Q of the last Newton step:
+ *   mean[s*C+c] = sum_n k(xs_s, x_n) v[n*C+c]
+ *   var[s*C+c]  = k(xs,xs) - sum_b (sum_n k(xs_s, x_n) Q[n*C+c, b])^2
+ *   probs[s*C+c]= softmax_c(mean / sqrt(1 + pi/8 var))
+ *   Xs   Ns x D row-major (model element type); mean (required), var and
+ *        probs (nullable) Ns*C each.  probs requires var.
+ *   ws   >= itergp_predict_ws_bytes(m, Ns) bytes. Asynchronous on `stream`. */
+size_t itergp_predict_ws_bytes(const igp_model* m, int64_t Ns);
+int itergp_predict(const igp_model* m, const void* Xs, int64_t Ns, void* mean,
+                   void* var, void* probs, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Read-only device views into the model state (for tests and checkpoints).
+ *   which: IGP_VIEW_F (N*C logits f_i), IGP_VIEW_V (representer weights),
+ *   IGP_VIEW_Q / IGP_VIEW_S / IGP_VIEW_T (rows=N*C, cols=buffer columns,
+ *   column j at ptr + j*ld), IGP_VIEW_RHS (yhat - m of the last step),
+ *   IGP_VIEW_X (the model's copy of X; centred for FP32/BF16). */
+typedef enum igp_view {
+  IGP_VIEW_F = 0, IGP_VIEW_V = 1, IGP_VIEW_Q = 2, IGP_VIEW_S = 3, IGP_VIEW_T = 4,
+  IGP_VIEW_RHS = 5, IGP_VIEW_X = 6
+} igp_view;
+int itergp_get_view(const igp_model* m, int32_t which, const void** ptr,
+                    int64_t* rows, int64_t* cols, int64_t* ld);
+
+/* Tracing: device time of the kernel-matrix products inside Newton steps,
+ * measured with HIP events recorded on the model's stream around each
+ * product (kernel evaluation, reduction of split partials).  Counters cover
+ * every itergp_newton_step since the last itergp_set_profiling call. */
+typedef struct igp_profile {
+  int64_t kv_launches;   /* products timed */
+  double kv_ms;          /* sum of their device durations, milliseconds */
+  double kv_evals;       /* kernel evaluations, sum of n1*n2 */
+  double kv_flops;       /* algorithmic flops, sum of 2*n1*n2*(d + C*nb) */
+  double step_ms;        /* device time of whole Newton steps (first to last kernel) */
+  int64_t steps;         /* Newton steps timed */
+} igp_profile;
+int itergp_set_profiling(igp_model* m, int32_t enable);   /* enables/disables and resets */
+int itergp_get_profile(const igp_model* m, igp_profile* out);
+
+/* Release the host-side handle (the arena stays the caller's). */
+int itergp_destroy(igp_model* m);
+
+/* Thread-local description of the last error of this thread ("" if none). */
+const char* igp_last_error(void);
+
+/* Library version string. */
+const char* igp_version(void);
+
+/* The host FP64 symmetric eigensolver used by Algorithm 3 for M = U Lambda U^T
+ * (host pointers, no device work):  A is n x n row-major symmetric (only its
+ * lower triangle is read); on return w holds the eigenvalues in decreasing
+ * order and Z (n x n, column k at Z + k*n) the matching orthonormal
+ * eigenvectors.  Errors: IGP_EINVAL (n < 0 or NULL pointer with n > 0),
+ * IGP_EDEVICE (no convergence). */
+int igp_host_eigh(int32_t n, const double* A, double* w, double* Z);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ITERGP_H */

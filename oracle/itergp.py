@@ -107,7 +107,8 @@ def itergp(apply_K: Apply, apply_Winv: Apply, rhs: np.ndarray,
     """Algorithm 2 for the system Khat v = rhs (rhs = yhat - m).
 
     Returns (v, Q, S, T, info).  ``policy`` is "cg" (s_j = r_{j-1}), "unit"
-    (s_j = e_j) or "user" (s_j = user_actions[:, j-1]).
+    (s_j = e_j) or "user" (s_j = user_actions[:, j-1]; the solve ends when the
+    supplied actions are used up).
     """
     n = rhs.shape[0]
     if recycle:
@@ -127,6 +128,8 @@ def itergp(apply_K: Apply, apply_Winv: Apply, rhs: np.ndarray,
         if rn < thresh:
             info.converged = True
             break
+        if policy == "user" and j >= user_actions.shape[1]:
+            break                                        # supplied actions used up
         j += 1
         if policy == "cg":
             s = r / rn if normalize_actions else r.copy()

@@ -1,0 +1,198 @@
+"""PyTorch-facing binding of the C ABI (include/itergp.h).
+
+Tensors are used only to hold device memory; every call hands raw device
+pointers, sizes and the current HIP stream to the library, where all of the
+arithmetic runs.  Names follow the C entry points.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+from typing import Optional
+
+import torch
+
+from . import _lib as L
+
+_DTYPE = {L.IGP_FP64: torch.float64, L.IGP_FP32: torch.float32, L.IGP_BF16: torch.float32}
+
+
+def _prec(p) -> int:
+    return L.PRECISION_CODE[p] if isinstance(p, str) else int(p)
+
+
+def _kind(k) -> int:
+    return L.KIND_CODE[k] if isinstance(k, str) else int(k)
+
+
+def _stream() -> ct.c_void_p:
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> ct.c_void_p:
+    return ct.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _need(t: torch.Tensor, dtype, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def kernel_params(kind, lengthscale, outputscale) -> L.KernelParams:
+    return L.KernelParams(_kind(kind), 0, float(lengthscale), float(outputscale))
+
+
+def glm_kernel_matmul(X1: torch.Tensor, X2: torch.Tensor, V: torch.Tensor, C: int, kind,
+                      lengthscale: float, outputscale: float, precision="fp32",
+                      beta: float = 0.0, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Out_b = (K_X(X1, X2) (x) I_C) V_b (+ beta Out_b).
+
+    V: (n2*C,) or (nb, n2*C) -- each row one CN-ordered vector.  Returns a
+    tensor of the same layout with n1*C entries per vector.
+    """
+    lib = L.load()
+    p = _prec(precision)
+    dt = _DTYPE[p]
+    for t, nm in ((X1, "X1"), (X2, "X2"), (V, "V")):
+        _need(t, dt, nm)
+    n1, d = X1.shape
+    n2 = X2.shape[0]
+    vec = V.dim() == 1
+    V2 = V.view(1, -1) if vec else V
+    nb = V2.shape[0]
+    if V2.shape[1] != n2 * C:
+        raise ValueError("V rows must have n2*C entries")
+    if out is None:
+        out = torch.empty((nb, n1 * C), dtype=dt, device=X1.device)
+    O2 = out.view(nb, n1 * C)
+    wsb = lib.glm_kernel_matmul_ws_bytes(n1, n2, d, C, nb, p)
+    ws = torch.empty(max(int(wsb), 1), dtype=torch.uint8, device=X1.device)
+    kp = kernel_params(kind, lengthscale, outputscale)
+    L.check(lib.glm_kernel_matmul(ct.byref(kp), _ptr(X1), n1, _ptr(X2), n2, d, _ptr(V2), C, nb,
+                                  n2 * C, _ptr(O2), n1 * C, float(beta), p, _ptr(ws), wsb,
+                                  _stream()))
+    return out.view(-1) if vec else out
+
+
+def glm_softmax_hessian_apply(F: torch.Tensor, V: torch.Tensor, mode="pinv",
+                              out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Out_n = W_n V_n (mode "w") or W_n^+ V_n (mode "pinv"); F is (N, C)."""
+    lib = L.load()
+    dt = F.dtype
+    p = L.IGP_FP64 if dt == torch.float64 else L.IGP_FP32
+    _need(F, dt, "F")
+    _need(V, dt, "V")
+    N, C = F.shape
+    vec = V.dim() == 1
+    V2 = V.view(1, -1) if vec else V
+    nb = V2.shape[0]
+    if out is None:
+        out = torch.empty_like(V2)
+    m = L.IGP_W_PINV if mode == "pinv" else L.IGP_W
+    L.check(lib.glm_softmax_hessian_apply(_ptr(F), N, C, _ptr(V2), nb, N * C, _ptr(out), N * C,
+                                          m, p, _stream()))
+    return out.view(-1) if vec else out
+
+
+def solver_config(policy="cg", j_max=100, rank_limit=-1, recycle=True, tol_abs=1e-5,
+                  tol_rel=1e-5, precision="fp32", residual_mode="explicit",
+                  max_buffer=None) -> L.SolverConfig:
+    pol = {"cg": L.IGP_POLICY_CG, "unit": L.IGP_POLICY_UNIT, "user": L.IGP_POLICY_USER}[policy]
+    rm = {"explicit": L.IGP_RESIDUAL_EXPLICIT,
+          "recurrence": L.IGP_RESIDUAL_RECURRENCE}[residual_mode]
+    if max_buffer is None:
+        max_buffer = j_max + (rank_limit if rank_limit is not None and rank_limit >= 0 else j_max)
+        max_buffer = max(max_buffer, 1)
+    return L.SolverConfig(pol, int(j_max), int(-1 if rank_limit is None else rank_limit),
+                          1 if recycle else 0, float(tol_abs), float(tol_rel), _prec(precision),
+                          rm, int(max_buffer), 0)
+
+
+class IterNCGP:
+    """A model handle: itergp_init / itergp_newton_step / itergp_predict."""
+
+    def __init__(self, X: torch.Tensor, y: torch.Tensor, C: int, kind, lengthscale: float,
+                 outputscale: float, **cfg):
+        self.lib = L.load()
+        self.cfg = solver_config(**cfg)
+        self.precision = self.cfg.precision
+        self.dtype = _DTYPE[self.precision]
+        _need(X, self.dtype, "X")
+        _need(y, torch.int32, "y")
+        self.N, self.D = X.shape
+        self.C = int(C)
+        self.y = y                       # kept alive: the model reads it every step
+        self.kp = kernel_params(kind, lengthscale, outputscale)
+        nbytes = self.lib.itergp_state_bytes(self.N, self.D, self.C, ct.byref(self.cfg))
+        if nbytes == 0:
+            raise ValueError("invalid model configuration")
+        self.arena = torch.empty(int(nbytes), dtype=torch.uint8, device=X.device)
+        self.handle = ct.c_void_p()
+        L.check(self.lib.itergp_init(ct.byref(self.handle), ct.byref(self.kp),
+                                     ct.byref(self.cfg), _ptr(X), _ptr(y), self.N, self.D,
+                                     self.C, _ptr(self.arena), nbytes, _stream()))
+        self._user = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.itergp_destroy(h)
+            self.handle = None
+
+    def newton_step(self) -> dict:
+        info = L.StepInfo()
+        L.check(self.lib.itergp_newton_step(self.handle, ct.byref(info)))
+        return info.as_dict()
+
+    def set_profiling(self, enable: bool = True):
+        L.check(self.lib.itergp_set_profiling(self.handle, 1 if enable else 0))
+
+    def profile(self) -> dict:
+        p = L.Profile()
+        L.check(self.lib.itergp_get_profile(self.handle, ct.byref(p)))
+        return p.as_dict()
+
+    def set_user_actions(self, actions: torch.Tensor):
+        """actions: (ncols, N*C), row j is the action of iteration j+1."""
+        _need(actions, self.dtype, "actions")
+        self._user = actions
+        L.check(self.lib.itergp_set_user_actions(self.handle, _ptr(actions), actions.shape[0],
+                                                 actions.shape[1]))
+
+    def view(self, which) -> torch.Tensor:
+        """A copy of a state buffer: vectors as (N*C,), buffers as (cols, N*C)."""
+        ptr, rows, cols, ld = ct.c_void_p(), ct.c_int64(), ct.c_int64(), ct.c_int64()
+        L.check(self.lib.itergp_get_view(self.handle, which, ct.byref(ptr), ct.byref(rows),
+                                         ct.byref(cols), ct.byref(ld)))
+        torch.cuda.synchronize()
+        esz = torch.empty(0, dtype=self.dtype).element_size()
+        off = (ptr.value or 0) - self.arena.data_ptr()
+        if cols.value == 0:
+            return torch.empty((0, rows.value), dtype=self.dtype, device=self.arena.device)
+        span = ((cols.value - 1) * ld.value + rows.value) * esz
+        raw = self.arena[off:off + span]
+        full = raw.view(self.dtype)
+        if which in (L.IGP_VIEW_Q, L.IGP_VIEW_S, L.IGP_VIEW_T):
+            out = torch.stack([full[b * ld.value: b * ld.value + rows.value]
+                               for b in range(cols.value)])
+            return out.clone()
+        if which == L.IGP_VIEW_X:
+            return full[: rows.value * cols.value].view(rows.value, cols.value).clone()
+        return full[: rows.value].clone()
+
+    def predict(self, Xs: torch.Tensor, var: bool = True, probs: bool = True):
+        _need(Xs, self.dtype, "Xs")
+        Ns = Xs.shape[0]
+        mean = torch.empty(Ns * self.C, dtype=self.dtype, device=Xs.device)
+        v = torch.empty_like(mean) if var else None
+        p = torch.empty_like(mean) if (probs and var) else None
+        wsb = self.lib.itergp_predict_ws_bytes(self.handle, Ns)
+        ws = torch.empty(max(int(wsb), 1), dtype=torch.uint8, device=Xs.device)
+        L.check(self.lib.itergp_predict(self.handle, _ptr(Xs), Ns, _ptr(mean), _ptr(v), _ptr(p),
+                                        _ptr(ws), wsb, _stream()))
+        shape = (Ns, self.C)
+        return (mean.view(shape), None if v is None else v.view(shape),
+                None if p is None else p.view(shape))

@@ -1,0 +1,188 @@
+// Softmax likelihood pieces, one thread per data point with its C logits in
+// registers (CN-ordering keeps a point's C entries contiguous, so a wave's
+// loads cover one contiguous 64*C-element span).
+//
+//   pi_n  = softmax(F_n)                          (log-sum-exp)
+//   rhs_n = F_n + W_n^+ (onehot(y_n) - pi_n)       pseudo-targets minus m (m = 0)
+//   W_n   v = pi_n * v - pi_n (pi_n^T v)
+//   W_n^+ v = P ((P v) / pi_n),  P = I - 11^T / C  (explicit pseudo-inverse from
+//             the paper's appendix lemma for multi-class classification)
+#include "ops.hpp"
+
+namespace igp {
+namespace {
+
+template <typename T, int CMAX>
+__device__ inline void load_softmax(const T* F, int64_t n, int C, T (&p)[CMAX]) {
+  T mx = -INFINITY;
+#pragma unroll
+  for (int c = 0; c < CMAX; ++c)
+    if (c < C) {
+      p[c] = F[n * C + c];
+      mx = p[c] > mx ? p[c] : mx;
+    }
+  T sum = T(0);
+#pragma unroll
+  for (int c = 0; c < CMAX; ++c)
+    if (c < C) {
+      p[c] = exp(p[c] - mx);
+      sum += p[c];
+    }
+  const T inv = T(1) / sum;
+#pragma unroll
+  for (int c = 0; c < CMAX; ++c)
+    if (c < C) p[c] *= inv;
+}
+
+// u <- W^+ u  (mode 1)  or  u <- W u  (mode 0), in place
+template <typename T, int CMAX>
+__device__ inline void apply_block(int mode, int C, const T (&p)[CMAX], T (&u)[CMAX]) {
+  if (mode == IGP_W_PINV) {
+    T m = T(0);
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c)
+      if (c < C) m += u[c];
+    m /= T(C);
+    T m2 = T(0);
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c)
+      if (c < C) {
+        u[c] = (u[c] - m) / p[c];
+        m2 += u[c];
+      }
+    m2 /= T(C);
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c)
+      if (c < C) u[c] -= m2;
+  } else {
+    T pv = T(0);
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c)
+      if (c < C) pv += p[c] * u[c];
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c)
+      if (c < C) u[c] = p[c] * u[c] - p[c] * pv;
+  }
+}
+
+template <typename T, int CMAX>
+__global__ void __launch_bounds__(256)
+k_softmax_pi_rhs(const T* __restrict__ F, const int32_t* __restrict__ y, int64_t N, int C,
+                 T* __restrict__ pi, T* __restrict__ rhs, double* __restrict__ ll_part) {
+  __shared__ double red[4];
+  const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  double ll = 0.0;
+  if (n < N) {
+    T p[CMAX], u[CMAX];
+    load_softmax<T, CMAX>(F, n, C, p);
+    const int yn = y[n];
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c)
+      if (c < C) {
+        u[c] = (c == yn ? T(1) : T(0)) - p[c];
+        pi[n * C + c] = p[c];
+      }
+    // log p(y_n | f_n) = f_y - lse(f_n), in FP64
+    double mx = -INFINITY;
+    for (int c = 0; c < C; ++c) mx = fmax(mx, static_cast<double>(F[n * C + c]));
+    double se = 0.0;
+    for (int c = 0; c < C; ++c) se += exp(static_cast<double>(F[n * C + c]) - mx);
+    ll = static_cast<double>(F[n * C + yn]) - mx - log(se);
+    apply_block<T, CMAX>(IGP_W_PINV, C, p, u);
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c)
+      if (c < C) rhs[n * C + c] = F[n * C + c] + u[c];
+  }
+  const double s = block_sum(ll, red);
+  if (threadIdx.x == 0) ll_part[blockIdx.x] = s;
+}
+
+template <typename T, int CMAX>
+__global__ void __launch_bounds__(256)
+k_winv_apply(const T* __restrict__ pi, int logits, int mode, int64_t N, int C,
+             const T* __restrict__ V, int64_t nb, int64_t ldv, const T* __restrict__ Add,
+             int64_t lda, T* __restrict__ Out, int64_t ldo) {
+  const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  const int64_t b = blockIdx.y;
+  if (n >= N || b >= nb) return;
+  T p[CMAX], u[CMAX];
+  if (logits) {
+    load_softmax<T, CMAX>(pi, n, C, p);
+  } else {
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c)
+      if (c < C) p[c] = pi[n * C + c];
+  }
+#pragma unroll
+  for (int c = 0; c < CMAX; ++c)
+    if (c < C) u[c] = V[b * ldv + n * C + c];
+  apply_block<T, CMAX>(mode, C, p, u);
+#pragma unroll
+  for (int c = 0; c < CMAX; ++c)
+    if (c < C) {
+      T o = u[c];
+      if (Add) o += Add[b * lda + n * C + c];
+      Out[b * ldo + n * C + c] = o;
+    }
+}
+
+}  // namespace
+
+#define IGP_DISPATCH_C(C, BODY)                    \
+  do {                                             \
+    if ((C) <= 4) {                                \
+      constexpr int CM = 4;                        \
+      BODY;                                        \
+    } else if ((C) <= 8) {                         \
+      constexpr int CM = 8;                        \
+      BODY;                                        \
+    } else if ((C) <= 16) {                        \
+      constexpr int CM = 16;                       \
+      BODY;                                        \
+    } else {                                       \
+      constexpr int CM = 64;                       \
+      BODY;                                        \
+    }                                              \
+  } while (0)
+
+template <typename T>
+int softmax_pi_rhs(const T* F, const int32_t* y, int64_t N, int64_t C, T* pi, T* rhs,
+                   double* ll_part, int* nblocks_out, hipStream_t s) {
+  if (C > 64) {
+    set_error("C = %lld classes exceeds the supported maximum of 64", (long long)C);
+    return IGP_EUNSUPPORTED;
+  }
+  const int blocks = static_cast<int>(ceil_div(N, 256));
+  *nblocks_out = blocks;
+  if (blocks == 0) return IGP_OK;
+  IGP_DISPATCH_C(C, (k_softmax_pi_rhs<T, CM><<<blocks, 256, 0, s>>>(F, y, N, (int)C, pi, rhs, ll_part)));
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template <typename T>
+int winv_apply(const T* pi, bool pi_is_logits, int mode, int64_t N, int64_t C, const T* V,
+               int64_t nb, int64_t ldv, const T* Add, int64_t lda, T* Out, int64_t ldo,
+               hipStream_t s) {
+  if (C > 64) {
+    set_error("C = %lld classes exceeds the supported maximum of 64", (long long)C);
+    return IGP_EUNSUPPORTED;
+  }
+  if (N == 0 || nb == 0) return IGP_OK;
+  dim3 grid(static_cast<unsigned>(ceil_div(N, 256)), static_cast<unsigned>(nb));
+  IGP_DISPATCH_C(C, (k_winv_apply<T, CM><<<grid, 256, 0, s>>>(pi, pi_is_logits ? 1 : 0, mode, N, (int)C, V, nb, ldv, Add, lda, Out, ldo)));
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template int softmax_pi_rhs<float>(const float*, const int32_t*, int64_t, int64_t, float*,
+                                   float*, double*, int*, hipStream_t);
+template int softmax_pi_rhs<double>(const double*, const int32_t*, int64_t, int64_t, double*,
+                                    double*, double*, int*, hipStream_t);
+template int winv_apply<float>(const float*, bool, int, int64_t, int64_t, const float*, int64_t,
+                               int64_t, const float*, int64_t, float*, int64_t, hipStream_t);
+template int winv_apply<double>(const double*, bool, int, int64_t, int64_t, const double*,
+                                int64_t, int64_t, const double*, int64_t, double*, int64_t,
+                                hipStream_t);
+
+}  // namespace igp

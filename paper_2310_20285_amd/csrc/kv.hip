@@ -1,0 +1,207 @@
+// Matrix-free product with the prior covariance, K_X(X1, X2) V, with the
+// kernel evaluated on the fly and never stored (the paper's lazily evaluated
+// products with K, appendix on matrix-vector products).
+//
+// kv_valu: tiled VALU kernel, FP64 or FP32.  A workgroup owns 64 output rows
+// and a contiguous range of X2 columns (split-N2 for occupancy); each of its
+// four waves evaluates k on 64 rows x 16 columns of every 64-column X2 tile
+// from explicit coordinate differences, then accumulates against the V tile
+// staged in LDS.  Partial sums per split are reduced in a fixed order by
+// kv_reduce, so results do not depend on scheduling.
+#include "ops.hpp"
+
+namespace igp {
+namespace {
+
+constexpr int TM = 64;    // rows of X1 per workgroup
+constexpr int TN = 64;    // columns of X2 per tile
+constexpr int DC = 32;    // feature chunk staged in LDS
+
+template <typename T, int KIND, int WC>
+__global__ void __launch_bounds__(256)
+kv_valu(const T* __restrict__ X1, const T* __restrict__ X2, int64_t n1, int64_t n2, int d,
+        const T* __restrict__ V, int C, int W, int64_t ldv, T* __restrict__ P,
+        int64_t cols_per_split, T inv_l2, const int* skip) {
+  if (skip && *skip) return;
+  constexpr int TILE_BYTES = 2 * TM * (DC + 1) * sizeof(T);
+  constexpr int RED_BYTES = 4 * TM * WC * sizeof(T);
+  constexpr int U_BYTES = TILE_BYTES > RED_BYTES ? TILE_BYTES : RED_BYTES;
+  __shared__ __align__(16) unsigned char smem[U_BYTES];
+  __shared__ T sV[TN][WC];
+  T(*sX1)[DC + 1] = reinterpret_cast<T(*)[DC + 1]>(smem);
+  T(*sX2)[DC + 1] = reinterpret_cast<T(*)[DC + 1]>(smem + TM * (DC + 1) * sizeof(T));
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * TM;
+  const int w0 = blockIdx.z * WC;
+  const int64_t m_begin = static_cast<int64_t>(blockIdx.y) * cols_per_split;
+  const int64_t m_end = m_begin + cols_per_split < n2 ? m_begin + cols_per_split : n2;
+
+  T acc[WC];
+#pragma unroll
+  for (int w = 0; w < WC; ++w) acc[w] = T(0);
+
+  for (int64_t m0 = m_begin; m0 < m_end; m0 += TN) {
+    T r2[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) r2[c] = T(0);
+    for (int k0 = 0; k0 < d; k0 += DC) {
+      for (int e = tid; e < TM * DC; e += 256) {
+        const int i = e / DC, k = e % DC, gk = k0 + k;
+        const int64_t gi = r0 + i, gm = m0 + i;
+        sX1[i][k] = (gi < n1 && gk < d) ? X1[gi * d + gk] : T(0);
+        sX2[i][k] = (gm < m_end && gk < d) ? X2[gm * d + gk] : T(0);
+      }
+      __syncthreads();
+      const int kmax = d - k0 < DC ? d - k0 : DC;
+      for (int k = 0; k < kmax; ++k) {
+        const T a = sX1[lane][k];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const T df = a - sX2[wv * 16 + c][k];
+          r2[c] += df * df;
+        }
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < TN * WC; e += 256) {
+      const int m = e / WC, w = e % WC, gw = w0 + w;
+      const int64_t gm = m0 + m;
+      T val = T(0);
+      if (gm < m_end && gw < W) val = V[(gw / C) * ldv + gm * C + (gw % C)];
+      sV[m][w] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const T kv = kfun<KIND>(r2[c] * inv_l2);
+#pragma unroll
+      for (int w = 0; w < WC; ++w) acc[w] += kv * sV[wv * 16 + c][w];
+    }
+    __syncthreads();
+  }
+
+  T(*sRed)[TM][WC] = reinterpret_cast<T(*)[TM][WC]>(smem);
+#pragma unroll
+  for (int w = 0; w < WC; ++w) sRed[wv][lane][w] = acc[w];
+  __syncthreads();
+  for (int e = tid; e < TM * WC; e += 256) {
+    const int i = e / WC, w = e % WC;
+    const int64_t gi = r0 + i;
+    if (gi < n1 && w0 + w < W) {
+      const T s = sRed[0][i][w] + sRed[1][i][w] + sRed[2][i][w] + sRed[3][i][w];
+      P[(static_cast<int64_t>(blockIdx.y) * n1 + gi) * W + w0 + w] = s;
+    }
+  }
+}
+
+template <typename T>
+__global__ void kv_reduce(const T* __restrict__ P, int nsplit, int64_t n1, int W, int C,
+                          T* __restrict__ Out, int64_t ldo, T os, T beta, const int* skip) {
+  if (skip && *skip) return;
+  const int64_t total = n1 * W;
+  for (int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; idx < total;
+       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t n = idx / W;
+    const int w = static_cast<int>(idx % W);
+    T s = T(0);
+    for (int sp = 0; sp < nsplit; ++sp) s += P[(sp * n1 + n) * W + w];
+    T* o = Out + (w / C) * ldo + n * C + (w % C);
+    *o = (beta != T(0)) ? os * s + beta * *o : os * s;
+  }
+}
+
+struct SplitPlan {
+  int wc, gx, gz, nsplit;
+  int64_t cols_per_split;
+};
+
+SplitPlan plan_valu(int64_t n1, int64_t n2, int64_t W) {
+  SplitPlan p{};
+  p.wc = W <= 4 ? 4 : (W <= 8 ? 8 : 16);
+  p.gx = static_cast<int>(ceil_div(n1, TM));
+  p.gz = static_cast<int>(ceil_div(W, p.wc));
+  const int64_t tiles = ceil_div(n2, TN);
+  int64_t want = ceil_div(2048, static_cast<int64_t>(p.gx) * p.gz);
+  if (want < 1) want = 1;
+  if (want > tiles) want = tiles;
+  if (tiles == 0) {
+    p.nsplit = 0;
+    p.cols_per_split = TN;
+    return p;
+  }
+  p.cols_per_split = ceil_div(tiles, want) * TN;
+  p.nsplit = static_cast<int>(ceil_div(n2, p.cols_per_split));
+  return p;
+}
+
+template <typename T, int KIND>
+void launch_valu_kind(const KVProblem& p, const SplitPlan& sp, T* P, hipStream_t s) {
+  dim3 grid(sp.gx, sp.nsplit, sp.gz);
+  const T inv_l2 = static_cast<T>(1.0 / (p.kp.lengthscale * p.kp.lengthscale));
+  const int W = static_cast<int>(p.C * p.nb);
+  const T* X1 = static_cast<const T*>(p.X1);
+  const T* X2 = static_cast<const T*>(p.X2);
+  const T* V = static_cast<const T*>(p.V);
+  const int d = static_cast<int>(p.d), C = static_cast<int>(p.C);
+  if (sp.wc == 4)
+    kv_valu<T, KIND, 4><<<grid, 256, 0, s>>>(X1, X2, p.n1, p.n2, d, V, C, W, p.ldv, P,
+                                             sp.cols_per_split, inv_l2, p.skip);
+  else if (sp.wc == 8)
+    kv_valu<T, KIND, 8><<<grid, 256, 0, s>>>(X1, X2, p.n1, p.n2, d, V, C, W, p.ldv, P,
+                                             sp.cols_per_split, inv_l2, p.skip);
+  else
+    kv_valu<T, KIND, 16><<<grid, 256, 0, s>>>(X1, X2, p.n1, p.n2, d, V, C, W, p.ldv, P,
+                                              sp.cols_per_split, inv_l2, p.skip);
+}
+
+template <typename T>
+int launch_valu(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t s) {
+  const int64_t W = p.C * p.nb;
+  SplitPlan sp = plan_valu(p.n1, p.n2, W);
+  const size_t need = static_cast<size_t>(sp.nsplit) * p.n1 * W * sizeof(T);
+  if (need > ws_bytes) {
+    set_error("kernel-product workspace too small: need %zu bytes, have %zu", need, ws_bytes);
+    return IGP_ENOMEM;
+  }
+  T* P = static_cast<T*>(ws);
+  if (sp.nsplit > 0) {
+    switch (p.kp.kind) {
+      case IGP_RBF: launch_valu_kind<T, IGP_RBF>(p, sp, P, s); break;
+      case IGP_MATERN12: launch_valu_kind<T, IGP_MATERN12>(p, sp, P, s); break;
+      case IGP_MATERN32: launch_valu_kind<T, IGP_MATERN32>(p, sp, P, s); break;
+      default: launch_valu_kind<T, IGP_MATERN52>(p, sp, P, s); break;
+    }
+    IGP_CHECK_LAUNCH();
+  }
+  const int64_t total = p.n1 * W;
+  int blocks = static_cast<int>(ceil_div(total, 256));
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  kv_reduce<T><<<blocks, 256, 0, s>>>(P, sp.nsplit, p.n1, static_cast<int>(W),
+                                      static_cast<int>(p.C), static_cast<T*>(p.Out), p.ldo,
+                                      static_cast<T>(p.kp.outputscale), static_cast<T>(p.beta),
+                                      p.skip);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+}  // namespace
+
+size_t kv_ws_bytes(int64_t n1, int64_t n2, int64_t d, int64_t C, int64_t nb, int precision) {
+  (void)d;
+  const int64_t W = C * nb;
+  SplitPlan sp = plan_valu(n1, n2, W);
+  const size_t elt = precision == IGP_FP64 ? sizeof(double) : sizeof(float);
+  return align_up(static_cast<size_t>(sp.nsplit) * n1 * W * elt + 256);
+}
+
+int kv_launch(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (p.n1 == 0 || p.nb == 0) return IGP_OK;
+  if (p.precision == IGP_FP64) return launch_valu<double>(p, ws, ws_bytes, s);
+  if (p.precision == IGP_FP32) return launch_valu<float>(p, ws, ws_bytes, s);
+  set_error("IGP_BF16 kernel product is not available in this build");
+  return IGP_EUNSUPPORTED;
+}
+
+}  // namespace igp

@@ -1,0 +1,532 @@
+// Skinny linear algebra of the IterGP loop and of the virtual solver run.
+// Every reduction accumulates in FP64 and is finished by a single block in a
+// fixed order, so repeated runs are bitwise identical.
+//
+// Buffers S, T, Q are stored column by column: column b of an n-row buffer
+// starts at element b*ld (each column is one CN-ordered vector).
+#include "ops.hpp"
+
+namespace igp {
+namespace {
+
+constexpr int NT = 256;
+
+__global__ void k_finish_sum(const double* __restrict__ part, int nblk, double* __restrict__ out) {
+  __shared__ double red[NT / 64];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += NT) s += part[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) *out = s;
+}
+
+int grid_for(int64_t n) {
+  int64_t b = ceil_div(n, NT * 4);
+  if (b > RED_BLOCKS) b = RED_BLOCKS;
+  if (b < 1) b = 1;
+  return static_cast<int>(b);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_residual(const T* __restrict__ rhs, const T* __restrict__ kv, const T* __restrict__ wv,
+           T* __restrict__ r, int64_t n, double* __restrict__ part) {
+  __shared__ double red[NT / 64];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(NT) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * NT) {
+    const T ri = rhs[i] - kv[i] - wv[i];
+    r[i] = ri;
+    acc += static_cast<double>(ri) * static_cast<double>(ri);
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_dot(const T* __restrict__ a, const T* __restrict__ b, int64_t n, double* __restrict__ part) {
+  __shared__ double red[NT / 64];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(NT) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * NT)
+    acc += static_cast<double>(a[i]) * static_cast<double>(b[i]);
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+template <typename T>
+__global__ void k_action_cg(const T* __restrict__ r, const double* __restrict__ rr,
+                            T* __restrict__ s, int64_t n) {
+  const double inv = 1.0 / sqrt(*rr);
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    s[i] = static_cast<T>(static_cast<double>(r[i]) * inv);
+}
+
+template <typename T>
+__global__ void k_fill_unit(T* __restrict__ s, int64_t n, int64_t idx) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    s[i] = (i == idx) ? T(1) : T(0);
+}
+
+template <typename T>
+__global__ void k_copy(const T* __restrict__ a, T* __restrict__ b, int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    b[i] = a[i];
+}
+
+template <typename T>
+__global__ void k_add(const T* __restrict__ a, const T* __restrict__ b, T* __restrict__ o, int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    o[i] = a[i] + b[i];
+}
+
+// y partials: block (rx, cy) covers rows [rx*RCH, (rx+1)*RCH) and columns
+// [cy*CG, cy*CG + CG); part[rx * ncols + b].
+constexpr int RCH = 2048;   // rows per block (8 per thread)
+constexpr int CG = 32;      // columns per block
+
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_gemv_t(const T* __restrict__ Q, int64_t ldq, int64_t n, int ncols, const T* __restrict__ z,
+         double* __restrict__ part) {
+  __shared__ double sred[NT / 64][CG];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RCH;
+  const int b0 = blockIdx.y * CG;
+  double zr[RCH / NT];
+#pragma unroll
+  for (int k = 0; k < RCH / NT; ++k) {
+    const int64_t i = r0 + tid + k * NT;
+    zr[k] = i < n ? static_cast<double>(z[i]) : 0.0;
+  }
+  const int bend = b0 + CG < ncols ? b0 + CG : ncols;
+  for (int b = b0; b < bend; ++b) {
+    const T* q = Q + static_cast<int64_t>(b) * ldq;
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < RCH / NT; ++k) {
+      const int64_t i = r0 + tid + k * NT;
+      if (i < n) acc += static_cast<double>(q[i]) * zr[k];
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) sred[w][b - b0] = acc;
+  }
+  __syncthreads();
+  if (tid < bend - b0) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) s += sred[k][tid];
+    part[static_cast<int64_t>(blockIdx.x) * ncols + b0 + tid] = s;
+  }
+}
+
+__global__ void k_finish_cols(const double* __restrict__ part, int nrow_blocks, int ncols,
+                              double* __restrict__ y) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= ncols) return;
+  double s = 0.0;
+  for (int r = 0; r < nrow_blocks; ++r) s += part[static_cast<int64_t>(r) * ncols + b];
+  y[b] = s;
+}
+
+// d = s - Q y ; eta partial = z^T d.  One row per thread; y staged in LDS.
+constexpr int MAXCOLS_LDS = 4096;
+
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_dir_update(const T* __restrict__ sv, const T* __restrict__ Q, int64_t ldq, int64_t n,
+             int ncols, const double* __restrict__ y, const T* __restrict__ z,
+             T* __restrict__ d, double* __restrict__ part) {
+  __shared__ double sy[MAXCOLS_LDS];
+  __shared__ double red[NT / 64];
+  for (int b = threadIdx.x; b < ncols; b += NT) sy[b] = y[b];
+  __syncthreads();
+  const int64_t i = blockIdx.x * static_cast<int64_t>(NT) + threadIdx.x;
+  double e = 0.0;
+  if (i < n) {
+    double acc = 0.0;
+    int b = 0;
+    for (; b + 4 <= ncols; b += 4) {
+      const double q0 = Q[static_cast<int64_t>(b) * ldq + i];
+      const double q1 = Q[static_cast<int64_t>(b + 1) * ldq + i];
+      const double q2 = Q[static_cast<int64_t>(b + 2) * ldq + i];
+      const double q3 = Q[static_cast<int64_t>(b + 3) * ldq + i];
+      acc += q0 * sy[b] + q1 * sy[b + 1] + q2 * sy[b + 2] + q3 * sy[b + 3];
+    }
+    for (; b < ncols; ++b) acc += static_cast<double>(Q[static_cast<int64_t>(b) * ldq + i]) * sy[b];
+    const T di = static_cast<T>(static_cast<double>(sv[i]) - acc);
+    d[i] = di;
+    e = static_cast<double>(z[i]) * static_cast<double>(di);
+  }
+  e = block_sum(e, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = e;
+}
+
+template <typename T>
+__global__ void k_gemv_n(const T* __restrict__ Q, int64_t ldq, int64_t n, int ncols,
+                         const double* __restrict__ y, T* __restrict__ out) {
+  __shared__ double sy[MAXCOLS_LDS];
+  for (int b = threadIdx.x; b < ncols; b += blockDim.x) sy[b] = y[b];
+  __syncthreads();
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int b = 0; b < ncols; ++b) acc += static_cast<double>(Q[static_cast<int64_t>(b) * ldq + i]) * sy[b];
+  out[i] = static_cast<T>(acc);
+}
+
+template <typename T>
+__global__ void k_append_step(const T* __restrict__ d, const double* __restrict__ scal,
+                              T* __restrict__ qcol, T* __restrict__ v, int64_t n) {
+  const double eta = scal[SC_ETA];
+  if (!(eta > 0.0)) return;
+  const double qs = 1.0 / sqrt(eta);
+  const double step = scal[SC_ALPHA] / eta;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double di = static_cast<double>(d[i]);
+    qcol[i] = static_cast<T>(di * qs);
+    v[i] = static_cast<T>(static_cast<double>(v[i]) + step * di);
+  }
+}
+
+// Gram matrix M = A^T B over a chunk of rows; 32 x 32 output tile per block,
+// 4 outputs per thread, rows staged in LDS 32 at a time.
+constexpr int GT = 32;
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_gram(const T* __restrict__ A, const T* __restrict__ B, int64_t ld, int64_t n, int ncols,
+       int64_t rows_per_chunk, double* __restrict__ part) {
+  __shared__ double sA[GT][GT + 1];
+  __shared__ double sB[GT][GT + 1];
+  const int tid = threadIdx.x;
+  const int a0 = blockIdx.x * GT, b0 = blockIdx.y * GT;
+  const int64_t i_begin = static_cast<int64_t>(blockIdx.z) * rows_per_chunk;
+  const int64_t i_end = i_begin + rows_per_chunk < n ? i_begin + rows_per_chunk : n;
+  const int ta = tid % 16, tb = tid / 16;   // outputs (a0+ta+16*u, b0+tb+16*v)
+  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  for (int64_t i0 = i_begin; i0 < i_end; i0 += GT) {
+    for (int e = tid; e < GT * GT; e += NT) {
+      const int col = e / GT, row = e % GT;     // column-major: rows contiguous
+      const int64_t gi = i0 + row;
+      const int ga = a0 + col, gb = b0 + col;
+      sA[col][row] = (gi < i_end && ga < ncols) ? static_cast<double>(A[static_cast<int64_t>(ga) * ld + gi]) : 0.0;
+      sB[col][row] = (gi < i_end && gb < ncols) ? static_cast<double>(B[static_cast<int64_t>(gb) * ld + gi]) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int k = 0; k < GT; ++k) {
+      const double x0 = sA[ta][k], x1 = sA[ta + 16][k];
+      const double y0 = sB[tb][k], y1 = sB[tb + 16][k];
+      acc[0][0] += x0 * y0;
+      acc[0][1] += x0 * y1;
+      acc[1][0] += x1 * y0;
+      acc[1][1] += x1 * y1;
+    }
+    __syncthreads();
+  }
+  double* P = part + static_cast<int64_t>(blockIdx.z) * ncols * ncols;
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int a = a0 + ta + 16 * u, b = b0 + tb + 16 * v;
+      if (a < ncols && b < ncols) P[static_cast<int64_t>(a) * ncols + b] = acc[u][v];
+    }
+}
+
+__global__ void k_finish_gram(const double* __restrict__ part, int nchunks, int ncols,
+                              double* __restrict__ M) {
+  const int64_t total = static_cast<int64_t>(ncols) * ncols;
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += part[c * total + e];
+    M[e] = s;
+  }
+}
+
+// Out[:, r] = (A U[:, r]) * colscale[r]; 16 output columns per block, U tile in LDS.
+constexpr int RM_COLS = 16;
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_right_mul(const T* __restrict__ A, int64_t lda, int64_t n, int ncols,
+            const double* __restrict__ U, int R, const double* __restrict__ colscale,
+            T* __restrict__ Out, int64_t ldo) {
+  extern __shared__ double sU[];   // ncols x RM_COLS
+  const int r0 = blockIdx.y * RM_COLS;
+  for (int e = threadIdx.x; e < ncols * RM_COLS; e += NT) {
+    const int b = e / RM_COLS, rr = e % RM_COLS;
+    sU[e] = (r0 + rr < R) ? U[static_cast<int64_t>(r0 + rr) * ncols + b] : 0.0;
+  }
+  __syncthreads();
+  const int64_t i = blockIdx.x * static_cast<int64_t>(NT) + threadIdx.x;
+  if (i >= n) return;
+  double acc[RM_COLS];
+#pragma unroll
+  for (int rr = 0; rr < RM_COLS; ++rr) acc[rr] = 0.0;
+  for (int b = 0; b < ncols; ++b) {
+    const double a = static_cast<double>(A[static_cast<int64_t>(b) * lda + i]);
+#pragma unroll
+    for (int rr = 0; rr < RM_COLS; ++rr) acc[rr] += a * sU[b * RM_COLS + rr];
+  }
+#pragma unroll
+  for (int rr = 0; rr < RM_COLS; ++rr)
+    if (r0 + rr < R) {
+      const double sc = colscale ? colscale[r0 + rr] : 1.0;
+      Out[static_cast<int64_t>(r0 + rr) * ldo + i] = static_cast<T>(acc[rr] * sc);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_newton_stats(const T* __restrict__ fnew, const T* __restrict__ f, const T* __restrict__ v,
+               const int32_t* __restrict__ y, int64_t N, int C, double* __restrict__ part) {
+  __shared__ double red[NT / 64];
+  const int64_t n = blockIdx.x * static_cast<int64_t>(NT) + threadIdx.x;
+  double dd = 0.0, ff = 0.0, ll = 0.0, gv = 0.0;
+  if (n < N) {
+    double mx = -INFINITY;
+    for (int c = 0; c < C; ++c) {
+      const double a = static_cast<double>(fnew[n * C + c]);
+      const double b = static_cast<double>(f[n * C + c]);
+      dd += (a - b) * (a - b);
+      ff += a * a;
+      gv += a * static_cast<double>(v[n * C + c]);
+      mx = fmax(mx, a);
+    }
+    double se = 0.0;
+    for (int c = 0; c < C; ++c) se += exp(static_cast<double>(fnew[n * C + c]) - mx);
+    ll = static_cast<double>(fnew[n * C + y[n]]) - mx - log(se);
+  }
+  const int nb = gridDim.x;
+  double s;
+  s = block_sum(dd, red); if (threadIdx.x == 0) part[0 * nb + blockIdx.x] = s;
+  s = block_sum(ff, red); if (threadIdx.x == 0) part[1 * nb + blockIdx.x] = s;
+  s = block_sum(ll, red); if (threadIdx.x == 0) part[2 * nb + blockIdx.x] = s;
+  s = block_sum(gv, red); if (threadIdx.x == 0) part[3 * nb + blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ void k_predict_epilogue(const T* __restrict__ A, int64_t lda, int64_t nrows,
+                                   int ncols, double os, const T* __restrict__ mean, int64_t Ns,
+                                   int C, T* __restrict__ var, T* __restrict__ probs) {
+  const int64_t s = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (s >= Ns) return;
+  double z[64];
+  double mx = -INFINITY;
+  for (int c = 0; c < C; ++c) {
+    const int64_t row = s * C + c;
+    double acc = 0.0;
+    for (int b = 0; b < ncols; ++b) {
+      const double a = static_cast<double>(A[static_cast<int64_t>(b) * lda + row]);
+      acc += a * a;
+    }
+    const double vv = os - acc;
+    if (var) var[row] = static_cast<T>(vv);
+    if (probs) {
+      const double vz = vv > 0.0 ? vv : 0.0;
+      z[c] = static_cast<double>(mean[row]) / sqrt(1.0 + 0.39269908169872414 * vz);
+      mx = fmax(mx, z[c]);
+    }
+  }
+  if (probs) {
+    double se = 0.0;
+    for (int c = 0; c < C; ++c) {
+      z[c] = exp(z[c] - mx);
+      se += z[c];
+    }
+    for (int c = 0; c < C; ++c) probs[s * C + c] = static_cast<T>(z[c] / se);
+  }
+}
+
+}  // namespace
+
+// ------------------------------ launchers ---------------------------------------
+
+template <typename T>
+int residual(const T* rhs, const T* kv, const T* wv, T* r, int64_t n, double* part,
+             double* out, hipStream_t s) {
+  const int g = grid_for(n);
+  k_residual<T><<<g, NT, 0, s>>>(rhs, kv, wv, r, n, part);
+  k_finish_sum<<<1, NT, 0, s>>>(part, g, out);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template <typename T>
+int dot_into(const T* a, const T* b, int64_t n, double* part, double* out, hipStream_t s) {
+  const int g = grid_for(n);
+  k_dot<T><<<g, NT, 0, s>>>(a, b, n, part);
+  k_finish_sum<<<1, NT, 0, s>>>(part, g, out);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template <typename T>
+int action_cg(const T* r, const double* rr, T* sv, int64_t n, hipStream_t s) {
+  k_action_cg<T><<<grid_for(n), NT, 0, s>>>(r, rr, sv, n);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template <typename T>
+int fill_unit(T* sv, int64_t n, int64_t idx, hipStream_t s) {
+  k_fill_unit<T><<<grid_for(n), NT, 0, s>>>(sv, n, idx);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template <typename T>
+int copy_vec(const T* a, T* b, int64_t n, hipStream_t s) {
+  k_copy<T><<<grid_for(n), NT, 0, s>>>(a, b, n);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template <typename T>
+int add_vec(const T* a, const T* b, T* o, int64_t n, hipStream_t s) {
+  k_add<T><<<grid_for(n), NT, 0, s>>>(a, b, o, n);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template <typename T>
+int gemv_t(const T* Q, int64_t ldq, int64_t n, int ncols, const T* z, double* part, double* y,
+           hipStream_t s) {
+  if (ncols == 0) return IGP_OK;
+  const int rb = static_cast<int>(ceil_div(n, RCH));
+  dim3 grid(rb, static_cast<unsigned>(ceil_div(ncols, CG)));
+  k_gemv_t<T><<<grid, NT, 0, s>>>(Q, ldq, n, ncols, z, part);
+  k_finish_cols<<<static_cast<unsigned>(ceil_div(ncols, 64)), 64, 0, s>>>(part, rb, ncols, y);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template <typename T>
+int dir_update(const T* sv, const T* Q, int64_t ldq, int64_t n, int ncols, const double* y,
+               const T* z, T* d, double* part, double* eta_out, hipStream_t s) {
+  if (ncols > MAXCOLS_LDS) {
+    set_error("buffer of %d columns exceeds %d", ncols, MAXCOLS_LDS);
+    return IGP_EUNSUPPORTED;
+  }
+  const int g = static_cast<int>(ceil_div(n, NT));
+  k_dir_update<T><<<g, NT, 0, s>>>(sv, Q, ldq, n, ncols, y, z, d, part);
+  k_finish_sum<<<1, NT, 0, s>>>(part, g, eta_out);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template <typename T>
+int append_and_step(const T* d, const double* scal, T* qcol, T* v, int64_t n, hipStream_t s) {
+  k_append_step<T><<<grid_for(n), NT, 0, s>>>(d, scal, qcol, v, n);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template <typename T>
+int gemv_n(const T* Q, int64_t ldq, int64_t n, int ncols, const double* y, T* out,
+           hipStream_t s) {
+  if (ncols > MAXCOLS_LDS) {
+    set_error("buffer of %d columns exceeds %d", ncols, MAXCOLS_LDS);
+    return IGP_EUNSUPPORTED;
+  }
+  k_gemv_n<T><<<static_cast<unsigned>(ceil_div(n, NT)), NT, 0, s>>>(Q, ldq, n, ncols, y, out);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template <typename T>
+int gram(const T* A, const T* B, int64_t ld, int64_t n, int ncols, double* part,
+         size_t part_cap, double* M, hipStream_t s) {
+  if (ncols == 0) return IGP_OK;
+  const int tiles = static_cast<int>(ceil_div(ncols, GT));
+  int64_t nchunks = ceil_div(2048, static_cast<int64_t>(tiles) * tiles);
+  const size_t per = static_cast<size_t>(ncols) * ncols;
+  if (nchunks * per > part_cap) nchunks = static_cast<int64_t>(part_cap / per);
+  if (nchunks < 1) {
+    set_error("Gram workspace too small for %d columns", ncols);
+    return IGP_ENOMEM;
+  }
+  int64_t rows_per = ceil_div(ceil_div(n, nchunks), GT) * GT;
+  if (rows_per < GT) rows_per = GT;
+  nchunks = ceil_div(n, rows_per);
+  if (nchunks < 1) nchunks = 1;
+  dim3 grid(tiles, tiles, static_cast<unsigned>(nchunks));
+  k_gram<T><<<grid, NT, 0, s>>>(A, B, ld, n, ncols, rows_per, part);
+  k_finish_gram<<<static_cast<unsigned>(ceil_div(static_cast<int64_t>(per), NT)), NT, 0, s>>>(
+      part, static_cast<int>(nchunks), ncols, M);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template <typename T>
+int right_mul(const T* A, int64_t lda, int64_t n, int ncols, const double* U, int R,
+              const double* colscale, T* Out, int64_t ldo, hipStream_t s) {
+  if (R == 0 || n == 0) return IGP_OK;
+  const size_t lds = static_cast<size_t>(ncols) * RM_COLS * sizeof(double);
+  if (lds > 150 * 1024) {
+    set_error("buffer of %d columns too wide for the re-weighting kernel", ncols);
+    return IGP_EUNSUPPORTED;
+  }
+  dim3 grid(static_cast<unsigned>(ceil_div(n, NT)), static_cast<unsigned>(ceil_div(R, RM_COLS)));
+  k_right_mul<T><<<grid, NT, lds, s>>>(A, lda, n, ncols, U, R, colscale, Out, ldo);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template <typename T>
+int newton_stats(const T* fnew, const T* f, const T* v, const int32_t* y, int64_t N, int64_t C,
+                 double* part, double* scal, hipStream_t s) {
+  const int g = static_cast<int>(ceil_div(N, NT));
+  if (g == 0) return IGP_OK;
+  k_newton_stats<T><<<g, NT, 0, s>>>(fnew, f, v, y, N, static_cast<int>(C), part);
+  k_finish_sum<<<1, NT, 0, s>>>(part + 0 * g, g, scal + SC_DIFF2);
+  k_finish_sum<<<1, NT, 0, s>>>(part + 1 * g, g, scal + SC_FNEW2);
+  k_finish_sum<<<1, NT, 0, s>>>(part + 2 * g, g, scal + SC_LOGLIK);
+  k_finish_sum<<<1, NT, 0, s>>>(part + 3 * g, g, scal + SC_GV);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template <typename T>
+int predict_epilogue(const T* A, int64_t lda, int64_t nrows, int ncols, double os, const T* mean,
+                     int64_t Ns, int64_t C, T* var, T* probs, hipStream_t s) {
+  (void)nrows;
+  if (Ns == 0) return IGP_OK;
+  k_predict_epilogue<T><<<static_cast<unsigned>(ceil_div(Ns, 128)), 128, 0, s>>>(
+      A, lda, nrows, ncols, os, mean, Ns, static_cast<int>(C), var, probs);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+#define IGP_INST(T)                                                                             \
+  template int residual<T>(const T*, const T*, const T*, T*, int64_t, double*, double*,        \
+                           hipStream_t);                                                       \
+  template int dot_into<T>(const T*, const T*, int64_t, double*, double*, hipStream_t);        \
+  template int action_cg<T>(const T*, const double*, T*, int64_t, hipStream_t);                \
+  template int fill_unit<T>(T*, int64_t, int64_t, hipStream_t);                                \
+  template int copy_vec<T>(const T*, T*, int64_t, hipStream_t);                                \
+  template int add_vec<T>(const T*, const T*, T*, int64_t, hipStream_t);                       \
+  template int gemv_t<T>(const T*, int64_t, int64_t, int, const T*, double*, double*,         \
+                         hipStream_t);                                                         \
+  template int dir_update<T>(const T*, const T*, int64_t, int64_t, int, const double*,         \
+                             const T*, T*, double*, double*, hipStream_t);                     \
+  template int append_and_step<T>(const T*, const double*, T*, T*, int64_t, hipStream_t);     \
+  template int gemv_n<T>(const T*, int64_t, int64_t, int, const double*, T*, hipStream_t);     \
+  template int gram<T>(const T*, const T*, int64_t, int64_t, int, double*, size_t, double*,   \
+                       hipStream_t);                                                           \
+  template int right_mul<T>(const T*, int64_t, int64_t, int, const double*, int,              \
+                            const double*, T*, int64_t, hipStream_t);                          \
+  template int newton_stats<T>(const T*, const T*, const T*, const int32_t*, int64_t, int64_t, \
+                               double*, double*, hipStream_t);                                 \
+  template int predict_epilogue<T>(const T*, int64_t, int64_t, int, double, const T*, int64_t, \
+                                   int64_t, T*, T*, hipStream_t);
+IGP_INST(float)
+IGP_INST(double)
+
+}  // namespace igp

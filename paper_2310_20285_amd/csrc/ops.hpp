@@ -1,0 +1,134 @@
+// Internal launchers of the HIP kernels (not part of the public ABI).
+#pragma once
+#include "common.hpp"
+
+// Host-side handle behind the opaque igp_model of the public header.
+struct igp_model {
+  virtual ~igp_model() = default;
+  virtual int newton_step(igp_step_info* info) = 0;
+  virtual int predict(const void* Xs, int64_t Ns, void* mean, void* var, void* probs, void* ws,
+                      size_t ws_bytes, hipStream_t s) const = 0;
+  virtual size_t predict_ws_bytes(int64_t Ns) const = 0;
+  virtual int view(int which, const void** ptr, int64_t* rows, int64_t* cols,
+                   int64_t* ld) const = 0;
+  virtual int set_user_actions(const void* a, int64_t ncols, int64_t ld) = 0;
+  virtual int set_profiling(int enable) = 0;
+  virtual int get_profile(igp_profile* out) const = 0;
+};
+
+namespace igp {
+
+// ---- matrix-free kernel product ------------------------------------------
+// Out_b = os * (K_X(X1, X2) (x) I_C) V_b + beta * Out_b for b < nb.
+// `skip` (device, nullable): when *skip != 0 the launch does nothing.
+struct KVProblem {
+  igp_kernel_params kp;
+  int precision;          // igp_precision
+  const void* X1;         // n1 x d (T); for IGP_BF16 float rows (centred)
+  const void* X2;
+  int64_t n1, n2, d;
+  const void* V;          // nb CN vectors, stride ldv
+  int64_t C, nb, ldv;
+  void* Out;
+  int64_t ldo;
+  double beta;
+  // optional precomputed data (FP32 / BF16 MFMA paths): squared norms of the
+  // rows scaled by 1/l^2 and BF16 copies of the scaled rows
+  const float* norm1 = nullptr;
+  const float* norm2 = nullptr;
+  const uint16_t* Xb1 = nullptr;
+  const uint16_t* Xb2 = nullptr;
+  const int* skip = nullptr;
+};
+
+size_t kv_ws_bytes(int64_t n1, int64_t n2, int64_t d, int64_t C, int64_t nb, int precision);
+int kv_launch(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t s);
+
+// Row preparation for the MFMA paths: out rows = (X - centre) / l, their
+// squared norms, and (BF16) rounded copies whose norms are taken after rounding.
+size_t prep_ws_bytes(int64_t n, int64_t d, int precision);
+int prep_rows(const float* X, int64_t n, int64_t d, const float* centre, double inv_l,
+              int precision, float* Xs_out, float* norms_out, uint16_t* Xb_out,
+              hipStream_t s);
+int column_mean(const void* X, int64_t n, int64_t d, int precision, float* mean_out,
+                double* scratch, hipStream_t s);
+
+// ---- softmax Hessian blocks ---------------------------------------------------
+// pi = softmax(F) per point; rhs = F + W^+ (onehot(y) - pi); loglik partials.
+template <typename T>
+int softmax_pi_rhs(const T* F, const int32_t* y, int64_t N, int64_t C, T* pi, T* rhs,
+                   double* loglik_partials, int* nblocks_out, hipStream_t s);
+// Out_b = W^+ V_b (+ Add_b) using stored pi, or from logits when pi_is_logits.
+template <typename T>
+int winv_apply(const T* pi, bool pi_is_logits, int mode, int64_t N, int64_t C,
+               const T* V, int64_t nb, int64_t ldv, const T* Add, int64_t lda,
+               T* Out, int64_t ldo, hipStream_t s);
+
+// ---- reductions and projections (FP64 accumulation) ---------------------------
+constexpr int RED_THREADS = 256;
+constexpr int RED_BLOCKS = 1024;   // max partial blocks of a grid-stride reduction
+
+enum Scalar {
+  SC_RR = 0,       // ||r||^2
+  SC_ALPHA,        // s^T r
+  SC_ETA,          // z^T d
+  SC_RHS2,         // ||rhs||^2
+  SC_DIFF2,        // ||f_new - f||^2
+  SC_FNEW2,        // ||f_new||^2
+  SC_LOGLIK,       // log p(y | f)
+  SC_GV,           // g^T v
+  SC_COUNT
+};
+
+template <typename T>
+int residual(const T* rhs, const T* kv, const T* wv, T* r, int64_t n, double* partials,
+             double* out_scalar, hipStream_t s);
+template <typename T>
+int dot_into(const T* a, const T* b, int64_t n, double* partials, double* out_scalar,
+             hipStream_t s);
+template <typename T>
+int action_cg(const T* r, const double* rr, T* s_out, int64_t n, hipStream_t s);
+template <typename T>
+int fill_unit(T* s_out, int64_t n, int64_t idx, hipStream_t s);
+template <typename T>
+int copy_vec(const T* src, T* dst, int64_t n, hipStream_t s);
+template <typename T>
+int add_vec(const T* a, const T* b, T* out, int64_t n, hipStream_t s);
+// y[b] = sum_i Q[b*ldq + i] z[i], b < ncols
+template <typename T>
+int gemv_t(const T* Q, int64_t ldq, int64_t n, int ncols, const T* z, double* partials,
+           double* y, hipStream_t s);
+// d = s - Q y ; eta partials of z^T d
+template <typename T>
+int dir_update(const T* sv, const T* Q, int64_t ldq, int64_t n, int ncols, const double* y,
+               const T* z, T* d, double* partials, double* eta_out, hipStream_t s);
+// Q[:, col] = d / sqrt(eta); v += (alpha/eta) d   (no-op when eta <= 0)
+template <typename T>
+int append_and_step(const T* d, const double* scal, T* qcol, T* v, int64_t n, hipStream_t s);
+// v = Q y
+template <typename T>
+int gemv_n(const T* Q, int64_t ldq, int64_t n, int ncols, const double* y, T* out,
+           hipStream_t s);
+// Gram partials: M = A^T B (ncols x ncols), FP64 out (row-major, ld = ncols)
+template <typename T>
+int gram(const T* A, const T* B, int64_t ld, int64_t n, int ncols, double* partials,
+         size_t partial_cap, double* M, hipStream_t s);
+// Out[:, r] = A U[:, r] * scale[r] for r < R (U: ncols x R col-major FP64)
+template <typename T>
+int right_mul(const T* A, int64_t lda, int64_t n, int ncols, const double* U, int R,
+              const double* colscale, T* Out, int64_t ldo, hipStream_t s);
+// Newton update bookkeeping: ||fnew - f||^2, ||fnew||^2, loglik(fnew), fnew^T v
+template <typename T>
+int newton_stats(const T* fnew, const T* f, const T* v, const int32_t* y, int64_t N,
+                 int64_t C, double* partials, double* scal, hipStream_t s);
+// predict epilogue: var = os - sum_b A_b^2 ; probs = softmax(mean / sqrt(1 + pi/8 var))
+template <typename T>
+int predict_epilogue(const T* A, int64_t lda, int64_t nrows, int ncols, double os,
+                     const T* mean, int64_t Ns, int64_t C, T* var, T* probs, hipStream_t s);
+
+// ---- host FP64 symmetric eigensolver ---------------------------------------------
+// A (n x n, row-major, symmetric; only the lower triangle is read) =
+// Z diag(w) Z^T, eigenvalues descending, Z column-major (column k at Z + k*n).
+int eigh_desc(int n, const double* A, double* w, double* Z);
+
+}  // namespace igp
