@@ -20,17 +20,24 @@ template <typename T>
 struct Layout {
   T *X, *f, *fnew, *pi, *rhs, *v, *r, *z, *d, *kv, *wv;
   T *S, *Tb, *Q, *S2, *T2;
+  T *KQ, *kd;   // recurrence mode: K Q and K d
   double *part, *scal, *yb, *M, *U, *lamscale, *gram_part;
   size_t gram_cap;
   void* kvws;
   size_t kvws_bytes;
   int* flags;
+  // matrix-core paths: common centre, centred zero-padded rows, squared norms
+  float *centre, *Xp, *nrm;
+  double* meanpart;
 };
 
 int64_t col_stride(int64_t n) { return ceil_div(n, 64) * 64; }
 
+constexpr int64_t MEAN_BLOCKS = 1024;
+
 template <typename T>
-Layout<T> carve(Carver& cv, int64_t N, int64_t D, int64_t C, const igp_solver_config& cfg) {
+Layout<T> carve(Carver& cv, int64_t N, int64_t D, int64_t C, const igp_solver_config& cfg,
+                bool prepared) {
   Layout<T> L{};
   const int64_t n = N * C, ld = col_stride(n);
   const int64_t B = cfg.max_buffer;
@@ -50,6 +57,10 @@ Layout<T> carve(Carver& cv, int64_t N, int64_t D, int64_t C, const igp_solver_co
   L.Q = cv.take<T>(ld * B);
   L.S2 = cv.take<T>(ld * B);
   L.T2 = cv.take<T>(ld * B);
+  if (cfg.residual_mode == IGP_RESIDUAL_RECURRENCE) {
+    L.KQ = cv.take<T>(ld * B);
+    L.kd = cv.take<T>(n);
+  }
   int64_t npart = PARTIAL_DOUBLES;
   const int64_t gemv_need = (ceil_div(n, 2048) + 1) * std::max<int64_t>(B, 1);
   npart = std::max(npart, gemv_need);
@@ -62,9 +73,16 @@ Layout<T> carve(Carver& cv, int64_t N, int64_t D, int64_t C, const igp_solver_co
   L.lamscale = cv.take<double>(std::max<int64_t>(B, 1));
   L.gram_cap = static_cast<size_t>(std::max<int64_t>(B * B, 1)) * 16;
   L.gram_part = cv.take<double>(L.gram_cap);
-  L.kvws_bytes = kv_ws_bytes(N, N, D, C, 1, cfg.precision);
+  L.kvws_bytes = prepared ? kv_ws_bytes_prepared(N, N, D, C, 1, cfg.precision)
+                          : kv_ws_bytes(N, N, D, C, 1, cfg.precision);
   L.kvws = cv.take<char>(L.kvws_bytes);
   L.flags = cv.take<int>(64);
+  if (prepared) {
+    L.centre = cv.take<float>(D);
+    L.Xp = cv.take<float>(N * padded_dim(D));
+    L.nrm = cv.take<float>(N);
+    L.meanpart = cv.take<double>(MEAN_BLOCKS * D);
+  }
   return L;
 }
 
@@ -139,9 +157,18 @@ struct Model final : igp_model {
     return IGP_OK;
   }
 
+  bool prepared = false;
+
   KVProblem kv_problem(const T* X1, int64_t n1, const T* V, int64_t nb, int64_t ldv, T* Out,
-                       int64_t ldo) const {
+                       int64_t ldo, const float* X1p = nullptr,
+                       const float* norm1 = nullptr) const {
     KVProblem p{};
+    if (prepared) {
+      p.X1p = X1p ? X1p : L.Xp;
+      p.norm1 = X1p ? norm1 : L.nrm;
+      p.X2p = L.Xp;
+      p.norm2 = L.nrm;
+    }
     p.kp = kp;
     p.precision = cfg.precision;
     p.X1 = X1;
@@ -158,6 +185,8 @@ struct Model final : igp_model {
     p.beta = 0.0;
     return p;
   }
+
+  bool recurrence() const { return cfg.residual_mode == IGP_RESIDUAL_RECURRENCE; }
 
   int apply_K(const T* V, T* Out) {
     hipEvent_t a = nullptr, b = nullptr;
@@ -216,6 +245,8 @@ struct Model final : igp_model {
       IGP_TRY(right_mul<T>(L.S, ld, n, B, L.U, keep, nullptr, L.S2, ld, stream));
       IGP_TRY(right_mul<T>(L.Tb, ld, n, B, L.U, keep, nullptr, L.T2, ld, stream));
       IGP_TRY(right_mul<T>(L.S, ld, n, B, L.U, keep, L.lamscale, L.Q, ld, stream));
+      if (recurrence())   // K Q_0 = K S U Lambda^{-1/2} = T U Lambda^{-1/2}
+        IGP_TRY(right_mul<T>(L.Tb, ld, n, B, L.U, keep, L.lamscale, L.KQ, ld, stream));
       std::swap(L.S, L.S2);
       std::swap(L.Tb, L.T2);
     }
@@ -251,8 +282,10 @@ struct Model final : igp_model {
     if (ncols > 0) {
       IGP_TRY(gemv_t<T>(L.Q, ld, n, ncols, L.rhs, L.part, L.yb, stream));
       IGP_TRY(gemv_n<T>(L.Q, ld, n, ncols, L.yb, L.v, stream));
+      if (recurrence()) IGP_TRY(gemv_n<T>(L.KQ, ld, n, ncols, L.yb, L.kv, stream));
     } else {
       IGP_CHECK_HIP(hipMemsetAsync(L.v, 0, n * sizeof(T), stream));
+      if (recurrence()) IGP_CHECK_HIP(hipMemsetAsync(L.kv, 0, n * sizeof(T), stream));
     }
     IGP_TRY(read_scalars(sc));
     info.rhs_norm = std::sqrt(sc[SC_RHS2]);
@@ -260,9 +293,11 @@ struct Model final : igp_model {
     int kprod = 0;
     int j = 0;
     while (j < cfg.j_max) {
-      // r_{j-1} = (yhat - m) - K v - W^+ v
-      IGP_TRY(apply_K(L.v, L.kv));
-      ++kprod;
+      // r_{j-1} = (yhat - m) - K v - W^+ v   (K v carried by the recurrence, or formed)
+      if (!recurrence()) {
+        IGP_TRY(apply_K(L.v, L.kv));
+        ++kprod;
+      }
       IGP_TRY(winv_apply<T>(L.pi, false, IGP_W_PINV, N, C, L.v, 1, n, nullptr, 0, L.wv, n, stream));
       IGP_TRY(residual<T>(L.rhs, L.kv, L.wv, L.r, n, L.part, L.scal + SC_RR, stream));
       IGP_TRY(read_scalars(sc));
@@ -293,7 +328,8 @@ struct Model final : igp_model {
                             stream));                                            // z_j
       IGP_TRY(gemv_t<T>(L.Q, ld, n, ncols, L.z, L.part, L.yb, stream));          // Q^T z
       IGP_TRY(dir_update<T>(s_col, L.Q, ld, n, ncols, L.yb, L.z, L.d, L.part,
-                            L.scal + SC_ETA, stream));                           // d_j, eta_j
+                            L.scal + SC_ETA, stream, t_col, recurrence() ? L.KQ : nullptr,
+                            L.kd));                                              // d_j, eta_j
       IGP_TRY(read_scalars(sc));
       const double eta = sc[SC_ETA];
       if (!(eta > 0.0)) {
@@ -303,7 +339,9 @@ struct Model final : igp_model {
       }
       info.eta_min = std::min(info.eta_min, eta);
       IGP_TRY(append_and_step<T>(L.d, L.scal, L.Q + static_cast<int64_t>(ncols) * ld, L.v, n,
-                                 stream));
+                                 stream, recurrence() ? L.kd : nullptr,
+                                 recurrence() ? L.KQ + static_cast<int64_t>(ncols) * ld : nullptr,
+                                 L.kv));
       ++ncols;
     }
     info.iters = j;
@@ -325,12 +363,21 @@ struct Model final : igp_model {
     return IGP_OK;
   }
 
+  size_t kvws_for(int64_t n1, int64_t nb) const {
+    return prepared ? kv_ws_bytes_prepared(n1, N, D, C, nb, cfg.precision)
+                    : kv_ws_bytes(n1, N, D, C, nb, cfg.precision);
+  }
+
   size_t predict_ws_bytes(int64_t Ns) const override {
     Carver cv(nullptr, 0);
     const int64_t B = std::max(ncols, 1);
     cv.take<T>(Ns * C * B);
-    cv.take<char>(kv_ws_bytes(Ns, N, D, C, 1, cfg.precision));
-    cv.take<char>(kv_ws_bytes(Ns, N, D, C, B, cfg.precision));
+    cv.take<char>(kvws_for(Ns, 1));
+    cv.take<char>(kvws_for(Ns, B));
+    if (prepared) {
+      cv.take<float>(Ns * padded_dim(D));
+      cv.take<float>(Ns);
+    }
     return cv.used + 256;
   }
 
@@ -349,14 +396,20 @@ struct Model final : igp_model {
     Carver cv(ws, ws_bytes);
     const int64_t B = std::max(ncols, 1);
     T* A = cv.take<T>(Ns * C * B);
-    const size_t w1 = kv_ws_bytes(Ns, N, D, C, 1, cfg.precision);
+    const size_t w1 = kvws_for(Ns, 1);
     void* ws1 = cv.take<char>(w1);
-    const size_t w2 = kv_ws_bytes(Ns, N, D, C, B, cfg.precision);
+    const size_t w2 = kvws_for(Ns, B);
     void* ws2 = cv.take<char>(w2);
-    IGP_TRY(kv_launch(kv_problem(Xs, Ns, L.v, 1, n, mean, Ns * C), ws1, w1, s));
+    float *xsp = nullptr, *nsp = nullptr;
+    if (prepared) {
+      xsp = cv.take<float>(Ns * padded_dim(D));
+      nsp = cv.take<float>(Ns);
+      IGP_TRY(prep_rows_f32(reinterpret_cast<const float*>(Xs), Ns, D, L.centre, xsp, nsp, s));
+    }
+    IGP_TRY(kv_launch(kv_problem(Xs, Ns, L.v, 1, n, mean, Ns * C, xsp, nsp), ws1, w1, s));
     if (var_) {
       if (ncols > 0) {
-        IGP_TRY(kv_launch(kv_problem(Xs, Ns, L.Q, ncols, ld, A, Ns * C), ws2, w2, s));
+        IGP_TRY(kv_launch(kv_problem(Xs, Ns, L.Q, ncols, ld, A, Ns * C, xsp, nsp), ws2, w2, s));
       }
       IGP_TRY(predict_epilogue<T>(A, Ns * C, Ns * C, ncols, kp.outputscale, mean, Ns, C,
                                   static_cast<T*>(var_), static_cast<T*>(probs_), s));
@@ -415,7 +468,9 @@ int validate_common(const igp_kernel_params* kp, const igp_solver_config* cfg, i
   IGP_REQUIRE(cfg->max_buffer >= 1 && cfg->max_buffer <= 4096, "max_buffer must be in [1, 4096]");
   IGP_REQUIRE(cfg->max_buffer >= cfg->j_max, "max_buffer must be >= j_max");
   IGP_REQUIRE(cfg->precision >= IGP_FP64 && cfg->precision <= IGP_BF16, "unknown precision");
-  IGP_REQUIRE(cfg->residual_mode == IGP_RESIDUAL_EXPLICIT, "only the explicit residual is available");
+  IGP_REQUIRE(cfg->residual_mode == IGP_RESIDUAL_EXPLICIT ||
+                  cfg->residual_mode == IGP_RESIDUAL_RECURRENCE,
+              "unknown residual mode %d", cfg->residual_mode);
   IGP_REQUIRE(std::isfinite(cfg->tol_abs) && std::isfinite(cfg->tol_rel) && cfg->tol_abs >= 0 &&
                   cfg->tol_rel >= 0,
               "tolerances must be finite and >= 0");
@@ -423,9 +478,9 @@ int validate_common(const igp_kernel_params* kp, const igp_solver_config* cfg, i
 }
 
 template <typename T>
-size_t state_bytes_t(int64_t N, int64_t D, int64_t C, const igp_solver_config& cfg) {
+size_t state_bytes_t(int64_t N, int64_t D, int64_t C, const igp_solver_config& cfg, int kind) {
   Carver cv(nullptr, 0);
-  carve<T>(cv, N, D, C, cfg);
+  carve<T>(cv, N, D, C, cfg, kv_uses_prepared(cfg.precision, kind, D));
   return cv.used + 256;
 }
 
@@ -433,7 +488,7 @@ template <typename T>
 int init_t(igp_model** out, const igp_kernel_params* kp, const igp_solver_config* cfg,
            const void* X, const int32_t* y, int64_t N, int64_t D, int64_t C, void* arena,
            size_t arena_bytes, hipStream_t stream) {
-  const size_t need = state_bytes_t<T>(N, D, C, *cfg);
+  const size_t need = state_bytes_t<T>(N, D, C, *cfg, kp->kind);
   if (arena_bytes < need) {
     set_error("arena too small: need %zu bytes, have %zu", need, arena_bytes);
     return IGP_ENOMEM;
@@ -450,8 +505,14 @@ int init_t(igp_model** out, const igp_kernel_params* kp, const igp_solver_config
   m->y = y;
   m->stream = stream;
   Carver cv(arena, arena_bytes);
-  m->L = carve<T>(cv, N, D, C, *cfg);
+  m->prepared = kv_uses_prepared(cfg->precision, kp->kind, D);
+  m->L = carve<T>(cv, N, D, C, *cfg, m->prepared);
   IGP_CHECK_HIP(hipMemcpyAsync(m->L.X, X, N * D * sizeof(T), hipMemcpyDeviceToDevice, stream));
+  if (m->prepared) {
+    const float* Xf = reinterpret_cast<const float*>(m->L.X);
+    IGP_TRY(column_mean_f32(Xf, N, D, m->L.centre, m->L.meanpart, MEAN_BLOCKS * D, stream));
+    IGP_TRY(prep_rows_f32(Xf, N, D, m->L.centre, m->L.Xp, m->L.nrm, stream));
+  }
   IGP_CHECK_HIP(hipMemsetAsync(m->L.f, 0, m->n * sizeof(T), stream));
   IGP_CHECK_HIP(hipMemsetAsync(m->L.v, 0, m->n * sizeof(T), stream));
   IGP_CHECK_HIP(hipMemsetAsync(m->L.flags, 0, 64 * sizeof(int), stream));
@@ -472,8 +533,10 @@ int init_t(igp_model** out, const igp_kernel_params* kp, const igp_solver_config
 
 size_t state_bytes(int64_t N, int64_t D, int64_t C, const igp_solver_config* cfg) {
   if (!cfg || N < 1 || D < 1 || C < 1 || cfg->max_buffer < 1) return 0;
-  return cfg->precision == IGP_FP64 ? state_bytes_t<double>(N, D, C, *cfg)
-                                    : state_bytes_t<float>(N, D, C, *cfg);
+  if (cfg->precision == IGP_FP64) return state_bytes_t<double>(N, D, C, *cfg, IGP_RBF);
+  // the query does not know the kernel: size for the larger (matrix-core) layout
+  return std::max(state_bytes_t<float>(N, D, C, *cfg, IGP_RBF),
+                  state_bytes_t<float>(N, D, C, *cfg, IGP_MATERN12));
 }
 
 int model_init(igp_model** out, const igp_kernel_params* kp, const igp_solver_config* cfg,

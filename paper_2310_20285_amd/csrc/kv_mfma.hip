@@ -1,1 +1,369 @@
-// placeholder
+// Fused kernel-matrix product on the FP32 matrix cores of gfx950:
+//
+//   Out[n, w] = sum_m k(x1_n, x2_m) V[m, w]
+//
+// per 16 x 16 block of (m, n) and per wave:
+//   1. D^T = X2_blk X1_blk^T with v_mfma_f32_16x16x4f32 (the distance term of
+//      r^2 = |x1|^2 + |x2|^2 - 2 x1.x2, inputs centred on a common point);
+//   2. the kernel function applied in registers to the 4 accumulator values;
+//   3. Out_blk += K_blk V_blk with the same instruction.  Because step 1 is
+//      computed transposed, lane l holds K[n = l%16][m = 4(l/16) + v] in its
+//      accumulator register v -- exactly the A-operand lane layout of the
+//      MFMA whose k-index v*4+l/16 enumerates m -- so K never leaves
+//      registers and is never written to LDS or HBM.
+// The contraction order over features inside step 1 is chosen so that every
+// lane's four A (and B) values are one contiguous float4.
+//
+// A workgroup holds 64 rows of X1 (four waves x 16, kept in registers) and
+// streams a contiguous range of X2 rows (split-N2) in tiles of 64 through
+// LDS, double-buffered through registers: the next tile's global loads are in
+// flight while the current tile is computed.  Partial sums per split are
+// reduced in a fixed order (kv_reduce), so the product is deterministic.
+#include "ops.hpp"
+
+namespace igp {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr float LOG2E = 1.4426950408889634f;
+
+// Scale kappa applied to r^2 = |x - x'|^2 / l^2 before the transform below.
+template <int KIND>
+constexpr float kappa() {
+  if constexpr (KIND == IGP_RBF) return 0.5f * LOG2E;
+  else if constexpr (KIND == IGP_MATERN12) return LOG2E * LOG2E;
+  else if constexpr (KIND == IGP_MATERN32) return 3.0f * LOG2E * LOG2E;
+  else return 5.0f * LOG2E * LOG2E;
+}
+
+// k as a function of t = kappa r^2 (outputscale applied later):
+//   RBF  2^-t;  Matern-nu  poly(a) 2^-a with a = sqrt(t) = sqrt(c_nu) r log2(e)
+template <int KIND>
+__device__ inline float ktransform(float t) {
+  if constexpr (KIND == IGP_RBF) {
+    return __builtin_amdgcn_exp2f(-t);
+  } else {
+    const float a = __builtin_amdgcn_sqrtf(fmaxf(t, 0.0f));
+    const float e = __builtin_amdgcn_exp2f(-a);
+    if constexpr (KIND == IGP_MATERN12) {
+      return e;
+    } else if constexpr (KIND == IGP_MATERN32) {
+      return __builtin_fmaf(a, 1.0f / LOG2E, 1.0f) * e;
+    } else {
+      const float p = __builtin_fmaf(t, 1.0f / (3.0f * LOG2E * LOG2E), 1.0f);
+      return __builtin_fmaf(a, 1.0f / LOG2E, p) * e;
+    }
+  }
+}
+
+constexpr int TN = 64;   // X2 rows per LDS tile
+
+template <int KIND, int DCH, int WCH>
+__global__ void __launch_bounds__(256)
+kv_mfma_f32(const float* __restrict__ X1p, const float* __restrict__ nrm1,
+            const float* __restrict__ X2p, const float* __restrict__ nrm2, int64_t n1,
+            int64_t n2, const float* __restrict__ V, int C, int W, int64_t ldv,
+            float* __restrict__ P, int64_t cols_per_split, float cnorm, float cdot,
+            const int* skip) {
+  if (skip && *skip) return;
+  constexpr int DP = DCH * 16;        // padded feature count
+  constexpr int XS = DP + 4;          // LDS row stride of the X2 tile (floats)
+  constexpr int WT = WCH * 16;        // output columns per workgroup
+  constexpr int VS = TN + 4;          // LDS row stride of the transposed V tile
+  constexpr int XQ = TN * DP / 4;     // float4 loads per X2 tile
+  constexpr int XQT = XQ / 256;       // ... per thread (DCH)
+  constexpr int VE = TN * WT / 256;   // V elements per thread (4*WCH)
+  __shared__ __align__(16) float sX[2][TN * XS];
+  __shared__ __align__(16) float sN[2][TN];
+  __shared__ __align__(16) float sV[2][WT * VS];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * 64 + wave * 16;
+  const int w0 = blockIdx.z * WT;
+  const int64_t m_begin = static_cast<int64_t>(blockIdx.y) * cols_per_split;
+  const int64_t m_end = m_begin + cols_per_split < n2 ? m_begin + cols_per_split : n2;
+
+  // this lane's X1 row (as B operand of the distance MFMA) and its norm
+  const int64_t nrow = row0 + r;
+  const bool nvalid = nrow < n1;
+  f4 xb[DCH];
+#pragma unroll
+  for (int c = 0; c < DCH; ++c)
+    xb[c] = nvalid ? *reinterpret_cast<const f4*>(X1p + nrow * DP + 16 * c + 4 * g) : f4{0, 0, 0, 0};
+  const float n1v = nvalid ? nrm1[nrow] * cnorm : 0.0f;
+
+  f4 out[WCH];
+#pragma unroll
+  for (int wc = 0; wc < WCH; ++wc) out[wc] = f4{0, 0, 0, 0};
+
+  // register staging of one tile
+  f4 px[XQT];
+  float pv[VE];
+  float pn = 0.0f;
+  auto fetch = [&](int64_t m0) {
+#pragma unroll
+    for (int q = 0; q < XQT; ++q) {
+      const int e = tid + q * 256;
+      const int row = e / (DP / 4), col = e % (DP / 4);
+      const int64_t m = m0 + row;
+      px[q] = m < m_end ? *reinterpret_cast<const f4*>(X2p + m * DP + col * 4) : f4{0, 0, 0, 0};
+    }
+    if (tid < TN) {
+      const int64_t m = m0 + tid;
+      pn = m < m_end ? nrm2[m] * cnorm : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < VE; ++q) {
+      const int e = tid + q * 256;
+      const int m = e / WT, wl = e % WT;
+      const int64_t gm = m0 + m;
+      const int w = w0 + wl;
+      pv[q] = (gm < m_end && w < W) ? V[(w / C) * ldv + gm * C + (w % C)] : 0.0f;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < XQT; ++q) {
+      const int e = tid + q * 256;
+      const int row = e / (DP / 4), col = e % (DP / 4);
+      *reinterpret_cast<f4*>(&sX[buf][row * XS + col * 4]) = px[q];
+    }
+    if (tid < TN) sN[buf][tid] = pn;
+#pragma unroll
+    for (int q = 0; q < VE; ++q) {
+      const int e = tid + q * 256;
+      const int m = e / WT, wl = e % WT;
+      sV[buf][wl * VS + m] = pv[q];
+    }
+  };
+
+  if (m_begin < m_end) {
+    fetch(m_begin);
+    stash(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t m0 = m_begin; m0 < m_end; m0 += TN) {
+    const bool more = m0 + TN < m_end;
+    if (more) fetch(m0 + TN);
+#pragma unroll
+    for (int mb = 0; mb < TN / 16; ++mb) {
+      f4 acc = {0, 0, 0, 0};
+#pragma unroll
+      for (int c = 0; c < DCH; ++c) {
+        const f4 a = *reinterpret_cast<const f4*>(&sX[buf][(mb * 16 + r) * XS + 16 * c + 4 * g]);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], xb[c][0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], xb[c][1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], xb[c][2], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], xb[c][3], acc, 0, 0, 0);
+      }
+      const f4 n2v = *reinterpret_cast<const f4*>(&sN[buf][mb * 16 + 4 * g]);
+      f4 kv;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        kv[v] = ktransform<KIND>(__builtin_fmaf(acc[v], cdot, n1v + n2v[v]));
+#pragma unroll
+      for (int wc = 0; wc < WCH; ++wc) {
+        const f4 vb = *reinterpret_cast<const f4*>(&sV[buf][(wc * 16 + r) * VS + mb * 16 + 4 * g]);
+        out[wc] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[0], vb[0], out[wc], 0, 0, 0);
+        out[wc] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[1], vb[1], out[wc], 0, 0, 0);
+        out[wc] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[2], vb[2], out[wc], 0, 0, 0);
+        out[wc] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[3], vb[3], out[wc], 0, 0, 0);
+      }
+    }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  // out[wc][j] = Out[row0 + 4g + j][w0 + 16 wc + r]
+#pragma unroll
+  for (int wc = 0; wc < WCH; ++wc) {
+    const int w = w0 + wc * 16 + r;
+    if (w >= W) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t n = row0 + 4 * g + j;
+      if (n < n1) P[(static_cast<int64_t>(blockIdx.y) * n1 + n) * W + w] = out[wc][j];
+    }
+  }
+}
+
+// Centred, zero-padded copies of rows (DP floats each) and their squared norms.
+__global__ void k_prep_rows(const float* __restrict__ X, int64_t n, int d, int DP,
+                            const float* __restrict__ centre, float* __restrict__ Xp,
+                            float* __restrict__ norms) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < DP; ++k) {
+    float v = 0.0f;
+    if (k < d) v = X[i * d + k] - (centre ? centre[k] : 0.0f);
+    Xp[i * DP + k] = v;
+    s += static_cast<double>(v) * v;
+  }
+  norms[i] = static_cast<float>(s);
+}
+
+__global__ void k_col_partial(const float* __restrict__ X, int64_t n, int d, int64_t rows_per,
+                              double* __restrict__ part) {
+  const int64_t r0 = blockIdx.x * rows_per;
+  const int64_t r1 = r0 + rows_per < n ? r0 + rows_per : n;
+  for (int k = threadIdx.x; k < d; k += blockDim.x) {
+    double s = 0.0;
+    for (int64_t i = r0; i < r1; ++i) s += X[i * d + k];
+    part[blockIdx.x * static_cast<int64_t>(d) + k] = s;
+  }
+}
+
+__global__ void k_col_finish(const double* __restrict__ part, int nblk, int d, int64_t n,
+                             float* __restrict__ mean) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= d) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[static_cast<int64_t>(b) * d + k];
+  mean[k] = static_cast<float>(n > 0 ? s / n : 0.0);
+}
+
+struct Plan {
+  int dch, wch, gx, gz, nsplit;
+  int64_t cols_per_split;
+};
+
+Plan plan_mfma(int64_t n1, int64_t n2, int64_t d, int64_t W) {
+  Plan p{};
+  p.dch = static_cast<int>(ceil_div(d, 16));
+  p.wch = W <= 16 ? 1 : (W <= 32 ? 2 : 4);
+  p.gx = static_cast<int>(ceil_div(n1, 64));
+  p.gz = static_cast<int>(ceil_div(W, 16 * p.wch));
+  const int64_t tiles = ceil_div(n2, TN);
+  if (tiles == 0) {
+    p.nsplit = 0;
+    p.cols_per_split = TN;
+    return p;
+  }
+  // about 8192 workgroups (several rounds over 256 CUs, small tail)
+  int64_t want = ceil_div(8192, static_cast<int64_t>(p.gx) * p.gz);
+  if (want < 1) want = 1;
+  if (want > tiles) want = tiles;
+  p.cols_per_split = ceil_div(tiles, want) * TN;
+  p.nsplit = static_cast<int>(ceil_div(n2, p.cols_per_split));
+  return p;
+}
+
+template <int KIND, int DCH>
+int launch_kind_dch(const Plan& pl, const float* X1p, const float* n1p, const float* X2p,
+                    const float* n2p, int64_t n1, int64_t n2, const float* V, int C, int W,
+                    int64_t ldv, float* P, float cnorm, float cdot, const int* skip,
+                    hipStream_t s) {
+  dim3 grid(pl.gx, pl.nsplit, pl.gz);
+  if (pl.wch == 1)
+    kv_mfma_f32<KIND, DCH, 1><<<grid, 256, 0, s>>>(X1p, n1p, X2p, n2p, n1, n2, V, C, W, ldv, P,
+                                                   pl.cols_per_split, cnorm, cdot, skip);
+  else if (pl.wch == 2)
+    kv_mfma_f32<KIND, DCH, 2><<<grid, 256, 0, s>>>(X1p, n1p, X2p, n2p, n1, n2, V, C, W, ldv, P,
+                                                   pl.cols_per_split, cnorm, cdot, skip);
+  else
+    kv_mfma_f32<KIND, DCH, 4><<<grid, 256, 0, s>>>(X1p, n1p, X2p, n2p, n1, n2, V, C, W, ldv, P,
+                                                   pl.cols_per_split, cnorm, cdot, skip);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template <int KIND>
+int launch_kind(const Plan& pl, const float* X1p, const float* n1p, const float* X2p,
+                const float* n2p, int64_t n1, int64_t n2, const float* V, int C, int W,
+                int64_t ldv, float* P, float cnorm, float cdot, const int* skip, hipStream_t s) {
+  switch (pl.dch) {
+#define IGP_DCH(K) \
+  case K: return launch_kind_dch<KIND, K>(pl, X1p, n1p, X2p, n2p, n1, n2, V, C, W, ldv, P, cnorm, cdot, skip, s);
+    IGP_DCH(1) IGP_DCH(2) IGP_DCH(3) IGP_DCH(4) IGP_DCH(5) IGP_DCH(6) IGP_DCH(7) IGP_DCH(8)
+#undef IGP_DCH
+    default:
+      set_error("feature count outside the FP32 matrix-core kernel's range");
+      return IGP_EUNSUPPORTED;
+  }
+}
+
+}  // namespace
+
+bool mfma_f32_supported(int kind, int64_t d) {
+  return kind != IGP_MATERN12 && d >= 1 && d <= 128;
+}
+
+size_t mfma_f32_partial_bytes(int64_t n1, int64_t n2, int64_t d, int64_t W) {
+  Plan pl = plan_mfma(n1, n2, d, W);
+  return static_cast<size_t>(pl.nsplit) * n1 * W * sizeof(float);
+}
+
+int64_t padded_dim(int64_t d) { return ceil_div(d, 16) * 16; }
+
+int column_mean_f32(const float* X, int64_t n, int64_t d, float* mean, double* part,
+                    int64_t part_cap, hipStream_t s) {
+  if (n == 0) {
+    IGP_CHECK_HIP(hipMemsetAsync(mean, 0, d * sizeof(float), s));
+    return IGP_OK;
+  }
+  int64_t nblk = std::min<int64_t>(ceil_div(n, 256), std::max<int64_t>(part_cap / d, 1));
+  const int64_t rows_per = ceil_div(n, nblk);
+  nblk = ceil_div(n, rows_per);
+  k_col_partial<<<static_cast<unsigned>(nblk), 64, 0, s>>>(X, n, static_cast<int>(d), rows_per, part);
+  k_col_finish<<<static_cast<unsigned>(ceil_div(d, 64)), 64, 0, s>>>(part, static_cast<int>(nblk),
+                                                                      static_cast<int>(d), n, mean);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+int prep_rows_f32(const float* X, int64_t n, int64_t d, const float* centre, float* Xp,
+                  float* norms, hipStream_t s) {
+  if (n == 0) return IGP_OK;
+  k_prep_rows<<<static_cast<unsigned>(ceil_div(n, 256)), 256, 0, s>>>(
+      X, n, static_cast<int>(d), static_cast<int>(padded_dim(d)), centre, Xp, norms);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+// Out = os * K(X1, X2) V from prepared (centred, padded) rows; partials in ws.
+int kv_mfma_f32_launch(const KVProblem& p, const float* X1p, const float* n1p,
+                       const float* X2p, const float* n2p, float* P, size_t P_bytes,
+                       hipStream_t s, int* nsplit_out) {
+  const int64_t W = p.C * p.nb;
+  Plan pl = plan_mfma(p.n1, p.n2, p.d, W);
+  *nsplit_out = pl.nsplit;
+  if (static_cast<size_t>(pl.nsplit) * p.n1 * W * sizeof(float) > P_bytes) {
+    set_error("kernel-product workspace too small for the split partials");
+    return IGP_ENOMEM;
+  }
+  if (pl.nsplit == 0) return IGP_OK;
+  const double inv_l2 = 1.0 / (p.kp.lengthscale * p.kp.lengthscale);
+  const float* V = static_cast<const float*>(p.V);
+  const int C = static_cast<int>(p.C), Wi = static_cast<int>(W);
+  switch (p.kp.kind) {
+    case IGP_RBF: {
+      const float k = kappa<IGP_RBF>();
+      return launch_kind<IGP_RBF>(pl, X1p, n1p, X2p, n2p, p.n1, p.n2, V, C, Wi, p.ldv, P,
+                                  static_cast<float>(k * inv_l2), static_cast<float>(-2.0 * k * inv_l2),
+                                  p.skip, s);
+    }
+    case IGP_MATERN32: {
+      const float k = kappa<IGP_MATERN32>();
+      return launch_kind<IGP_MATERN32>(pl, X1p, n1p, X2p, n2p, p.n1, p.n2, V, C, Wi, p.ldv, P,
+                                       static_cast<float>(k * inv_l2),
+                                       static_cast<float>(-2.0 * k * inv_l2), p.skip, s);
+    }
+    case IGP_MATERN52: {
+      const float k = kappa<IGP_MATERN52>();
+      return launch_kind<IGP_MATERN52>(pl, X1p, n1p, X2p, n2p, p.n1, p.n2, V, C, Wi, p.ldv, P,
+                                       static_cast<float>(k * inv_l2),
+                                       static_cast<float>(-2.0 * k * inv_l2), p.skip, s);
+    }
+    default:
+      set_error("Matern-1/2 runs on the direct-difference kernel");
+      return IGP_EUNSUPPORTED;
+  }
+}
+
+}  // namespace igp

@@ -136,11 +136,12 @@ __global__ void k_finish_cols(const double* __restrict__ part, int nrow_blocks, 
 // d = s - Q y ; eta partial = z^T d.  One row per thread; y staged in LDS.
 constexpr int MAXCOLS_LDS = 4096;
 
-template <typename T>
+template <typename T, bool KQ>
 __global__ void __launch_bounds__(NT)
 k_dir_update(const T* __restrict__ sv, const T* __restrict__ Q, int64_t ldq, int64_t n,
              int ncols, const double* __restrict__ y, const T* __restrict__ z,
-             T* __restrict__ d, double* __restrict__ part) {
+             T* __restrict__ d, double* __restrict__ part, const T* __restrict__ tv,
+             const T* __restrict__ KQm, T* __restrict__ kd) {
   __shared__ double sy[MAXCOLS_LDS];
   __shared__ double red[NT / 64];
   for (int b = threadIdx.x; b < ncols; b += NT) sy[b] = y[b];
@@ -148,7 +149,7 @@ k_dir_update(const T* __restrict__ sv, const T* __restrict__ Q, int64_t ldq, int
   const int64_t i = blockIdx.x * static_cast<int64_t>(NT) + threadIdx.x;
   double e = 0.0;
   if (i < n) {
-    double acc = 0.0;
+    double acc = 0.0, acck = 0.0;
     int b = 0;
     for (; b + 4 <= ncols; b += 4) {
       const double q0 = Q[static_cast<int64_t>(b) * ldq + i];
@@ -156,10 +157,21 @@ k_dir_update(const T* __restrict__ sv, const T* __restrict__ Q, int64_t ldq, int
       const double q2 = Q[static_cast<int64_t>(b + 2) * ldq + i];
       const double q3 = Q[static_cast<int64_t>(b + 3) * ldq + i];
       acc += q0 * sy[b] + q1 * sy[b + 1] + q2 * sy[b + 2] + q3 * sy[b + 3];
+      if constexpr (KQ) {
+        const double k0 = KQm[static_cast<int64_t>(b) * ldq + i];
+        const double k1 = KQm[static_cast<int64_t>(b + 1) * ldq + i];
+        const double k2 = KQm[static_cast<int64_t>(b + 2) * ldq + i];
+        const double k3 = KQm[static_cast<int64_t>(b + 3) * ldq + i];
+        acck += k0 * sy[b] + k1 * sy[b + 1] + k2 * sy[b + 2] + k3 * sy[b + 3];
+      }
     }
-    for (; b < ncols; ++b) acc += static_cast<double>(Q[static_cast<int64_t>(b) * ldq + i]) * sy[b];
+    for (; b < ncols; ++b) {
+      acc += static_cast<double>(Q[static_cast<int64_t>(b) * ldq + i]) * sy[b];
+      if constexpr (KQ) acck += static_cast<double>(KQm[static_cast<int64_t>(b) * ldq + i]) * sy[b];
+    }
     const T di = static_cast<T>(static_cast<double>(sv[i]) - acc);
     d[i] = di;
+    if constexpr (KQ) kd[i] = static_cast<T>(static_cast<double>(tv[i]) - acck);
     e = static_cast<double>(z[i]) * static_cast<double>(di);
   }
   e = block_sum(e, red);
@@ -179,9 +191,11 @@ __global__ void k_gemv_n(const T* __restrict__ Q, int64_t ldq, int64_t n, int nc
   out[i] = static_cast<T>(acc);
 }
 
-template <typename T>
+template <typename T, bool KQ>
 __global__ void k_append_step(const T* __restrict__ d, const double* __restrict__ scal,
-                              T* __restrict__ qcol, T* __restrict__ v, int64_t n) {
+                              T* __restrict__ qcol, T* __restrict__ v, int64_t n,
+                              const T* __restrict__ kd, T* __restrict__ kqcol,
+                              T* __restrict__ kv) {
   const double eta = scal[SC_ETA];
   if (!(eta > 0.0)) return;
   const double qs = 1.0 / sqrt(eta);
@@ -191,6 +205,11 @@ __global__ void k_append_step(const T* __restrict__ d, const double* __restrict_
     const double di = static_cast<double>(d[i]);
     qcol[i] = static_cast<T>(di * qs);
     v[i] = static_cast<T>(static_cast<double>(v[i]) + step * di);
+    if constexpr (KQ) {
+      const double ki = static_cast<double>(kd[i]);
+      kqcol[i] = static_cast<T>(ki * qs);
+      kv[i] = static_cast<T>(static_cast<double>(kv[i]) + step * ki);
+    }
   }
 }
 
@@ -409,21 +428,31 @@ int gemv_t(const T* Q, int64_t ldq, int64_t n, int ncols, const T* z, double* pa
 
 template <typename T>
 int dir_update(const T* sv, const T* Q, int64_t ldq, int64_t n, int ncols, const double* y,
-               const T* z, T* d, double* part, double* eta_out, hipStream_t s) {
+               const T* z, T* d, double* part, double* eta_out, hipStream_t s, const T* tv,
+               const T* KQm, T* kd) {
   if (ncols > MAXCOLS_LDS) {
     set_error("buffer of %d columns exceeds %d", ncols, MAXCOLS_LDS);
     return IGP_EUNSUPPORTED;
   }
   const int g = static_cast<int>(ceil_div(n, NT));
-  k_dir_update<T><<<g, NT, 0, s>>>(sv, Q, ldq, n, ncols, y, z, d, part);
+  if (KQm)
+    k_dir_update<T, true><<<g, NT, 0, s>>>(sv, Q, ldq, n, ncols, y, z, d, part, tv, KQm, kd);
+  else
+    k_dir_update<T, false><<<g, NT, 0, s>>>(sv, Q, ldq, n, ncols, y, z, d, part, nullptr,
+                                            nullptr, nullptr);
   k_finish_sum<<<1, NT, 0, s>>>(part, g, eta_out);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
 
 template <typename T>
-int append_and_step(const T* d, const double* scal, T* qcol, T* v, int64_t n, hipStream_t s) {
-  k_append_step<T><<<grid_for(n), NT, 0, s>>>(d, scal, qcol, v, n);
+int append_and_step(const T* d, const double* scal, T* qcol, T* v, int64_t n, hipStream_t s,
+                    const T* kd, T* kqcol, T* kv) {
+  if (kd)
+    k_append_step<T, true><<<grid_for(n), NT, 0, s>>>(d, scal, qcol, v, n, kd, kqcol, kv);
+  else
+    k_append_step<T, false><<<grid_for(n), NT, 0, s>>>(d, scal, qcol, v, n, nullptr, nullptr,
+                                                       nullptr);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
@@ -515,8 +544,10 @@ int predict_epilogue(const T* A, int64_t lda, int64_t nrows, int ncols, double o
   template int gemv_t<T>(const T*, int64_t, int64_t, int, const T*, double*, double*,         \
                          hipStream_t);                                                         \
   template int dir_update<T>(const T*, const T*, int64_t, int64_t, int, const double*,         \
-                             const T*, T*, double*, double*, hipStream_t);                     \
-  template int append_and_step<T>(const T*, const double*, T*, T*, int64_t, hipStream_t);     \
+                             const T*, T*, double*, double*, hipStream_t, const T*, const T*,  \
+                             T*);                                                              \
+  template int append_and_step<T>(const T*, const double*, T*, T*, int64_t, hipStream_t,      \
+                                  const T*, T*, T*);                                           \
   template int gemv_n<T>(const T*, int64_t, int64_t, int, const double*, T*, hipStream_t);     \
   template int gram<T>(const T*, const T*, int64_t, int64_t, int, double*, size_t, double*,   \
                        hipStream_t);                                                           \

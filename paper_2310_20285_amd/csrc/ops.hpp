@@ -32,26 +32,35 @@ struct KVProblem {
   void* Out;
   int64_t ldo;
   double beta;
-  // optional precomputed data (FP32 / BF16 MFMA paths): squared norms of the
-  // rows scaled by 1/l^2 and BF16 copies of the scaled rows
+  // optional prepared rows for the matrix-core paths: X - centre (common
+  // centre for X1 and X2), zero-padded to a multiple of 16 features, and the
+  // squared norms of those rows.  When absent the launcher prepares them in ws.
+  const float* X1p = nullptr;
+  const float* X2p = nullptr;
   const float* norm1 = nullptr;
   const float* norm2 = nullptr;
-  const uint16_t* Xb1 = nullptr;
-  const uint16_t* Xb2 = nullptr;
   const int* skip = nullptr;
 };
 
 size_t kv_ws_bytes(int64_t n1, int64_t n2, int64_t d, int64_t C, int64_t nb, int precision);
+// bytes of ws needed when X1p/X2p/norms are supplied (partials only)
+size_t kv_ws_bytes_prepared(int64_t n1, int64_t n2, int64_t d, int64_t C, int64_t nb,
+                            int precision);
 int kv_launch(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t s);
+// whether (precision, kind, d) runs on the matrix cores from prepared rows
+bool kv_uses_prepared(int precision, int kind, int64_t d);
 
-// Row preparation for the MFMA paths: out rows = (X - centre) / l, their
-// squared norms, and (BF16) rounded copies whose norms are taken after rounding.
-size_t prep_ws_bytes(int64_t n, int64_t d, int precision);
-int prep_rows(const float* X, int64_t n, int64_t d, const float* centre, double inv_l,
-              int precision, float* Xs_out, float* norms_out, uint16_t* Xb_out,
-              hipStream_t s);
-int column_mean(const void* X, int64_t n, int64_t d, int precision, float* mean_out,
-                double* scratch, hipStream_t s);
+// FP32 matrix-core kernel product (kv_mfma.hip)
+bool mfma_f32_supported(int kind, int64_t d);
+size_t mfma_f32_partial_bytes(int64_t n1, int64_t n2, int64_t d, int64_t W);
+int64_t padded_dim(int64_t d);
+int column_mean_f32(const float* X, int64_t n, int64_t d, float* mean, double* part,
+                    int64_t part_cap, hipStream_t s);
+int prep_rows_f32(const float* X, int64_t n, int64_t d, const float* centre, float* Xp,
+                  float* norms, hipStream_t s);
+int kv_mfma_f32_launch(const KVProblem& p, const float* X1p, const float* n1p,
+                       const float* X2p, const float* n2p, float* P, size_t P_bytes,
+                       hipStream_t s, int* nsplit_out);
 
 // ---- softmax Hessian blocks ---------------------------------------------------
 // pi = softmax(F) per point; rhs = F + W^+ (onehot(y) - pi); loglik partials.
@@ -98,13 +107,16 @@ int add_vec(const T* a, const T* b, T* out, int64_t n, hipStream_t s);
 template <typename T>
 int gemv_t(const T* Q, int64_t ldq, int64_t n, int ncols, const T* z, double* partials,
            double* y, hipStream_t s);
-// d = s - Q y ; eta partials of z^T d
+// d = s - Q y ; eta partials of z^T d ; with KQ: also kd = t - KQ y (= K d)
 template <typename T>
 int dir_update(const T* sv, const T* Q, int64_t ldq, int64_t n, int ncols, const double* y,
-               const T* z, T* d, double* partials, double* eta_out, hipStream_t s);
+               const T* z, T* d, double* partials, double* eta_out, hipStream_t s,
+               const T* tv = nullptr, const T* KQ = nullptr, T* kd = nullptr);
 // Q[:, col] = d / sqrt(eta); v += (alpha/eta) d   (no-op when eta <= 0)
+// with kd: also KQ[:, col] = kd / sqrt(eta); kv += (alpha/eta) kd
 template <typename T>
-int append_and_step(const T* d, const double* scal, T* qcol, T* v, int64_t n, hipStream_t s);
+int append_and_step(const T* d, const double* scal, T* qcol, T* v, int64_t n, hipStream_t s,
+                    const T* kd = nullptr, T* kqcol = nullptr, T* kv = nullptr);
 // v = Q y
 template <typename T>
 int gemv_n(const T* Q, int64_t ldq, int64_t n, int ncols, const double* y, T* out,

@@ -35,6 +35,9 @@ SHAPES = [  # n1, n2, d, C, nb  -- several tiles plus ragged tails
     (130, 129, 33, 1, 3),
     (1, 1, 1, 1, 1),
     (257, 64, 8, 2, 1),
+    (1000, 2311, 16, 5, 1),     # solver product shape (matrix-core path in FP32)
+    (129, 700, 32, 5, 40),      # predict shape: W = C * nb = 200 output columns
+    (70, 90, 128, 3, 2),        # widest feature count of the FP32 matrix-core path
 ]
 
 

@@ -9,6 +9,8 @@ itergp_predict) against the FP64 oracle.
   within 1e-5; prediction kernels within 1e-10 of the oracle on the same state.
 * FP32 with the oracle's own actions replayed (policy USER): the iterates and
   the predictive mean stay within 1e-4 relative of the FP64 oracle.
+Every case runs with the residual formed by a fresh product with K (as the
+algorithm is printed) and with K v carried by the K Q recurrence.
 """
 import numpy as np
 import pytest
@@ -40,11 +42,15 @@ def _model(w, X, **kw):
     return api.IterNCGP(Xd, yd, w.C, w.kernel, w.lengthscale, w.outputscale, **kw), dt
 
 
-def test_config1_unit_full_budget_is_exact_newton(gpu_lib, cfg1):
+RESIDUAL = pytest.mark.parametrize("residual", ["explicit", "recurrence"])
+
+
+@RESIDUAL
+def test_config1_unit_full_budget_is_exact_newton(gpu_lib, cfg1, residual):
     w = cfg1
     n = w.N * w.C
     m, dt = _model(w, w.X, policy="unit", j_max=n, recycle=False, tol_abs=0.0, tol_rel=0.0,
-                   precision="fp64", max_buffer=n)
+                   precision="fp64", max_buffer=n, residual_mode=residual)
     Kf = ok.full_kernel_cn(ok.kernel_matrix(w.X, w.X, w.kernel, w.lengthscale, w.outputscale), w.C)
     Fs, vs = on.exact_newton(Kf, w.y, w.C, 5)
     for i in range(5):
@@ -56,7 +62,8 @@ def test_config1_unit_full_budget_is_exact_newton(gpu_lib, cfg1):
     assert _rel(v, vs[-1]) <= 1e-8
 
 
-def test_config1_fp64_user_replay_matches_oracle(gpu_lib, cfg1):
+@RESIDUAL
+def test_config1_fp64_user_replay_matches_oracle(gpu_lib, cfg1, residual):
     """The oracle's CG actions replayed through the GPU path (FP64): with the
     actions fixed, every remaining operation is a fixed linear-algebra
     pipeline, reproducible to ~1e-15 between rounding orders on the CPU."""
@@ -64,7 +71,8 @@ def test_config1_fp64_user_replay_matches_oracle(gpu_lib, cfg1):
     kw = dict(j_max=60, rank_limit=40, recycle=True, tol_abs=1e-5, tol_rel=1e-5)
     Kf = ok.full_kernel_cn(ok.kernel_matrix(w.X, w.X, w.kernel, w.lengthscale, w.outputscale), w.C)
     recs = oi.iterncgp(lambda V: Kf @ V, w.y, w.C, 4, policy="cg", **kw)
-    m, dt = _model(w, w.X, policy="user", precision="fp64", max_buffer=100, **kw)
+    m, dt = _model(w, w.X, policy="user", precision="fp64", max_buffer=100,
+                   residual_mode=residual, **kw)
     for i, rec in enumerate(recs):
         m.set_user_actions(torch.tensor(np.stack(rec.info.actions), dtype=dt, device="cuda"))
         info = m.newton_step()
@@ -79,7 +87,8 @@ def test_config1_fp64_user_replay_matches_oracle(gpu_lib, cfg1):
         assert _rel(Q @ (Q.T @ z), rec.Q @ (rec.Q.T @ z)) <= 1e-9
 
 
-def test_config1_cg_recycling_free_running(gpu_lib, cfg1):
+@RESIDUAL
+def test_config1_cg_recycling_free_running(gpu_lib, cfg1, residual):
     """Free-running CG in FP64 against the oracle.  The CG iterate itself is
     sensitive to rounding order here (two FP64 oracle runs that differ only in
     how K v is summed move F by ~1e-7 after 15 iterations: rounding excites the
@@ -88,7 +97,7 @@ def test_config1_cg_recycling_free_running(gpu_lib, cfg1):
     are checked tightly against the oracle evaluated on the GPU's own v, Q."""
     w = cfg1
     kw = dict(policy="cg", j_max=60, rank_limit=40, recycle=True, tol_abs=1e-5, tol_rel=1e-5)
-    m, dt = _model(w, w.X, precision="fp64", max_buffer=100, **kw)
+    m, dt = _model(w, w.X, precision="fp64", max_buffer=100, residual_mode=residual, **kw)
     Kf = ok.full_kernel_cn(ok.kernel_matrix(w.X, w.X, w.kernel, w.lengthscale, w.outputscale), w.C)
     recs = oi.iterncgp(lambda V: Kf @ V, w.y, w.C, 4, **kw)
     for i, rec in enumerate(recs):
@@ -111,7 +120,8 @@ def test_config1_cg_recycling_free_running(gpu_lib, cfg1):
     assert np.all(var.cpu().numpy() <= w.outputscale + 1e-12)
 
 
-def test_fp32_user_replay_matches_fp64_oracle(gpu_lib):
+@RESIDUAL
+def test_fp32_user_replay_matches_fp64_oracle(gpu_lib, residual):
     w = datagen.config2(N=1500, Ns=300)
     n = w.N * w.C
     KX = ok.kernel_matrix(w.X, w.X, w.kernel, w.lengthscale, w.outputscale)
@@ -120,7 +130,8 @@ def test_fp32_user_replay_matches_fp64_oracle(gpu_lib):
     recs = oi.iterncgp(aK, w.y, w.C, steps, policy="cg", j_max=jmax, rank_limit=R,
                        recycle=True, tol_abs=1e-5, tol_rel=1e-5)
     m, dt = _model(w, w.X, policy="user", j_max=jmax, rank_limit=R, recycle=True,
-                   tol_abs=1e-5, tol_rel=1e-5, precision="fp32", max_buffer=jmax + R)
+                   tol_abs=1e-5, tol_rel=1e-5, precision="fp32", max_buffer=jmax + R,
+                   residual_mode=residual)
     for i, rec in enumerate(recs):
         acts = np.stack(rec.info.actions) if rec.info.actions else np.zeros((0, n))
         A = torch.tensor(acts, dtype=dt, device="cuda")
