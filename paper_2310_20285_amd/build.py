@@ -23,7 +23,7 @@ LIB = os.path.join(HERE, "libitergp.so")
 SOURCES = ["kv.hip", "kv_mfma.hip", "hessian.hip", "linalg.hip", "itergp.cpp", "abi.cpp",
            "eigh.cpp"]
 ARCH = "gfx950"
-COMMON = ["-O3", "-fPIC", "-std=c++17", f"-I{INCLUDE}", "-Wall", "-Wno-unused-function",
+COMMON = [*os.environ.get("IGP_EXTRA_FLAGS", "").split(), "-O3", "-fPIC", "-std=c++17", f"-I{INCLUDE}", "-Wall", "-Wno-unused-function",
           "-Wno-unused-parameter"]
 # Packed FP32 instructions stay disabled on this target.
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

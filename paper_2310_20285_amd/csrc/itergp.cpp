@@ -292,20 +292,28 @@ struct Model final : igp_model {
     const double thresh = std::max(cfg.tol_abs, cfg.tol_rel * info.rhs_norm);
     int kprod = 0;
     int j = 0;
-    while (j < cfg.j_max) {
-      // r_{j-1} = (yhat - m) - K v - W^+ v   (K v carried by the recurrence, or formed)
+    // r = (yhat - m) - K v - W^+ v with K v formed (explicit) or carried (recurrence)
+    auto enqueue_residual = [&]() -> int {
       if (!recurrence()) {
         IGP_TRY(apply_K(L.v, L.kv));
         ++kprod;
       }
-      IGP_TRY(winv_apply<T>(L.pi, false, IGP_W_PINV, N, C, L.v, 1, n, nullptr, 0, L.wv, n, stream));
-      IGP_TRY(residual<T>(L.rhs, L.kv, L.wv, L.r, n, L.part, L.scal + SC_RR, stream));
+      IGP_TRY(winv_apply<T>(L.pi, false, IGP_W_PINV, N, C, L.v, 1, n, nullptr, 0, L.wv, n,
+                            stream));
+      return residual<T>(L.rhs, L.kv, L.wv, L.r, n, L.part, L.scal + SC_RR, stream);
+    };
+    bool have_r = false;
+    if (cfg.j_max > 0) {
+      IGP_TRY(enqueue_residual());   // r_0
       IGP_TRY(read_scalars(sc));
       info.res_norm = std::sqrt(sc[SC_RR]);
-      if (!(info.res_norm >= thresh)) {
-        info.converged = 1;
-        break;
-      }
+      have_r = true;
+      if (!(info.res_norm >= thresh)) info.converged = 1;
+    }
+    // One host synchronisation per iteration: the update of Q and v is guarded
+    // on the device by eta_j > 0, and the next residual is enqueued before the
+    // host reads eta_j and ||r_j|| together.
+    while (have_r && !info.converged && j < cfg.j_max) {
       if (ncols >= cfg.max_buffer) {
         set_error("buffer full: %d columns (max_buffer too small)", ncols);
         return IGP_ENOMEM;
@@ -330,6 +338,12 @@ struct Model final : igp_model {
       IGP_TRY(dir_update<T>(s_col, L.Q, ld, n, ncols, L.yb, L.z, L.d, L.part,
                             L.scal + SC_ETA, stream, t_col, recurrence() ? L.KQ : nullptr,
                             L.kd));                                              // d_j, eta_j
+      IGP_TRY(append_and_step<T>(L.d, L.scal, L.Q + static_cast<int64_t>(ncols) * ld, L.v, n,
+                                 stream, recurrence() ? L.kd : nullptr,
+                                 recurrence() ? L.KQ + static_cast<int64_t>(ncols) * ld : nullptr,
+                                 L.kv));                                         // eta > 0 only
+      const bool next_r = j < cfg.j_max;
+      if (next_r) IGP_TRY(enqueue_residual());                                   // r_j
       IGP_TRY(read_scalars(sc));
       const double eta = sc[SC_ETA];
       if (!(eta > 0.0)) {
@@ -338,11 +352,11 @@ struct Model final : igp_model {
         break;
       }
       info.eta_min = std::min(info.eta_min, eta);
-      IGP_TRY(append_and_step<T>(L.d, L.scal, L.Q + static_cast<int64_t>(ncols) * ld, L.v, n,
-                                 stream, recurrence() ? L.kd : nullptr,
-                                 recurrence() ? L.KQ + static_cast<int64_t>(ncols) * ld : nullptr,
-                                 L.kv));
       ++ncols;
+      if (next_r) {
+        info.res_norm = std::sqrt(sc[SC_RR]);
+        if (!(info.res_norm >= thresh)) info.converged = 1;
+      }
     }
     info.iters = j;
     // f_{i+1} = K v + m

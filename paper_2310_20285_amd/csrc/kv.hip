@@ -106,8 +106,18 @@ __global__ void kv_reduce(const T* __restrict__ P, int nsplit, int64_t n1, int W
        idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const int64_t n = idx / W;
     const int w = static_cast<int>(idx % W);
-    T s = T(0);
-    for (int sp = 0; sp < nsplit; ++sp) s += P[(sp * n1 + n) * W + w];
+    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+    const int64_t stride = n1 * W;
+    const T* p = P + n * W + w;
+    int sp = 0;
+    for (; sp + 4 <= nsplit; sp += 4) {
+      s0 += p[sp * stride];
+      s1 += p[(sp + 1) * stride];
+      s2 += p[(sp + 2) * stride];
+      s3 += p[(sp + 3) * stride];
+    }
+    for (; sp < nsplit; ++sp) s0 += p[sp * stride];
+    const T s = (s0 + s1) + (s2 + s3);
     T* o = Out + (w / C) * ldo + n * C + (w % C);
     *o = (beta != T(0)) ? os * s + beta * *o : os * s;
   }

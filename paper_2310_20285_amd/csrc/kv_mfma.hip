@@ -192,6 +192,175 @@ kv_mfma_f32(const float* __restrict__ X1p, const float* __restrict__ nrm1,
   }
 }
 
+// Narrow-output variant (W <= 8, the solver products K s and K v): the
+// contraction with V runs on VALU FMAs, which on gfx950 costs fewer issue
+// cycles than four 16x16x4 MFMAs for W <= 8 (FP32 MFMA and VALU work do not
+// overlap on a SIMD, so the kernel minimises their sum).  Each wave owns two
+// 16-row strips of X1 (32 rows), so every X2 and V value read from LDS serves
+// 32 output rows.  Lane l accumulates, for its rows r and 16 + r, the sum over
+// the m assigned to its lane group g = l/16; the four group partials are
+// added with cross-lane shuffles at the end.
+constexpr int WV = 8;    // widest output of the narrow variant
+#ifndef IGP_NARROW_NS
+#define IGP_NARROW_NS 2
+#endif
+constexpr int NSTRIP = IGP_NARROW_NS;   // 16-row strips of X1 per wave
+
+template <int KIND, int DCH, int WX, int NS>
+__global__ void __launch_bounds__(256)
+kv_mfma_f32_narrow(const float* __restrict__ X1p, const float* __restrict__ nrm1,
+                   const float* __restrict__ X2p, const float* __restrict__ nrm2, int64_t n1,
+                   int64_t n2, const float* __restrict__ V, int C, int64_t ldv,
+                   float* __restrict__ P, int64_t cols_per_split, float cnorm, float cdot,
+                   const int* skip) {
+  if (skip && *skip) return;
+  constexpr int DP = DCH * 16;
+  constexpr int XS = DP + 4;
+  constexpr int XQT = TN * DP / 4 / 256;   // float4 of X2 per thread per tile (= DCH)
+  constexpr int VT = TN * WX;              // V values per tile, layout [m][WX]
+  constexpr int VE = (VT + 255) / 256;     // V elements per thread per tile
+  __shared__ __align__(16) float sX[2][TN * XS];
+  __shared__ __align__(16) float sN[2][TN];
+  __shared__ __align__(16) float sV[2][VE * 256];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * (64 * NS) + wave * (16 * NS);
+  const int64_t m_begin = static_cast<int64_t>(blockIdx.y) * cols_per_split;
+  const int64_t m_end = m_begin + cols_per_split < n2 ? m_begin + cols_per_split : n2;
+
+  f4 xb[NS][DCH];
+  float n1v[NS];
+#pragma unroll
+  for (int st = 0; st < NS; ++st) {
+    const int64_t nrow = row0 + st * 16 + r;
+    const bool ok = nrow < n1;
+#pragma unroll
+    for (int c = 0; c < DCH; ++c)
+      xb[st][c] = ok ? *reinterpret_cast<const f4*>(X1p + nrow * DP + 16 * c + 4 * g)
+                     : f4{0, 0, 0, 0};
+    n1v[st] = ok ? nrm1[nrow] * cnorm : 0.0f;
+  }
+  float acc[NS][WX];
+#pragma unroll
+  for (int st = 0; st < NS; ++st)
+#pragma unroll
+    for (int w = 0; w < WX; ++w) acc[st][w] = 0.0f;
+
+  // V tile element e = tid + q*256 is (m = e / WX, w = e % WX); its global
+  // offset from row m is (w / C) ldv + w % C, fixed per (tid, q): hoisted.
+  int vm[VE];
+  int64_t voff[VE];
+#pragma unroll
+  for (int q = 0; q < VE; ++q) {
+    const int e = tid + q * 256;
+    const int w = e % WX;
+    vm[q] = e < VT ? e / WX : TN;   // TN marks an unused slot
+    voff[q] = static_cast<int64_t>(w / C) * ldv + (w % C);
+  }
+
+  f4 px[XQT];
+  float pv[VE];
+  float pn = 0.0f;
+  auto fetch = [&](int64_t m0) {
+#pragma unroll
+    for (int q = 0; q < XQT; ++q) {
+      const int e = tid + q * 256;
+      const int row = e / (DP / 4), col = e % (DP / 4);
+      const int64_t m = m0 + row;
+      px[q] = m < m_end ? *reinterpret_cast<const f4*>(X2p + m * DP + col * 4) : f4{0, 0, 0, 0};
+    }
+    if (tid < TN) {
+      const int64_t m = m0 + tid;
+      pn = m < m_end ? nrm2[m] * cnorm : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < VE; ++q) {
+      const int64_t gm = m0 + vm[q];
+      pv[q] = (vm[q] < TN && gm < m_end) ? V[voff[q] + gm * C] : 0.0f;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < XQT; ++q) {
+      const int e = tid + q * 256;
+      const int row = e / (DP / 4), col = e % (DP / 4);
+      *reinterpret_cast<f4*>(&sX[buf][row * XS + col * 4]) = px[q];
+    }
+    if (tid < TN) sN[buf][tid] = pn;
+#pragma unroll
+    for (int q = 0; q < VE; ++q) sV[buf][tid + q * 256] = pv[q];
+  };
+
+  if (m_begin < m_end) {
+    fetch(m_begin);
+    stash(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t m0 = m_begin; m0 < m_end; m0 += TN) {
+    const bool more = m0 + TN < m_end;
+    if (more) fetch(m0 + TN);
+#pragma unroll 2
+    for (int mb = 0; mb < TN / 16; ++mb) {
+      f4 dd[NS];
+#pragma unroll
+      for (int st = 0; st < NS; ++st) dd[st] = f4{0, 0, 0, 0};
+#pragma unroll
+      for (int c = 0; c < DCH; ++c) {
+        const f4 a = *reinterpret_cast<const f4*>(&sX[buf][(mb * 16 + r) * XS + 16 * c + 4 * g]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int st = 0; st < NS; ++st)
+            dd[st] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], xb[st][c][k], dd[st], 0, 0, 0);
+      }
+      const f4 n2v = *reinterpret_cast<const f4*>(&sN[buf][mb * 16 + 4 * g]);
+      // V rows m = mb*16 + 4g .. +3 are 4*WX contiguous floats (16-byte aligned)
+      f4 vv[WX];
+      const f4* vsrc = reinterpret_cast<const f4*>(&sV[buf][(mb * 16 + 4 * g) * WX]);
+#pragma unroll
+      for (int q = 0; q < WX; ++q) vv[q] = vsrc[q];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+          const float kk = ktransform<KIND>(__builtin_fmaf(dd[st][v], cdot, n1v[st] + n2v[v]));
+#pragma unroll
+          for (int w = 0; w < WX; ++w) {
+            const int idx = v * WX + w;
+            acc[st][w] = __builtin_fmaf(kk, vv[idx / 4][idx % 4], acc[st][w]);
+          }
+        }
+      }
+    }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  // add the four lane-group partials (lanes r, r+16, r+32, r+48)
+#pragma unroll
+  for (int st = 0; st < NS; ++st)
+#pragma unroll
+    for (int w = 0; w < WX; ++w) {
+      float x = acc[st][w];
+      x += __shfl_xor(x, 16, 64);
+      x += __shfl_xor(x, 32, 64);
+      acc[st][w] = x;
+    }
+  if (g == 0) {
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+      const int64_t n = row0 + st * 16 + r;
+      if (n < n1) {
+        float* dst = P + (static_cast<int64_t>(blockIdx.y) * n1 + n) * WX;
+#pragma unroll
+        for (int w = 0; w < WX; ++w) dst[w] = acc[st][w];
+      }
+    }
+  }
+}
+
 // Centred, zero-padded copies of rows (DP floats each) and their squared norms.
 __global__ void k_prep_rows(const float* __restrict__ X, int64_t n, int d, int DP,
                             const float* __restrict__ centre, float* __restrict__ Xp,
@@ -230,15 +399,17 @@ __global__ void k_col_finish(const double* __restrict__ part, int nblk, int d, i
 
 struct Plan {
   int dch, wch, gx, gz, nsplit;
+  bool narrow;
   int64_t cols_per_split;
 };
 
 Plan plan_mfma(int64_t n1, int64_t n2, int64_t d, int64_t W) {
   Plan p{};
   p.dch = static_cast<int>(ceil_div(d, 16));
+  p.narrow = W <= WV && p.dch <= 2;
   p.wch = W <= 16 ? 1 : (W <= 32 ? 2 : 4);
-  p.gx = static_cast<int>(ceil_div(n1, 64));
-  p.gz = static_cast<int>(ceil_div(W, 16 * p.wch));
+  p.gx = static_cast<int>(ceil_div(n1, p.narrow ? 64 * NSTRIP : 64));
+  p.gz = p.narrow ? 1 : static_cast<int>(ceil_div(W, 16 * p.wch));
   const int64_t tiles = ceil_div(n2, TN);
   if (tiles == 0) {
     p.nsplit = 0;
@@ -260,7 +431,17 @@ int launch_kind_dch(const Plan& pl, const float* X1p, const float* n1p, const fl
                     int64_t ldv, float* P, float cnorm, float cdot, const int* skip,
                     hipStream_t s) {
   dim3 grid(pl.gx, pl.nsplit, pl.gz);
-  if (pl.wch == 1)
+  if (pl.narrow) {
+    if constexpr (DCH <= 2) {
+      switch (W) {
+#define IGP_NW(K) \
+  case K: kv_mfma_f32_narrow<KIND, DCH, K, NSTRIP><<<grid, 256, 0, s>>>(X1p, n1p, X2p, n2p, n1, n2, V, C, ldv, P, pl.cols_per_split, cnorm, cdot, skip); break;
+        IGP_NW(1) IGP_NW(2) IGP_NW(3) IGP_NW(4) IGP_NW(5) IGP_NW(6) IGP_NW(7) IGP_NW(8)
+#undef IGP_NW
+        default: break;
+      }
+    }
+  } else if (pl.wch == 1)
     kv_mfma_f32<KIND, DCH, 1><<<grid, 256, 0, s>>>(X1p, n1p, X2p, n2p, n1, n2, V, C, W, ldv, P,
                                                    pl.cols_per_split, cnorm, cdot, skip);
   else if (pl.wch == 2)

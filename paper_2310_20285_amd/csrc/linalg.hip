@@ -4,6 +4,8 @@
 //
 // Buffers S, T, Q are stored column by column: column b of an n-row buffer
 // starts at element b*ld (each column is one CN-ordered vector).
+#include <algorithm>
+
 #include "ops.hpp"
 
 namespace igp {
@@ -84,53 +86,48 @@ __global__ void k_add(const T* __restrict__ a, const T* __restrict__ b, T* __res
     o[i] = a[i] + b[i];
 }
 
-// y partials: block (rx, cy) covers rows [rx*RCH, (rx+1)*RCH) and columns
-// [cy*CG, cy*CG + CG); part[rx * ncols + b].
-constexpr int RCH = 2048;   // rows per block (8 per thread)
-constexpr int CG = 32;      // columns per block
+// y = Q^T z for a column-major Q: one wave per (column, chunk of GV_ROWS rows),
+// each lane accumulating GV_ROWS/64 consecutive-in-wave elements in FP64, a
+// single wave reduction per (column, chunk); chunk partials are summed in a
+// fixed order by k_finish_cols.
+constexpr int GV_ROWS = 4096;
 
 template <typename T>
 __global__ void __launch_bounds__(NT)
 k_gemv_t(const T* __restrict__ Q, int64_t ldq, int64_t n, int ncols, const T* __restrict__ z,
-         double* __restrict__ part) {
-  __shared__ double sred[NT / 64][CG];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RCH;
-  const int b0 = blockIdx.y * CG;
-  double zr[RCH / NT];
-#pragma unroll
-  for (int k = 0; k < RCH / NT; ++k) {
-    const int64_t i = r0 + tid + k * NT;
-    zr[k] = i < n ? static_cast<double>(z[i]) : 0.0;
+         double* __restrict__ part, int nchunks) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wid = blockIdx.x * static_cast<int64_t>(NT / 64) + (threadIdx.x >> 6);
+  if (wid >= static_cast<int64_t>(nchunks) * ncols) return;
+  const int b = static_cast<int>(wid % ncols);
+  const int64_t chunk = wid / ncols;
+  const int64_t r0 = chunk * GV_ROWS;
+  const T* q = Q + static_cast<int64_t>(b) * ldq;
+  double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll 4
+  for (int k = 0; k < GV_ROWS / 64; k += 2) {
+    const int64_t i0 = r0 + k * 64 + lane, i1 = i0 + 64;
+    if (i0 < n) acc0 += static_cast<double>(q[i0]) * static_cast<double>(z[i0]);
+    if (i1 < n) acc1 += static_cast<double>(q[i1]) * static_cast<double>(z[i1]);
   }
-  const int bend = b0 + CG < ncols ? b0 + CG : ncols;
-  for (int b = b0; b < bend; ++b) {
-    const T* q = Q + static_cast<int64_t>(b) * ldq;
-    double acc = 0.0;
-#pragma unroll
-    for (int k = 0; k < RCH / NT; ++k) {
-      const int64_t i = r0 + tid + k * NT;
-      if (i < n) acc += static_cast<double>(q[i]) * zr[k];
-    }
-    acc = wave_sum(acc);
-    if (lane == 0) sred[w][b - b0] = acc;
-  }
-  __syncthreads();
-  if (tid < bend - b0) {
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < NT / 64; ++k) s += sred[k][tid];
-    part[static_cast<int64_t>(blockIdx.x) * ncols + b0 + tid] = s;
-  }
+  const double s = wave_sum(acc0 + acc1);
+  if (lane == 0) part[chunk * ncols + b] = s;
 }
 
 __global__ void k_finish_cols(const double* __restrict__ part, int nrow_blocks, int ncols,
                               double* __restrict__ y) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= ncols) return;
-  double s = 0.0;
-  for (int r = 0; r < nrow_blocks; ++r) s += part[static_cast<int64_t>(r) * ncols + b];
-  y[b] = s;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int r = 0;
+  for (; r + 4 <= nrow_blocks; r += 4) {
+    s0 += part[static_cast<int64_t>(r) * ncols + b];
+    s1 += part[static_cast<int64_t>(r + 1) * ncols + b];
+    s2 += part[static_cast<int64_t>(r + 2) * ncols + b];
+    s3 += part[static_cast<int64_t>(r + 3) * ncols + b];
+  }
+  for (; r < nrow_blocks; ++r) s0 += part[static_cast<int64_t>(r) * ncols + b];
+  y[b] = (s0 + s1) + (s2 + s3);
 }
 
 // d = s - Q y ; eta partial = z^T d.  One row per thread; y staged in LDS.
@@ -263,9 +260,16 @@ __global__ void k_finish_gram(const double* __restrict__ part, int nchunks, int 
   const int64_t total = static_cast<int64_t>(ncols) * ncols;
   for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
        e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += part[c * total + e];
-    M[e] = s;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int c = 0;
+    for (; c + 4 <= nchunks; c += 4) {
+      s0 += part[c * total + e];
+      s1 += part[(c + 1) * total + e];
+      s2 += part[(c + 2) * total + e];
+      s3 += part[(c + 3) * total + e];
+    }
+    for (; c < nchunks; ++c) s0 += part[c * total + e];
+    M[e] = (s0 + s1) + (s2 + s3);
   }
 }
 
@@ -418,10 +422,11 @@ template <typename T>
 int gemv_t(const T* Q, int64_t ldq, int64_t n, int ncols, const T* z, double* part, double* y,
            hipStream_t s) {
   if (ncols == 0) return IGP_OK;
-  const int rb = static_cast<int>(ceil_div(n, RCH));
-  dim3 grid(rb, static_cast<unsigned>(ceil_div(ncols, CG)));
-  k_gemv_t<T><<<grid, NT, 0, s>>>(Q, ldq, n, ncols, z, part);
-  k_finish_cols<<<static_cast<unsigned>(ceil_div(ncols, 64)), 64, 0, s>>>(part, rb, ncols, y);
+  const int nchunks = static_cast<int>(ceil_div(n, GV_ROWS));
+  const int64_t waves = static_cast<int64_t>(nchunks) * ncols;
+  k_gemv_t<T><<<static_cast<unsigned>(ceil_div(waves, NT / 64)), NT, 0, s>>>(Q, ldq, n, ncols, z,
+                                                                             part, nchunks);
+  k_finish_cols<<<static_cast<unsigned>(ceil_div(ncols, 64)), 64, 0, s>>>(part, nchunks, ncols, y);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
@@ -474,7 +479,7 @@ int gram(const T* A, const T* B, int64_t ld, int64_t n, int ncols, double* part,
          size_t part_cap, double* M, hipStream_t s) {
   if (ncols == 0) return IGP_OK;
   const int tiles = static_cast<int>(ceil_div(ncols, GT));
-  int64_t nchunks = ceil_div(2048, static_cast<int64_t>(tiles) * tiles);
+  int64_t nchunks = std::min<int64_t>(64, ceil_div(2048, static_cast<int64_t>(tiles) * tiles));
   const size_t per = static_cast<size_t>(ncols) * ncols;
   if (nchunks * per > part_cap) nchunks = static_cast<int64_t>(part_cap / per);
   if (nchunks < 1) {
