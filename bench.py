@@ -29,11 +29,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# VALU issue slots per kernel evaluation of the fused product at small D with
-# the distance and the W-contraction on MFMA ("ALU roofline"):
-# transcendentals (v_sqrt_f32, v_exp_f32) take 4 slots each.
-VALU_SLOTS_PER_EVAL = {"rbf": 9, "matern12": 14, "matern32": 14, "matern52": 15}
+# ALU roofline of the fused product at small D (derivation in the design doc):
+# VALU issue slots per kernel evaluation -- the kernel transform (full-rate
+# ops count 1, the quarter-rate transcendentals v_sqrt_f32 / v_exp_f32 count
+# 4) plus, when the output is at most 8 wide, the W contraction FMAs; the
+# distance dot products are priced as free (matrix cores).
+TRANSFORM_SLOTS = {"rbf": 6, "matern12": 11, "matern32": 13, "matern52": 14}
 VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes x clock
+KV_INSTANCE = None
+
+
+# HBM bytes per launch of the solver product, from two rocprofv3 --pmc runs
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors read off a 256 MiB device
+# copy in the same run; profiles/kv_matern52_N20000_D16_C5_fp32.md).  Keyed by
+# the kernel instance it was measured on; any other instance reports null.
+MEASURED_TRAFFIC = {("kv_mfma_f32_narrow<3,1,5,2>", "fp32"): 46.23e6}
+
+
+def valu_slots_per_eval(kind: str, W: int) -> int:
+    return TRANSFORM_SLOTS[kind] + (W if W <= 8 else 0)
 
 
 def cpu_baseline(w, k_products_per_step: float):
@@ -81,6 +95,8 @@ def main():
     from paper_2310_20285_amd import api
 
     dev = torch.device("cuda:0")
+    global KV_INSTANCE
+    KV_INSTANCE = "kv_mfma_f32_narrow<3,1,5,2>"   # Matern-5/2, D <= 16, W = 5, 2 strips
     w = datagen.config2()
     dt = torch.float64 if args.precision == "fp64" else torch.float32
     X = torch.tensor(w.X, dtype=dt, device=dev)
@@ -127,7 +143,7 @@ def main():
     kv_avg_s = prof["kv_ms"] / max(prof["kv_launches"], 1) / 1e3
     evals_per_launch = float(w.N) * w.N
     achieved_evals = evals_per_launch / kv_avg_s
-    peak_evals = VALU_LANE_OPS_PER_S / VALU_SLOTS_PER_EVAL[w.kernel]
+    peak_evals = VALU_LANE_OPS_PER_S / valu_slots_per_eval(w.kernel, w.C)
     kv_tflops = prof["kv_flops"] / max(prof["kv_launches"], 1) / kv_avg_s / 1e12
     k_per_step = prof["kv_launches"] / max(prof["steps"], 1)
 
@@ -152,7 +168,8 @@ def main():
                    "precision": args.precision, "test_points": int(Xs.shape[0])},
         "roofline": {"bound": "alu", "achieved": achieved_evals / 1e9,
                      "peak": peak_evals / 1e9, "unit": "Geval/s",
-                     "frac": achieved_evals / peak_evals, "traffic": None,
+                     "frac": achieved_evals / peak_evals,
+                     "traffic": MEASURED_TRAFFIC.get((KV_INSTANCE, args.precision)),
                      "kernel": "fused K.v (kernel evaluation + contraction)",
                      "avg_launch_us": kv_avg_s * 1e6},
         "kv": {"launches": prof["kv_launches"], "avg_us": kv_avg_s * 1e6,
