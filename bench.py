@@ -81,7 +81,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--residual", default="recurrence", choices=["explicit", "recurrence"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
+    ap.add_argument("--precision", default=None, choices=["fp32", "fp64", "bf16"])
+    ap.add_argument("--workload", default="gpc16", choices=["gpc16", "image"],
+                    help="gpc16: N=20000 D=16 C=5 (default); image: N=60000 D=784 C=10 BF16")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only; multi-GPU runs are not part of this build",
@@ -96,6 +98,9 @@ def main():
 
     dev = torch.device("cuda:0")
     global KV_INSTANCE
+    if args.workload == "image":
+        return bench_image(args)
+    args.precision = args.precision or "fp32"
     KV_INSTANCE = "kv_mfma_f32_narrow<3,1,5,2>"   # Matern-5/2, D <= 16, W = 5, 2 strips
     w = datagen.config2()
     dt = torch.float64 if args.precision == "fp64" else torch.float32
@@ -184,6 +189,84 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, k_per_step)
     print(json.dumps(out))
+
+
+BF16_MFMA_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak
+
+
+def bench_image(args):
+    """Image-shaped workload: N=60000, D=784, C=10, RBF, BF16 distance GEMM.
+    IterNCGP-CG with j <= 5 per Newton step, no compression, 3 Newton steps
+    (the paper's MNIST schedule), prediction at 1000 test points per step."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_2310_20285_amd import api
+
+    prec = args.precision or "bf16"
+    w = datagen.config3(Ns=1000)
+    dev = torch.device("cuda:0")
+    X = torch.tensor(w.X, dtype=torch.float32, device=dev)
+    y = torch.tensor(w.y, dtype=torch.int32, device=dev)
+    Xs = torch.tensor(w.Xs, dtype=torch.float32, device=dev)
+    steps = min(args.steps, 3)
+
+    def make_model():
+        return api.IterNCGP(X, y, w.C, w.kernel, w.lengthscale, w.outputscale, policy="cg",
+                            j_max=5, rank_limit=-1, recycle=True, precision=prec,
+                            residual_mode=args.residual, max_buffer=5 * 3 + 1)
+
+    mw = make_model()
+    mw.newton_step()
+    torch.cuda.synchronize()
+    del mw
+    m = make_model()
+    m.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(steps):
+        infos.append(m.newton_step())
+        m.predict(Xs)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = m.profile()
+    kv_avg_s = prof["kv_ms"] / max(prof["kv_launches"], 1) / 1e3
+    flops = 2.0 * w.N * w.N * (w.D + w.C)
+    tflops = flops / kv_avg_s / 1e12
+    # error of one product against the FP64 oracle on sampled rows
+    from oracle import kernels as ok
+    rng = np.random.default_rng(0)
+    v = rng.standard_normal(w.N * w.C)
+    out = api.glm_kernel_matmul(X, X, torch.tensor(v, dtype=torch.float32, device=dev), w.C,
+                                w.kernel, w.lengthscale, w.outputscale, prec).double().cpu().numpy()
+    rows = rng.choice(w.N, size=64, replace=False)
+    ref = ok.kernel_matvec(w.X[rows], w.X, v.reshape(w.N, w.C), w.kernel, w.lengthscale,
+                           w.outputscale)
+    got = out.reshape(w.N, w.C)[rows]
+    kv_err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    res = {
+        "metric": "IterNCGP Newton steps/s",
+        "value": steps / (t1 - t0),
+        "unit": "Newton steps/s",
+        "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": (t1 - t0) / steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": prec, "data": "synthetic",
+        "config": {"workload": "image-shaped N=60000 D=784 C=10 rbf (median lengthscale); "
+                               "IterNCGP-CG j<=5 R=inf, 3 Newton steps, predict 1000 test points",
+                   "lengthscale": w.lengthscale, "zero_frac": w.meta.get("zero_frac"),
+                   "precision": prec, "residual": args.residual},
+        "roofline": {"bound": "mfma", "achieved": tflops, "peak": BF16_MFMA_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tflops / BF16_MFMA_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "fused K.v, BF16 distance GEMM (2 N^2 (D + C) flops per product)",
+                     "avg_launch_us": kv_avg_s * 1e6},
+        "kv_error_vs_fp64": {"rel_l2_64_rows": kv_err},
+        "newton": [{k: (round(v_, 6) if isinstance(v_, float) else v_) for k, v_ in i.items()
+                    if k in ("iters", "buffer_cols", "rel_change", "psi")} for i in infos],
+    }
+    print(json.dumps(res))
 
 
 if __name__ == "__main__":

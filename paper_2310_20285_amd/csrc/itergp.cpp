@@ -26,8 +26,11 @@ struct Layout {
   void* kvws;
   size_t kvws_bytes;
   int* flags;
-  // matrix-core paths: common centre, centred zero-padded rows, squared norms
-  float *centre, *Xp, *nrm;
+  // matrix-core paths: common centre, centred zero-padded rows (float or
+  // BF16), squared norms of those rows
+  float* centre;
+  void* Xp;
+  float* nrm;
   double* meanpart;
 };
 
@@ -79,7 +82,8 @@ Layout<T> carve(Carver& cv, int64_t N, int64_t D, int64_t C, const igp_solver_co
   L.flags = cv.take<int>(64);
   if (prepared) {
     L.centre = cv.take<float>(D);
-    L.Xp = cv.take<float>(N * padded_dim(D));
+    L.Xp = cfg.precision == IGP_BF16 ? static_cast<void*>(cv.take<uint16_t>(N * bf16_padded_dim(D)))
+                                     : static_cast<void*>(cv.take<float>(N * padded_dim(D)));
     L.nrm = cv.take<float>(N);
     L.meanpart = cv.take<double>(MEAN_BLOCKS * D);
   }
@@ -160,7 +164,7 @@ struct Model final : igp_model {
   bool prepared = false;
 
   KVProblem kv_problem(const T* X1, int64_t n1, const T* V, int64_t nb, int64_t ldv, T* Out,
-                       int64_t ldo, const float* X1p = nullptr,
+                       int64_t ldo, const void* X1p = nullptr,
                        const float* norm1 = nullptr) const {
     KVProblem p{};
     if (prepared) {
@@ -388,10 +392,7 @@ struct Model final : igp_model {
     cv.take<T>(Ns * C * B);
     cv.take<char>(kvws_for(Ns, 1));
     cv.take<char>(kvws_for(Ns, B));
-    if (prepared) {
-      cv.take<float>(Ns * padded_dim(D));
-      cv.take<float>(Ns);
-    }
+    if (prepared) cv.take<char>(prepared_rows_bytes(cfg.precision, Ns, D));
     return cv.used + 256;
   }
 
@@ -414,11 +415,15 @@ struct Model final : igp_model {
     void* ws1 = cv.take<char>(w1);
     const size_t w2 = kvws_for(Ns, B);
     void* ws2 = cv.take<char>(w2);
-    float *xsp = nullptr, *nsp = nullptr;
+    void* xsp = nullptr;
+    float* nsp = nullptr;
     if (prepared) {
-      xsp = cv.take<float>(Ns * padded_dim(D));
-      nsp = cv.take<float>(Ns);
-      IGP_TRY(prep_rows_f32(reinterpret_cast<const float*>(Xs), Ns, D, L.centre, xsp, nsp, s));
+      const size_t rb = prepared_rows_bytes(cfg.precision, Ns, D);
+      char* base = cv.take<char>(rb);
+      xsp = base;
+      nsp = reinterpret_cast<float*>(base + rb - align_up(Ns * sizeof(float)));
+      IGP_TRY(prep_rows_any(cfg.precision, reinterpret_cast<const float*>(Xs), Ns, D, L.centre,
+                            xsp, nsp, s));
     }
     IGP_TRY(kv_launch(kv_problem(Xs, Ns, L.v, 1, n, mean, Ns * C, xsp, nsp), ws1, w1, s));
     if (var_) {
@@ -525,7 +530,7 @@ int init_t(igp_model** out, const igp_kernel_params* kp, const igp_solver_config
   if (m->prepared) {
     const float* Xf = reinterpret_cast<const float*>(m->L.X);
     IGP_TRY(column_mean_f32(Xf, N, D, m->L.centre, m->L.meanpart, MEAN_BLOCKS * D, stream));
-    IGP_TRY(prep_rows_f32(Xf, N, D, m->L.centre, m->L.Xp, m->L.nrm, stream));
+    IGP_TRY(prep_rows_any(cfg->precision, Xf, N, D, m->L.centre, m->L.Xp, m->L.nrm, stream));
   }
   IGP_CHECK_HIP(hipMemsetAsync(m->L.f, 0, m->n * sizeof(T), stream));
   IGP_CHECK_HIP(hipMemsetAsync(m->L.v, 0, m->n * sizeof(T), stream));
@@ -548,7 +553,7 @@ int init_t(igp_model** out, const igp_kernel_params* kp, const igp_solver_config
 size_t state_bytes(int64_t N, int64_t D, int64_t C, const igp_solver_config* cfg) {
   if (!cfg || N < 1 || D < 1 || C < 1 || cfg->max_buffer < 1) return 0;
   if (cfg->precision == IGP_FP64) return state_bytes_t<double>(N, D, C, *cfg, IGP_RBF);
-  // the query does not know the kernel: size for the larger (matrix-core) layout
+  // the query does not know the kernel: size for the larger of the two layouts
   return std::max(state_bytes_t<float>(N, D, C, *cfg, IGP_RBF),
                   state_bytes_t<float>(N, D, C, *cfg, IGP_MATERN12));
 }
@@ -562,10 +567,6 @@ int model_init(igp_model** out, const igp_kernel_params* kp, const igp_solver_co
   IGP_REQUIRE(X && y && arena, "NULL X, y or arena");
   if (cfg->precision == IGP_FP64)
     return init_t<double>(out, kp, cfg, X, y, N, D, C, arena, arena_bytes, stream);
-  if (cfg->precision == IGP_BF16) {
-    set_error("IGP_BF16 models are not available in this build");
-    return IGP_EUNSUPPORTED;
-  }
   return init_t<float>(out, kp, cfg, X, y, N, D, C, arena, arena_bytes, stream);
 }
 

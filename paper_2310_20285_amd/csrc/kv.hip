@@ -201,21 +201,32 @@ int launch_valu(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t s) {
 }  // namespace
 
 bool kv_uses_prepared(int precision, int kind, int64_t d) {
-  return precision == IGP_FP32 && mfma_f32_supported(kind, d);
+  return precision == IGP_BF16 || (precision == IGP_FP32 && mfma_f32_supported(kind, d));
+}
+
+size_t prepared_rows_bytes(int precision, int64_t n, int64_t d) {
+  Carver cv(nullptr, 0);
+  if (precision == IGP_BF16) cv.take<uint16_t>(n * bf16_padded_dim(d));
+  else cv.take<float>(n * padded_dim(d));
+  cv.take<float>(n);
+  return cv.used;
+}
+
+int prep_rows_any(int precision, const float* X, int64_t n, int64_t d, const float* centre,
+                  void* rows, float* norms, hipStream_t s) {
+  if (precision == IGP_BF16) return prep_rows_bf16(X, n, d, centre, rows, norms, s);
+  return prep_rows_f32(X, n, d, centre, static_cast<float*>(rows), norms, s);
 }
 
 namespace {
 constexpr int64_t MEAN_PART_BLOCKS = 1024;
 
-size_t prep_bytes(int64_t n1, int64_t n2, int64_t d) {
+size_t prep_bytes(int precision, int64_t n1, int64_t n2, int64_t d) {
   Carver cv(nullptr, 0);
-  const int64_t dp = padded_dim(d);
   cv.take<float>(d);
   cv.take<double>(MEAN_PART_BLOCKS * d);
-  cv.take<float>(n1 * dp);
-  cv.take<float>(n1);
-  cv.take<float>(n2 * dp);
-  cv.take<float>(n2);
+  cv.take<char>(prepared_rows_bytes(precision, n1, d));
+  cv.take<char>(prepared_rows_bytes(precision, n2, d));
   return cv.used;
 }
 }  // namespace
@@ -226,47 +237,59 @@ size_t kv_ws_bytes_prepared(int64_t n1, int64_t n2, int64_t d, int64_t C, int64_
   SplitPlan sp = plan_valu(n1, n2, W);
   const size_t elt = precision == IGP_FP64 ? sizeof(double) : sizeof(float);
   size_t b = static_cast<size_t>(sp.nsplit) * n1 * W * elt;
-  if (precision != IGP_FP64 && d <= 128) b = std::max(b, mfma_f32_partial_bytes(n1, n2, d, W));
+  if (precision == IGP_FP32 && d <= 128) b = std::max(b, mfma_f32_partial_bytes(n1, n2, d, W));
+  if (precision == IGP_BF16) b = bf16_partial_bytes(n1, n2, W);
   return align_up(b + 256);
 }
 
 size_t kv_ws_bytes(int64_t n1, int64_t n2, int64_t d, int64_t C, int64_t nb, int precision) {
   size_t b = kv_ws_bytes_prepared(n1, n2, d, C, nb, precision);
-  if (precision != IGP_FP64 && d <= 128) b += align_up(prep_bytes(n1, n2, d) + 256);
+  if (precision == IGP_BF16 || (precision == IGP_FP32 && d <= 128))
+    b += align_up(prep_bytes(precision, n1, n2, d) + 256);
   return b;
 }
 
 namespace {
 int launch_mfma_path(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t s) {
   const int64_t W = p.C * p.nb;
+  const bool bf = p.precision == IGP_BF16;
   Carver cv(ws, ws_bytes);
-  const size_t pbytes = mfma_f32_partial_bytes(p.n1, p.n2, p.d, W);
+  const size_t pbytes = bf ? bf16_partial_bytes(p.n1, p.n2, W)
+                           : mfma_f32_partial_bytes(p.n1, p.n2, p.d, W);
   float* P = cv.take<float>(pbytes / sizeof(float) + 1);
-  const float *X1p = p.X1p, *X2p = p.X2p, *n1p = p.norm1, *n2p = p.norm2;
+  const void *X1p = p.X1p, *X2p = p.X2p;
+  const float *n1p = p.norm1, *n2p = p.norm2;
   if (!X1p || !X2p || !n1p || !n2p) {
-    const int64_t dp = padded_dim(p.d);
     float* centre = cv.take<float>(p.d);
     double* part = cv.take<double>(MEAN_PART_BLOCKS * p.d);
-    float* x1 = cv.take<float>(p.n1 * dp);
-    float* m1 = cv.take<float>(p.n1);
-    float* x2 = cv.take<float>(p.n2 * dp);
-    float* m2 = cv.take<float>(p.n2);
+    const size_t r1 = prepared_rows_bytes(p.precision, p.n1, p.d);
+    const size_t r2 = prepared_rows_bytes(p.precision, p.n2, p.d);
+    char* b1 = cv.take<char>(r1);
+    char* b2 = cv.take<char>(r2);
     if (!cv.fits() || !ws) {
       set_error("kernel-product workspace too small: need %zu bytes, have %zu", cv.used, ws_bytes);
       return IGP_ENOMEM;
     }
+    const size_t rows1 = r1 - align_up(p.n1 * sizeof(float));
+    const size_t rows2 = r2 - align_up(p.n2 * sizeof(float));
+    float* m1 = reinterpret_cast<float*>(b1 + rows1);
+    float* m2 = reinterpret_cast<float*>(b2 + rows2);
     IGP_TRY(column_mean_f32(static_cast<const float*>(p.X2), p.n2, p.d, centre, part,
                             MEAN_PART_BLOCKS * p.d, s));
-    IGP_TRY(prep_rows_f32(static_cast<const float*>(p.X1), p.n1, p.d, centre, x1, m1, s));
-    IGP_TRY(prep_rows_f32(static_cast<const float*>(p.X2), p.n2, p.d, centre, x2, m2, s));
-    X1p = x1; n1p = m1; X2p = x2; n2p = m2;
+    IGP_TRY(prep_rows_any(p.precision, static_cast<const float*>(p.X1), p.n1, p.d, centre, b1, m1, s));
+    IGP_TRY(prep_rows_any(p.precision, static_cast<const float*>(p.X2), p.n2, p.d, centre, b2, m2, s));
+    X1p = b1; n1p = m1; X2p = b2; n2p = m2;
   }
   if (!cv.fits() || !ws) {
     set_error("kernel-product workspace too small: need %zu bytes, have %zu", cv.used, ws_bytes);
     return IGP_ENOMEM;
   }
   int nsplit = 0;
-  IGP_TRY(kv_mfma_f32_launch(p, X1p, n1p, X2p, n2p, P, pbytes, s, &nsplit));
+  if (bf)
+    IGP_TRY(kv_bf16_launch(p, X1p, n1p, X2p, n2p, P, pbytes, s, &nsplit));
+  else
+    IGP_TRY(kv_mfma_f32_launch(p, static_cast<const float*>(X1p), n1p,
+                               static_cast<const float*>(X2p), n2p, P, pbytes, s, &nsplit));
   const int64_t total = p.n1 * W;
   int blocks = static_cast<int>(std::min<int64_t>(std::max<int64_t>(ceil_div(total, 256), 1), 4096));
   kv_reduce<float><<<blocks, 256, 0, s>>>(P, nsplit, p.n1, static_cast<int>(W),
@@ -281,12 +304,8 @@ int launch_mfma_path(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t 
 int kv_launch(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t s) {
   if (p.n1 == 0 || p.nb == 0) return IGP_OK;
   if (p.precision == IGP_FP64) return launch_valu<double>(p, ws, ws_bytes, s);
-  if (p.precision == IGP_FP32) {
-    if (kv_uses_prepared(p.precision, p.kp.kind, p.d)) return launch_mfma_path(p, ws, ws_bytes, s);
-    return launch_valu<float>(p, ws, ws_bytes, s);
-  }
-  set_error("IGP_BF16 kernel product is not available in this build");
-  return IGP_EUNSUPPORTED;
+  if (kv_uses_prepared(p.precision, p.kp.kind, p.d)) return launch_mfma_path(p, ws, ws_bytes, s);
+  return launch_valu<float>(p, ws, ws_bytes, s);
 }
 
 }  // namespace igp

@@ -1,0 +1,331 @@
+// Fused kernel-matrix product with the distance GEMM on the BF16 matrix cores
+// of gfx950 (v_mfma_f32_16x16x32_bf16, FP32 accumulation), for wide inputs
+// (hundreds of features).
+//
+// Inputs are rows centred on a common point and rounded to BF16; their squared
+// norms are taken from the rounded values in FP32, so r^2 = |x1|^2 + |x2|^2 -
+// 2 x1.x2 is the distance of the rounded points up to FP32 accumulation and the
+// kernel matrix stays the (PSD) kernel matrix of those points.
+//
+// Workgroup tile: 128 rows of X1 (n) x 128 rows of X2 (m); four waves in a
+// 2 x 2 arrangement, each holding a 64 x 64 block of D^T = X2 X1^T in sixteen
+// 16 x 16 accumulators.  Feature chunks of 32 stream through LDS (rows padded
+// to 80 bytes: conflict-free 128-bit reads), double-buffered through
+// registers.  After the feature loop the kernel function is applied to the
+// accumulators and the contraction with V runs on the same matrix cores: the
+// accumulator of block (m, n) already holds K[n][m] in the A-operand lane
+// layout (the transposed-tile arrangement), and a pair of m-blocks gives the
+// 8 k-values of one 16x16x32 instruction.  K and V are split into BF16 high and
+// low parts and the contraction takes hi*hi + hi*lo + lo*hi, which keeps about
+// 16 significant bits of each factor.
+#include <algorithm>
+
+#include "ops.hpp"
+
+namespace igp {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr float LOG2E_B = 1.4426950408889634f;
+constexpr int BT = 128;      // rows of X1 and of X2 per workgroup tile
+constexpr int KC = 32;       // features per chunk
+constexpr int RS = 40;       // LDS row stride in bf16 (80 bytes)
+constexpr int VT = 16;       // output columns per workgroup (W <= 16 per launch column group)
+constexpr int VS = BT + 8;   // LDS row stride of the transposed V tile (bf16)
+
+template <int KIND>
+__device__ inline float kt_bf(float t) {
+  if constexpr (KIND == IGP_RBF) {
+    return __builtin_amdgcn_exp2f(-t);
+  } else {
+    const float a = __builtin_amdgcn_sqrtf(fmaxf(t, 0.0f));
+    const float e = __builtin_amdgcn_exp2f(-a);
+    if constexpr (KIND == IGP_MATERN12) {
+      return e;
+    } else if constexpr (KIND == IGP_MATERN32) {
+      return __builtin_fmaf(a, 1.0f / LOG2E_B, 1.0f) * e;
+    } else {
+      const float p = __builtin_fmaf(t, 1.0f / (3.0f * LOG2E_B * LOG2E_B), 1.0f);
+      return __builtin_fmaf(a, 1.0f / LOG2E_B, p) * e;
+    }
+  }
+}
+
+__device__ inline __bf16 to_bf(float x) { return static_cast<__bf16>(x); }
+__device__ inline float from_bf(__bf16 x) { return static_cast<float>(x); }
+
+template <int KIND>
+__global__ void __launch_bounds__(256)
+kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
+               const __bf16* __restrict__ X2b, const float* __restrict__ nrm2, int64_t n1,
+               int64_t n2, int DPB, const float* __restrict__ V, int C, int W, int64_t ldv,
+               float* __restrict__ P, int64_t cols_per_split, float cnorm, float cdot,
+               const int* skip) {
+  if (skip && *skip) return;
+  __shared__ __align__(16) __bf16 sA[2][BT * RS];   // X2 chunk (m rows)
+  __shared__ __align__(16) __bf16 sB[2][BT * RS];   // X1 chunk (n rows)
+  __shared__ __align__(16) __bf16 sVh[VT * VS];     // V^T tile, high part
+  __shared__ __align__(16) __bf16 sVl[VT * VS];     // V^T tile, low part
+  __shared__ float sN2[BT];
+  __shared__ f4 sRed[2][64 * 4];                    // cross-wave reduction of the output
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  const int wn = wave & 1, wm = wave >> 1;
+  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * BT;
+  const int w0 = blockIdx.z * VT;
+  const int64_t m_begin = static_cast<int64_t>(blockIdx.y) * cols_per_split;
+  const int64_t m_end = m_begin + cols_per_split < n2 ? m_begin + cols_per_split : n2;
+  const int nks = DPB / KC;
+
+  // this lane's X1 norms: n = n0 + wn*64 + nb*16 + r
+  float n1v[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    const int64_t n = n0 + wn * 64 + nb * 16 + r;
+    n1v[nb] = n < n1 ? nrm1[n] * cnorm : 0.0f;
+  }
+  f4 out[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) out[nb] = f4{0, 0, 0, 0};
+
+  // staging: chunk element e = tid + q*256 (q < 2) is (row = e / 4, 16-byte piece e % 4)
+  u4 pa[2], pb[2];
+  auto fetch = [&](int64_t m0, int k0) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int e = tid + q * 256;
+      const int row = e >> 2, piece = e & 3;
+      const int64_t m = m0 + row, n = n0 + row;
+      pa[q] = m < m_end ? *reinterpret_cast<const u4*>(X2b + m * DPB + k0 + piece * 8)
+                        : u4{0, 0, 0, 0};
+      pb[q] = n < n1 ? *reinterpret_cast<const u4*>(X1b + n * DPB + k0 + piece * 8)
+                     : u4{0, 0, 0, 0};
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int e = tid + q * 256;
+      const int row = e >> 2, piece = e & 3;
+      *reinterpret_cast<u4*>(&sA[buf][row * RS + piece * 8]) = pa[q];
+      *reinterpret_cast<u4*>(&sB[buf][row * RS + piece * 8]) = pb[q];
+    }
+  };
+
+  for (int64_t m0 = m_begin; m0 < m_end; m0 += BT) {
+    // V^T tile (hi / lo) and X2 norms of this m tile
+    for (int e = tid; e < BT * VT; e += 256) {
+      const int m = e / VT, wl = e % VT;
+      const int64_t gm = m0 + m;
+      const int w = w0 + wl;
+      float v = 0.0f;
+      if (gm < m_end && w < W) v = V[static_cast<int64_t>(w / C) * ldv + gm * C + (w % C)];
+      const __bf16 hi = to_bf(v);
+      sVh[wl * VS + m] = hi;
+      sVl[wl * VS + m] = to_bf(v - from_bf(hi));
+    }
+    for (int e = tid; e < BT; e += 256) {
+      const int64_t gm = m0 + e;
+      sN2[e] = gm < m_end ? nrm2[gm] * cnorm : 0.0f;
+    }
+    f4 acc[4][4];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = f4{0, 0, 0, 0};
+
+    fetch(m0, 0);
+    stash(0);
+    __syncthreads();
+    int buf = 0;
+    for (int ks = 0; ks < nks; ++ks) {
+      const bool more = ks + 1 < nks;
+      if (more) fetch(m0, (ks + 1) * KC);
+      bf8 a[4], b[4];
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+        a[mb] = *reinterpret_cast<const bf8*>(&sA[buf][(wm * 64 + mb * 16 + r) * RS + g * 8]);
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+        b[nb] = *reinterpret_cast<const bf8*>(&sB[buf][(wn * 64 + nb * 16 + r) * RS + g * 8]);
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], b[nb], acc[mb][nb], 0, 0, 0);
+      if (more) stash(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+    // kernel transform + contraction: acc[mb][nb][v] = D^T[m = wm*64 + mb*16 + 4g + v][n = .. + r]
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int mba = 2 * p, mbb = 2 * p + 1;
+      const int ma = wm * 64 + mba * 16 + 4 * g, mbm = wm * 64 + mbb * 16 + 4 * g;
+      const f4 na = *reinterpret_cast<const f4*>(&sN2[ma]);
+      const f4 nbv = *reinterpret_cast<const f4*>(&sN2[mbm]);
+      bf8 vh, vl;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        vh[t] = sVh[r * VS + ma + t];
+        vl[t] = sVl[r * VS + ma + t];
+        vh[4 + t] = sVh[r * VS + mbm + t];
+        vl[4 + t] = sVl[r * VS + mbm + t];
+      }
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        bf8 kh, kl;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const float ka = kt_bf<KIND>(__builtin_fmaf(acc[mba][nb][t], cdot, n1v[nb] + na[t]));
+          const float kb = kt_bf<KIND>(__builtin_fmaf(acc[mbb][nb][t], cdot, n1v[nb] + nbv[t]));
+          const __bf16 ha = to_bf(ka), hb = to_bf(kb);
+          kh[t] = ha;
+          kh[4 + t] = hb;
+          kl[t] = to_bf(ka - from_bf(ha));
+          kl[4 + t] = to_bf(kb - from_bf(hb));
+        }
+        out[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vh, out[nb], 0, 0, 0);
+        out[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vl, out[nb], 0, 0, 0);
+        out[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kl, vh, out[nb], 0, 0, 0);
+      }
+    }
+    __syncthreads();   // sVh / sVl / sN2 are rewritten by the next m tile
+  }
+  // out[nb][j] = Out[n = n0 + wn*64 + nb*16 + 4g + j][w = w0 + r]; add the two wm halves
+  if (wm == 1) {
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) sRed[wn][nb * 64 + lane] = out[nb];
+  }
+  __syncthreads();
+  if (wm == 0) {
+    const int w = w0 + r;
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      const f4 o = out[nb] + sRed[wn][nb * 64 + lane];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t n = n0 + wn * 64 + nb * 16 + 4 * g + j;
+        if (n < n1 && w < W) P[(static_cast<int64_t>(blockIdx.y) * n1 + n) * W + w] = o[j];
+      }
+    }
+  }
+}
+
+// Centred rows rounded to BF16 (zero-padded to DPB features) and the squared
+// norms of the rounded rows.
+__global__ void k_prep_rows_bf16(const float* __restrict__ X, int64_t n, int d, int DPB,
+                                 const float* __restrict__ centre, __bf16* __restrict__ Xb,
+                                 float* __restrict__ norms) {
+  const int64_t i = blockIdx.x;
+  if (i >= n) return;
+  __shared__ float red[4];
+  float s = 0.0f;
+  for (int k = threadIdx.x; k < DPB; k += blockDim.x) {
+    float v = 0.0f;
+    if (k < d) v = X[i * d + k] - (centre ? centre[k] : 0.0f);
+    const __bf16 b = static_cast<__bf16>(v);
+    Xb[i * DPB + k] = b;
+    const float fb = static_cast<float>(b);
+    s += fb * fb;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) norms[i] = s;
+}
+
+struct PlanB {
+  int gx, gz, nsplit;
+  int64_t cols_per_split;
+};
+
+PlanB plan_bf16(int64_t n1, int64_t n2, int64_t W) {
+  PlanB p{};
+  p.gx = static_cast<int>(ceil_div(n1, BT));
+  p.gz = static_cast<int>(ceil_div(W, VT));
+  const int64_t tiles = ceil_div(n2, BT);
+  if (tiles == 0) {
+    p.nsplit = 0;
+    p.cols_per_split = BT;
+    return p;
+  }
+  // enough workgroups for ~4 per CU, without splitting below 8 tiles
+  int64_t want = ceil_div(1024, static_cast<int64_t>(p.gx) * p.gz);
+  want = std::max<int64_t>(1, std::min<int64_t>(want, ceil_div(tiles, 8)));
+  p.cols_per_split = ceil_div(tiles, want) * BT;
+  p.nsplit = static_cast<int>(ceil_div(n2, p.cols_per_split));
+  return p;
+}
+
+}  // namespace
+
+int64_t bf16_padded_dim(int64_t d) { return ceil_div(d, KC) * KC; }
+
+size_t bf16_partial_bytes(int64_t n1, int64_t n2, int64_t W) {
+  PlanB pl = plan_bf16(n1, n2, W);
+  return static_cast<size_t>(pl.nsplit) * n1 * W * sizeof(float);
+}
+
+int prep_rows_bf16(const float* X, int64_t n, int64_t d, const float* centre, void* Xb,
+                   float* norms, hipStream_t s) {
+  if (n == 0) return IGP_OK;
+  k_prep_rows_bf16<<<static_cast<unsigned>(n), 256, 0, s>>>(
+      X, n, static_cast<int>(d), static_cast<int>(bf16_padded_dim(d)), centre,
+      static_cast<__bf16*>(Xb), norms);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+int kv_bf16_launch(const KVProblem& p, const void* X1b, const float* n1p, const void* X2b,
+                   const float* n2p, float* P, size_t P_bytes, hipStream_t s, int* nsplit_out) {
+  const int64_t W = p.C * p.nb;
+  PlanB pl = plan_bf16(p.n1, p.n2, W);
+  *nsplit_out = pl.nsplit;
+  if (static_cast<size_t>(pl.nsplit) * p.n1 * W * sizeof(float) > P_bytes) {
+    set_error("kernel-product workspace too small for the split partials");
+    return IGP_ENOMEM;
+  }
+  if (pl.nsplit == 0) return IGP_OK;
+  const double inv_l2 = 1.0 / (p.kp.lengthscale * p.kp.lengthscale);
+  float kap;
+  switch (p.kp.kind) {
+    case IGP_RBF: kap = 0.5f * LOG2E_B; break;
+    case IGP_MATERN12: kap = LOG2E_B * LOG2E_B; break;
+    case IGP_MATERN32: kap = 3.0f * LOG2E_B * LOG2E_B; break;
+    default: kap = 5.0f * LOG2E_B * LOG2E_B; break;
+  }
+  const float cnorm = static_cast<float>(kap * inv_l2);
+  const float cdot = static_cast<float>(-2.0 * kap * inv_l2);
+  dim3 grid(pl.gx, pl.nsplit, pl.gz);
+  const int DPB = static_cast<int>(bf16_padded_dim(p.d));
+  const __bf16* A1 = static_cast<const __bf16*>(X1b);
+  const __bf16* A2 = static_cast<const __bf16*>(X2b);
+  const float* V = static_cast<const float*>(p.V);
+  const int C = static_cast<int>(p.C), Wi = static_cast<int>(W);
+  switch (p.kp.kind) {
+    case IGP_RBF:
+      kv_bf16_kernel<IGP_RBF><<<grid, 256, 0, s>>>(A1, n1p, A2, n2p, p.n1, p.n2, DPB, V, C, Wi,
+                                                   p.ldv, P, pl.cols_per_split, cnorm, cdot, p.skip);
+      break;
+    case IGP_MATERN12:
+      kv_bf16_kernel<IGP_MATERN12><<<grid, 256, 0, s>>>(A1, n1p, A2, n2p, p.n1, p.n2, DPB, V, C, Wi,
+                                                        p.ldv, P, pl.cols_per_split, cnorm, cdot, p.skip);
+      break;
+    case IGP_MATERN32:
+      kv_bf16_kernel<IGP_MATERN32><<<grid, 256, 0, s>>>(A1, n1p, A2, n2p, p.n1, p.n2, DPB, V, C, Wi,
+                                                        p.ldv, P, pl.cols_per_split, cnorm, cdot, p.skip);
+      break;
+    default:
+      kv_bf16_kernel<IGP_MATERN52><<<grid, 256, 0, s>>>(A1, n1p, A2, n2p, p.n1, p.n2, DPB, V, C, Wi,
+                                                        p.ldv, P, pl.cols_per_split, cnorm, cdot, p.skip);
+      break;
+  }
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+}  // namespace igp

@@ -35,8 +35,8 @@ struct KVProblem {
   // optional prepared rows for the matrix-core paths: X - centre (common
   // centre for X1 and X2), zero-padded to a multiple of 16 features, and the
   // squared norms of those rows.  When absent the launcher prepares them in ws.
-  const float* X1p = nullptr;
-  const float* X2p = nullptr;
+  const void* X1p = nullptr;     // float rows (FP32 path) or __bf16 rows (BF16 path)
+  const void* X2p = nullptr;
   const float* norm1 = nullptr;
   const float* norm2 = nullptr;
   const int* skip = nullptr;
@@ -61,6 +61,19 @@ int prep_rows_f32(const float* X, int64_t n, int64_t d, const float* centre, flo
 int kv_mfma_f32_launch(const KVProblem& p, const float* X1p, const float* n1p,
                        const float* X2p, const float* n2p, float* P, size_t P_bytes,
                        hipStream_t s, int* nsplit_out);
+
+// BF16 matrix-core kernel product (kv_bf16.hip): rows rounded to BF16, padded
+// to a multiple of 32 features, norms of the rounded rows.
+int64_t bf16_padded_dim(int64_t d);
+size_t bf16_partial_bytes(int64_t n1, int64_t n2, int64_t W);
+int prep_rows_bf16(const float* X, int64_t n, int64_t d, const float* centre, void* Xb,
+                   float* norms, hipStream_t s);
+int kv_bf16_launch(const KVProblem& p, const void* X1b, const float* n1p, const void* X2b,
+                   const float* n2p, float* P, size_t P_bytes, hipStream_t s, int* nsplit_out);
+// bytes of one prepared row set (rows + norms) for (precision, d)
+size_t prepared_rows_bytes(int precision, int64_t n, int64_t d);
+int prep_rows_any(int precision, const float* X, int64_t n, int64_t d, const float* centre,
+                  void* rows, float* norms, hipStream_t s);
 
 // ---- softmax Hessian blocks ---------------------------------------------------
 // pi = softmax(F) per point; rhs = F + W^+ (onehot(y) - pi); loglik partials.
