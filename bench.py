@@ -81,9 +81,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--residual", default="recurrence", choices=["explicit", "recurrence"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain FP32 PyTorch comparison")
     ap.add_argument("--precision", default=None, choices=["fp32", "fp64", "bf16"])
-    ap.add_argument("--workload", default="gpc16", choices=["gpc16", "image"],
-                    help="gpc16: N=20000 D=16 C=5 (default); image: N=60000 D=784 C=10 BF16")
+    ap.add_argument("--workload", default="gpc16", choices=["gpc16", "image", "batched"],
+                    help="gpc16: N=20000 D=16 C=5 (default); image: N=60000 D=784 C=10 BF16; "
+                         "batched: 64 independent problems in one persistent launch")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only; multi-GPU runs are not part of this build",
@@ -100,6 +103,8 @@ def main():
     global KV_INSTANCE
     if args.workload == "image":
         return bench_image(args)
+    if args.workload == "batched":
+        return bench_batched(args)
     args.precision = args.precision or "fp32"
     KV_INSTANCE = "kv_mfma_f32_narrow<3,1,5,2>"   # Matern-5/2, D <= 16, W = 5, 2 strips
     w = datagen.config2()
@@ -186,9 +191,132 @@ def main():
                     if k in ("iters", "buffer_cols", "converged", "res_norm", "rel_change", "psi")}
                    for i in infos],
     }
+    if not args.no_plain:
+        out["plain_fp32"] = plain_comparison(w, X, y, Xs, args.steps, jmax, R, elapsed / args.steps,
+                                             float(np.percentile(pred_ms, 99)))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, k_per_step)
     print(json.dumps(out))
+
+
+def plain_comparison(w, X, y, Xs, steps, jmax, R, ours_s_per_step, ours_p99_ms):
+    """The same schedule with the plain FP32 PyTorch form on the same GPU."""
+    import numpy as np
+    import torch
+
+    from plain_fp32 import PlainIterNCGP
+    pm = PlainIterNCGP(X.float(), y, w.C, w.kernel, w.lengthscale, w.outputscale, j_max=jmax,
+                       rank_limit=R)
+    torch.cuda.synchronize()
+    lat = []
+    its = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        its.append(pm.newton_step()["iters"])
+        a = time.perf_counter()
+        pm.predict(Xs.float())
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - a) * 1e3)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    # one product with K, timed alone (the kernel comparison)
+    v = torch.randn(w.N * w.C, device=X.device)
+    pm.apply_K(v)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(5):
+        pm.apply_K(v)
+    torch.cuda.synchronize()
+    kv_ms = (time.perf_counter() - a) / 5 * 1e3
+    return {"value": 1.0 / dt, "unit": "Newton steps/s", "ms_per_step": dt * 1e3,
+            "iters_per_step": its,
+            "kv_product_ms": kv_ms,
+            "speedup_of_library": dt / ours_s_per_step,
+            "predict_latency_ms": {"p50": float(np.percentile(lat, 50)),
+                                   "p99": float(np.percentile(lat, 99))},
+            "p99_ratio_plain_over_library": float(np.percentile(lat, 99)) / ours_p99_ms}
+
+
+def bench_batched(args):
+    """64 independent problems (N ~ U{1000..16000}, D=8, C ~ U{2..8},
+    Matern-3/2), IterNCGP-CG j<=200, R=100, FP32: one batched Newton step over
+    all problems per step (one persistent launch per solver iteration),
+    against the same steps run problem by problem with the library and with
+    the plain FP32 form.  value = aggregate Newton steps/s (problems x steps /
+    time)."""
+    import torch
+
+    import datagen
+    from paper_2310_20285_amd import api
+
+    ws_ = datagen.config4()
+    dev = torch.device("cuda:0")
+    data = [(torch.tensor(w.X, dtype=torch.float32, device=dev),
+             torch.tensor(w.y, dtype=torch.int32, device=dev)) for w in ws_]
+    steps = max(1, min(args.steps, 3))
+
+    def models():
+        return [api.IterNCGP(X, y, w.C, w.kernel, w.lengthscale, w.outputscale, policy="cg",
+                             j_max=200, rank_limit=100, recycle=True, precision="fp32",
+                             residual_mode="recurrence", max_buffer=300)
+                for w, (X, y) in zip(ws_, data)]
+
+    # warm-up (also runs the launch-shape tuning of the batched product)
+    wm = models()
+    buf = None
+    _, buf = api.newton_step_batched(wm, buf)
+    del wm
+    torch.cuda.synchronize()
+    ms = models()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for _ in range(steps):
+        infos, buf = api.newton_step_batched(ms, buf)
+        iters.append(sum(i["iters"] for i in infos))
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    del ms
+    ms = models()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for m in ms:
+            m.newton_step()
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    del ms
+    res = {
+        "metric": "IterNCGP Newton steps/s (aggregate over problems)",
+        "value": len(ws_) * steps / t_batch,
+        "unit": "Newton steps/s",
+        "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": t_batch / steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "64 problems N~U{1000..16000} D=8 C~U{2..8} matern32; "
+                               "IterNCGP-CG j<=200 R=100; batched Newton steps",
+                   "problems": len(ws_), "sum_N": int(sum(w.N for w in ws_))},
+        "solver_iterations_per_batched_step": iters,
+        "sequential_library": {"value": len(ws_) * steps / t_seq, "unit": "Newton steps/s",
+                               "speedup_of_batched": t_seq / t_batch},
+        "tuning": api.batched_tuning(),
+    }
+    if not args.no_plain:
+        from plain_fp32 import PlainIterNCGP
+        pms = [PlainIterNCGP(X, y, w.C, w.kernel, w.lengthscale, w.outputscale, j_max=200,
+                             rank_limit=100) for w, (X, y) in zip(ws_, data)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for pm in pms:
+                pm.newton_step()
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        res["plain_fp32_sequential"] = {"value": len(ws_) * steps / t_plain,
+                                        "unit": "Newton steps/s",
+                                        "speedup_of_batched": t_plain / t_batch}
+    print(json.dumps(res))
 
 
 BF16_MFMA_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak

@@ -188,13 +188,14 @@ def config3(seed: int = 2, N: int = 60000, Ns: int = 10000) -> Workload:
 
 
 def config4(seed: int = 3, n_problems: int = 64, n_lo: int = 1000,
-            n_hi: int = 16000, c_lo: int = 2, c_hi: int = 8, D: int = 8):
-    """Many independent problems of uneven size (batched form)."""
+            n_hi: int = 16000, c_lo: int = 2, c_hi: int = 8, D: int = 8, F: int = 512):
+    """Many independent problems of uneven size (batched form); RFF draws with
+    ``F`` features per problem."""
     rng = np.random.default_rng(seed)
     Ns = rng.integers(n_lo, n_hi + 1, size=n_problems)
     Cs = rng.integers(c_lo, c_hi + 1, size=n_problems)
     seeds = rng.integers(0, 2**31 - 1, size=n_problems)
-    return [gp_classification(int(s), int(n), D, int(c), "matern32", 1.0, 1.0,
+    return [gp_classification(int(s), int(n), D, int(c), "matern32", 1.0, 1.0, F=F,
                               name=f"config4[{i}]")
             for i, (n, c, s) in enumerate(zip(Ns, Cs, seeds))]
 

@@ -232,6 +232,26 @@ typedef struct igp_profile {
 int itergp_set_profiling(igp_model* m, int32_t enable);   /* enables/disables and resets */
 int itergp_get_profile(const igp_model* m, igp_profile* out);
 
+/* Batched form: one Newton step of n independent models together.  Every
+ * solver iteration issues ONE persistent launch covering the products K s of
+ * all models still iterating (a work queue of (model, row block, split)
+ * tiles), then the per-model projections; the host reads all models' scalars
+ * with one transfer per iteration, and the eigendecompositions of the virtual
+ * solver runs run in parallel host threads.  Results match itergp_newton_step
+ * on each model up to the summation order of the products (the batched launch
+ * may split the X2 rows differently).
+ * Requirements: FP32 models on one stream, recurrence residual, RBF or
+ * Matern-3/2 or -5/2, D <= 32, C <= 8, each model at most once.  The launch
+ * shape (rows per wave, X2 rows per split) is chosen by timing candidates on
+ * the first batch of each (kernel, feature class, size class) and cached for
+ * the process; itergp_batched_tuning returns the table as JSON.
+ *   ws  device workspace of >= itergp_batched_ws_bytes(models, n) bytes.
+ *   infos  n entries (nullable).  Synchronises the models' stream. */
+size_t itergp_batched_ws_bytes(igp_model* const* models, int32_t n);
+int itergp_newton_step_batched(igp_model* const* models, int32_t n, igp_step_info* infos,
+                               void* ws, size_t ws_bytes);
+int itergp_batched_tuning(char* buf, size_t len);
+
 /* Release the host-side handle (the arena stays the caller's). */
 int itergp_destroy(igp_model* m);
 

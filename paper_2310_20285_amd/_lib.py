@@ -85,6 +85,10 @@ SIGNATURES = {
     "igp_host_eigh": (ct.c_int, [_I32, _P, _P, _P]),
     "itergp_set_profiling": (ct.c_int, [_P, _I32]),
     "itergp_get_profile": (ct.c_int, [_P, ct.POINTER(Profile)]),
+    "itergp_batched_ws_bytes": (_SZ, [ct.POINTER(_P), _I32]),
+    "itergp_newton_step_batched": (ct.c_int, [ct.POINTER(_P), _I32, ct.POINTER(StepInfo), _P,
+                                              _SZ]),
+    "itergp_batched_tuning": (ct.c_int, [ct.c_char_p, _SZ]),
 }
 
 _LIB = None

@@ -196,3 +196,25 @@ class IterNCGP:
         shape = (Ns, self.C)
         return (mean.view(shape), None if v is None else v.view(shape),
                 None if p is None else p.view(shape))
+
+
+def newton_step_batched(models, ws: Optional[torch.Tensor] = None):
+    """itergp_newton_step_batched over a list of IterNCGP models."""
+    lib = L.load()
+    n = len(models)
+    arr = (ct.c_void_p * n)(*[m.handle.value for m in models])
+    wsb = lib.itergp_batched_ws_bytes(arr, n)
+    if wsb == 0:
+        raise L.IterGPError(L.IGP_EINVAL, lib.igp_last_error().decode() or "incompatible batch")
+    if ws is None or ws.numel() < wsb:
+        ws = torch.empty(int(wsb), dtype=torch.uint8, device="cuda")
+    infos = (L.StepInfo * n)()
+    L.check(lib.itergp_newton_step_batched(arr, n, infos, _ptr(ws), wsb))
+    return [i.as_dict() for i in infos], ws
+
+
+def batched_tuning() -> str:
+    lib = L.load()
+    buf = ct.create_string_buffer(1 << 16)
+    L.check(lib.itergp_batched_tuning(buf, len(buf)))
+    return buf.value.decode()

@@ -2,11 +2,16 @@
 // and dispatch only; the work runs in the HIP kernels behind ops.hpp.
 #include <cmath>
 #include <cstdarg>
+#include <cstring>
 #include <string>
 
 #include "ops.hpp"
 
 namespace igp {
+size_t batched_ws_bytes(igp_model* const* models, int n);
+int newton_step_batched(igp_model* const* models, int n, igp_step_info* infos, void* ws,
+                        size_t ws_bytes);
+std::string batched_tuning_json();
 size_t state_bytes(int64_t N, int64_t D, int64_t C, const igp_solver_config* cfg);
 int model_init(igp_model** out, const igp_kernel_params* kp, const igp_solver_config* cfg,
                const void* X, const int32_t* y, int64_t N, int64_t D, int64_t C, void* arena,
@@ -202,6 +207,33 @@ int itergp_get_profile(const igp_model* m, igp_profile* out) {
     clear_error();
     IGP_REQUIRE(m && out, "NULL model or output");
     return m->get_profile(out);
+  });
+}
+
+size_t itergp_batched_ws_bytes(igp_model* const* models, int32_t n) {
+  try {
+    return batched_ws_bytes(models, n);
+  } catch (...) {
+    return 0;
+  }
+}
+
+int itergp_newton_step_batched(igp_model* const* models, int32_t n, igp_step_info* infos,
+                               void* ws, size_t ws_bytes) {
+  return guarded([&]() -> int {
+    clear_error();
+    return newton_step_batched(models, n, infos, ws, ws_bytes);
+  });
+}
+
+int itergp_batched_tuning(char* buf, size_t len) {
+  return guarded([&]() -> int {
+    clear_error();
+    const std::string js = batched_tuning_json();
+    IGP_REQUIRE(buf && len > js.size(), "buffer of %zu bytes too small (need %zu)", len,
+                js.size() + 1);
+    memcpy(buf, js.c_str(), js.size() + 1);
+    return IGP_OK;
   });
 }
 

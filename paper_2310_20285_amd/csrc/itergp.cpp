@@ -3,9 +3,15 @@
 // operation running in the library's HIP kernels and only B x B algebra and
 // scalar control on the host.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <tuple>
 #include <vector>
 
 #include "ops.hpp"
@@ -102,7 +108,7 @@ struct Model final : igp_model {
   const T* user = nullptr;
   int64_t user_cols = 0, user_ld = 0;
   int steps_done = 0;
-  std::vector<double> hM, hMs, hU, hlam;
+  std::vector<double> hM, hMs, hU, hlam, hscale;
   // tracing
   bool prof = false;
   std::vector<hipEvent_t> evpool;
@@ -214,171 +220,255 @@ struct Model final : igp_model {
     return IGP_OK;
   }
 
-  // Algorithm 3: M = S^T (T + W^+ S); M = U Lambda U^T (descending);
-  // keep eigenvalues above the floor and at most R of them; S <- S U,
-  // T <- T U, Q_0 = S U Lambda^{-1/2}.
-  int virtual_solver_run(igp_step_info* info) {
+  // ---- one Newton step, in phases (a single model runs them back to back;
+  // the batched driver interleaves the phases of many models) ----------------
+  struct StepState {
+    igp_step_info info{};
+    double thresh = 0.0;
+    int j = 0, kprod = 0;
+    bool active = false;      // still taking actions
+    bool next_r = false;      // the last iteration enqueued a residual
+    hipEvent_t step_b = nullptr;
+    int keep = 0, dropped = 0;
+  } st;
+  double sc[SC_COUNT];
+
+  // pseudo-targets yhat - m = g + W^+ (onehot(y) - pi), m = 0
+  int phase_begin() {
+    st = StepState{};
+    st.info.eta_min = INFINITY;
+    evused = 0;
+    if (prof) {
+      hipEvent_t a;
+      IGP_TRY(event_pair(&a, &st.step_b));
+      IGP_CHECK_HIP(hipEventRecord(a, stream));
+    }
+    int nblk = 0;
+    IGP_TRY(softmax_pi_rhs<T>(L.f, y, N, C, L.pi, L.rhs, L.part, &nblk, stream));
+    IGP_TRY(dot_into<T>(L.rhs, L.rhs, n, L.part, L.scal + SC_RHS2, stream));
+    const bool recycle = cfg.recycle && cfg.policy != IGP_POLICY_UNIT;
+    if (!recycle) ncols = 0;
+    return IGP_OK;
+  }
+
+  // Algorithm 3, device part 1: M = S^T (T + W^+ S) (FP64 accumulation)
+  int phase_vsr_gram() {
+    if (ncols == 0) return IGP_OK;
     const int B = ncols;
-    if (B == 0) return IGP_OK;
     IGP_TRY(winv_apply<T>(L.pi, false, IGP_W_PINV, N, C, L.S, B, ld, L.Tb, ld, L.S2, ld, stream));
-    IGP_TRY(gram<T>(L.S, L.S2, ld, n, B, L.gram_part, L.gram_cap, L.M, stream));
-    hM.resize(static_cast<size_t>(B) * B);
+    return gram<T>(L.S, L.S2, ld, n, B, L.gram_part, L.gram_cap, L.M, stream);
+  }
+
+  int phase_vsr_fetch() {
+    if (ncols == 0) return IGP_OK;
+    hM.resize(static_cast<size_t>(ncols) * ncols);
     IGP_CHECK_HIP(hipMemcpyAsync(hM.data(), L.M, hM.size() * sizeof(double),
                                  hipMemcpyDeviceToHost, stream));
     IGP_CHECK_HIP(hipStreamSynchronize(stream));
+    return IGP_OK;
+  }
+
+  // host part: M = U Lambda U^T (descending), tiny-eigenvalue floor, keep <= R.
+  // Touches only this model's host buffers (safe to run concurrently).
+  int phase_vsr_host() {
+    const int B = ncols;
+    if (B == 0) return IGP_OK;
     hMs.resize(hM.size());
     for (int i = 0; i < B; ++i)
-      for (int j = 0; j < B; ++j)
-        hMs[static_cast<size_t>(i) * B + j] =
-            0.5 * (hM[static_cast<size_t>(i) * B + j] + hM[static_cast<size_t>(j) * B + i]);
+      for (int k = 0; k < B; ++k)
+        hMs[static_cast<size_t>(i) * B + k] =
+            0.5 * (hM[static_cast<size_t>(i) * B + k] + hM[static_cast<size_t>(k) * B + i]);
     hlam.resize(B);
     hU.resize(static_cast<size_t>(B) * B);
     IGP_TRY(eigh_desc(B, hMs.data(), hlam.data(), hU.data()));
     int keep = 0;
     const double floor = hlam[0] > 0.0 ? hlam[0] * B * 2.220446049250313e-16 : INFINITY;
     while (keep < B && hlam[keep] > floor) ++keep;
-    const int dropped_floor = B - keep;
+    st.dropped = B - keep;
     if (cfg.rank_limit >= 0 && keep > cfg.rank_limit) keep = cfg.rank_limit;
-    std::vector<double> scale(std::max(keep, 1));
-    for (int k = 0; k < keep; ++k) scale[k] = 1.0 / std::sqrt(hlam[k]);
+    st.keep = keep;
+    hscale.resize(std::max(keep, 1));
+    for (int k = 0; k < keep; ++k) hscale[k] = 1.0 / std::sqrt(hlam[k]);
+    return IGP_OK;
+  }
+
+  // device part 2: S <- S U, T <- T U, Q_0 = S U Lambda^{-1/2} (and K Q_0 = T U Lambda^{-1/2})
+  int phase_vsr_apply() {
+    const int B = ncols;
+    if (B == 0) return IGP_OK;
+    const int keep = st.keep;
     if (keep > 0) {
       IGP_CHECK_HIP(hipMemcpyAsync(L.U, hU.data(), static_cast<size_t>(B) * keep * sizeof(double),
                                    hipMemcpyHostToDevice, stream));
-      IGP_CHECK_HIP(hipMemcpyAsync(L.lamscale, scale.data(), keep * sizeof(double),
+      IGP_CHECK_HIP(hipMemcpyAsync(L.lamscale, hscale.data(), keep * sizeof(double),
                                    hipMemcpyHostToDevice, stream));
       IGP_TRY(right_mul<T>(L.S, ld, n, B, L.U, keep, nullptr, L.S2, ld, stream));
       IGP_TRY(right_mul<T>(L.Tb, ld, n, B, L.U, keep, nullptr, L.T2, ld, stream));
       IGP_TRY(right_mul<T>(L.S, ld, n, B, L.U, keep, L.lamscale, L.Q, ld, stream));
-      if (recurrence())   // K Q_0 = K S U Lambda^{-1/2} = T U Lambda^{-1/2}
+      if (recurrence())
         IGP_TRY(right_mul<T>(L.Tb, ld, n, B, L.U, keep, L.lamscale, L.KQ, ld, stream));
       std::swap(L.S, L.S2);
       std::swap(L.Tb, L.T2);
     }
-    // host buffers must outlive the async copies
-    IGP_CHECK_HIP(hipStreamSynchronize(stream));
     ncols = keep;
-    if (info) {
-      info->recycled_cols = keep;
-      info->eig_dropped = dropped_floor;
-    }
+    st.info.recycled_cols = keep;
+    st.info.eig_dropped = st.dropped;
     return IGP_OK;
   }
 
-  int newton_step(igp_step_info* info_out) override {
-    clear_error();
-    igp_step_info info{};
-    info.eta_min = INFINITY;
-    double sc[SC_COUNT];
-    int nblk = 0;
-    hipEvent_t step_a = nullptr, step_b = nullptr;
-    evused = 0;
-    if (prof) {
-      IGP_TRY(event_pair(&step_a, &step_b));
-      IGP_CHECK_HIP(hipEventRecord(step_a, stream));
-    }
-    // pseudo-targets yhat - m = g + W^+ (onehot(y) - pi), m = 0
-    IGP_TRY(softmax_pi_rhs<T>(L.f, y, N, C, L.pi, L.rhs, L.part, &nblk, stream));
-    IGP_TRY(dot_into<T>(L.rhs, L.rhs, n, L.part, L.scal + SC_RHS2, stream));
-    const bool recycle = cfg.recycle && cfg.policy != IGP_POLICY_UNIT;
-    if (!recycle) ncols = 0;
-    IGP_TRY(virtual_solver_run(&info));
-    // v_0 = C_0 (yhat - m) = Q (Q^T (yhat - m))
+  // v_0 = C_0 (yhat - m) = Q (Q^T (yhat - m)); then r_0 when j_max > 0
+  int phase_v0() {
     if (ncols > 0) {
       IGP_TRY(gemv_t<T>(L.Q, ld, n, ncols, L.rhs, L.part, L.yb, stream));
       IGP_TRY(gemv_n<T>(L.Q, ld, n, ncols, L.yb, L.v, stream));
       if (recurrence()) IGP_TRY(gemv_n<T>(L.KQ, ld, n, ncols, L.yb, L.kv, stream));
     } else {
-      IGP_CHECK_HIP(hipMemsetAsync(L.v, 0, n * sizeof(T), stream));
-      if (recurrence()) IGP_CHECK_HIP(hipMemsetAsync(L.kv, 0, n * sizeof(T), stream));
+      IGP_TRY(fill_zero<T>(L.v, n, stream));
+      if (recurrence()) IGP_TRY(fill_zero<T>(L.kv, n, stream));
     }
-    IGP_TRY(read_scalars(sc));
-    info.rhs_norm = std::sqrt(sc[SC_RHS2]);
-    const double thresh = std::max(cfg.tol_abs, cfg.tol_rel * info.rhs_norm);
-    int kprod = 0;
-    int j = 0;
-    // r = (yhat - m) - K v - W^+ v with K v formed (explicit) or carried (recurrence)
-    auto enqueue_residual = [&]() -> int {
-      if (!recurrence()) {
-        IGP_TRY(apply_K(L.v, L.kv));
-        ++kprod;
-      }
-      IGP_TRY(winv_apply<T>(L.pi, false, IGP_W_PINV, N, C, L.v, 1, n, nullptr, 0, L.wv, n,
-                            stream));
-      return residual<T>(L.rhs, L.kv, L.wv, L.r, n, L.part, L.scal + SC_RR, stream);
-    };
-    bool have_r = false;
+    if (cfg.j_max > 0) IGP_TRY(enqueue_residual());
+    return IGP_OK;
+  }
+
+  // r = (yhat - m) - K v - W^+ v with K v formed (explicit) or carried (recurrence)
+  int enqueue_residual() {
+    if (!recurrence()) {
+      IGP_TRY(apply_K(L.v, L.kv));
+      ++st.kprod;
+    }
+    IGP_TRY(winv_apply<T>(L.pi, false, IGP_W_PINV, N, C, L.v, 1, n, nullptr, 0, L.wv, n, stream));
+    return residual<T>(L.rhs, L.kv, L.wv, L.r, n, L.part, L.scal + SC_RR, stream);
+  }
+
+  // after the scalars of phase_v0 are on the host
+  void phase_start_iterations() {
+    st.info.rhs_norm = std::sqrt(sc[SC_RHS2]);
+    st.thresh = std::max(cfg.tol_abs, cfg.tol_rel * st.info.rhs_norm);
+    st.active = false;
     if (cfg.j_max > 0) {
-      IGP_TRY(enqueue_residual());   // r_0
-      IGP_TRY(read_scalars(sc));
-      info.res_norm = std::sqrt(sc[SC_RR]);
-      have_r = true;
-      if (!(info.res_norm >= thresh)) info.converged = 1;
+      st.info.res_norm = std::sqrt(sc[SC_RR]);
+      if (!(st.info.res_norm >= st.thresh)) st.info.converged = 1;
+      else st.active = true;
     }
-    // One host synchronisation per iteration: the update of Q and v is guarded
-    // on the device by eta_j > 0, and the next residual is enqueued before the
-    // host reads eta_j and ||r_j|| together.
-    while (have_r && !info.converged && j < cfg.j_max) {
-      if (ncols >= cfg.max_buffer) {
-        set_error("buffer full: %d columns (max_buffer too small)", ncols);
-        return IGP_ENOMEM;
-      }
-      if (cfg.policy == IGP_POLICY_USER && (!user || j >= user_cols)) break;  // actions used up
-      ++j;
-      T* s_col = L.S + static_cast<int64_t>(ncols) * ld;
-      T* t_col = L.Tb + static_cast<int64_t>(ncols) * ld;
-      if (cfg.policy == IGP_POLICY_CG) {
-        IGP_TRY(action_cg<T>(L.r, L.scal + SC_RR, s_col, n, stream));
-      } else if (cfg.policy == IGP_POLICY_UNIT) {
-        IGP_TRY(fill_unit<T>(s_col, n, j - 1, stream));
-      } else {
-        IGP_TRY(copy_vec<T>(user + static_cast<int64_t>(j - 1) * user_ld, s_col, n, stream));
-      }
-      IGP_TRY(dot_into<T>(s_col, L.r, n, L.part, L.scal + SC_ALPHA, stream));   // alpha_j
-      IGP_TRY(apply_K(s_col, t_col));                                            // t_j = K s_j
-      ++kprod;
-      IGP_TRY(winv_apply<T>(L.pi, false, IGP_W_PINV, N, C, s_col, 1, n, t_col, n, L.z, n,
-                            stream));                                            // z_j
-      IGP_TRY(gemv_t<T>(L.Q, ld, n, ncols, L.z, L.part, L.yb, stream));          // Q^T z
-      IGP_TRY(dir_update<T>(s_col, L.Q, ld, n, ncols, L.yb, L.z, L.d, L.part,
-                            L.scal + SC_ETA, stream, t_col, recurrence() ? L.KQ : nullptr,
-                            L.kd));                                              // d_j, eta_j
-      IGP_TRY(append_and_step<T>(L.d, L.scal, L.Q + static_cast<int64_t>(ncols) * ld, L.v, n,
-                                 stream, recurrence() ? L.kd : nullptr,
-                                 recurrence() ? L.KQ + static_cast<int64_t>(ncols) * ld : nullptr,
-                                 L.kv));                                         // eta > 0 only
-      const bool next_r = j < cfg.j_max;
-      if (next_r) IGP_TRY(enqueue_residual());                                   // r_j
-      IGP_TRY(read_scalars(sc));
-      const double eta = sc[SC_ETA];
-      if (!(eta > 0.0)) {
-        info.breakdown = 1;   // s_j and t_j are dropped: ncols is not advanced
-        --j;
-        break;
-      }
-      info.eta_min = std::min(info.eta_min, eta);
-      ++ncols;
-      if (next_r) {
-        info.res_norm = std::sqrt(sc[SC_RR]);
-        if (!(info.res_norm >= thresh)) info.converged = 1;
+  }
+
+  // whether another action is taken (sets st.active = false otherwise)
+  int phase_can_act() {
+    if (!st.active) return IGP_OK;
+    if (st.j >= cfg.j_max) {
+      st.active = false;
+      return IGP_OK;
+    }
+    if (ncols >= cfg.max_buffer) {
+      set_error("buffer full: %d columns (max_buffer too small)", ncols);
+      return IGP_ENOMEM;
+    }
+    if (cfg.policy == IGP_POLICY_USER && (!user || st.j >= user_cols)) st.active = false;
+    return IGP_OK;
+  }
+
+  T* s_col() const { return L.S + static_cast<int64_t>(ncols) * ld; }
+  T* t_col() const { return L.Tb + static_cast<int64_t>(ncols) * ld; }
+
+  // s_j (policy) and alpha_j = s_j^T r_{j-1}
+  int phase_action() {
+    ++st.j;
+    if (cfg.policy == IGP_POLICY_CG) {
+      IGP_TRY(action_cg<T>(L.r, L.scal + SC_RR, s_col(), n, stream));
+    } else if (cfg.policy == IGP_POLICY_UNIT) {
+      IGP_TRY(fill_unit<T>(s_col(), n, st.j - 1, stream));
+    } else {
+      IGP_TRY(copy_vec<T>(user + static_cast<int64_t>(st.j - 1) * user_ld, s_col(), n, stream));
+    }
+    return dot_into<T>(s_col(), L.r, n, L.part, L.scal + SC_ALPHA, stream);
+  }
+
+  // after t_j = K s_j: z_j, Q^T z_j, d_j, eta_j, guarded append, next residual
+  int phase_after_product() {
+    ++st.kprod;
+    IGP_TRY(winv_apply<T>(L.pi, false, IGP_W_PINV, N, C, s_col(), 1, n, t_col(), n, L.z, n,
+                          stream));
+    IGP_TRY(gemv_t<T>(L.Q, ld, n, ncols, L.z, L.part, L.yb, stream));
+    IGP_TRY(dir_update<T>(s_col(), L.Q, ld, n, ncols, L.yb, L.z, L.d, L.part, L.scal + SC_ETA,
+                          stream, t_col(), recurrence() ? L.KQ : nullptr, L.kd));
+    IGP_TRY(append_and_step<T>(L.d, L.scal, L.Q + static_cast<int64_t>(ncols) * ld, L.v, n,
+                               stream, recurrence() ? L.kd : nullptr,
+                               recurrence() ? L.KQ + static_cast<int64_t>(ncols) * ld : nullptr,
+                               L.kv));
+    st.next_r = st.j < cfg.j_max;
+    if (st.next_r) IGP_TRY(enqueue_residual());
+    return IGP_OK;
+  }
+
+  // after the iteration's scalars are on the host
+  void phase_consume() {
+    const double eta = sc[SC_ETA];
+    if (!(eta > 0.0)) {
+      st.info.breakdown = 1;   // s_j and t_j are dropped: ncols is not advanced
+      --st.j;
+      st.active = false;
+      return;
+    }
+    st.info.eta_min = std::min(st.info.eta_min, eta);
+    ++ncols;
+    if (st.next_r) {
+      st.info.res_norm = std::sqrt(sc[SC_RR]);
+      if (!(st.info.res_norm >= st.thresh)) {
+        st.info.converged = 1;
+        st.active = false;
       }
     }
-    info.iters = j;
-    // f_{i+1} = K v + m
-    IGP_TRY(apply_K(L.v, L.fnew));
-    ++kprod;
+  }
+
+  // after f_{i+1} = K v + m has been enqueued into fnew
+  int phase_stats() {
+    ++st.kprod;
     IGP_TRY(newton_stats<T>(L.fnew, L.f, L.v, y, N, C, L.part, L.scal, stream));
-    if (prof) IGP_CHECK_HIP(hipEventRecord(step_b, stream));
-    IGP_TRY(read_scalars(sc));
+    if (prof) IGP_CHECK_HIP(hipEventRecord(st.step_b, stream));
+    return IGP_OK;
+  }
+
+  int phase_finish(igp_step_info* info_out) {
     IGP_TRY(collect_profile());
     std::swap(L.f, L.fnew);
+    igp_step_info& info = st.info;
+    info.iters = st.j;
     info.buffer_cols = ncols;
-    info.k_products = kprod;
+    info.k_products = st.kprod;
     info.rel_change = sc[SC_FNEW2] > 0.0 ? std::sqrt(sc[SC_DIFF2] / sc[SC_FNEW2]) : INFINITY;
     info.psi = sc[SC_LOGLIK] - 0.5 * sc[SC_GV];
     if (!std::isfinite(info.eta_min)) info.eta_min = 0.0;
     ++steps_done;
     if (info_out) *info_out = info;
     return IGP_OK;
+  }
+
+  KVProblem product_action() const { return kv_problem(L.X, N, s_col(), 1, n, t_col(), n); }
+  KVProblem product_update() const { return kv_problem(L.X, N, L.v, 1, n, L.fnew, n); }
+
+  int newton_step(igp_step_info* info_out) override {
+    clear_error();
+    IGP_TRY(phase_begin());
+    IGP_TRY(phase_vsr_gram());
+    IGP_TRY(phase_vsr_fetch());
+    IGP_TRY(phase_vsr_host());
+    IGP_TRY(phase_vsr_apply());
+    IGP_TRY(phase_v0());
+    IGP_TRY(read_scalars(sc));
+    phase_start_iterations();
+    for (;;) {
+      IGP_TRY(phase_can_act());
+      if (!st.active) break;
+      IGP_TRY(phase_action());
+      IGP_TRY(apply_K(s_col(), t_col()));
+      IGP_TRY(phase_after_product());
+      IGP_TRY(read_scalars(sc));
+      phase_consume();
+    }
+    IGP_TRY(apply_K(L.v, L.fnew));
+    IGP_TRY(phase_stats());
+    IGP_TRY(read_scalars(sc));
+    return phase_finish(info_out);
   }
 
   size_t kvws_for(int64_t n1, int64_t nb) const {
@@ -465,6 +555,287 @@ struct Model final : igp_model {
     return IGP_OK;
   }
 };
+
+// ---- batched form: many independent models advance together -------------------
+__global__ void k_gather_scalars(const double* const* __restrict__ src, int n,
+                                 double* __restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * SC_COUNT) return;
+  dst[i] = src[i / SC_COUNT][i % SC_COUNT];
+}
+
+struct TuneKey {
+  int kind, dch, nbucket;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(kind, dch, nbucket) < std::tie(o.kind, o.dch, o.nbucket);
+  }
+};
+struct TuneVal {
+  int ns;
+  int64_t split_rows;
+  double us;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+constexpr int64_t TUNE_SPLITS[] = {1024, 4096};
+constexpr int TUNE_NS[] = {1, 2};
+
+struct Batch {
+  std::vector<Model<float>*> ms;
+  hipStream_t stream = nullptr;
+  int kind = 0, dch = 1;
+  // workspace
+  BatchProblem* dtab = nullptr;
+  int* counter = nullptr;
+  const double** dscal = nullptr;
+  double* gathered = nullptr;
+  float* partials = nullptr;
+  std::vector<double> hgather;
+  std::vector<BatchProblem> htab;
+
+  static size_t partial_floats(const Model<float>* m) {
+    return static_cast<size_t>(ceil_div(m->N, TUNE_SPLITS[0]) + 1) * m->N * m->C;
+  }
+
+  static size_t ws_bytes(const std::vector<Model<float>*>& ms) {
+    Carver cv(nullptr, 0);
+    cv.take<BatchProblem>(ms.size());
+    cv.take<int64_t>(1);
+    cv.take<const double*>(ms.size());
+    cv.take<double>(ms.size() * SC_COUNT);
+    size_t pf = 0;
+    for (auto* m : ms) pf += align_up(partial_floats(m) * sizeof(float)) / sizeof(float);
+    cv.take<float>(pf);
+    return cv.used + 256;
+  }
+
+  int carve_ws(void* ws, size_t bytes) {
+    Carver cv(ws, bytes);
+    dtab = cv.take<BatchProblem>(ms.size());
+    counter = reinterpret_cast<int*>(cv.take<int64_t>(1));
+    dscal = cv.take<const double*>(ms.size());
+    gathered = cv.take<double>(ms.size() * SC_COUNT);
+    size_t pf = 0;
+    for (auto* m : ms) pf += align_up(partial_floats(m) * sizeof(float)) / sizeof(float);
+    partials = cv.take<float>(pf);
+    if (!cv.fits() || !ws) {
+      set_error("batched workspace too small: need %zu bytes", ws_bytes(ms));
+      return IGP_ENOMEM;
+    }
+    std::vector<const double*> hs(ms.size());
+    for (size_t i = 0; i < ms.size(); ++i) hs[i] = ms[i]->L.scal;
+    IGP_CHECK_HIP(hipMemcpyAsync(dscal, hs.data(), hs.size() * sizeof(double*),
+                                 hipMemcpyHostToDevice, stream));
+    IGP_CHECK_HIP(hipStreamSynchronize(stream));
+    hgather.resize(ms.size() * SC_COUNT);
+    return IGP_OK;
+  }
+
+  // copy every model's scalar block to its host array (one transfer)
+  int read_all() {
+    const int n = static_cast<int>(ms.size());
+    k_gather_scalars<<<static_cast<unsigned>(ceil_div(n * SC_COUNT, 256)), 256, 0, stream>>>(
+        dscal, n, gathered);
+    IGP_CHECK_LAUNCH();
+    IGP_CHECK_HIP(hipMemcpyAsync(hgather.data(), gathered, hgather.size() * sizeof(double),
+                                 hipMemcpyDeviceToHost, stream));
+    IGP_CHECK_HIP(hipStreamSynchronize(stream));
+    for (int i = 0; i < n; ++i)
+      std::copy(&hgather[static_cast<size_t>(i) * SC_COUNT],
+                &hgather[static_cast<size_t>(i) * SC_COUNT] + SC_COUNT, ms[i]->sc);
+    return IGP_OK;
+  }
+
+  // one persistent launch for the products of the selected models
+  int run_products(const std::vector<int>& idx, bool update, int ns, int64_t split_rows) {
+    htab.clear();
+    int64_t tiles = 0, outs = 0;
+    size_t poff = 0;
+    for (int i : idx) {
+      Model<float>* m = ms[i];
+      const KVProblem kp = update ? m->product_update() : m->product_action();
+      BatchProblem bp{};
+      bp.X1p = static_cast<const float*>(kp.X1p);
+      bp.nrm1 = kp.norm1;
+      bp.X2p = static_cast<const float*>(kp.X2p);
+      bp.nrm2 = kp.norm2;
+      bp.n1 = kp.n1;
+      bp.n2 = kp.n2;
+      bp.V = static_cast<const float*>(kp.V);
+      bp.ldv = kp.ldv;
+      bp.C = static_cast<int>(kp.C);
+      bp.W = static_cast<int>(kp.C * kp.nb);
+      batched_plan(bp.n1, bp.n2, bp.W, ns, split_rows, &bp);
+      bp.P = partials + poff;
+      poff += align_up(partial_floats(m) * sizeof(float)) / sizeof(float);
+      const double inv_l2 = 1.0 / (kp.kp.lengthscale * kp.kp.lengthscale);
+      const float kap = kv_kappa(kp.kp.kind);
+      bp.cnorm = static_cast<float>(kap * inv_l2);
+      bp.cdot = static_cast<float>(-2.0 * kap * inv_l2);
+      bp.os = static_cast<float>(kp.kp.outputscale);
+      bp.Out = static_cast<float*>(kp.Out);
+      bp.ldo = kp.ldo;
+      bp.tile_begin = tiles;
+      bp.out_begin = outs;
+      tiles += static_cast<int64_t>(bp.gx) * bp.nsplit;
+      outs += bp.n1 * bp.W;
+      htab.push_back(bp);
+      if (m->prof) {
+        m->pending_evals += static_cast<double>(bp.n1) * bp.n2;
+        m->pending_flops += 2.0 * bp.n1 * bp.n2 * (m->D + bp.W);
+      }
+    }
+    if (htab.empty()) return IGP_OK;
+    IGP_CHECK_HIP(hipMemcpyAsync(dtab, htab.data(), htab.size() * sizeof(BatchProblem),
+                                 hipMemcpyHostToDevice, stream));
+    return kv_batched_run(kind, dch, ns, dtab, static_cast<int>(htab.size()), tiles, outs, counter,
+                          stream);
+  }
+
+  // the tuned launch shape for this batch (timed on first use, then cached)
+  int products(const std::vector<int>& idx, bool update) {
+    int64_t total = 0;
+    for (int i : idx) total += ms[i]->N;
+    const TuneKey key{kind, dch, static_cast<int>(std::log2(std::max<int64_t>(total, 1)))};
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune.find(key);
+      if (it != g_tune.end()) return run_products(idx, update, it->second.ns, it->second.split_rows);
+    }
+    hipEvent_t a, b;
+    IGP_CHECK_HIP(hipEventCreate(&a));
+    IGP_CHECK_HIP(hipEventCreate(&b));
+    TuneVal best{2, TUNE_SPLITS[1], INFINITY};
+    for (int ns : TUNE_NS)
+      for (int64_t sr : TUNE_SPLITS) {
+        IGP_TRY(run_products(idx, update, ns, sr));   // warm
+        IGP_CHECK_HIP(hipEventRecord(a, stream));
+        IGP_TRY(run_products(idx, update, ns, sr));
+        IGP_CHECK_HIP(hipEventRecord(b, stream));
+        IGP_CHECK_HIP(hipEventSynchronize(b));
+        float ms_ = 0.f;
+        IGP_CHECK_HIP(hipEventElapsedTime(&ms_, a, b));
+        if (ms_ * 1e3 < best.us) best = TuneVal{ns, sr, ms_ * 1e3};
+      }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[key] = best;
+    }
+    // the last candidate ran last; run the chosen one so its result stands
+    return run_products(idx, update, best.ns, best.split_rows);
+  }
+};
+
+template <typename F>
+int parallel_for(int n, F&& f) {
+  const int nt = std::max(1, std::min<int>(n, static_cast<int>(std::thread::hardware_concurrency())));
+  std::vector<int> rc(nt, IGP_OK);
+  std::atomic<int> next{0};
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&, t]() {
+      for (int i; (i = next.fetch_add(1)) < n;) {
+        const int r = f(i);
+        if (r != IGP_OK) rc[t] = r;
+      }
+    });
+  for (auto& x : th) x.join();
+  for (int r : rc)
+    if (r != IGP_OK) return r;
+  return IGP_OK;
+}
+
+int batch_models(igp_model* const* models, int n, std::vector<Model<float>*>* out, int* kind,
+                 int* dch, hipStream_t* stream) {
+  IGP_REQUIRE(models && n >= 1, "no models");
+  out->clear();
+  for (int i = 0; i < n; ++i) {
+    auto* m = dynamic_cast<Model<float>*>(models[i]);
+    IGP_REQUIRE(m, "batched steps need FP32 models (model %d is not)", i);
+    IGP_REQUIRE(m->prepared && m->cfg.precision == IGP_FP32,
+                "model %d: batched steps need the FP32 matrix-core path", i);
+    IGP_REQUIRE(m->recurrence(), "model %d: batched steps need the recurrence residual", i);
+    IGP_REQUIRE(batched_supported(m->kp.kind, m->D, m->C), "model %d: kernel, D <= 32 and C <= 8 "
+                "are required for the batched launch", i);
+    if (i == 0) {
+      *kind = m->kp.kind;
+      *dch = static_cast<int>(ceil_div(m->D, 16));
+      *stream = m->stream;
+    }
+    IGP_REQUIRE(m->kp.kind == *kind && ceil_div(m->D, 16) == *dch && m->stream == *stream,
+                "model %d: all models of a batch share kernel family, feature count class and "
+                "stream", i);
+    for (auto* o : *out) IGP_REQUIRE(o != m, "model %d appears twice", i);
+    out->push_back(m);
+  }
+  return IGP_OK;
+}
+
+}  // namespace
+
+size_t batched_ws_bytes(igp_model* const* models, int n) {
+  std::vector<Model<float>*> ms;
+  int kind, dch;
+  hipStream_t st;
+  if (batch_models(models, n, &ms, &kind, &dch, &st) != IGP_OK) return 0;
+  return Batch::ws_bytes(ms);
+}
+
+int newton_step_batched(igp_model* const* models, int n, igp_step_info* infos, void* ws,
+                        size_t ws_bytes) {
+  Batch b;
+  IGP_TRY(batch_models(models, n, &b.ms, &b.kind, &b.dch, &b.stream));
+  IGP_TRY(b.carve_ws(ws, ws_bytes));
+  auto& ms = b.ms;
+  for (auto* m : ms) IGP_TRY(m->phase_begin());
+  for (auto* m : ms) IGP_TRY(m->phase_vsr_gram());
+  for (auto* m : ms) IGP_TRY(m->phase_vsr_fetch());
+  IGP_TRY(parallel_for(n, [&](int i) { return ms[i]->phase_vsr_host(); }));
+  for (auto* m : ms) IGP_TRY(m->phase_vsr_apply());
+  for (auto* m : ms) IGP_TRY(m->phase_v0());
+  IGP_TRY(b.read_all());
+  for (auto* m : ms) m->phase_start_iterations();
+  std::vector<int> act;
+  for (;;) {
+    act.clear();
+    for (int i = 0; i < n; ++i) {
+      IGP_TRY(ms[i]->phase_can_act());
+      if (ms[i]->st.active) act.push_back(i);
+    }
+    if (act.empty()) break;
+    for (int i : act) IGP_TRY(ms[i]->phase_action());
+    IGP_TRY(b.products(act, false));                    // t_j = K s_j for every active model
+    for (int i : act) IGP_TRY(ms[i]->phase_after_product());
+    IGP_TRY(b.read_all());
+    for (int i : act) ms[i]->phase_consume();
+  }
+  std::vector<int> all(n);
+  for (int i = 0; i < n; ++i) all[i] = i;
+  IGP_TRY(b.products(all, true));                       // f_{i+1} = K v for every model
+  for (auto* m : ms) IGP_TRY(m->phase_stats());
+  IGP_TRY(b.read_all());
+  for (int i = 0; i < n; ++i) IGP_TRY(ms[i]->phase_finish(infos ? &infos[i] : nullptr));
+  return IGP_OK;
+}
+
+std::string batched_tuning_json() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::string s = "[";
+  for (auto& kv : g_tune) {
+    char buf[256];
+    snprintf(buf, sizeof(buf),
+             "%s{\"kind\": %d, \"feature_chunks\": %d, \"log2_rows\": %d, \"strips\": %d, "
+             "\"split_rows\": %lld, \"us\": %.2f}",
+             s.size() > 1 ? ", " : "", kv.first.kind, kv.first.dch, kv.first.nbucket,
+             kv.second.ns, (long long)kv.second.split_rows, kv.second.us);
+    s += buf;
+  }
+  return s + "]";
+}
+
+namespace {
 
 template <typename T>
 __global__ void k_check_labels(const int32_t* y, int64_t N, int C, int* bad) {

@@ -19,6 +19,8 @@
 // LDS, double-buffered through registers: the next tile's global loads are in
 // flight while the current tile is computed.  Partial sums per split are
 // reduced in a fixed order (kv_reduce), so the product is deterministic.
+#include <algorithm>
+
 #include "ops.hpp"
 
 namespace igp {
@@ -206,29 +208,37 @@ constexpr int WV = 8;    // widest output of the narrow variant
 #endif
 constexpr int NSTRIP = IGP_NARROW_NS;   // 16-row strips of X1 per wave
 
+template <int DCH, int WX>
+struct NarrowSmem {
+  static constexpr int DP = DCH * 16;
+  static constexpr int XS = DP + 4;
+  static constexpr int VE = (TN * WX + 255) / 256;
+  float sX[2][TN * XS];
+  float sN[2][TN];
+  float sV[2][VE * 256];
+};
+
+// One workgroup tile of the narrow variant: rows [row_base, row_base + 64 NS) of
+// X1 against X2 rows [m_begin, m_end), partial outputs to P (row stride WX).
 template <int KIND, int DCH, int WX, int NS>
-__global__ void __launch_bounds__(256)
-kv_mfma_f32_narrow(const float* __restrict__ X1p, const float* __restrict__ nrm1,
-                   const float* __restrict__ X2p, const float* __restrict__ nrm2, int64_t n1,
-                   int64_t n2, const float* __restrict__ V, int C, int64_t ldv,
-                   float* __restrict__ P, int64_t cols_per_split, float cnorm, float cdot,
-                   const int* skip) {
-  if (skip && *skip) return;
+__device__ inline void narrow_tile(NarrowSmem<DCH, WX>& sm, const float* __restrict__ X1p,
+                                   const float* __restrict__ nrm1, const float* __restrict__ X2p,
+                                   const float* __restrict__ nrm2, int64_t n1, int64_t row_base,
+                                   int64_t m_begin, int64_t m_end, const float* __restrict__ V,
+                                   int C, int64_t ldv, float* __restrict__ P, float cnorm,
+                                   float cdot) {
   constexpr int DP = DCH * 16;
   constexpr int XS = DP + 4;
   constexpr int XQT = TN * DP / 4 / 256;   // float4 of X2 per thread per tile (= DCH)
   constexpr int VT = TN * WX;              // V values per tile, layout [m][WX]
   constexpr int VE = (VT + 255) / 256;     // V elements per thread per tile
-  __shared__ __align__(16) float sX[2][TN * XS];
-  __shared__ __align__(16) float sN[2][TN];
-  __shared__ __align__(16) float sV[2][VE * 256];
+  auto& sX = sm.sX;
+  auto& sN = sm.sN;
+  auto& sV = sm.sV;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, r = lane & 15;
-  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * (64 * NS) + wave * (16 * NS);
-  const int64_t m_begin = static_cast<int64_t>(blockIdx.y) * cols_per_split;
-  const int64_t m_end = m_begin + cols_per_split < n2 ? m_begin + cols_per_split : n2;
-
+  const int64_t row0 = row_base + wave * (16 * NS);
   f4 xb[NS][DCH];
   float n1v[NS];
 #pragma unroll
@@ -353,11 +363,107 @@ kv_mfma_f32_narrow(const float* __restrict__ X1p, const float* __restrict__ nrm1
     for (int st = 0; st < NS; ++st) {
       const int64_t n = row0 + st * 16 + r;
       if (n < n1) {
-        float* dst = P + (static_cast<int64_t>(blockIdx.y) * n1 + n) * WX;
+        float* dst = P + n * WX;
 #pragma unroll
         for (int w = 0; w < WX; ++w) dst[w] = acc[st][w];
       }
     }
+  }
+}
+
+template <int KIND, int DCH, int WX, int NS>
+__global__ void __launch_bounds__(256)
+kv_mfma_f32_narrow(const float* __restrict__ X1p, const float* __restrict__ nrm1,
+                   const float* __restrict__ X2p, const float* __restrict__ nrm2, int64_t n1,
+                   int64_t n2, const float* __restrict__ V, int C, int64_t ldv,
+                   float* __restrict__ P, int64_t cols_per_split, float cnorm, float cdot,
+                   const int* skip) {
+  if (skip && *skip) return;
+  __shared__ __align__(16) NarrowSmem<DCH, WX> sm;
+  const int64_t m_begin = static_cast<int64_t>(blockIdx.y) * cols_per_split;
+  const int64_t m_end = m_begin + cols_per_split < n2 ? m_begin + cols_per_split : n2;
+  narrow_tile<KIND, DCH, WX, NS>(sm, X1p, nrm1, X2p, nrm2, n1,
+                                 static_cast<int64_t>(blockIdx.x) * (64 * NS), m_begin, m_end, V,
+                                 C, ldv, P + static_cast<int64_t>(blockIdx.y) * n1 * WX, cnorm,
+                                 cdot);
+}
+
+// ---- persistent batched launch -------------------------------------------------
+// Every product of a batch (independent problems of different sizes, output
+// widths and hyperparameters; same kernel family and feature count) is cut
+// into workgroup tiles (problem, 64*NS-row block, X2 split); a fixed grid of
+// workgroups takes tiles from an atomic counter until none are left, so one
+// launch covers all problems x classes and keeps every CU busy while small
+// problems finish.  The counter is cleared by a kernel before each launch.
+template <int KIND, int DCH, int NS>
+__global__ void __launch_bounds__(256)
+kv_batched_persistent(const BatchProblem* __restrict__ probs, int np, int64_t ntiles,
+                      int* __restrict__ counter) {
+  __shared__ __align__(16) unsigned char smem_raw[sizeof(NarrowSmem<DCH, WV>)];
+  __shared__ int64_t s_tile;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(reinterpret_cast<unsigned long long*>(counter), 1ull);
+    __syncthreads();
+    const int64_t t = s_tile;
+    __syncthreads();
+    if (t >= ntiles) break;
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (probs[mid].tile_begin <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const BatchProblem& pb = probs[lo];
+    const int64_t local = t - pb.tile_begin;
+    const int64_t rb = local % pb.gx, sp = local / pb.gx;
+    const int64_t m_begin = sp * pb.cols_per_split;
+    const int64_t m_end = m_begin + pb.cols_per_split < pb.n2 ? m_begin + pb.cols_per_split : pb.n2;
+    float* P = pb.P + sp * pb.n1 * pb.W;
+    switch (pb.W) {
+#define IGP_BW(K)                                                                              \
+  case K:                                                                                      \
+    narrow_tile<KIND, DCH, K, NS>(*reinterpret_cast<NarrowSmem<DCH, K>*>(smem_raw), pb.X1p,    \
+                                  pb.nrm1, pb.X2p, pb.nrm2, pb.n1, rb * (64 * NS), m_begin,      \
+                                  m_end, pb.V, pb.C, pb.ldv, P, pb.cnorm, pb.cdot);            \
+    break;
+      IGP_BW(1) IGP_BW(2) IGP_BW(3) IGP_BW(4) IGP_BW(5) IGP_BW(6) IGP_BW(7) IGP_BW(8)
+#undef IGP_BW
+      default: break;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_counter(int* c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) reinterpret_cast<unsigned long long*>(c)[0] = 0ull;
+}
+
+__global__ void kv_reduce_batched(const BatchProblem* __restrict__ probs, int np,
+                                  int64_t total) {
+  for (int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; idx < total;
+       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (probs[mid].out_begin <= idx) lo = mid;
+      else hi = mid - 1;
+    }
+    const BatchProblem& pb = probs[lo];
+    const int64_t e = idx - pb.out_begin;
+    const int64_t n = e / pb.W;
+    const int w = static_cast<int>(e % pb.W);
+    const int64_t stride = pb.n1 * pb.W;
+    const float* q = pb.P + n * pb.W + w;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int sp = 0;
+    for (; sp + 4 <= pb.nsplit; sp += 4) {
+      s0 += q[sp * stride];
+      s1 += q[(sp + 1) * stride];
+      s2 += q[(sp + 2) * stride];
+      s3 += q[(sp + 3) * stride];
+    }
+    for (; sp < pb.nsplit; ++sp) s0 += q[sp * stride];
+    pb.Out[(w / pb.C) * pb.ldo + n * pb.C + (w % pb.C)] = pb.os * ((s0 + s1) + (s2 + s3));
   }
 }
 
@@ -471,6 +577,15 @@ int launch_kind(const Plan& pl, const float* X1p, const float* n1p, const float*
 
 }  // namespace
 
+float kv_kappa(int kind) {
+  switch (kind) {
+    case IGP_RBF: return kappa<IGP_RBF>();
+    case IGP_MATERN12: return kappa<IGP_MATERN12>();
+    case IGP_MATERN32: return kappa<IGP_MATERN32>();
+    default: return kappa<IGP_MATERN52>();
+  }
+}
+
 bool mfma_f32_supported(int kind, int64_t d) {
   return kind != IGP_MATERN12 && d >= 1 && d <= 128;
 }
@@ -545,6 +660,59 @@ int kv_mfma_f32_launch(const KVProblem& p, const float* X1p, const float* n1p,
       set_error("Matern-1/2 runs on the direct-difference kernel");
       return IGP_EUNSUPPORTED;
   }
+}
+
+namespace {
+template <int KIND, int NS>
+void launch_batched_kind(int dch, const BatchProblem* dprobs, int np, int64_t ntiles, int* counter,
+                         int grid, hipStream_t s) {
+  switch (dch) {
+    case 1: kv_batched_persistent<KIND, 1, NS><<<grid, 256, 0, s>>>(dprobs, np, ntiles, counter); break;
+    default: kv_batched_persistent<KIND, 2, NS><<<grid, 256, 0, s>>>(dprobs, np, ntiles, counter); break;
+  }
+}
+}  // namespace
+
+bool batched_supported(int kind, int64_t d, int64_t W) {
+  return kind != IGP_MATERN12 && d >= 1 && d <= 32 && W >= 1 && W <= WV;
+}
+
+void batched_plan(int64_t n1, int64_t n2, int64_t W, int ns, int64_t split_rows,
+                  BatchProblem* bp) {
+  const int64_t tiles = ceil_div(n2, TN);
+  bp->gx = static_cast<int>(ceil_div(n1, 64 * ns));
+  int64_t per = std::max<int64_t>(1, ceil_div(split_rows, TN));
+  if (tiles == 0) per = 1;
+  bp->cols_per_split = per * TN;
+  bp->nsplit = tiles == 0 ? 0 : static_cast<int>(ceil_div(n2, bp->cols_per_split));
+  (void)W;
+}
+
+int kv_batched_run(int kind, int dch, int ns, const BatchProblem* dprobs, int np, int64_t ntiles,
+                   int64_t total_out, int* counter, hipStream_t s) {
+  k_zero_counter<<<1, 64, 0, s>>>(counter);
+  if (ntiles > 0) {
+    const int grid = static_cast<int>(std::min<int64_t>(ntiles, 256 * 4));
+    if (ns == 1) {
+      switch (kind) {
+        case IGP_RBF: launch_batched_kind<IGP_RBF, 1>(dch, dprobs, np, ntiles, counter, grid, s); break;
+        case IGP_MATERN32: launch_batched_kind<IGP_MATERN32, 1>(dch, dprobs, np, ntiles, counter, grid, s); break;
+        default: launch_batched_kind<IGP_MATERN52, 1>(dch, dprobs, np, ntiles, counter, grid, s); break;
+      }
+    } else {
+      switch (kind) {
+        case IGP_RBF: launch_batched_kind<IGP_RBF, 2>(dch, dprobs, np, ntiles, counter, grid, s); break;
+        case IGP_MATERN32: launch_batched_kind<IGP_MATERN32, 2>(dch, dprobs, np, ntiles, counter, grid, s); break;
+        default: launch_batched_kind<IGP_MATERN52, 2>(dch, dprobs, np, ntiles, counter, grid, s); break;
+      }
+    }
+  }
+  if (total_out > 0) {
+    const int blocks = static_cast<int>(std::min<int64_t>(ceil_div(total_out, 256), 4096));
+    kv_reduce_batched<<<blocks, 256, 0, s>>>(dprobs, np, total_out);
+  }
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
 }
 
 }  // namespace igp

@@ -73,6 +73,13 @@ __global__ void k_fill_unit(T* __restrict__ s, int64_t n, int64_t idx) {
 }
 
 template <typename T>
+__global__ void k_fill_zero(T* __restrict__ a, int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    a[i] = T(0);
+}
+
+template <typename T>
 __global__ void k_copy(const T* __restrict__ a, T* __restrict__ b, int64_t n) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
@@ -405,6 +412,13 @@ int fill_unit(T* sv, int64_t n, int64_t idx, hipStream_t s) {
 }
 
 template <typename T>
+int fill_zero(T* a, int64_t n, hipStream_t s) {
+  k_fill_zero<T><<<grid_for(n), NT, 0, s>>>(a, n);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template <typename T>
 int copy_vec(const T* a, T* b, int64_t n, hipStream_t s) {
   k_copy<T><<<grid_for(n), NT, 0, s>>>(a, b, n);
   IGP_CHECK_LAUNCH();
@@ -545,6 +559,7 @@ int predict_epilogue(const T* A, int64_t lda, int64_t nrows, int ncols, double o
   template int action_cg<T>(const T*, const double*, T*, int64_t, hipStream_t);                \
   template int fill_unit<T>(T*, int64_t, int64_t, hipStream_t);                                \
   template int copy_vec<T>(const T*, T*, int64_t, hipStream_t);                                \
+  template int fill_zero<T>(T*, int64_t, hipStream_t);                                         \
   template int add_vec<T>(const T*, const T*, T*, int64_t, hipStream_t);                       \
   template int gemv_t<T>(const T*, int64_t, int64_t, int, const T*, double*, double*,         \
                          hipStream_t);                                                         \

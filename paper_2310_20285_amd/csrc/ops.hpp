@@ -62,6 +62,32 @@ int kv_mfma_f32_launch(const KVProblem& p, const float* X1p, const float* n1p,
                        const float* X2p, const float* n2p, float* P, size_t P_bytes,
                        hipStream_t s, int* nsplit_out);
 
+// Batched persistent product (kv_mfma.hip): one launch covers the narrow
+// products (W <= 8) of many independent problems.
+struct BatchProblem {
+  const float* X1p;
+  const float* nrm1;
+  const float* X2p;
+  const float* nrm2;
+  int64_t n1, n2;
+  const float* V;
+  int64_t ldv;
+  int C, W;
+  float* P;                 // split partials: nsplit * n1 * W floats
+  int64_t cols_per_split;
+  int nsplit, gx;
+  float cnorm, cdot, os;
+  float* Out;
+  int64_t ldo;
+  int64_t tile_begin;       // prefix over problems of gx * nsplit
+  int64_t out_begin;        // prefix over problems of n1 * W
+};
+bool batched_supported(int kind, int64_t d, int64_t W);
+void batched_plan(int64_t n1, int64_t n2, int64_t W, int ns, int64_t split_rows, BatchProblem* bp);
+int kv_batched_run(int kind, int dch, int ns, const BatchProblem* dprobs, int np, int64_t ntiles,
+                   int64_t total_out, int* counter, hipStream_t s);
+float kv_kappa(int kind);
+
 // BF16 matrix-core kernel product (kv_bf16.hip): rows rounded to BF16, padded
 // to a multiple of 32 features, norms of the rounded rows.
 int64_t bf16_padded_dim(int64_t d);
@@ -114,6 +140,8 @@ template <typename T>
 int fill_unit(T* s_out, int64_t n, int64_t idx, hipStream_t s);
 template <typename T>
 int copy_vec(const T* src, T* dst, int64_t n, hipStream_t s);
+template <typename T>
+int fill_zero(T* a, int64_t n, hipStream_t s);
 template <typename T>
 int add_vec(const T* a, const T* b, T* out, int64_t n, hipStream_t s);
 // y[b] = sum_i Q[b*ldq + i] z[i], b < ncols

@@ -1,0 +1,131 @@
+"""Plain FP32 PyTorch form of IterNCGP on the GPU -- the comparison baseline
+that ``bench.py`` times beside the HIP library.
+
+The same Algorithms 1-3 (IterNCGP outer loop, IterGP with residual actions,
+virtual solver run with compression) written with stock PyTorch operations:
+products with K formed blockwise as |x|^2 + |x'|^2 - 2 X X'^T -> kernel ->
+@ V (tiles of K discarded after use), the residual formed with a fresh
+product as Algorithm 2 prints it, FP64 only for scalars and the B x B
+eigendecomposition, TF32 disabled.  Problems run one at a time and
+prediction requests are served one by one.  This is a baseline, not the
+product path.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+LOG2E = 1.4426950408889634
+
+
+class PlainIterNCGP:
+    def __init__(self, X: torch.Tensor, y: torch.Tensor, C: int, kind: str, lengthscale: float,
+                 outputscale: float, j_max: int = 200, rank_limit: int = 100,
+                 tol_abs: float = 1e-5, tol_rel: float = 1e-5, block: int = 4096):
+        torch.backends.cuda.matmul.allow_tf32 = False
+        self.X = X.float().contiguous()
+        self.y = y.long()
+        self.N, self.C = X.shape[0], C
+        self.kind, self.ell, self.os = kind, lengthscale, outputscale
+        self.j_max, self.R = j_max, rank_limit
+        self.tol_abs, self.tol_rel = tol_abs, tol_rel
+        self.block = block
+        self.sq = (self.X * self.X).sum(1)
+        n = self.N * C
+        dev = X.device
+        self.f = torch.zeros(n, device=dev)
+        self.S = torch.zeros(n, 0, device=dev)
+        self.T = torch.zeros(n, 0, device=dev)
+        self.v = torch.zeros(n, device=dev)
+        self.Q = torch.zeros(n, 0, device=dev)
+
+    def kfun(self, r2):
+        r2 = r2.clamp_min(0) / (self.ell * self.ell)
+        if self.kind == "rbf":
+            return self.os * torch.exp(-0.5 * r2)
+        r = torch.sqrt(r2)
+        if self.kind == "matern12":
+            return self.os * torch.exp(-r)
+        if self.kind == "matern32":
+            a = math.sqrt(3.0) * r
+            return self.os * (1 + a) * torch.exp(-a)
+        a = math.sqrt(5.0) * r
+        return self.os * (1 + a + a * a / 3.0) * torch.exp(-a)
+
+    def apply_K(self, V: torch.Tensor, X1: torch.Tensor = None) -> torch.Tensor:
+        """(K_X(X1, X) (x) I_C) V for CN-ordered V of shape (N*C,) or (N*C, b)."""
+        X1 = self.X if X1 is None else X1
+        sq1 = (X1 * X1).sum(1)
+        Vm = V.view(self.N, self.C, -1).reshape(self.N, -1)
+        out = torch.empty(X1.shape[0], Vm.shape[1], device=V.device)
+        for i0 in range(0, X1.shape[0], self.block):
+            xb = X1[i0:i0 + self.block]
+            r2 = sq1[i0:i0 + self.block, None] + self.sq[None, :] - 2.0 * (xb @ self.X.T)
+            out[i0:i0 + self.block] = self.kfun(r2) @ Vm
+        return out.reshape(-1) if V.dim() == 1 else out.reshape(X1.shape[0] * self.C, -1)
+
+    def winv(self, pi: torch.Tensor, V: torch.Tensor) -> torch.Tensor:
+        """W^+ V per point: P diag(1/pi) P with P = I - 11^T/C."""
+        b = V.view(self.N, self.C, -1)
+        u = b - b.mean(1, keepdim=True)
+        w = u / pi.view(self.N, self.C, 1)
+        return (w - w.mean(1, keepdim=True)).reshape(V.shape)
+
+    def newton_step(self) -> dict:
+        N, C = self.N, self.C
+        F = self.f.view(N, C)
+        pi = torch.softmax(F, dim=1)
+        onehot = torch.nn.functional.one_hot(self.y, C).float()
+        rhs = self.f + self.winv(pi.reshape(-1), (onehot - pi).reshape(-1))
+        # Algorithm 3
+        if self.S.shape[1] > 0:
+            M = (self.S.T @ (self.T + self.winv(pi.reshape(-1), self.S))).double()
+            lam, U = torch.linalg.eigh(0.5 * (M + M.T))
+            lam, U = lam.flip(0), U.flip(1)
+            B = lam.numel()
+            keep = lam > lam[0] * B * 2.220446049250313e-16 if lam[0] > 0 else lam < -1
+            lam, U = lam[keep], U[:, keep]
+            if self.R >= 0:
+                lam, U = lam[: self.R], U[:, : self.R]
+            Uf = U.float()
+            self.S, self.T = self.S @ Uf, self.T @ Uf
+            self.Q = self.S / torch.sqrt(lam).float()[None, :]
+        else:
+            self.Q = self.S.clone()
+        v = self.Q @ (self.Q.T @ rhs)
+        thresh = max(self.tol_abs, self.tol_rel * float(rhs.double().norm()))
+        j = 0
+        while j < self.j_max:
+            r = rhs - self.apply_K(v) - self.winv(pi.reshape(-1), v)
+            rn = float(r.double().norm())
+            if rn < thresh:
+                break
+            j += 1
+            s = r / rn
+            alpha = float(s.double() @ r.double())
+            t = self.apply_K(s)
+            self.S = torch.cat([self.S, s[:, None]], 1)
+            self.T = torch.cat([self.T, t[:, None]], 1)
+            z = t + self.winv(pi.reshape(-1), s)
+            d = s - self.Q @ (self.Q.T @ z)
+            eta = float(z.double() @ d.double())
+            if eta <= 0:
+                self.S, self.T = self.S[:, :-1], self.T[:, :-1]
+                j -= 1
+                break
+            self.Q = torch.cat([self.Q, (d / math.sqrt(eta))[:, None]], 1)
+            v = v + (alpha / eta) * d
+        self.v = v
+        fnew = self.apply_K(v)
+        rel = float((fnew - self.f).double().norm() / fnew.double().norm())
+        self.f = fnew
+        return {"iters": j, "buffer_cols": self.S.shape[1], "rel_change": rel}
+
+    def predict(self, Xs: torch.Tensor):
+        mean = self.apply_K(self.v, Xs).view(-1, self.C)
+        A = self.apply_K(self.Q, Xs) if self.Q.shape[1] else torch.zeros(Xs.shape[0] * self.C, 0,
+                                                                           device=Xs.device)
+        var = (self.os - (A * A).sum(1)).view(-1, self.C)
+        probs = torch.softmax(mean / torch.sqrt(1 + math.pi / 8 * var.clamp_min(0)), dim=1)
+        return mean, var, probs
