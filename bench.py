@@ -84,9 +84,14 @@ def main():
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain FP32 PyTorch comparison")
     ap.add_argument("--precision", default=None, choices=["fp32", "fp64", "bf16"])
-    ap.add_argument("--workload", default="gpc16", choices=["gpc16", "image", "batched"],
+    ap.add_argument("--workload", default="gpc16",
+                    choices=["gpc16", "image", "batched", "serving"],
                     help="gpc16: N=20000 D=16 C=5 (default); image: N=60000 D=784 C=10 BF16; "
-                         "batched: 64 independent problems in one persistent launch")
+                         "batched: 64 independent problems in one persistent launch; "
+                         "serving: request stream against a fitted N=100000 D=32 C=10 model")
+    ap.add_argument("--requests", type=int, default=160, help="serving: stream length")
+    ap.add_argument("--load", type=float, nargs="+", default=[0.5],
+                    help="serving: arrival rates as fractions of the measured capacity")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only; multi-GPU runs are not part of this build",
@@ -105,6 +110,8 @@ def main():
         return bench_image(args)
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "serving":
+        return bench_serving(args)
     args.precision = args.precision or "fp32"
     KV_INSTANCE = "kv_mfma_f32_narrow<3,1,5,2>"   # Matern-5/2, D <= 16, W = 5, 2 strips
     w = datagen.config2()
@@ -394,6 +401,157 @@ def bench_image(args):
         "newton": [{k: (round(v_, 6) if isinstance(v_, float) else v_) for k, v_ in i.items()
                     if k in ("iters", "buffer_cols", "rel_change", "psi")} for i in infos],
     }
+    print(json.dumps(res))
+
+
+FP32_MFMA_PEAK_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
+
+
+def bench_serving(args):
+    """Serving workload.  Fitted model: N=100000, D=32, C=10, RBF (lengthscale
+    sqrt(2D), outputscale 1), IterNCGP-CG j<=100, R=100, 3 Newton steps, then
+    compressed to B=100 directions (Algorithm 3).  Stream: Poisson arrivals,
+    95% predictive queries of ceil(exp(U(0, ln 4096))) test points, 5% new fits
+    with N ~ U{2000..50000} (j<=50, R=50, 2 Newton steps), HBM budget 8 GB.
+
+    capacity = requests/s with the whole stream submitted at once.  The stream
+    is then replayed in real time at each --load fraction of that capacity, by
+    the continuous-batching server and by the plain FP32 form serving the same
+    fitted state one request at a time (FIFO).  value = p99 latency of the
+    predictive queries at the first --load fraction."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_2310_20285_amd import api
+    from paper_2310_20285_amd.serving import Server, latency_stats
+
+    prec = args.precision or "fp32"
+    dev = torch.device("cuda:0")
+    w = datagen.config5_model()
+    X = torch.tensor(w.X, dtype=torch.float32, device=dev)
+    y = torch.tensor(w.y, dtype=torch.int32, device=dev)
+    B = 100
+    m = api.IterNCGP(X, y, w.C, w.kernel, w.lengthscale, w.outputscale, policy="cg", j_max=100,
+                     rank_limit=100, recycle=True, precision=prec, residual_mode="recurrence",
+                     max_buffer=200)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fit_info = [m.newton_step() for _ in range(3)]
+    kept = m.compress(B)
+    fit_s = time.perf_counter() - t0
+
+    fit_cfg = dict(policy="cg", j_max=50, rank_limit=50, recycle=True, precision=prec,
+                   residual_mode="recurrence", max_buffer=100)
+    reqs = datagen.config5_requests(n_requests=args.requests, rate_hz=100.0, D=w.D)
+    for r in reqs:
+        if r["kind"] == "fit":
+            f = datagen.config5_fit(r["seed"], r["n"], D=w.D, C=w.C)
+            r.update(X=f.X, y=f.y, C=w.C, kernel=f.kernel, lengthscale=f.lengthscale,
+                     outputscale=f.outputscale)
+    budget = 8 * 10**9
+
+    def server():
+        return Server(m, budget_bytes=budget, max_batch_rows=8192, slots=2, fit_workers=2,
+                      fit_config=dict(fit_cfg, steps=2))
+
+    # warm-up: a short stream through a server (kernels, allocator, threads)
+    server().replay(reqs[:12], realtime=False)
+    torch.cuda.synchronize()
+    srv = server()
+    tk = srv.replay(reqs, realtime=False)
+    makespan = max(t.t_done for t in tk)
+    capacity = len(reqs) / makespan
+    n_fit = sum(1 for r in reqs if r["kind"] == "fit")
+    pts = sum(r["X"].shape[0] for r in reqs if r["kind"] == "predict")
+
+    def scaled(frac):
+        scale = 100.0 / (frac * capacity)
+        return [dict(r, t=r["t"] * scale) for r in reqs]
+
+    runs = []
+    for frac in args.load:
+        srv = server()
+        tk = srv.replay(scaled(frac), realtime=True)
+        span = max(t.t_done for t in tk)
+        runs.append({"load": frac, "rate_rps": frac * capacity,
+                     "predict": latency_stats(tk, "predict"), "fit": latency_stats(tk, "fit"),
+                     "refused": sum(1 for t in tk if t.status == "refused"),
+                     "batches": srv.batches,
+                     "mean_batch_rows": float(np.mean(srv.batch_rows)) if srv.batch_rows else 0.0,
+                     "queries_per_s": (len(reqs) - n_fit) / span,
+                     "test_points_per_s": pts / span,
+                     "newton_steps_per_s": 2 * n_fit / span})
+        if frac == args.load[0]:
+            first = tk
+    # alone vs in the mix, on a few of the served queries (tolerance: bitwise)
+    mism = 0
+    for t in [t for t in first if t.kind == "predict"][:8]:
+        mean, var, probs = m.predict(torch.tensor(t.payload["X"], device=dev))
+        for key, ref in (("mean", mean), ("var", var), ("probs", probs)):
+            mism += int(not np.array_equal(t.result[key], ref.cpu().numpy()))
+
+    # the dominant kernel: K(X*, X) [v | Q] at 4096 test points
+    Xs = torch.tensor(np.random.default_rng(9).standard_normal((4096, w.D)), dtype=torch.float32,
+                      device=dev)
+    ws = torch.empty(m.predict_ws_bytes(4096), dtype=torch.uint8, device=dev)
+    out = torch.empty((3, 4096 * w.C), device=dev)
+    st = torch.cuda.current_stream()
+    for _ in range(2):
+        m.predict_into(Xs, out[0], out[1], out[2], ws, st)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(st)
+    reps = 10
+    for _ in range(reps):
+        m.predict_into(Xs, out[0], out[1], out[2], ws, st)
+    ev[1].record(st)
+    ev[1].synchronize()
+    pred_ms = ev[0].elapsed_time(ev[1]) / reps
+    flops = 2.0 * 4096 * w.N * (2 * w.D + w.C * (1 + kept))
+    tflops = flops / (pred_ms / 1e3) / 1e12
+    peak = FP32_MFMA_PEAK_TFLOPS if prec == "fp32" else BF16_MFMA_PEAK_TFLOPS
+
+    res = {
+        "metric": "p99 predict latency (served stream at %.2gx capacity)" % args.load[0],
+        "value": runs[0]["predict"].get("p99_ms"),
+        "unit": "ms",
+        "n_gpus": 1, "steps": len(reqs), "warmup": 12,
+        "ms_per_step": makespan / len(reqs) * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "bf16": "bf16"}[prec], "data": "synthetic",
+        "config": {"workload": "serving: fitted N=100000 D=32 C=10 rbf, B=100; Poisson stream "
+                               "95% predict (1..4096 points, log-uniform) / 5% fits "
+                               "(N~U{2000..50000}, j<=50 R=50, 2 steps); HBM budget 8 GB",
+                   "requests": len(reqs), "fits": n_fit, "test_points": pts,
+                   "precision": prec, "budget_bytes": budget},
+        "served_model": {"fit_s": fit_s, "kept_directions": kept,
+                         "iters": [i["iters"] for i in fit_info]},
+        "capacity_rps": capacity,
+        "runs": runs,
+        "alone_vs_mix_mismatches": mism,
+        "roofline": {"bound": "mfma", "achieved": tflops, "peak": peak, "unit": "TFLOP/s",
+                     "frac": tflops / peak, "traffic": None,
+                     "kernel": "prediction at 4096 points: K(X*,X) v and K(X*,X) Q "
+                               "(2 N* N (2D + C(1+B)) flops)",
+                     "avg_call_ms": pred_ms},
+    }
+    if not args.no_plain:
+        from plain_fp32 import PlainIterNCGP, fifo_replay
+        pm = PlainIterNCGP(X, y, w.C, w.kernel, w.lengthscale, w.outputscale)
+        pm.v = m.view(1).float()
+        pm.Q = m.view(2).float().t().contiguous()
+        pr = {}
+        for frac in args.load[:1]:
+            rec = fifo_replay(pm, scaled(frac), dict(j_max=50, rank_limit=50), 2)
+            lat = np.array([d - a for k, a, d in rec if k == "predict"]) * 1e3
+            flat = np.array([d - a for k, a, d in rec if k == "fit"]) * 1e3
+            pr = {"load": frac, "predict": {"p50_ms": float(np.percentile(lat, 50)),
+                                            "p99_ms": float(np.percentile(lat, 99))},
+                  "fit": {"p50_ms": float(np.percentile(flat, 50)) if flat.size else None,
+                          "p99_ms": float(np.percentile(flat, 99)) if flat.size else None},
+                  "span_s": max(d for _, _, d in rec)}
+        pr["p99_ratio_plain_over_library"] = pr["predict"]["p99_ms"] / res["value"]
+        res["plain_fp32_fifo"] = pr
     print(json.dumps(res))
 
 

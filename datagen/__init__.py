@@ -231,6 +231,13 @@ def config5_requests(seed: int = 5, n_requests: int = 256, rate_hz: float = 100.
     return reqs
 
 
+def config5_fit(seed: int, N: int, D: int = 32, C: int = 10, F: int = 1024) -> Workload:
+    """Training data of one fit request of the serving stream (same prior as
+    the served model: RBF with lengthscale sqrt(2D), outputscale 1)."""
+    return gp_classification(seed, N, D, C, "rbf", math.sqrt(2.0 * D), 1.0, F=F,
+                             name=f"config5-fit[{N}]")
+
+
 def gmm(seed: int = 6, per_class: int = 10000, per_class_test: int = 1000,
         C: int = 10, D: int = 3, mix_seed: int = 1234) -> Workload:
     """3-D Gaussian mixture (the paper's large-scale classification data).

@@ -192,6 +192,15 @@ int itergp_set_user_actions(igp_model* m, const void* actions, int64_t ncols, in
  * Host control flow; synchronises the model's stream.  info may be NULL. */
 int itergp_newton_step(igp_model* m, igp_step_info* info);
 
+/* Compression of the fitted state for serving (Algorithm 3 alone): the
+ * virtual solver run over the stored buffer S, T with W(f)^+ at the current
+ * iterate f, keeping at most rank_limit eigendirections (-1: all above the
+ * tiny-eigenvalue floor).  Replaces S, T and the root Q by S U, T U and
+ * S U Lambda^{-1/2}; v and f are unchanged, so the predictive mean is too and
+ * the marginal variance uses the compressed root.  kept (nullable) receives
+ * the number of columns left.  Synchronises the model's stream. */
+int itergp_compress(igp_model* m, int32_t rank_limit, int32_t* kept);
+
 /* Predictive mean, marginal variance and probit class probabilities at Xs
  * (paper eqs. for m_{i,j} and k_{i,j}; probit as in its large-scale
  * experiment), using the v and root Q of the last Newton step:

@@ -172,6 +172,8 @@ class NewtonRecord:
     rhs: np.ndarray        # yhat - m of the step
     info: SolveInfo
     rel_change: float
+    S: Optional[np.ndarray] = None   # action buffer S and T = K S after the step
+    T: Optional[np.ndarray] = None
 
 
 def iterncgp(apply_K: Apply, y: np.ndarray, C: int, steps: int,
@@ -202,7 +204,7 @@ def iterncgp(apply_K: Apply, y: np.ndarray, C: int, steps: int,
         g_old, g_new = F.reshape(-1), F_new.reshape(-1)
         nn = float(np.linalg.norm(g_new))
         rel = float(np.linalg.norm(g_new - g_old) / nn) if nn > 0 else float("inf")
-        recs.append(NewtonRecord(F_new, v, Q, rhs, info, rel))
+        recs.append(NewtonRecord(F_new, v, Q, rhs, info, rel, S, T))
         F = F_new
         if outer_tol is not None and rel <= outer_tol:
             break

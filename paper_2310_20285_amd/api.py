@@ -111,6 +111,12 @@ def solver_config(policy="cg", j_max=100, rank_limit=-1, recycle=True, tol_abs=1
                           rm, int(max_buffer), 0)
 
 
+def state_bytes(N: int, D: int, C: int, **cfg) -> int:
+    """itergp_state_bytes: the arena a model of this shape and configuration needs."""
+    c = solver_config(**cfg)
+    return int(L.load().itergp_state_bytes(int(N), int(D), int(C), ct.byref(c)))
+
+
 class IterNCGP:
     """A model handle: itergp_init / itergp_newton_step / itergp_predict."""
 
@@ -130,6 +136,7 @@ class IterNCGP:
         if nbytes == 0:
             raise ValueError("invalid model configuration")
         self.arena = torch.empty(int(nbytes), dtype=torch.uint8, device=X.device)
+        self.stream = torch.cuda.current_stream()   # the model runs all its work here
         self.handle = ct.c_void_p()
         L.check(self.lib.itergp_init(ct.byref(self.handle), ct.byref(self.kp),
                                      ct.byref(self.cfg), _ptr(X), _ptr(y), self.N, self.D,
@@ -167,7 +174,7 @@ class IterNCGP:
         ptr, rows, cols, ld = ct.c_void_p(), ct.c_int64(), ct.c_int64(), ct.c_int64()
         L.check(self.lib.itergp_get_view(self.handle, which, ct.byref(ptr), ct.byref(rows),
                                          ct.byref(cols), ct.byref(ld)))
-        torch.cuda.synchronize()
+        self.stream.synchronize()
         esz = torch.empty(0, dtype=self.dtype).element_size()
         off = (ptr.value or 0) - self.arena.data_ptr()
         if cols.value == 0:
@@ -178,24 +185,52 @@ class IterNCGP:
         if which in (L.IGP_VIEW_Q, L.IGP_VIEW_S, L.IGP_VIEW_T):
             out = torch.stack([full[b * ld.value: b * ld.value + rows.value]
                                for b in range(cols.value)])
-            return out.clone()
+            return out
         if which == L.IGP_VIEW_X:
             return full[: rows.value * cols.value].view(rows.value, cols.value).clone()
         return full[: rows.value].clone()
 
-    def predict(self, Xs: torch.Tensor, var: bool = True, probs: bool = True):
+    def compress(self, rank_limit: int) -> int:
+        """itergp_compress: Algorithm 3 over the stored buffer; returns the columns kept."""
+        kept = ct.c_int32()
+        L.check(self.lib.itergp_compress(self.handle, int(rank_limit), ct.byref(kept)))
+        return kept.value
+
+    def predict_ws_bytes(self, Ns: int) -> int:
+        return int(self.lib.itergp_predict_ws_bytes(self.handle, int(Ns)))
+
+    def predict(self, Xs: torch.Tensor, var: bool = True, probs: bool = True,
+                ws: Optional[torch.Tensor] = None, stream=None):
+        """Asynchronous on ``stream`` (default: the current stream).  ``ws``, when
+        given, is a uint8 workspace of at least predict_ws_bytes(len(Xs)) bytes."""
         _need(Xs, self.dtype, "Xs")
         Ns = Xs.shape[0]
         mean = torch.empty(Ns * self.C, dtype=self.dtype, device=Xs.device)
         v = torch.empty_like(mean) if var else None
         p = torch.empty_like(mean) if (probs and var) else None
         wsb = self.lib.itergp_predict_ws_bytes(self.handle, Ns)
-        ws = torch.empty(max(int(wsb), 1), dtype=torch.uint8, device=Xs.device)
+        if ws is None:
+            ws = torch.empty(max(int(wsb), 1), dtype=torch.uint8, device=Xs.device)
+        elif ws.numel() < wsb:
+            raise ValueError(f"predict workspace of {ws.numel()} bytes, {wsb} needed")
+        st = _stream() if stream is None else ct.c_void_p(stream.cuda_stream)
         L.check(self.lib.itergp_predict(self.handle, _ptr(Xs), Ns, _ptr(mean), _ptr(v), _ptr(p),
-                                        _ptr(ws), wsb, _stream()))
+                                        _ptr(ws), wsb, st))
         shape = (Ns, self.C)
         return (mean.view(shape), None if v is None else v.view(shape),
                 None if p is None else p.view(shape))
+
+    def predict_into(self, Xs: torch.Tensor, mean: torch.Tensor, var: Optional[torch.Tensor],
+                     probs: Optional[torch.Tensor], ws: torch.Tensor, stream) -> None:
+        """itergp_predict into caller-owned buffers (Ns*C elements each, var and
+        probs nullable), asynchronous on ``stream``; nothing is allocated."""
+        Ns = Xs.shape[0]
+        for t in (mean, var, probs):
+            if t is not None and (t.numel() < Ns * self.C or not t.is_contiguous()):
+                raise ValueError("output buffers must be contiguous with Ns*C elements")
+        L.check(self.lib.itergp_predict(self.handle, _ptr(Xs), Ns, _ptr(mean), _ptr(var),
+                                        _ptr(probs), _ptr(ws), ws.numel(),
+                                        ct.c_void_p(stream.cuda_stream)))
 
 
 def newton_step_batched(models, ws: Optional[torch.Tensor] = None):

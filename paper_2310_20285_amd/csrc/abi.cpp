@@ -160,6 +160,13 @@ int itergp_newton_step(igp_model* m, igp_step_info* info) {
   });
 }
 
+int itergp_compress(igp_model* m, int32_t rank_limit, int32_t* kept) {
+  return guarded([&]() -> int {
+    IGP_REQUIRE(m, "NULL model");
+    return m->compress(rank_limit, kept);
+  });
+}
+
 size_t itergp_predict_ws_bytes(const igp_model* m, int64_t Ns) {
   if (!m || Ns < 0) return 0;
   return m->predict_ws_bytes(Ns);

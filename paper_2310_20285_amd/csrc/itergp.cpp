@@ -471,9 +471,34 @@ struct Model final : igp_model {
     return phase_finish(info_out);
   }
 
+  // Algorithm 3 on its own: the virtual solver run over the stored buffer with
+  // W^+ taken at the current f (the point the predictive covariance is formed
+  // at), keeping at most rank_limit directions; v and f are left as they are.
+  int compress(int32_t rank_limit, int32_t* kept) override {
+    clear_error();
+    IGP_REQUIRE(rank_limit >= -1, "rank_limit must be >= -1");
+    int nblk = 0;
+    // pi at f; the pseudo-targets it also forms go to scratch (rhs is kept)
+    IGP_TRY(softmax_pi_rhs<T>(L.f, y, N, C, L.pi, L.wv, L.part, &nblk, stream));
+    st = StepState{};
+    const int saved = cfg.rank_limit;
+    cfg.rank_limit = rank_limit;
+    int rc = phase_vsr_gram();
+    if (rc == IGP_OK) rc = phase_vsr_fetch();
+    if (rc == IGP_OK) rc = phase_vsr_host();
+    if (rc == IGP_OK) rc = phase_vsr_apply();
+    cfg.rank_limit = saved;
+    IGP_TRY(rc);
+    IGP_CHECK_HIP(hipStreamSynchronize(stream));
+    if (kept) *kept = ncols;
+    return IGP_OK;
+  }
+
+  // prediction launches split X2 independently of the number of test rows, so
+  // a test row's result does not depend on which rows share its launch
   size_t kvws_for(int64_t n1, int64_t nb) const {
-    return prepared ? kv_ws_bytes_prepared(n1, N, D, C, nb, cfg.precision)
-                    : kv_ws_bytes(n1, N, D, C, nb, cfg.precision);
+    return prepared ? kv_ws_bytes_prepared(n1, N, D, C, nb, cfg.precision, true)
+                    : kv_ws_bytes(n1, N, D, C, nb, cfg.precision, true);
   }
 
   size_t predict_ws_bytes(int64_t Ns) const override {
@@ -515,10 +540,14 @@ struct Model final : igp_model {
       IGP_TRY(prep_rows_any(cfg.precision, reinterpret_cast<const float*>(Xs), Ns, D, L.centre,
                             xsp, nsp, s));
     }
-    IGP_TRY(kv_launch(kv_problem(Xs, Ns, L.v, 1, n, mean, Ns * C, xsp, nsp), ws1, w1, s));
+    KVProblem pm = kv_problem(Xs, Ns, L.v, 1, n, mean, Ns * C, xsp, nsp);
+    pm.fixed_split = true;
+    IGP_TRY(kv_launch(pm, ws1, w1, s));
     if (var_) {
       if (ncols > 0) {
-        IGP_TRY(kv_launch(kv_problem(Xs, Ns, L.Q, ncols, ld, A, Ns * C, xsp, nsp), ws2, w2, s));
+        KVProblem pv = kv_problem(Xs, Ns, L.Q, ncols, ld, A, Ns * C, xsp, nsp);
+        pv.fixed_split = true;
+        IGP_TRY(kv_launch(pv, ws2, w2, s));
       }
       IGP_TRY(predict_epilogue<T>(A, Ns * C, Ns * C, ncols, kp.outputscale, mean, Ns, C,
                                   static_cast<T*>(var_), static_cast<T*>(probs_), s));

@@ -128,7 +128,7 @@ struct SplitPlan {
   int64_t cols_per_split;
 };
 
-SplitPlan plan_valu(int64_t n1, int64_t n2, int64_t W) {
+SplitPlan plan_valu(int64_t n1, int64_t n2, int64_t W, bool fixed = false) {
   SplitPlan p{};
   p.wc = W <= 4 ? 4 : (W <= 8 ? 8 : 16);
   p.gx = static_cast<int>(ceil_div(n1, TM));
@@ -142,7 +142,7 @@ SplitPlan plan_valu(int64_t n1, int64_t n2, int64_t W) {
     p.cols_per_split = TN;
     return p;
   }
-  p.cols_per_split = ceil_div(tiles, want) * TN;
+  p.cols_per_split = fixed ? FIXED_SPLIT_ROWS : ceil_div(tiles, want) * TN;
   p.nsplit = static_cast<int>(ceil_div(n2, p.cols_per_split));
   return p;
 }
@@ -170,7 +170,7 @@ void launch_valu_kind(const KVProblem& p, const SplitPlan& sp, T* P, hipStream_t
 template <typename T>
 int launch_valu(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t s) {
   const int64_t W = p.C * p.nb;
-  SplitPlan sp = plan_valu(p.n1, p.n2, W);
+  SplitPlan sp = plan_valu(p.n1, p.n2, W, p.fixed_split);
   const size_t need = static_cast<size_t>(sp.nsplit) * p.n1 * W * sizeof(T);
   if (need > ws_bytes) {
     set_error("kernel-product workspace too small: need %zu bytes, have %zu", need, ws_bytes);
@@ -232,18 +232,20 @@ size_t prep_bytes(int precision, int64_t n1, int64_t n2, int64_t d) {
 }  // namespace
 
 size_t kv_ws_bytes_prepared(int64_t n1, int64_t n2, int64_t d, int64_t C, int64_t nb,
-                            int precision) {
+                            int precision, bool fixed) {
   const int64_t W = C * nb;
-  SplitPlan sp = plan_valu(n1, n2, W);
+  SplitPlan sp = plan_valu(n1, n2, W, fixed);
   const size_t elt = precision == IGP_FP64 ? sizeof(double) : sizeof(float);
   size_t b = static_cast<size_t>(sp.nsplit) * n1 * W * elt;
-  if (precision == IGP_FP32 && d <= 128) b = std::max(b, mfma_f32_partial_bytes(n1, n2, d, W));
-  if (precision == IGP_BF16) b = bf16_partial_bytes(n1, n2, W);
+  if (precision == IGP_FP32 && d <= 128)
+    b = std::max(b, mfma_f32_partial_bytes(n1, n2, d, W, fixed));
+  if (precision == IGP_BF16) b = bf16_partial_bytes(n1, n2, W, fixed);
   return align_up(b + 256);
 }
 
-size_t kv_ws_bytes(int64_t n1, int64_t n2, int64_t d, int64_t C, int64_t nb, int precision) {
-  size_t b = kv_ws_bytes_prepared(n1, n2, d, C, nb, precision);
+size_t kv_ws_bytes(int64_t n1, int64_t n2, int64_t d, int64_t C, int64_t nb, int precision,
+                   bool fixed) {
+  size_t b = kv_ws_bytes_prepared(n1, n2, d, C, nb, precision, fixed);
   if (precision == IGP_BF16 || (precision == IGP_FP32 && d <= 128))
     b += align_up(prep_bytes(precision, n1, n2, d) + 256);
   return b;
@@ -254,8 +256,8 @@ int launch_mfma_path(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t 
   const int64_t W = p.C * p.nb;
   const bool bf = p.precision == IGP_BF16;
   Carver cv(ws, ws_bytes);
-  const size_t pbytes = bf ? bf16_partial_bytes(p.n1, p.n2, W)
-                           : mfma_f32_partial_bytes(p.n1, p.n2, p.d, W);
+  const size_t pbytes = bf ? bf16_partial_bytes(p.n1, p.n2, W, p.fixed_split)
+                           : mfma_f32_partial_bytes(p.n1, p.n2, p.d, W, p.fixed_split);
   float* P = cv.take<float>(pbytes / sizeof(float) + 1);
   const void *X1p = p.X1p, *X2p = p.X2p;
   const float *n1p = p.norm1, *n2p = p.norm2;

@@ -243,7 +243,7 @@ struct PlanB {
   int64_t cols_per_split;
 };
 
-PlanB plan_bf16(int64_t n1, int64_t n2, int64_t W) {
+PlanB plan_bf16(int64_t n1, int64_t n2, int64_t W, bool fixed = false) {
   PlanB p{};
   p.gx = static_cast<int>(ceil_div(n1, BT));
   p.gz = static_cast<int>(ceil_div(W, VT));
@@ -256,7 +256,7 @@ PlanB plan_bf16(int64_t n1, int64_t n2, int64_t W) {
   // enough workgroups for ~4 per CU, without splitting below 8 tiles
   int64_t want = ceil_div(1024, static_cast<int64_t>(p.gx) * p.gz);
   want = std::max<int64_t>(1, std::min<int64_t>(want, ceil_div(tiles, 8)));
-  p.cols_per_split = ceil_div(tiles, want) * BT;
+  p.cols_per_split = fixed ? FIXED_SPLIT_ROWS : ceil_div(tiles, want) * BT;
   p.nsplit = static_cast<int>(ceil_div(n2, p.cols_per_split));
   return p;
 }
@@ -265,8 +265,8 @@ PlanB plan_bf16(int64_t n1, int64_t n2, int64_t W) {
 
 int64_t bf16_padded_dim(int64_t d) { return ceil_div(d, KC) * KC; }
 
-size_t bf16_partial_bytes(int64_t n1, int64_t n2, int64_t W) {
-  PlanB pl = plan_bf16(n1, n2, W);
+size_t bf16_partial_bytes(int64_t n1, int64_t n2, int64_t W, bool fixed) {
+  PlanB pl = plan_bf16(n1, n2, W, fixed);
   return static_cast<size_t>(pl.nsplit) * n1 * W * sizeof(float);
 }
 
@@ -283,7 +283,7 @@ int prep_rows_bf16(const float* X, int64_t n, int64_t d, const float* centre, vo
 int kv_bf16_launch(const KVProblem& p, const void* X1b, const float* n1p, const void* X2b,
                    const float* n2p, float* P, size_t P_bytes, hipStream_t s, int* nsplit_out) {
   const int64_t W = p.C * p.nb;
-  PlanB pl = plan_bf16(p.n1, p.n2, W);
+  PlanB pl = plan_bf16(p.n1, p.n2, W, p.fixed_split);
   *nsplit_out = pl.nsplit;
   if (static_cast<size_t>(pl.nsplit) * p.n1 * W * sizeof(float) > P_bytes) {
     set_error("kernel-product workspace too small for the split partials");

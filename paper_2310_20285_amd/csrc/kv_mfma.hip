@@ -509,7 +509,7 @@ struct Plan {
   int64_t cols_per_split;
 };
 
-Plan plan_mfma(int64_t n1, int64_t n2, int64_t d, int64_t W) {
+Plan plan_mfma(int64_t n1, int64_t n2, int64_t d, int64_t W, bool fixed = false) {
   Plan p{};
   p.dch = static_cast<int>(ceil_div(d, 16));
   p.narrow = W <= WV && p.dch <= 2;
@@ -526,7 +526,7 @@ Plan plan_mfma(int64_t n1, int64_t n2, int64_t d, int64_t W) {
   int64_t want = ceil_div(8192, static_cast<int64_t>(p.gx) * p.gz);
   if (want < 1) want = 1;
   if (want > tiles) want = tiles;
-  p.cols_per_split = ceil_div(tiles, want) * TN;
+  p.cols_per_split = fixed ? FIXED_SPLIT_ROWS : ceil_div(tiles, want) * TN;
   p.nsplit = static_cast<int>(ceil_div(n2, p.cols_per_split));
   return p;
 }
@@ -590,8 +590,8 @@ bool mfma_f32_supported(int kind, int64_t d) {
   return kind != IGP_MATERN12 && d >= 1 && d <= 128;
 }
 
-size_t mfma_f32_partial_bytes(int64_t n1, int64_t n2, int64_t d, int64_t W) {
-  Plan pl = plan_mfma(n1, n2, d, W);
+size_t mfma_f32_partial_bytes(int64_t n1, int64_t n2, int64_t d, int64_t W, bool fixed) {
+  Plan pl = plan_mfma(n1, n2, d, W, fixed);
   return static_cast<size_t>(pl.nsplit) * n1 * W * sizeof(float);
 }
 
@@ -627,7 +627,7 @@ int kv_mfma_f32_launch(const KVProblem& p, const float* X1p, const float* n1p,
                        const float* X2p, const float* n2p, float* P, size_t P_bytes,
                        hipStream_t s, int* nsplit_out) {
   const int64_t W = p.C * p.nb;
-  Plan pl = plan_mfma(p.n1, p.n2, p.d, W);
+  Plan pl = plan_mfma(p.n1, p.n2, p.d, W, p.fixed_split);
   *nsplit_out = pl.nsplit;
   if (static_cast<size_t>(pl.nsplit) * p.n1 * W * sizeof(float) > P_bytes) {
     set_error("kernel-product workspace too small for the split partials");

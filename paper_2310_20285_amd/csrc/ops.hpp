@@ -14,6 +14,7 @@ struct igp_model {
   virtual int set_user_actions(const void* a, int64_t ncols, int64_t ld) = 0;
   virtual int set_profiling(int enable) = 0;
   virtual int get_profile(igp_profile* out) const = 0;
+  virtual int compress(int32_t rank_limit, int32_t* kept) = 0;
 };
 
 namespace igp {
@@ -40,19 +41,24 @@ struct KVProblem {
   const float* norm1 = nullptr;
   const float* norm2 = nullptr;
   const int* skip = nullptr;
+  // split the X2 rows into fixed 4096-row ranges regardless of n1, so that each
+  // output row is summed in the same order whatever rows share the launch
+  bool fixed_split = false;
 };
+constexpr int64_t FIXED_SPLIT_ROWS = 4096;
 
-size_t kv_ws_bytes(int64_t n1, int64_t n2, int64_t d, int64_t C, int64_t nb, int precision);
+size_t kv_ws_bytes(int64_t n1, int64_t n2, int64_t d, int64_t C, int64_t nb, int precision,
+                   bool fixed_split = false);
 // bytes of ws needed when X1p/X2p/norms are supplied (partials only)
 size_t kv_ws_bytes_prepared(int64_t n1, int64_t n2, int64_t d, int64_t C, int64_t nb,
-                            int precision);
+                            int precision, bool fixed_split = false);
 int kv_launch(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t s);
 // whether (precision, kind, d) runs on the matrix cores from prepared rows
 bool kv_uses_prepared(int precision, int kind, int64_t d);
 
 // FP32 matrix-core kernel product (kv_mfma.hip)
 bool mfma_f32_supported(int kind, int64_t d);
-size_t mfma_f32_partial_bytes(int64_t n1, int64_t n2, int64_t d, int64_t W);
+size_t mfma_f32_partial_bytes(int64_t n1, int64_t n2, int64_t d, int64_t W, bool fixed = false);
 int64_t padded_dim(int64_t d);
 int column_mean_f32(const float* X, int64_t n, int64_t d, float* mean, double* part,
                     int64_t part_cap, hipStream_t s);
@@ -91,7 +97,7 @@ float kv_kappa(int kind);
 // BF16 matrix-core kernel product (kv_bf16.hip): rows rounded to BF16, padded
 // to a multiple of 32 features, norms of the rounded rows.
 int64_t bf16_padded_dim(int64_t d);
-size_t bf16_partial_bytes(int64_t n1, int64_t n2, int64_t W);
+size_t bf16_partial_bytes(int64_t n1, int64_t n2, int64_t W, bool fixed = false);
 int prep_rows_bf16(const float* X, int64_t n, int64_t d, const float* centre, void* Xb,
                    float* norms, hipStream_t s);
 int kv_bf16_launch(const KVProblem& p, const void* X1b, const float* n1p, const void* X2b,

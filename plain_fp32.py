@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import math
 
+import numpy as np
 import torch
 
 LOG2E = 1.4426950408889634
@@ -129,3 +130,36 @@ class PlainIterNCGP:
         var = (self.os - (A * A).sum(1)).view(-1, self.C)
         probs = torch.softmax(mean / torch.sqrt(1 + math.pi / 8 * var.clamp_min(0)), dim=1)
         return mean, var, probs
+
+
+def fifo_replay(served: PlainIterNCGP, requests, fit_config: dict, steps: int,
+                realtime: bool = True):
+    """Serve a request stream one request at a time in arrival order (no
+    batching, no overlap): predictive queries against ``served``, fits as new
+    PlainIterNCGP models.  Returns (kind, arrival, done) per request, times in
+    seconds from the start of the replay."""
+    import time
+    dev = served.X.device
+    t0 = time.perf_counter()
+    out = []
+    for r in sorted(requests, key=lambda q: q["t"]):
+        ta = r["t"] if realtime else 0.0
+        if realtime:
+            while time.perf_counter() - t0 < ta:
+                time.sleep(2e-5)
+        if r["kind"] == "predict":
+            Xs = torch.from_numpy(np.ascontiguousarray(r["X"], dtype=np.float32)).to(dev)
+            mean, var, probs = served.predict(Xs)
+            torch.stack([mean, var, probs]).cpu()
+        else:
+            X = torch.from_numpy(np.ascontiguousarray(r["X"], dtype=np.float32)).to(dev)
+            y = torch.from_numpy(np.ascontiguousarray(r["y"])).to(dev)
+            m = PlainIterNCGP(X, y, r["C"], r["kernel"], r["lengthscale"], r["outputscale"],
+                              **fit_config)
+            for _ in range(steps):
+                m.newton_step()
+            m.f.cpu()
+            del m
+        torch.cuda.synchronize()
+        out.append((r["kind"], ta, time.perf_counter() - t0))
+    return out
