@@ -7,18 +7,26 @@
 // 2 x1.x2 is the distance of the rounded points up to FP32 accumulation and the
 // kernel matrix stays the (PSD) kernel matrix of those points.
 //
-// Workgroup tile: 128 rows of X1 (n) x 128 rows of X2 (m); four waves in a
-// 2 x 2 arrangement, each holding a 64 x 64 block of D^T = X2 X1^T in sixteen
-// 16 x 16 accumulators.  Feature chunks of 32 stream through LDS (rows padded
-// to 80 bytes: conflict-free 128-bit reads), double-buffered through
-// registers.  After the feature loop the kernel function is applied to the
-// accumulators and the contraction with V runs on the same matrix cores: the
-// accumulator of block (m, n) already holds K[n][m] in the A-operand lane
-// layout (the transposed-tile arrangement), and a pair of m-blocks gives the
-// 8 k-values of one 16x16x32 instruction.  K and V are split into BF16 high and
-// low parts and the contraction takes hi*hi + hi*lo + lo*hi, which keeps about
-// 16 significant bits of each factor.
+// Workgroup tile: 256 rows of X1 (n) x 256 rows of X2 (m), eight waves in a
+// 2 (m) x 4 (n) arrangement, each holding a 128 x 64 block of D^T = X2 X1^T in
+// 32 accumulators of 16 x 16.  Feature chunks of 32 stream through LDS (rows
+// padded to 80 bytes: conflict-free 128-bit fragment reads), double-buffered
+// through registers; the loads are branch-free (rows past the end are clamped
+// to the last row: their products meet V = 0 or are never stored).  After the
+// feature loop the kernel function is applied to the accumulators and the
+// contraction with V runs on the same matrix cores: the accumulator of block
+// (m, n) already holds K[n][m] in the A-operand lane layout (the
+// transposed-tile arrangement), and a pair of m-blocks gives the 8 k-values of
+// one 16x16x32 instruction.  K and V are split into BF16 high and low parts
+// and the contraction takes hi*hi + hi*lo + lo*hi, which keeps about 16
+// significant bits of each factor.
+//
+// The grid is one-dimensional and remapped so that the workgroups the hardware
+// deals to one XCD (ids congruent mod 8) take consecutive tiles: the same X2
+// range with neighbouring X1 blocks, which then share that XCD's L2.
 #include <algorithm>
+#include <cstdint>
+#include <type_traits>
 
 #include "ops.hpp"
 
@@ -31,11 +39,9 @@ typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr float LOG2E_B = 1.4426950408889634f;
-constexpr int BT = 128;      // rows of X1 and of X2 per workgroup tile
 constexpr int KC = 32;       // features per chunk
 constexpr int RS = 40;       // LDS row stride in bf16 (80 bytes)
-constexpr int VT = 16;       // output columns per workgroup (W <= 16 per launch column group)
-constexpr int VS = BT + 8;   // LDS row stride of the transposed V tile (bf16)
+constexpr int VT = 16;       // output columns per workgroup
 
 template <int KIND>
 __device__ inline float kt_bf(float t) {
@@ -58,68 +64,91 @@ __device__ inline float kt_bf(float t) {
 __device__ inline __bf16 to_bf(float x) { return static_cast<__bf16>(x); }
 __device__ inline float from_bf(__bf16 x) { return static_cast<float>(x); }
 
+constexpr int WM = 2, WN = 4;          // waves along m and n
+constexpr int TMW = 128, TNW = 64;     // rows of m and n per wave
+constexpr int BM = WM * TMW;           // X2 rows per tile (256)
+constexpr int BN = WN * TNW;           // X1 rows per workgroup (256)
+constexpr int NT = 64 * WM * WN;       // threads per workgroup (512)
+constexpr int MB = TMW / 16, NB = TNW / 16;
+constexpr int VS = BM + 8;             // LDS row stride of the transposed V tile (bf16)
+constexpr int QA = BM * 4 / NT, QB = BN * 4 / NT;   // 16-byte pieces staged per thread
+
 template <int KIND>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(NT)
 kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
                const __bf16* __restrict__ X2b, const float* __restrict__ nrm2, int64_t n1,
                int64_t n2, int DPB, const float* __restrict__ V, int C, int W, int64_t ldv,
-               float* __restrict__ P, int64_t cols_per_split, float cnorm, float cdot,
-               const int* skip) {
+               float* __restrict__ P, int64_t cols_per_split, int gx, int nsplit, float cnorm,
+               float cdot, const int* skip) {
   if (skip && *skip) return;
-  __shared__ __align__(16) __bf16 sA[2][BT * RS];   // X2 chunk (m rows)
-  __shared__ __align__(16) __bf16 sB[2][BT * RS];   // X1 chunk (n rows)
+  __shared__ __align__(16) __bf16 sA[2][BM * RS];   // X2 chunk (m rows)
+  __shared__ __align__(16) __bf16 sB[2][BN * RS];   // X1 chunk (n rows)
   __shared__ __align__(16) __bf16 sVh[VT * VS];     // V^T tile, high part
   __shared__ __align__(16) __bf16 sVl[VT * VS];     // V^T tile, low part
-  __shared__ float sN2[BT];
-  __shared__ f4 sRed[2][64 * 4];                    // cross-wave reduction of the output
+  __shared__ __align__(16) float sN2[BM];
+
+  // ids congruent mod 8 run on one XCD: give each XCD a contiguous tile range
+  const int nwg = gridDim.x, bid = blockIdx.x;
+  const int xcd = bid & 7, loc = bid >> 3;
+  const int per = (nwg + 7) >> 3, rem = nwg & 7;
+  const int lin = (rem == 0 || xcd < rem) ? xcd * per + loc
+                                          : rem * per + (xcd - rem) * (per - 1) + loc;
+  const int bx = lin % gx;
+  const int by = (lin / gx) % nsplit;
+  const int bz = lin / gx / nsplit;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, r = lane & 15;
-  const int wn = wave & 1, wm = wave >> 1;
-  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * BT;
-  const int w0 = blockIdx.z * VT;
-  const int64_t m_begin = static_cast<int64_t>(blockIdx.y) * cols_per_split;
+  const int wn = wave % WN, wm = wave / WN;
+  const int64_t n0 = static_cast<int64_t>(bx) * BN;
+  const int w0 = bz * VT;
+  const int64_t m_begin = static_cast<int64_t>(by) * cols_per_split;
   const int64_t m_end = m_begin + cols_per_split < n2 ? m_begin + cols_per_split : n2;
   const int nks = DPB / KC;
 
-  // this lane's X1 norms: n = n0 + wn*64 + nb*16 + r
-  float n1v[4];
+  // this lane's X1 norms: n = n0 + wn*TNW + nb*16 + r
+  float n1v[NB];
 #pragma unroll
-  for (int nb = 0; nb < 4; ++nb) {
-    const int64_t n = n0 + wn * 64 + nb * 16 + r;
+  for (int nb = 0; nb < NB; ++nb) {
+    const int64_t n = n0 + wn * TNW + nb * 16 + r;
     n1v[nb] = n < n1 ? nrm1[n] * cnorm : 0.0f;
   }
-  f4 out[4];
+  f4 out[NB];
 #pragma unroll
-  for (int nb = 0; nb < 4; ++nb) out[nb] = f4{0, 0, 0, 0};
+  for (int nb = 0; nb < NB; ++nb) out[nb] = f4{0, 0, 0, 0};
 
-  // staging: chunk element e = tid + q*256 (q < 2) is (row = e / 4, 16-byte piece e % 4)
-  u4 pa[2], pb[2];
+  // staging: piece e = tid + q*NT is (row e / 4, 16-byte piece e % 4) of a chunk
+  u4 pa[QA], pb[QB];
   auto fetch = [&](int64_t m0, int k0) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int e = tid + q * 256;
-      const int row = e >> 2, piece = e & 3;
-      const int64_t m = m0 + row, n = n0 + row;
-      pa[q] = m < m_end ? *reinterpret_cast<const u4*>(X2b + m * DPB + k0 + piece * 8)
-                        : u4{0, 0, 0, 0};
-      pb[q] = n < n1 ? *reinterpret_cast<const u4*>(X1b + n * DPB + k0 + piece * 8)
-                     : u4{0, 0, 0, 0};
+    for (int q = 0; q < QA; ++q) {
+      const int e = tid + q * NT;
+      const int64_t m = m0 + (e >> 2) < m_end ? m0 + (e >> 2) : m_end - 1;
+      pa[q] = *reinterpret_cast<const u4*>(X2b + m * DPB + k0 + (e & 3) * 8);
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int e = tid + q * NT;
+      const int64_t n = n0 + (e >> 2) < n1 ? n0 + (e >> 2) : n1 - 1;
+      pb[q] = *reinterpret_cast<const u4*>(X1b + n * DPB + k0 + (e & 3) * 8);
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int e = tid + q * 256;
-      const int row = e >> 2, piece = e & 3;
-      *reinterpret_cast<u4*>(&sA[buf][row * RS + piece * 8]) = pa[q];
-      *reinterpret_cast<u4*>(&sB[buf][row * RS + piece * 8]) = pb[q];
+    for (int q = 0; q < QA; ++q) {
+      const int e = tid + q * NT;
+      *reinterpret_cast<u4*>(&sA[buf][(e >> 2) * RS + (e & 3) * 8]) = pa[q];
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int e = tid + q * NT;
+      *reinterpret_cast<u4*>(&sB[buf][(e >> 2) * RS + (e & 3) * 8]) = pb[q];
     }
   };
 
-  for (int64_t m0 = m_begin; m0 < m_end; m0 += BT) {
-    // V^T tile (hi / lo) and X2 norms of this m tile
-    for (int e = tid; e < BT * VT; e += 256) {
+  for (int64_t m0 = m_begin; m0 < m_end; m0 += BM) {
+    // V^T tile (hi / lo) and X2 norms of this m tile; V = 0 past the end
+    for (int e = tid; e < BM * VT; e += NT) {
       const int m = e / VT, wl = e % VT;
       const int64_t gm = m0 + m;
       const int w = w0 + wl;
@@ -129,15 +158,15 @@ kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
       sVh[wl * VS + m] = hi;
       sVl[wl * VS + m] = to_bf(v - from_bf(hi));
     }
-    for (int e = tid; e < BT; e += 256) {
+    for (int e = tid; e < BM; e += NT) {
       const int64_t gm = m0 + e;
       sN2[e] = gm < m_end ? nrm2[gm] * cnorm : 0.0f;
     }
-    f4 acc[4][4];
+    f4 acc[MB][NB];
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = f4{0, 0, 0, 0};
+      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f4{0, 0, 0, 0};
 
     fetch(m0, 0);
     stash(0);
@@ -146,27 +175,27 @@ kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
     for (int ks = 0; ks < nks; ++ks) {
       const bool more = ks + 1 < nks;
       if (more) fetch(m0, (ks + 1) * KC);
-      bf8 a[4], b[4];
+      bf8 b[NB];
 #pragma unroll
-      for (int mb = 0; mb < 4; ++mb)
-        a[mb] = *reinterpret_cast<const bf8*>(&sA[buf][(wm * 64 + mb * 16 + r) * RS + g * 8]);
+      for (int nb = 0; nb < NB; ++nb)
+        b[nb] = *reinterpret_cast<const bf8*>(&sB[buf][(wn * TNW + nb * 16 + r) * RS + g * 8]);
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb)
-        b[nb] = *reinterpret_cast<const bf8*>(&sB[buf][(wn * 64 + nb * 16 + r) * RS + g * 8]);
+      for (int mb = 0; mb < MB; ++mb) {
+        const bf8 a =
+            *reinterpret_cast<const bf8*>(&sA[buf][(wm * TMW + mb * 16 + r) * RS + g * 8]);
 #pragma unroll
-      for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb)
-          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], b[nb], acc[mb][nb], 0, 0, 0);
+        for (int nb = 0; nb < NB; ++nb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[mb][nb], 0, 0, 0);
+      }
       if (more) stash(buf ^ 1);
       __syncthreads();
       buf ^= 1;
     }
-    // kernel transform + contraction: acc[mb][nb][v] = D^T[m = wm*64 + mb*16 + 4g + v][n = .. + r]
+    // kernel transform + contraction: acc[mb][nb][v] = D^T[m = wm*TMW + mb*16 + 4g + v][n = .. + r]
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
+    for (int p = 0; p < MB / 2; ++p) {
       const int mba = 2 * p, mbb = 2 * p + 1;
-      const int ma = wm * 64 + mba * 16 + 4 * g, mbm = wm * 64 + mbb * 16 + 4 * g;
+      const int ma = wm * TMW + mba * 16 + 4 * g, mbm = wm * TMW + mbb * 16 + 4 * g;
       const f4 na = *reinterpret_cast<const f4*>(&sN2[ma]);
       const f4 nbv = *reinterpret_cast<const f4*>(&sN2[mbm]);
       bf8 vh, vl;
@@ -178,7 +207,7 @@ kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
         vl[4 + t] = sVl[r * VS + mbm + t];
       }
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
+      for (int nb = 0; nb < NB; ++nb) {
         bf8 kh, kl;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -195,25 +224,34 @@ kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
         out[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kl, vh, out[nb], 0, 0, 0);
       }
     }
-    __syncthreads();   // sVh / sVl / sN2 are rewritten by the next m tile
+    __syncthreads();   // sVh / sVl / sN2 / sA / sB are rewritten by the next m tile
   }
-  // out[nb][j] = Out[n = n0 + wn*64 + nb*16 + 4g + j][w = w0 + r]; add the two wm halves
-  if (wm == 1) {
+  // out[nb][j] = Out[n = n0 + wn*TNW + nb*16 + 4g + j][w = w0 + r]; add the WM wave rows
+  // in LDS (sA is free after the last m tile)
+  f4* red = reinterpret_cast<f4*>(&sA[0][0]);
+  static_assert(WN * NB * 64 * sizeof(f4) <= sizeof(sA[0]), "reduction fits in one A buffer");
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) sRed[wn][nb * 64 + lane] = out[nb];
+  for (int s = 1; s < WM; ++s) {
+    if (wm == s) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) red[(wn * NB + nb) * 64 + lane] = out[nb];
+    }
+    __syncthreads();
+    if (wm == 0) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) out[nb] += red[(wn * NB + nb) * 64 + lane];
+    }
+    __syncthreads();
   }
-  __syncthreads();
   if (wm == 0) {
     const int w = w0 + r;
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-      const f4 o = out[nb] + sRed[wn][nb * 64 + lane];
+    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int64_t n = n0 + wn * 64 + nb * 16 + 4 * g + j;
-        if (n < n1 && w < W) P[(static_cast<int64_t>(blockIdx.y) * n1 + n) * W + w] = o[j];
+        const int64_t n = n0 + wn * TNW + nb * 16 + 4 * g + j;
+        if (n < n1 && w < W) P[(static_cast<int64_t>(by) * n1 + n) * W + w] = out[nb][j];
       }
-    }
   }
 }
 
@@ -244,19 +282,21 @@ struct PlanB {
 };
 
 PlanB plan_bf16(int64_t n1, int64_t n2, int64_t W, bool fixed = false) {
+  static_assert(FIXED_SPLIT_ROWS % BM == 0, "fixed split is a whole number of tiles");
   PlanB p{};
-  p.gx = static_cast<int>(ceil_div(n1, BT));
+  p.gx = static_cast<int>(ceil_div(n1, BN));
   p.gz = static_cast<int>(ceil_div(W, VT));
-  const int64_t tiles = ceil_div(n2, BT);
+  const int64_t tiles = ceil_div(n2, BM);
   if (tiles == 0) {
     p.nsplit = 0;
-    p.cols_per_split = BT;
+    p.cols_per_split = BM;
     return p;
   }
-  // enough workgroups for ~4 per CU, without splitting below 8 tiles
-  int64_t want = ceil_div(1024, static_cast<int64_t>(p.gx) * p.gz);
-  want = std::max<int64_t>(1, std::min<int64_t>(want, ceil_div(tiles, 8)));
-  p.cols_per_split = fixed ? FIXED_SPLIT_ROWS : ceil_div(tiles, want) * BT;
+  // about 16 workgroups per CU (one resident at a time), without splitting
+  // below 4 tiles
+  int64_t want = ceil_div(4096, static_cast<int64_t>(p.gx) * p.gz);
+  want = std::max<int64_t>(1, std::min<int64_t>(want, ceil_div(tiles, 4)));
+  p.cols_per_split = fixed ? FIXED_SPLIT_ROWS : ceil_div(tiles, want) * BM;
   p.nsplit = static_cast<int>(ceil_div(n2, p.cols_per_split));
   return p;
 }
@@ -289,7 +329,7 @@ int kv_bf16_launch(const KVProblem& p, const void* X1b, const float* n1p, const 
     set_error("kernel-product workspace too small for the split partials");
     return IGP_ENOMEM;
   }
-  if (pl.nsplit == 0) return IGP_OK;
+  if (pl.nsplit == 0 || pl.gx == 0 || pl.gz == 0) return IGP_OK;
   const double inv_l2 = 1.0 / (p.kp.lengthscale * p.kp.lengthscale);
   float kap;
   switch (p.kp.kind) {
@@ -300,29 +340,27 @@ int kv_bf16_launch(const KVProblem& p, const void* X1b, const float* n1p, const 
   }
   const float cnorm = static_cast<float>(kap * inv_l2);
   const float cdot = static_cast<float>(-2.0 * kap * inv_l2);
-  dim3 grid(pl.gx, pl.nsplit, pl.gz);
+  const int64_t nwg = static_cast<int64_t>(pl.gx) * pl.nsplit * pl.gz;
+  if (nwg > INT32_MAX) {
+    set_error("kernel product too large for one launch");
+    return IGP_EINVAL;
+  }
+  const dim3 grid(static_cast<unsigned>(nwg));
   const int DPB = static_cast<int>(bf16_padded_dim(p.d));
   const __bf16* A1 = static_cast<const __bf16*>(X1b);
   const __bf16* A2 = static_cast<const __bf16*>(X2b);
   const float* V = static_cast<const float*>(p.V);
   const int C = static_cast<int>(p.C), Wi = static_cast<int>(W);
+  auto go = [&](auto kind) {
+    kv_bf16_kernel<decltype(kind)::value><<<grid, NT, 0, s>>>(
+        A1, n1p, A2, n2p, p.n1, p.n2, DPB, V, C, Wi, p.ldv, P, pl.cols_per_split, pl.gx,
+        pl.nsplit, cnorm, cdot, p.skip);
+  };
   switch (p.kp.kind) {
-    case IGP_RBF:
-      kv_bf16_kernel<IGP_RBF><<<grid, 256, 0, s>>>(A1, n1p, A2, n2p, p.n1, p.n2, DPB, V, C, Wi,
-                                                   p.ldv, P, pl.cols_per_split, cnorm, cdot, p.skip);
-      break;
-    case IGP_MATERN12:
-      kv_bf16_kernel<IGP_MATERN12><<<grid, 256, 0, s>>>(A1, n1p, A2, n2p, p.n1, p.n2, DPB, V, C, Wi,
-                                                        p.ldv, P, pl.cols_per_split, cnorm, cdot, p.skip);
-      break;
-    case IGP_MATERN32:
-      kv_bf16_kernel<IGP_MATERN32><<<grid, 256, 0, s>>>(A1, n1p, A2, n2p, p.n1, p.n2, DPB, V, C, Wi,
-                                                        p.ldv, P, pl.cols_per_split, cnorm, cdot, p.skip);
-      break;
-    default:
-      kv_bf16_kernel<IGP_MATERN52><<<grid, 256, 0, s>>>(A1, n1p, A2, n2p, p.n1, p.n2, DPB, V, C, Wi,
-                                                        p.ldv, P, pl.cols_per_split, cnorm, cdot, p.skip);
-      break;
+    case IGP_RBF: go(std::integral_constant<int, IGP_RBF>{}); break;
+    case IGP_MATERN12: go(std::integral_constant<int, IGP_MATERN12>{}); break;
+    case IGP_MATERN32: go(std::integral_constant<int, IGP_MATERN32>{}); break;
+    default: go(std::integral_constant<int, IGP_MATERN52>{}); break;
   }
   IGP_CHECK_LAUNCH();
   return IGP_OK;
