@@ -10,8 +10,9 @@
 // Workgroup tile: 256 rows of X1 (n) x 256 rows of X2 (m), eight waves in a
 // 2 (m) x 4 (n) arrangement, each holding a 128 x 64 block of D^T = X2 X1^T in
 // 32 accumulators of 16 x 16.  Feature chunks of 32 stream through LDS (rows
-// padded to 80 bytes: conflict-free 128-bit fragment reads), double-buffered
-// through registers; the loads are branch-free (rows past the end are clamped
+// padded to 80 bytes: conflict-free 128-bit fragment reads), double-buffered,
+// each chunk loaded into registers one iteration ahead and written to LDS
+// while the previous chunk is multiplied; the loads are branch-free (rows past the end are clamped
 // to the last row: their products meet V = 0 or are never stored).  After the
 // feature loop the kernel function is applied to the accumulators and the
 // contraction with V runs on the same matrix cores: the accumulator of block
@@ -168,13 +169,17 @@ kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f4{0, 0, 0, 0};
 
+    // chunk ks+1 (loaded during the previous iteration) goes to the other
+    // buffer before the products of chunk ks, so its LDS writes overlap them;
+    // the loads of chunk ks+2 are issued right after
     fetch(m0, 0);
     stash(0);
     __syncthreads();
+    if (nks > 1) fetch(m0, KC);
     int buf = 0;
     for (int ks = 0; ks < nks; ++ks) {
-      const bool more = ks + 1 < nks;
-      if (more) fetch(m0, (ks + 1) * KC);
+      if (ks + 1 < nks) stash(buf ^ 1);
+      if (ks + 2 < nks) fetch(m0, (ks + 2) * KC);
       bf8 b[NB];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
@@ -187,7 +192,6 @@ kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
         for (int nb = 0; nb < NB; ++nb)
           acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[mb][nb], 0, 0, 0);
       }
-      if (more) stash(buf ^ 1);
       __syncthreads();
       buf ^= 1;
     }

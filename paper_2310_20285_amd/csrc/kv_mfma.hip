@@ -603,10 +603,11 @@ int column_mean_f32(const float* X, int64_t n, int64_t d, float* mean, double* p
     IGP_CHECK_HIP(hipMemsetAsync(mean, 0, d * sizeof(float), s));
     return IGP_OK;
   }
-  int64_t nblk = std::min<int64_t>(ceil_div(n, 256), std::max<int64_t>(part_cap / d, 1));
+  // ~64 rows per block and 256 threads across the columns: short FP64 chains
+  int64_t nblk = std::min<int64_t>(ceil_div(n, 64), std::max<int64_t>(part_cap / d, 1));
   const int64_t rows_per = ceil_div(n, nblk);
   nblk = ceil_div(n, rows_per);
-  k_col_partial<<<static_cast<unsigned>(nblk), 64, 0, s>>>(X, n, static_cast<int>(d), rows_per, part);
+  k_col_partial<<<static_cast<unsigned>(nblk), 256, 0, s>>>(X, n, static_cast<int>(d), rows_per, part);
   k_col_finish<<<static_cast<unsigned>(ceil_div(d, 64)), 64, 0, s>>>(part, static_cast<int>(nblk),
                                                                       static_cast<int>(d), n, mean);
   IGP_CHECK_LAUNCH();

@@ -1,12 +1,20 @@
 """Profiling driver for rocprofv3.
 
-    python -m paper_2310_20285_amd.profile_driver [--reps 20] [--copy-mib 256]
+    python paper_2310_20285_amd/profile_driver.py [--workload gpc16|image|predict]
+                                                  [--reps 20] [--copy-mib 256]
 
-Runs the fused K.v product of the benchmark workload (N=20000, D=16, C=5,
-Matern-5/2, FP32; the product the Newton step issues) ``--reps`` times via
-glm_kernel_matmul, then one device-to-device copy of ``--copy-mib`` MiB.  The
-copy is a transfer of known size: its FETCH_SIZE / WRITE_SIZE readings give
-the factor that converts the counters of the K.v kernel to bytes.
+Workloads (each ends with one device-to-device copy of ``--copy-mib`` MiB, a
+transfer of known size whose FETCH_SIZE / WRITE_SIZE readings give the factor
+that converts the counters of the other kernels to bytes):
+
+* gpc16   the fused K.v product of the N=20000, D=16, C=5 Matern-5/2 workload
+          in FP32 (the product each solver iteration issues), ``--reps`` times
+          via glm_kernel_matmul;
+* image   the fused K.v product of the image-shaped N=60000, D=784, C=10 RBF
+          workload with the BF16 distance GEMM, ``--reps`` times;
+* predict prediction (mean, variance, probit) at 4096 test points against a
+          fitted N=100000, D=32, C=10 RBF model compressed to 100 directions
+          (the serving workload's model), ``--reps`` times.
 """
 from __future__ import annotations
 
@@ -21,31 +29,54 @@ if ROOT not in sys.path:
 
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="gpc16", choices=["gpc16", "image", "predict"])
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--copy-mib", type=int, default=256)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--precision", default=None, choices=["fp32", "bf16"])
     args = ap.parse_args()
 
+    import numpy as np
     import torch
 
     import datagen
     from paper_2310_20285_amd import api
 
-    w = datagen.config2()
-    X = torch.tensor(w.X, dtype=torch.float32, device="cuda")
-    v = torch.randn(w.N * w.C, dtype=torch.float32, device="cuda")
-    out = None
-    for _ in range(args.reps):
-        out = api.glm_kernel_matmul(X, X, v, w.C, w.kernel, w.lengthscale, w.outputscale,
-                                    args.precision, out=out)
+    if args.workload in ("gpc16", "image"):
+        w = datagen.config2() if args.workload == "gpc16" else datagen.config3(Ns=1000)
+        prec = args.precision or ("fp32" if args.workload == "gpc16" else "bf16")
+        X = torch.tensor(w.X, dtype=torch.float32, device="cuda")
+        v = torch.randn(w.N * w.C, dtype=torch.float32, device="cuda")
+        out = None
+        for _ in range(args.reps):
+            out = api.glm_kernel_matmul(X, X, v, w.C, w.kernel, w.lengthscale, w.outputscale,
+                                        prec, out=out)
+        what = f"{args.reps} K.v products (N={w.N}, D={w.D}, C={w.C}, {prec})"
+    else:
+        prec = args.precision or "fp32"
+        w = datagen.config5_model()
+        X = torch.tensor(w.X, dtype=torch.float32, device="cuda")
+        y = torch.tensor(w.y, dtype=torch.int32, device="cuda")
+        m = api.IterNCGP(X, y, w.C, w.kernel, w.lengthscale, w.outputscale, policy="cg",
+                         j_max=100, rank_limit=100, precision=prec, residual_mode="recurrence",
+                         max_buffer=200)
+        for _ in range(3):
+            m.newton_step()
+        kept = m.compress(100)
+        Xs = torch.tensor(np.random.default_rng(9).standard_normal((4096, w.D)),
+                          dtype=torch.float32, device="cuda")
+        ws = torch.empty(m.predict_ws_bytes(4096), dtype=torch.uint8, device="cuda")
+        o = torch.empty((3, 4096 * w.C), dtype=torch.float32, device="cuda")
+        st = torch.cuda.current_stream()
+        for _ in range(args.reps):
+            m.predict_into(Xs, o[0], o[1], o[2], ws, st)
+        what = f"{args.reps} predictions at 4096 points (N={w.N}, C={w.C}, B={kept}, {prec})"
     torch.cuda.synchronize()
     n = args.copy_mib * (1 << 20) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
-    print(f"profile_driver: {args.reps} K.v products (N={w.N}, D={w.D}, C={w.C}) and one "
-          f"{args.copy_mib} MiB device copy done")
+    print(f"profile_driver: {what} and one {args.copy_mib} MiB device copy done")
 
 
 if __name__ == "__main__":
