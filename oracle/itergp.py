@@ -26,6 +26,9 @@ Readings of points the paper leaves open (each also listed in the design doc):
 * The unit-vector policy restarts at e_1 in every Newton step and runs
   without recycling (the paper's Cholesky runs are without recycling).
 
+Likelihoods with a diagonal negative Hessian (Poisson with log link,
+Gaussian) run the same loop with W^{-1} diagonal (iterncgp_diag).
+
 Pins (tests/test_oracle_itergp.py): full-budget IterGP equals the dense
 Cholesky solve; C_j = S (S^T Khat S)^{-1} S^T equals Q Q^T; the unit policy
 equals exact GP regression on the leading coordinates; the residual policy
@@ -206,6 +209,61 @@ def iterncgp(apply_K: Apply, y: np.ndarray, C: int, steps: int,
         rel = float(np.linalg.norm(g_new - g_old) / nn) if nn > 0 else float("inf")
         recs.append(NewtonRecord(F_new, v, Q, rhs, info, rel, S, T))
         F = F_new
+        if outer_tol is not None and rel <= outer_tol:
+            break
+    return recs
+
+
+def diag_likelihood_terms(name: str, f: np.ndarray, y: np.ndarray, noise_var: float = 1.0):
+    """Gradient and diagonal of W(f)^{-1} of a likelihood whose negative
+    Hessian is diagonal.
+
+    poisson  (log link; appendix on the Poisson log likelihood):
+             grad = y - exp(f), W^{-1} = diag(exp(-f))
+    gaussian (observation variance noise_var; the conjugate case):
+             grad = (y - f) / noise_var, W^{-1} = noise_var I
+    """
+    f = np.asarray(f, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    if name == "poisson":
+        return lik.poisson_grad(f, y), lik.poisson_winv_diag(f)
+    if name == "gaussian":
+        return (y - f) / noise_var, np.full(f.shape, float(noise_var))
+    raise ValueError(f"unknown likelihood {name!r}")
+
+
+def iterncgp_diag(apply_K: Apply, y: np.ndarray, steps: int, likelihood: str = "poisson",
+                  noise_var: float = 1.0, policy: str = "cg", j_max: int = 100,
+                  rank_limit: Optional[int] = None, recycle: bool = True,
+                  tol_abs: float = 1e-5, tol_rel: float = 1e-5,
+                  outer_tol: Optional[float] = None,
+                  user_actions: Optional[List[np.ndarray]] = None,
+                  f0: Optional[np.ndarray] = None):
+    """Algorithm 1 for a likelihood with diagonal W^{-1} (Poisson, Gaussian),
+    m = 0, f_0 = m.  y and f are vectors of length n (n = N for one latent
+    function; n = N C CN-ordered for C independent ones).  The pseudo-targets
+    are yhat - m = f + W^{-1} grad (the Newton step of section 3.1 written as
+    a GP regression problem); IterGP (Algorithm 2) solves (K + W^{-1}) v =
+    yhat - m with the recycled buffers (Algorithm 3); f_{i+1} = K v.
+    Returns the list of NewtonRecord (F holds f as an (n, 1) array)."""
+    y = np.asarray(y, dtype=np.float64)
+    n = y.shape[0]
+    f = np.zeros(n) if f0 is None else np.array(f0, dtype=np.float64)
+    S, T = np.zeros((n, 0)), np.zeros((n, 0))
+    recs = []
+    for i in range(steps):
+        grad, wd = diag_likelihood_terms(likelihood, f, y, noise_var)
+        apply_Winv = (lambda wd_: (lambda V: (wd_[:, None] * V) if V.ndim == 2 else wd_ * V))(wd)
+        rhs = f + wd * grad
+        ua = None if user_actions is None else user_actions[i]
+        v, Q, S, T, info = itergp(apply_K, apply_Winv, rhs, S, T, policy, j_max,
+                                  tol_abs, tol_rel, rank_limit,
+                                  recycle and policy != "unit", ua)
+        f_new = apply_K(v)
+        nn = float(np.linalg.norm(f_new))
+        rel = float(np.linalg.norm(f_new - f) / nn) if nn > 0 else float("inf")
+        recs.append(NewtonRecord(f_new[:, None], v, Q, rhs, info, rel, S, T))
+        f = f_new
         if outer_tol is not None and rel <= outer_tol:
             break
     return recs
