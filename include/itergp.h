@@ -133,6 +133,18 @@ typedef enum igp_residual_mode {
   IGP_RESIDUAL_RECURRENCE = 1   /* K v kept up to date from K d_j (one K product per iteration) */
 } igp_residual_mode;
 
+/* Likelihood of the observations.  Softmax: multi-class classification, y
+ * int32 labels in [0, C), W_n the C x C softmax Hessian block (applied through
+ * its pseudo-inverse).  Poisson (log link) and Gaussian: one observation per
+ * latent value, y with N*C entries in CN-ordering (int32 counts >= 0 for
+ * Poisson; finite targets of the model's element type for Gaussian), W^{-1}
+ * diagonal: exp(-f) (appendix on the Poisson log likelihood) or noise_var. */
+typedef enum igp_likelihood {
+  IGP_LIK_SOFTMAX = 0,
+  IGP_LIK_POISSON = 1,
+  IGP_LIK_GAUSSIAN = 2
+} igp_likelihood;
+
 typedef struct igp_solver_config {
   int32_t policy;        /* igp_policy */
   int32_t j_max;         /* maximum new actions per Newton step (>= 0) */
@@ -144,7 +156,8 @@ typedef struct igp_solver_config {
   int32_t residual_mode; /* igp_residual_mode */
   int32_t max_buffer;    /* columns reserved for S, T, Q (>= j_max; >= R + j_max
                             with recycling and a rank limit) */
-  int32_t reserved;      /* must be 0 */
+  int32_t likelihood;    /* igp_likelihood (0: softmax) */
+  double noise_var;      /* Gaussian observation variance (> 0); unused otherwise */
 } igp_solver_config;
 
 typedef struct igp_step_info {
@@ -171,13 +184,15 @@ size_t itergp_state_bytes(int64_t N, int64_t D, int64_t C, const igp_solver_conf
 /* Create a model with f_0 = m = 0 and empty buffers (Algorithm 1, start).
  *   X      N x D row-major (double for IGP_FP64, float otherwise); copied
  *          into the arena, the caller may free it after the call returns.
- *   y      N int32 labels in [0, C); read by every Newton step, so the
- *          caller keeps it alive for the model's lifetime.
+ *   y      observations (see igp_likelihood): N int32 labels in [0, C) for
+ *          softmax; N*C int32 counts >= 0 for Poisson; N*C targets of the
+ *          model's element type for Gaussian.  Read by every Newton step, so
+ *          the caller keeps it alive for the model's lifetime.
  *   arena  device memory of >= itergp_state_bytes(...) bytes, 256-byte
  *          aligned, owned by the caller, alive for the model's lifetime.
  * Synchronises `stream`.  The model runs all its work on `stream`. */
 int itergp_init(igp_model** out, const igp_kernel_params* kp, const igp_solver_config* cfg,
-                const void* X, const int32_t* y, int64_t N, int64_t D, int64_t C,
+                const void* X, const void* y, int64_t N, int64_t D, int64_t C,
                 void* arena, size_t arena_bytes, hipStream_t stream);
 
 /* Actions for IGP_POLICY_USER in the next Newton step: ncols CN-ordered
@@ -208,7 +223,8 @@ int itergp_compress(igp_model* m, int32_t rank_limit, int32_t* kept);
  *   var[s*C+c]  = k(xs,xs) - sum_b (sum_n k(xs_s, x_n) Q[n*C+c, b])^2
  *   probs[s*C+c]= softmax_c(mean / sqrt(1 + pi/8 var))
  *   Xs   Ns x D row-major (model element type); mean (required), var and
- *        probs (nullable) Ns*C each.  probs requires var.
+ *        probs (nullable) Ns*C each.  probs requires var and the softmax
+ *        likelihood.
  *   ws   >= itergp_predict_ws_bytes(m, Ns) bytes. Asynchronous on `stream`. */
 size_t itergp_predict_ws_bytes(const igp_model* m, int64_t Ns);
 int itergp_predict(const igp_model* m, const void* Xs, int64_t Ns, void* mean,

@@ -31,11 +31,15 @@ class KernelParams(ct.Structure):
                 ("lengthscale", ct.c_double), ("outputscale", ct.c_double)]
 
 
+IGP_LIK_SOFTMAX, IGP_LIK_POISSON, IGP_LIK_GAUSSIAN = 0, 1, 2
+
+
 class SolverConfig(ct.Structure):
     _fields_ = [("policy", ct.c_int32), ("j_max", ct.c_int32), ("rank_limit", ct.c_int32),
                 ("recycle", ct.c_int32), ("tol_abs", ct.c_double), ("tol_rel", ct.c_double),
                 ("precision", ct.c_int32), ("residual_mode", ct.c_int32),
-                ("max_buffer", ct.c_int32), ("reserved", ct.c_int32)]
+                ("max_buffer", ct.c_int32), ("likelihood", ct.c_int32),
+                ("noise_var", ct.c_double)]
 
 
 class StepInfo(ct.Structure):

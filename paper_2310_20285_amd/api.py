@@ -97,9 +97,13 @@ def glm_softmax_hessian_apply(F: torch.Tensor, V: torch.Tensor, mode="pinv",
     return out.view(-1) if vec else out
 
 
+_LIK = {"softmax": L.IGP_LIK_SOFTMAX, "poisson": L.IGP_LIK_POISSON,
+        "gaussian": L.IGP_LIK_GAUSSIAN}
+
+
 def solver_config(policy="cg", j_max=100, rank_limit=-1, recycle=True, tol_abs=1e-5,
                   tol_rel=1e-5, precision="fp32", residual_mode="explicit",
-                  max_buffer=None) -> L.SolverConfig:
+                  max_buffer=None, likelihood="softmax", noise_var=1.0) -> L.SolverConfig:
     pol = {"cg": L.IGP_POLICY_CG, "unit": L.IGP_POLICY_UNIT, "user": L.IGP_POLICY_USER}[policy]
     rm = {"explicit": L.IGP_RESIDUAL_EXPLICIT,
           "recurrence": L.IGP_RESIDUAL_RECURRENCE}[residual_mode]
@@ -108,7 +112,7 @@ def solver_config(policy="cg", j_max=100, rank_limit=-1, recycle=True, tol_abs=1
         max_buffer = max(max_buffer, 1)
     return L.SolverConfig(pol, int(j_max), int(-1 if rank_limit is None else rank_limit),
                           1 if recycle else 0, float(tol_abs), float(tol_rel), _prec(precision),
-                          rm, int(max_buffer), 0)
+                          rm, int(max_buffer), _LIK[likelihood], float(noise_var))
 
 
 def state_bytes(N: int, D: int, C: int, **cfg) -> int:
@@ -127,7 +131,8 @@ class IterNCGP:
         self.precision = self.cfg.precision
         self.dtype = _DTYPE[self.precision]
         _need(X, self.dtype, "X")
-        _need(y, torch.int32, "y")
+        gaussian = self.cfg.likelihood == L.IGP_LIK_GAUSSIAN
+        _need(y, self.dtype if gaussian else torch.int32, "y")
         self.N, self.D = X.shape
         self.C = int(C)
         self.y = y                       # kept alive: the model reads it every step

@@ -14,7 +14,7 @@ int newton_step_batched(igp_model* const* models, int n, igp_step_info* infos, v
 std::string batched_tuning_json();
 size_t state_bytes(int64_t N, int64_t D, int64_t C, const igp_solver_config* cfg);
 int model_init(igp_model** out, const igp_kernel_params* kp, const igp_solver_config* cfg,
-               const void* X, const int32_t* y, int64_t N, int64_t D, int64_t C, void* arena,
+               const void* X, const void* y, int64_t N, int64_t D, int64_t C, void* arena,
                size_t arena_bytes, hipStream_t stream);
 
 namespace {
@@ -137,7 +137,7 @@ size_t itergp_state_bytes(int64_t N, int64_t D, int64_t C, const igp_solver_conf
 }
 
 int itergp_init(igp_model** out, const igp_kernel_params* kp, const igp_solver_config* cfg,
-                const void* X, const int32_t* y, int64_t N, int64_t D, int64_t C, void* arena,
+                const void* X, const void* y, int64_t N, int64_t D, int64_t C, void* arena,
                 size_t arena_bytes, hipStream_t stream) {
   return guarded([&]() -> int {
     clear_error();

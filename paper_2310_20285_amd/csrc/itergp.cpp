@@ -101,7 +101,7 @@ struct Model final : igp_model {
   igp_kernel_params kp{};
   igp_solver_config cfg{};
   int64_t N = 0, D = 0, C = 0, n = 0, ld = 0;
-  const int32_t* y = nullptr;
+  const void* y = nullptr;       // observations (igp_likelihood decides the type)
   hipStream_t stream = nullptr;
   Layout<T> L{};
   int ncols = 0;                 // columns of S, T and Q
@@ -233,7 +233,29 @@ struct Model final : igp_model {
   } st;
   double sc[SC_COUNT];
 
-  // pseudo-targets yhat - m = g + W^+ (onehot(y) - pi), m = 0
+  bool softmax() const { return cfg.likelihood == IGP_LIK_SOFTMAX; }
+
+  // W at f (pi for softmax, the diagonal of W^{-1} otherwise, both kept in
+  // L.pi) and the pseudo-targets yhat - m = f + W^{-1} grad into rhs
+  int likelihood_terms(T* rhs) {
+    if (softmax()) {
+      int nblk = 0;
+      return softmax_pi_rhs<T>(L.f, static_cast<const int32_t*>(y), N, C, L.pi, rhs, L.part,
+                               &nblk, stream);
+    }
+    return diag_begin<T>(cfg.likelihood, L.f, y, n, cfg.noise_var, L.pi, rhs, stream);
+  }
+
+  // Out[:, b] = W^+ V[:, b] (+ Add[:, b]) for b < nb
+  int apply_winv(const T* V, int64_t nb, int64_t ldv, const T* Add, int64_t lda, T* Out,
+                 int64_t ldo) {
+    if (softmax())
+      return winv_apply<T>(L.pi, false, IGP_W_PINV, N, C, V, nb, ldv, Add, lda, Out, ldo, stream);
+    return diag_apply<T>(L.pi, n, V, nb, ldv, Add, lda, Out, ldo, stream);
+  }
+
+  // pseudo-targets yhat - m = g + W^+ (onehot(y) - pi), m = 0 (softmax), or
+  // f + W^{-1} grad (diagonal W)
   int phase_begin() {
     st = StepState{};
     st.info.eta_min = INFINITY;
@@ -243,8 +265,7 @@ struct Model final : igp_model {
       IGP_TRY(event_pair(&a, &st.step_b));
       IGP_CHECK_HIP(hipEventRecord(a, stream));
     }
-    int nblk = 0;
-    IGP_TRY(softmax_pi_rhs<T>(L.f, y, N, C, L.pi, L.rhs, L.part, &nblk, stream));
+    IGP_TRY(likelihood_terms(L.rhs));
     IGP_TRY(dot_into<T>(L.rhs, L.rhs, n, L.part, L.scal + SC_RHS2, stream));
     const bool recycle = cfg.recycle && cfg.policy != IGP_POLICY_UNIT;
     if (!recycle) ncols = 0;
@@ -255,7 +276,7 @@ struct Model final : igp_model {
   int phase_vsr_gram() {
     if (ncols == 0) return IGP_OK;
     const int B = ncols;
-    IGP_TRY(winv_apply<T>(L.pi, false, IGP_W_PINV, N, C, L.S, B, ld, L.Tb, ld, L.S2, ld, stream));
+    IGP_TRY(apply_winv(L.S, B, ld, L.Tb, ld, L.S2, ld));
     return gram<T>(L.S, L.S2, ld, n, B, L.gram_part, L.gram_cap, L.M, stream);
   }
 
@@ -336,7 +357,7 @@ struct Model final : igp_model {
       IGP_TRY(apply_K(L.v, L.kv));
       ++st.kprod;
     }
-    IGP_TRY(winv_apply<T>(L.pi, false, IGP_W_PINV, N, C, L.v, 1, n, nullptr, 0, L.wv, n, stream));
+    IGP_TRY(apply_winv(L.v, 1, n, nullptr, 0, L.wv, n));
     return residual<T>(L.rhs, L.kv, L.wv, L.r, n, L.part, L.scal + SC_RR, stream);
   }
 
@@ -386,8 +407,7 @@ struct Model final : igp_model {
   // after t_j = K s_j: z_j, Q^T z_j, d_j, eta_j, guarded append, next residual
   int phase_after_product() {
     ++st.kprod;
-    IGP_TRY(winv_apply<T>(L.pi, false, IGP_W_PINV, N, C, s_col(), 1, n, t_col(), n, L.z, n,
-                          stream));
+    IGP_TRY(apply_winv(s_col(), 1, n, t_col(), n, L.z, n));
     IGP_TRY(gemv_t<T>(L.Q, ld, n, ncols, L.z, L.part, L.yb, stream));
     IGP_TRY(dir_update<T>(s_col(), L.Q, ld, n, ncols, L.yb, L.z, L.d, L.part, L.scal + SC_ETA,
                           stream, t_col(), recurrence() ? L.KQ : nullptr, L.kd));
@@ -423,7 +443,12 @@ struct Model final : igp_model {
   // after f_{i+1} = K v + m has been enqueued into fnew
   int phase_stats() {
     ++st.kprod;
-    IGP_TRY(newton_stats<T>(L.fnew, L.f, L.v, y, N, C, L.part, L.scal, stream));
+    if (softmax())
+      IGP_TRY(newton_stats<T>(L.fnew, L.f, L.v, static_cast<const int32_t*>(y), N, C, L.part,
+                              L.scal, stream));
+    else
+      IGP_TRY(diag_stats<T>(cfg.likelihood, cfg.noise_var, L.fnew, L.f, L.v, y, n, L.part,
+                            L.scal, stream));
     if (prof) IGP_CHECK_HIP(hipEventRecord(st.step_b, stream));
     return IGP_OK;
   }
@@ -477,9 +502,8 @@ struct Model final : igp_model {
   int compress(int32_t rank_limit, int32_t* kept) override {
     clear_error();
     IGP_REQUIRE(rank_limit >= -1, "rank_limit must be >= -1");
-    int nblk = 0;
-    // pi at f; the pseudo-targets it also forms go to scratch (rhs is kept)
-    IGP_TRY(softmax_pi_rhs<T>(L.f, y, N, C, L.pi, L.wv, L.part, &nblk, stream));
+    // W at f; the pseudo-targets it also forms go to scratch (rhs is kept)
+    IGP_TRY(likelihood_terms(L.wv));
     st = StepState{};
     const int saved = cfg.rank_limit;
     cfg.rank_limit = rank_limit;
@@ -517,6 +541,7 @@ struct Model final : igp_model {
     if (Ns == 0) return IGP_OK;
     IGP_REQUIRE(Xs_ && mean_, "predict: NULL Xs or mean");
     IGP_REQUIRE(!probs_ || var_, "predict: probs requires var");
+    IGP_REQUIRE(!probs_ || softmax(), "predict: class probabilities need the softmax likelihood");
     if (ws_bytes < predict_ws_bytes(Ns)) {
       set_error("predict workspace too small: need %zu bytes", predict_ws_bytes(Ns));
       return IGP_ENOMEM;
@@ -893,6 +918,11 @@ int validate_common(const igp_kernel_params* kp, const igp_solver_config* cfg, i
   IGP_REQUIRE(std::isfinite(cfg->tol_abs) && std::isfinite(cfg->tol_rel) && cfg->tol_abs >= 0 &&
                   cfg->tol_rel >= 0,
               "tolerances must be finite and >= 0");
+  IGP_REQUIRE(cfg->likelihood >= IGP_LIK_SOFTMAX && cfg->likelihood <= IGP_LIK_GAUSSIAN,
+              "unknown likelihood %d", cfg->likelihood);
+  IGP_REQUIRE(cfg->likelihood != IGP_LIK_GAUSSIAN ||
+                  (std::isfinite(cfg->noise_var) && cfg->noise_var > 0),
+              "the Gaussian likelihood needs a finite noise_var > 0");
   return IGP_OK;
 }
 
@@ -905,7 +935,7 @@ size_t state_bytes_t(int64_t N, int64_t D, int64_t C, const igp_solver_config& c
 
 template <typename T>
 int init_t(igp_model** out, const igp_kernel_params* kp, const igp_solver_config* cfg,
-           const void* X, const int32_t* y, int64_t N, int64_t D, int64_t C, void* arena,
+           const void* X, const void* y, int64_t N, int64_t D, int64_t C, void* arena,
            size_t arena_bytes, hipStream_t stream) {
   const size_t need = state_bytes_t<T>(N, D, C, *cfg, kp->kind);
   if (arena_bytes < need) {
@@ -935,13 +965,21 @@ int init_t(igp_model** out, const igp_kernel_params* kp, const igp_solver_config
   IGP_CHECK_HIP(hipMemsetAsync(m->L.f, 0, m->n * sizeof(T), stream));
   IGP_CHECK_HIP(hipMemsetAsync(m->L.v, 0, m->n * sizeof(T), stream));
   IGP_CHECK_HIP(hipMemsetAsync(m->L.flags, 0, 64 * sizeof(int), stream));
-  k_check_labels<T><<<256, 256, 0, stream>>>(y, N, static_cast<int>(C), m->L.flags);
-  IGP_CHECK_LAUNCH();
+  if (cfg->likelihood == IGP_LIK_SOFTMAX) {
+    k_check_labels<T><<<256, 256, 0, stream>>>(static_cast<const int32_t*>(y), N,
+                                               static_cast<int>(C), m->L.flags);
+    IGP_CHECK_LAUNCH();
+  } else {
+    IGP_TRY(diag_check_targets<T>(cfg->likelihood, y, m->n, m->L.flags, stream));
+  }
   int bad = 0;
   IGP_CHECK_HIP(hipMemcpyAsync(&bad, m->L.flags, sizeof(int), hipMemcpyDeviceToHost, stream));
   IGP_CHECK_HIP(hipStreamSynchronize(stream));
   if (bad) {
-    set_error("%d labels outside [0, C)", bad);
+    set_error(cfg->likelihood == IGP_LIK_SOFTMAX ? "%d labels outside [0, C)"
+              : cfg->likelihood == IGP_LIK_POISSON ? "%d negative counts"
+                                                   : "%d non-finite targets",
+              bad);
     return IGP_EINVAL;
   }
   *out = m.release();
@@ -959,7 +997,7 @@ size_t state_bytes(int64_t N, int64_t D, int64_t C, const igp_solver_config* cfg
 }
 
 int model_init(igp_model** out, const igp_kernel_params* kp, const igp_solver_config* cfg,
-               const void* X, const int32_t* y, int64_t N, int64_t D, int64_t C, void* arena,
+               const void* X, const void* y, int64_t N, int64_t D, int64_t C, void* arena,
                size_t arena_bytes, hipStream_t stream) {
   IGP_REQUIRE(out, "NULL output handle");
   *out = nullptr;

@@ -176,6 +176,20 @@ int gram(const T* A, const T* B, int64_t ld, int64_t n, int ncols, double* parti
 template <typename T>
 int right_mul(const T* A, int64_t lda, int64_t n, int ncols, const double* U, int R,
               const double* colscale, T* Out, int64_t ldo, hipStream_t s);
+// likelihoods with diagonal W (igp_likelihood POISSON / GAUSSIAN), elementwise
+// over n = N C values: W^{-1} diagonal and pseudo-targets f + W^{-1} grad;
+// Out = W^{-1} V (+ Add); Newton bookkeeping as newton_stats; target checks
+template <typename T>
+int diag_begin(int lik, const T* f, const void* y, int64_t n, double s2, T* winv, T* rhs,
+               hipStream_t s);
+template <typename T>
+int diag_apply(const T* winv, int64_t n, const T* V, int64_t nb, int64_t ldv, const T* Add,
+               int64_t lda, T* Out, int64_t ldo, hipStream_t s);
+template <typename T>
+int diag_stats(int lik, double s2, const T* fnew, const T* f, const T* v, const void* y,
+               int64_t n, double* part, double* scal, hipStream_t s);
+template <typename T>
+int diag_check_targets(int lik, const void* y, int64_t n, int* flag, hipStream_t s);
 // Newton update bookkeeping: ||fnew - f||^2, ||fnew||^2, loglik(fnew), fnew^T v
 template <typename T>
 int newton_stats(const T* fnew, const T* f, const T* v, const int32_t* y, int64_t N,

@@ -77,6 +77,13 @@ def test_argument_errors_without_device_work():
                            ct.c_void_p(1), 10, 2, 3, ct.c_void_p(256), 1 << 30,
                            None) == L.IGP_EINVAL
     assert b"max_buffer" in lib.igp_last_error()
+    for lik, noise, msg in ((7, 1.0, b"likelihood"), (L.IGP_LIK_GAUSSIAN, 0.0, b"noise_var"),
+                            (L.IGP_LIK_GAUSSIAN, float("nan"), b"noise_var")):
+        cfg = L.SolverConfig(0, 10, -1, 1, 1e-5, 1e-5, L.IGP_FP32, 0, 20, lik, noise)
+        assert lib.itergp_init(ct.byref(h), ct.byref(kp), ct.byref(cfg), ct.c_void_p(1),
+                               ct.c_void_p(1), 10, 2, 1, ct.c_void_p(256), 1 << 30,
+                               None) == L.IGP_EINVAL
+        assert msg in lib.igp_last_error()
 
 
 @pytest.mark.parametrize("n", [1, 2, 7, 40, 150])
