@@ -85,10 +85,12 @@ def main():
                     help="skip the plain FP32 PyTorch comparison")
     ap.add_argument("--precision", default=None, choices=["fp32", "fp64", "bf16"])
     ap.add_argument("--workload", default="gpc16",
-                    choices=["gpc16", "image", "batched", "serving"],
+                    choices=["gpc16", "image", "batched", "serving", "gmm", "poisson"],
                     help="gpc16: N=20000 D=16 C=5 (default); image: N=60000 D=784 C=10 BF16; "
                          "batched: 64 independent problems in one persistent launch; "
-                         "serving: request stream against a fitted N=100000 D=32 C=10 model")
+                         "serving: request stream against a fitted N=100000 D=32 C=10 model; "
+                         "gmm: the paper's Gaussian-mixture classification (N=100000, D=3, "
+                         "C=10); poisson: the paper's Poisson budget-split schedules")
     ap.add_argument("--requests", type=int, default=160, help="serving: stream length")
     ap.add_argument("--load", type=float, nargs="+", default=[0.5],
                     help="serving: arrival rates as fractions of the measured capacity")
@@ -112,6 +114,10 @@ def main():
         return bench_batched(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "gmm":
+        return bench_gmm(args)
+    if args.workload == "poisson":
+        return bench_poisson(args)
     args.precision = args.precision or "fp32"
     KV_INSTANCE = "kv_mfma_f32_narrow<3,1,5,2>"   # Matern-5/2, D <= 16, W = 5, 2 strips
     w = datagen.config2()
@@ -552,6 +558,135 @@ def bench_serving(args):
                   "span_s": max(d for _, _, d in rec)}
         pr["p99_ratio_plain_over_library"] = pr["predict"]["p99_ms"] / res["value"]
         res["plain_fp32_fifo"] = pr
+    print(json.dumps(res))
+
+
+def bench_gmm(args):
+    """The paper's large-scale classification workload: a 10-class Gaussian
+    mixture in 3-D, N = 100000 training and 10000 test points, Matern-3/2
+    (lengthscale 0.05, outputscale 0.05); IterNCGP-CG with j <= 5 actions per
+    Newton step and recycling, R = inf and R = 10.  After every Newton step the
+    probit predictions at the test points give accuracy and NLL; both are
+    reported against the cumulative device time.  value = Newton steps/s of
+    the R = inf run (predictions excluded)."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_2310_20285_amd import api
+
+    prec = args.precision or "fp32"
+    w = datagen.gmm()
+    dev = torch.device("cuda:0")
+    X = torch.tensor(w.X, dtype=torch.float32, device=dev)
+    y = torch.tensor(w.y, dtype=torch.int32, device=dev)
+    Xs = torch.tensor(w.Xs, dtype=torch.float32, device=dev)
+    steps = max(args.steps, 10)
+    runs = {}
+    for R in (-1, 10):
+        def make():
+            return api.IterNCGP(X, y, w.C, w.kernel, w.lengthscale, w.outputscale, policy="cg",
+                                j_max=5, rank_limit=R, recycle=True, precision=prec,
+                                residual_mode="recurrence",
+                                max_buffer=5 * steps + 5 if R < 0 else R + 5)
+        mw = make()
+        mw.newton_step()
+        torch.cuda.synchronize()
+        del mw
+        m = make()
+        torch.cuda.synchronize()
+        t_solve = 0.0
+        curve = []
+        for i in range(steps):
+            t0 = time.perf_counter()
+            info = m.newton_step()
+            t_solve += time.perf_counter() - t0
+            _, _, probs = m.predict(Xs)
+            p = probs.double().cpu().numpy()
+            acc = float((p.argmax(1) == w.ys).mean())
+            nll = float(-np.mean(np.log(np.maximum(p[np.arange(len(w.ys)), w.ys], 1e-300))))
+            curve.append({"step": i + 1, "solve_s": round(t_solve, 4), "iters": info["iters"],
+                          "buffer_cols": info["buffer_cols"], "accuracy": round(acc, 4),
+                          "nll": round(nll, 4)})
+        runs["R=inf" if R < 0 else f"R={R}"] = {"steps_per_s": steps / t_solve, "curve": curve}
+    res = {
+        "metric": "IterNCGP Newton steps/s",
+        "value": runs["R=inf"]["steps_per_s"],
+        "unit": "Newton steps/s",
+        "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": 1e3 / runs["R=inf"]["steps_per_s"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp64": "f64"}[prec], "data": "synthetic",
+        "config": {"workload": "Gaussian mixture N=100000 D=3 C=10 matern32 l=0.05 os=0.05; "
+                               "IterNCGP-CG j<=5, recycling, R=inf and R=10; probit "
+                               "predictions at 10000 test points after each step",
+                   "precision": prec},
+        "runs": runs,
+    }
+    print(json.dumps(res))
+
+
+def bench_poisson(args):
+    """The paper's Poisson regression schedules: N = 100 points on [0, 1], RBF
+    prior (lengthscale 0.1, outputscale 5), 100 solver iterations spread over
+    5, 10, 20 or 100 Newton steps (j <= 20, 10, 5, 1), recycling without
+    compression, outer tolerance 1e-3, 10 runs with re-drawn counts.  Reported
+    per schedule: Newton steps taken, device time, RMSE of the posterior mean
+    of the log rate against the true log rate.  value = Newton steps/s over all
+    runs of all schedules."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_2310_20285_amd import api
+
+    prec = args.precision or "fp64"
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    dev = torch.device("cuda:0")
+    sched = {}
+    total_steps, total_t = 0, 0.0
+    for jmax, nsteps in ((20, 5), (10, 10), (5, 20), (1, 100)):
+        rec = []
+        for run in range(10):
+            Xn, yn, f = datagen.poisson(seed=run)
+            X = torch.tensor(Xn, dtype=dt, device=dev)
+            y = torch.tensor(yn, dtype=torch.int32, device=dev)
+            m = api.IterNCGP(X, y, 1, "rbf", 0.1, 5.0, likelihood="poisson", policy="cg",
+                             j_max=jmax, rank_limit=-1, recycle=True, precision=prec,
+                             residual_mode="recurrence", max_buffer=105)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            taken = 0
+            for _ in range(nsteps):
+                info = m.newton_step()
+                taken += 1
+                if info["rel_change"] <= 1e-3:
+                    break
+            t = time.perf_counter() - t0
+            mean, _, _ = m.predict(X, probs=False)
+            rmse = float(np.sqrt(np.mean((mean.double().cpu().numpy()[:, 0] - f) ** 2)))
+            rec.append((taken, t, rmse))
+            total_steps += taken
+            total_t += t
+        a = np.array(rec)
+        sched[f"j<={jmax} x {nsteps} steps"] = {
+            "steps_taken_median": float(np.median(a[:, 0])),
+            "time_ms_median": float(np.median(a[:, 1]) * 1e3),
+            "rmse_log_rate_median": float(np.median(a[:, 2])),
+            "rmse_log_rate_min": float(a[:, 2].min()), "rmse_log_rate_max": float(a[:, 2].max())}
+    res = {
+        "metric": "IterNCGP Newton steps/s",
+        "value": total_steps / total_t,
+        "unit": "Newton steps/s",
+        "n_gpus": 1, "steps": total_steps, "warmup": 0,
+        "ms_per_step": total_t / total_steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16"}[prec], "data": "synthetic",
+        "config": {"workload": "Poisson regression N=100 D=1 rbf l=0.1 os=5; IterNCGP-CG, "
+                               "100 iterations over 5/10/20/100 steps, recycling, outer "
+                               "tolerance 1e-3, 10 count draws", "precision": prec},
+        "schedules": sched,
+    }
     print(json.dumps(res))
 
 
