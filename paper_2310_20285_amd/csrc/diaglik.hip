@@ -10,7 +10,7 @@
 //
 // The Newton step's pseudo-targets are yhat - m = f + W^{-1} grad (section 3.1
 // with m = 0): f + y exp(-f) - 1 for Poisson, y for Gaussian.
-#include "ops.hpp"
+#include "iter_ops.hpp"
 
 namespace igp {
 namespace {
@@ -47,11 +47,8 @@ __global__ void __launch_bounds__(NTD)
 k_diag_apply(const T* __restrict__ winv, int64_t n, const T* __restrict__ V, int64_t ldv,
              const T* __restrict__ Add, int64_t lda, T* __restrict__ Out, int64_t ldo) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(NTD) + threadIdx.x;
-  const int64_t b = blockIdx.y;
   if (i >= n) return;
-  T o = winv[i] * V[b * ldv + i];
-  if (Add) o += Add[b * lda + i];
-  Out[b * ldo + i] = o;
+  iter::winv_diag<T>(winv, i, V, blockIdx.y, ldv, Add, lda, Out, ldo);
 }
 
 template <typename T>

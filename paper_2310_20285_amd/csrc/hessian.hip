@@ -7,63 +7,13 @@
 //   W_n   v = pi_n * v - pi_n (pi_n^T v)
 //   W_n^+ v = P ((P v) / pi_n),  P = I - 11^T / C  (explicit pseudo-inverse from
 //             the paper's appendix lemma for multi-class classification)
-#include "ops.hpp"
+#include "iter_ops.hpp"
 
 namespace igp {
 namespace {
 
-template <typename T, int CMAX>
-__device__ inline void load_softmax(const T* F, int64_t n, int C, T (&p)[CMAX]) {
-  T mx = -INFINITY;
-#pragma unroll
-  for (int c = 0; c < CMAX; ++c)
-    if (c < C) {
-      p[c] = F[n * C + c];
-      mx = p[c] > mx ? p[c] : mx;
-    }
-  T sum = T(0);
-#pragma unroll
-  for (int c = 0; c < CMAX; ++c)
-    if (c < C) {
-      p[c] = exp(p[c] - mx);
-      sum += p[c];
-    }
-  const T inv = T(1) / sum;
-#pragma unroll
-  for (int c = 0; c < CMAX; ++c)
-    if (c < C) p[c] *= inv;
-}
-
-// u <- W^+ u  (mode 1)  or  u <- W u  (mode 0), in place
-template <typename T, int CMAX>
-__device__ inline void apply_block(int mode, int C, const T (&p)[CMAX], T (&u)[CMAX]) {
-  if (mode == IGP_W_PINV) {
-    T m = T(0);
-#pragma unroll
-    for (int c = 0; c < CMAX; ++c)
-      if (c < C) m += u[c];
-    m /= T(C);
-    T m2 = T(0);
-#pragma unroll
-    for (int c = 0; c < CMAX; ++c)
-      if (c < C) {
-        u[c] = (u[c] - m) / p[c];
-        m2 += u[c];
-      }
-    m2 /= T(C);
-#pragma unroll
-    for (int c = 0; c < CMAX; ++c)
-      if (c < C) u[c] -= m2;
-  } else {
-    T pv = T(0);
-#pragma unroll
-    for (int c = 0; c < CMAX; ++c)
-      if (c < C) pv += p[c] * u[c];
-#pragma unroll
-    for (int c = 0; c < CMAX; ++c)
-      if (c < C) u[c] = p[c] * u[c] - p[c] * pv;
-  }
-}
+using iter::apply_block;
+using iter::load_softmax;
 
 template <typename T, int CMAX>
 __global__ void __launch_bounds__(256)
@@ -105,25 +55,7 @@ k_winv_apply(const T* __restrict__ pi, int logits, int mode, int64_t N, int C,
   const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   const int64_t b = blockIdx.y;
   if (n >= N || b >= nb) return;
-  T p[CMAX], u[CMAX];
-  if (logits) {
-    load_softmax<T, CMAX>(pi, n, C, p);
-  } else {
-#pragma unroll
-    for (int c = 0; c < CMAX; ++c)
-      if (c < C) p[c] = pi[n * C + c];
-  }
-#pragma unroll
-  for (int c = 0; c < CMAX; ++c)
-    if (c < C) u[c] = V[b * ldv + n * C + c];
-  apply_block<T, CMAX>(mode, C, p, u);
-#pragma unroll
-  for (int c = 0; c < CMAX; ++c)
-    if (c < C) {
-      T o = u[c];
-      if (Add) o += Add[b * lda + n * C + c];
-      Out[b * ldo + n * C + c] = o;
-    }
+  iter::winv_point<T, CMAX>(pi, logits, mode, n, C, V, b, ldv, Add, lda, Out, ldo);
 }
 
 }  // namespace

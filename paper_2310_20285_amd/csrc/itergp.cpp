@@ -391,9 +391,33 @@ struct Model final : igp_model {
   T* s_col() const { return L.S + static_cast<int64_t>(ncols) * ld; }
   T* t_col() const { return L.Tb + static_cast<int64_t>(ncols) * ld; }
 
+  // host bookkeeping of an iteration (shared with the batched driver)
+  void host_action() { ++st.j; }
+  void host_after_product() {
+    ++st.kprod;
+    st.next_r = st.j < cfg.j_max;
+  }
+
+  // this model's part of a batched iteration (after host_action)
+  BIter biter() const {
+    BIter t{};
+    t.r = L.r; t.s = s_col(); t.t = t_col(); t.z = L.z; t.d = L.d; t.v = L.v; t.kv = L.kv;
+    t.kd = L.kd; t.rhs = L.rhs; t.wv = L.wv; t.Q = L.Q; t.KQ = L.KQ;
+    t.qcol = L.Q + static_cast<int64_t>(ncols) * ld;
+    t.kqcol = L.KQ + static_cast<int64_t>(ncols) * ld;
+    t.pi = L.pi;
+    t.user = cfg.policy == IGP_POLICY_USER && user
+                 ? user + static_cast<int64_t>(st.j - 1) * user_ld : nullptr;
+    t.scal = L.scal; t.part = L.part; t.yb = L.yb;
+    t.n = n; t.N = N; t.ld = ld; t.unit_idx = st.j - 1;
+    t.C = static_cast<int>(C); t.ncols = ncols; t.lik = cfg.likelihood; t.policy = cfg.policy;
+    t.nchunks = static_cast<int>(ceil_div(n, 4096));
+    return t;
+  }
+
   // s_j (policy) and alpha_j = s_j^T r_{j-1}
   int phase_action() {
-    ++st.j;
+    host_action();
     if (cfg.policy == IGP_POLICY_CG) {
       IGP_TRY(action_cg<T>(L.r, L.scal + SC_RR, s_col(), n, stream));
     } else if (cfg.policy == IGP_POLICY_UNIT) {
@@ -406,7 +430,7 @@ struct Model final : igp_model {
 
   // after t_j = K s_j: z_j, Q^T z_j, d_j, eta_j, guarded append, next residual
   int phase_after_product() {
-    ++st.kprod;
+    host_after_product();
     IGP_TRY(apply_winv(s_col(), 1, n, t_col(), n, L.z, n));
     IGP_TRY(gemv_t<T>(L.Q, ld, n, ncols, L.z, L.part, L.yb, stream));
     IGP_TRY(dir_update<T>(s_col(), L.Q, ld, n, ncols, L.yb, L.z, L.d, L.part, L.scal + SC_ETA,
@@ -415,7 +439,6 @@ struct Model final : igp_model {
                                stream, recurrence() ? L.kd : nullptr,
                                recurrence() ? L.KQ + static_cast<int64_t>(ncols) * ld : nullptr,
                                L.kv));
-    st.next_r = st.j < cfg.j_max;
     if (st.next_r) IGP_TRY(enqueue_residual());
     return IGP_OK;
   }
@@ -646,6 +669,9 @@ struct Batch {
   float* partials = nullptr;
   std::vector<double> hgather;
   std::vector<BatchProblem> htab;
+  BIter* dit = nullptr;            // iteration descriptors (device)
+  int64_t* dpre = nullptr;         // per-operation block prefixes (device)
+  std::vector<unsigned char> hitbuf;
 
   static size_t partial_floats(const Model<float>* m) {
     return static_cast<size_t>(ceil_div(m->N, TUNE_SPLITS[0]) + 1) * m->N * m->C;
@@ -653,6 +679,8 @@ struct Batch {
 
   static size_t ws_bytes(const std::vector<Model<float>*>& ms) {
     Carver cv(nullptr, 0);
+    cv.take<BIter>(ms.size());
+    cv.take<int64_t>(static_cast<size_t>(BOP_COUNT) * (ms.size() + 1));
     cv.take<BatchProblem>(ms.size());
     cv.take<int64_t>(1);
     cv.take<const double*>(ms.size());
@@ -665,6 +693,8 @@ struct Batch {
 
   int carve_ws(void* ws, size_t bytes) {
     Carver cv(ws, bytes);
+    dit = cv.take<BIter>(ms.size());
+    dpre = cv.take<int64_t>(static_cast<size_t>(BOP_COUNT) * (ms.size() + 1));
     dtab = cv.take<BatchProblem>(ms.size());
     counter = reinterpret_cast<int*>(cv.take<int64_t>(1));
     dscal = cv.take<const double*>(ms.size());
@@ -697,6 +727,40 @@ struct Batch {
     for (int i = 0; i < n; ++i)
       std::copy(&hgather[static_cast<size_t>(i) * SC_COUNT],
                 &hgather[static_cast<size_t>(i) * SC_COUNT] + SC_COUNT, ms[i]->sc);
+    return IGP_OK;
+  }
+
+  // operations [op_begin, op_end) of one iteration for the selected models,
+  // one launch each (descriptors and block prefixes uploaded in one copy)
+  int iter_group(const std::vector<int>& idx, int op_begin, int op_end) {
+    const size_t nm = idx.size();
+    if (nm == 0) return IGP_OK;
+    const size_t tab_bytes = nm * sizeof(BIter);
+    const size_t pre_len = nm + 1;
+    hitbuf.resize(tab_bytes + static_cast<size_t>(BOP_COUNT) * pre_len * sizeof(int64_t));
+    BIter* ht = reinterpret_cast<BIter*>(hitbuf.data());
+    int64_t* hp = reinterpret_cast<int64_t*>(hitbuf.data() + tab_bytes);
+    std::vector<char> resid(nm);
+    for (size_t k = 0; k < nm; ++k) {
+      ht[k] = ms[idx[k]]->biter();
+      resid[k] = ms[idx[k]]->st.next_r ? 1 : 0;
+    }
+    std::vector<int64_t> total(BOP_COUNT, 0);
+    for (int op = op_begin; op < op_end; ++op) {
+      int64_t* pre = hp + static_cast<size_t>(op) * pre_len;
+      pre[0] = 0;
+      for (size_t k = 0; k < nm; ++k) pre[k + 1] = pre[k] + biter_blocks(op, ht[k], resid[k]);
+      total[op] = pre[nm];
+    }
+    // the table goes to dit; the prefix block to the matching offset of dpre
+    IGP_CHECK_HIP(hipMemcpyAsync(dit, ht, tab_bytes, hipMemcpyHostToDevice, stream));
+    IGP_CHECK_HIP(hipMemcpyAsync(dpre + static_cast<size_t>(op_begin) * pre_len,
+                                 hp + static_cast<size_t>(op_begin) * pre_len,
+                                 static_cast<size_t>(op_end - op_begin) * pre_len * sizeof(int64_t),
+                                 hipMemcpyHostToDevice, stream));
+    for (int op = op_begin; op < op_end; ++op)
+      IGP_TRY(biter_launch(op, dit, dpre + static_cast<size_t>(op) * pre_len,
+                           static_cast<int>(nm), total[op], stream));
     return IGP_OK;
   }
 
@@ -859,9 +923,11 @@ int newton_step_batched(igp_model* const* models, int n, igp_step_info* infos, v
       if (ms[i]->st.active) act.push_back(i);
     }
     if (act.empty()) break;
-    for (int i : act) IGP_TRY(ms[i]->phase_action());
+    for (int i : act) ms[i]->host_action();
+    IGP_TRY(b.iter_group(act, BOP_ACTION, BOP_FIN_ALPHA + 1));   // s_j, alpha_j
     IGP_TRY(b.products(act, false));                    // t_j = K s_j for every active model
-    for (int i : act) IGP_TRY(ms[i]->phase_after_product());
+    for (int i : act) ms[i]->host_after_product();
+    IGP_TRY(b.iter_group(act, BOP_WINV_Z, BOP_COUNT));  // z_j .. r_j for every active model
     IGP_TRY(b.read_all());
     for (int i : act) ms[i]->phase_consume();
   }

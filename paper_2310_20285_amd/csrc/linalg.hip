@@ -6,26 +6,19 @@
 // starts at element b*ld (each column is one CN-ordered vector).
 #include <algorithm>
 
-#include "ops.hpp"
+#include "iter_ops.hpp"
 
 namespace igp {
 namespace {
 
-constexpr int NT = 256;
+using iter::GV_ROWS;
+using iter::MAXCOLS_LDS;
+using iter::NT;
+using iter::grid_for;
 
 __global__ void k_finish_sum(const double* __restrict__ part, int nblk, double* __restrict__ out) {
   __shared__ double red[NT / 64];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += NT) s += part[i];
-  s = block_sum(s, red);
-  if (threadIdx.x == 0) *out = s;
-}
-
-int grid_for(int64_t n) {
-  int64_t b = ceil_div(n, NT * 4);
-  if (b > RED_BLOCKS) b = RED_BLOCKS;
-  if (b < 1) b = 1;
-  return static_cast<int>(b);
+  iter::finish_sum(part, nblk, out, red);
 }
 
 template <typename T>
@@ -33,43 +26,25 @@ __global__ void __launch_bounds__(NT)
 k_residual(const T* __restrict__ rhs, const T* __restrict__ kv, const T* __restrict__ wv,
            T* __restrict__ r, int64_t n, double* __restrict__ part) {
   __shared__ double red[NT / 64];
-  double acc = 0.0;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(NT) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * NT) {
-    const T ri = rhs[i] - kv[i] - wv[i];
-    r[i] = ri;
-    acc += static_cast<double>(ri) * static_cast<double>(ri);
-  }
-  acc = block_sum(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+  iter::residual<T>(rhs, kv, wv, r, n, part, blockIdx.x, gridDim.x, red);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(NT)
 k_dot(const T* __restrict__ a, const T* __restrict__ b, int64_t n, double* __restrict__ part) {
   __shared__ double red[NT / 64];
-  double acc = 0.0;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(NT) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * NT)
-    acc += static_cast<double>(a[i]) * static_cast<double>(b[i]);
-  acc = block_sum(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+  iter::dot<T>(a, b, n, part, blockIdx.x, gridDim.x, red);
 }
 
 template <typename T>
-__global__ void k_action_cg(const T* __restrict__ r, const double* __restrict__ rr,
-                            T* __restrict__ s, int64_t n) {
-  const double inv = 1.0 / sqrt(*rr);
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    s[i] = static_cast<T>(static_cast<double>(r[i]) * inv);
+__global__ void __launch_bounds__(NT)
+k_action_cg(const T* __restrict__ r, const double* __restrict__ rr, T* __restrict__ s, int64_t n) {
+  iter::action_cg<T>(r, rr, s, n, blockIdx.x, gridDim.x);
 }
 
 template <typename T>
-__global__ void k_fill_unit(T* __restrict__ s, int64_t n, int64_t idx) {
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    s[i] = (i == idx) ? T(1) : T(0);
+__global__ void __launch_bounds__(NT) k_fill_unit(T* __restrict__ s, int64_t n, int64_t idx) {
+  iter::fill_unit<T>(s, n, idx, blockIdx.x, gridDim.x);
 }
 
 template <typename T>
@@ -80,10 +55,8 @@ __global__ void k_fill_zero(T* __restrict__ a, int64_t n) {
 }
 
 template <typename T>
-__global__ void k_copy(const T* __restrict__ a, T* __restrict__ b, int64_t n) {
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    b[i] = a[i];
+__global__ void __launch_bounds__(NT) k_copy(const T* __restrict__ a, T* __restrict__ b, int64_t n) {
+  iter::copy<T>(a, b, n, blockIdx.x, gridDim.x);
 }
 
 template <typename T>
@@ -97,49 +70,19 @@ __global__ void k_add(const T* __restrict__ a, const T* __restrict__ b, T* __res
 // each lane accumulating GV_ROWS/64 consecutive-in-wave elements in FP64, a
 // single wave reduction per (column, chunk); chunk partials are summed in a
 // fixed order by k_finish_cols.
-constexpr int GV_ROWS = 4096;
-
 template <typename T>
 __global__ void __launch_bounds__(NT)
 k_gemv_t(const T* __restrict__ Q, int64_t ldq, int64_t n, int ncols, const T* __restrict__ z,
          double* __restrict__ part, int nchunks) {
-  const int lane = threadIdx.x & 63;
-  const int64_t wid = blockIdx.x * static_cast<int64_t>(NT / 64) + (threadIdx.x >> 6);
-  if (wid >= static_cast<int64_t>(nchunks) * ncols) return;
-  const int b = static_cast<int>(wid % ncols);
-  const int64_t chunk = wid / ncols;
-  const int64_t r0 = chunk * GV_ROWS;
-  const T* q = Q + static_cast<int64_t>(b) * ldq;
-  double acc0 = 0.0, acc1 = 0.0;
-#pragma unroll 4
-  for (int k = 0; k < GV_ROWS / 64; k += 2) {
-    const int64_t i0 = r0 + k * 64 + lane, i1 = i0 + 64;
-    if (i0 < n) acc0 += static_cast<double>(q[i0]) * static_cast<double>(z[i0]);
-    if (i1 < n) acc1 += static_cast<double>(q[i1]) * static_cast<double>(z[i1]);
-  }
-  const double s = wave_sum(acc0 + acc1);
-  if (lane == 0) part[chunk * ncols + b] = s;
+  iter::gemv_t<T>(Q, ldq, n, ncols, z, part, nchunks, blockIdx.x);
 }
 
 __global__ void k_finish_cols(const double* __restrict__ part, int nrow_blocks, int ncols,
                               double* __restrict__ y) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= ncols) return;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int r = 0;
-  for (; r + 4 <= nrow_blocks; r += 4) {
-    s0 += part[static_cast<int64_t>(r) * ncols + b];
-    s1 += part[static_cast<int64_t>(r + 1) * ncols + b];
-    s2 += part[static_cast<int64_t>(r + 2) * ncols + b];
-    s3 += part[static_cast<int64_t>(r + 3) * ncols + b];
-  }
-  for (; r < nrow_blocks; ++r) s0 += part[static_cast<int64_t>(r) * ncols + b];
-  y[b] = (s0 + s1) + (s2 + s3);
+  iter::finish_col(part, nrow_blocks, ncols, blockIdx.x * blockDim.x + threadIdx.x, y);
 }
 
 // d = s - Q y ; eta partial = z^T d.  One row per thread; y staged in LDS.
-constexpr int MAXCOLS_LDS = 4096;
-
 template <typename T, bool KQ>
 __global__ void __launch_bounds__(NT)
 k_dir_update(const T* __restrict__ sv, const T* __restrict__ Q, int64_t ldq, int64_t n,
@@ -148,38 +91,7 @@ k_dir_update(const T* __restrict__ sv, const T* __restrict__ Q, int64_t ldq, int
              const T* __restrict__ KQm, T* __restrict__ kd) {
   __shared__ double sy[MAXCOLS_LDS];
   __shared__ double red[NT / 64];
-  for (int b = threadIdx.x; b < ncols; b += NT) sy[b] = y[b];
-  __syncthreads();
-  const int64_t i = blockIdx.x * static_cast<int64_t>(NT) + threadIdx.x;
-  double e = 0.0;
-  if (i < n) {
-    double acc = 0.0, acck = 0.0;
-    int b = 0;
-    for (; b + 4 <= ncols; b += 4) {
-      const double q0 = Q[static_cast<int64_t>(b) * ldq + i];
-      const double q1 = Q[static_cast<int64_t>(b + 1) * ldq + i];
-      const double q2 = Q[static_cast<int64_t>(b + 2) * ldq + i];
-      const double q3 = Q[static_cast<int64_t>(b + 3) * ldq + i];
-      acc += q0 * sy[b] + q1 * sy[b + 1] + q2 * sy[b + 2] + q3 * sy[b + 3];
-      if constexpr (KQ) {
-        const double k0 = KQm[static_cast<int64_t>(b) * ldq + i];
-        const double k1 = KQm[static_cast<int64_t>(b + 1) * ldq + i];
-        const double k2 = KQm[static_cast<int64_t>(b + 2) * ldq + i];
-        const double k3 = KQm[static_cast<int64_t>(b + 3) * ldq + i];
-        acck += k0 * sy[b] + k1 * sy[b + 1] + k2 * sy[b + 2] + k3 * sy[b + 3];
-      }
-    }
-    for (; b < ncols; ++b) {
-      acc += static_cast<double>(Q[static_cast<int64_t>(b) * ldq + i]) * sy[b];
-      if constexpr (KQ) acck += static_cast<double>(KQm[static_cast<int64_t>(b) * ldq + i]) * sy[b];
-    }
-    const T di = static_cast<T>(static_cast<double>(sv[i]) - acc);
-    d[i] = di;
-    if constexpr (KQ) kd[i] = static_cast<T>(static_cast<double>(tv[i]) - acck);
-    e = static_cast<double>(z[i]) * static_cast<double>(di);
-  }
-  e = block_sum(e, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = e;
+  iter::dir_update<T, KQ>(sv, Q, ldq, n, ncols, y, z, d, part, tv, KQm, kd, blockIdx.x, sy, red);
 }
 
 template <typename T>
@@ -196,25 +108,11 @@ __global__ void k_gemv_n(const T* __restrict__ Q, int64_t ldq, int64_t n, int nc
 }
 
 template <typename T, bool KQ>
-__global__ void k_append_step(const T* __restrict__ d, const double* __restrict__ scal,
-                              T* __restrict__ qcol, T* __restrict__ v, int64_t n,
-                              const T* __restrict__ kd, T* __restrict__ kqcol,
-                              T* __restrict__ kv) {
-  const double eta = scal[SC_ETA];
-  if (!(eta > 0.0)) return;
-  const double qs = 1.0 / sqrt(eta);
-  const double step = scal[SC_ALPHA] / eta;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const double di = static_cast<double>(d[i]);
-    qcol[i] = static_cast<T>(di * qs);
-    v[i] = static_cast<T>(static_cast<double>(v[i]) + step * di);
-    if constexpr (KQ) {
-      const double ki = static_cast<double>(kd[i]);
-      kqcol[i] = static_cast<T>(ki * qs);
-      kv[i] = static_cast<T>(static_cast<double>(kv[i]) + step * ki);
-    }
-  }
+__global__ void __launch_bounds__(NT)
+k_append_step(const T* __restrict__ d, const double* __restrict__ scal, T* __restrict__ qcol,
+              T* __restrict__ v, int64_t n, const T* __restrict__ kd, T* __restrict__ kqcol,
+              T* __restrict__ kv) {
+  iter::append_step<T, KQ>(d, scal, qcol, v, n, kd, kqcol, kv, blockIdx.x, gridDim.x);
 }
 
 // Gram matrix M = A^T B over a chunk of rows; 32 x 32 output tile per block,

@@ -88,6 +88,30 @@ struct BatchProblem {
   int64_t tile_begin;       // prefix over problems of gx * nsplit
   int64_t out_begin;        // prefix over problems of n1 * W
 };
+// One model's part of a batched solver iteration (recurrence residual, FP32):
+// the vectors and scalars the per-iteration operations touch.
+struct BIter {
+  float *r, *s, *t, *z, *d, *v, *kv, *kd, *rhs, *wv, *Q, *KQ, *qcol, *kqcol;
+  const float* pi;          // softmax probabilities, or the diagonal of W^{-1}
+  const float* user;        // this iteration's user action (policy USER)
+  double *scal, *part, *yb;
+  int64_t n, N, ld, unit_idx;
+  int C, ncols, lik, policy, nchunks, pad;
+};
+// operations of a batched iteration, in launch order
+enum BIterOp {
+  BOP_ACTION = 0, BOP_DOT_ALPHA, BOP_FIN_ALPHA,               // s_j, alpha_j
+  BOP_WINV_Z, BOP_GEMV, BOP_FIN_COLS, BOP_DIR, BOP_FIN_ETA,   // z_j, Q^T z_j, d_j, eta_j
+  BOP_APPEND,                                                 // Q, K Q, v, K v
+  BOP_WINV_V, BOP_RESID, BOP_FIN_RR,                          // r_j, ||r_j||^2
+  BOP_COUNT
+};
+// blocks of operation `op` for one model (0: the model skips it)
+int64_t biter_blocks(int op, const BIter& t, bool residual);
+// runs operation `op` for nm models: tab[nm] (device), pre[nm + 1] (device,
+// prefix of biter_blocks), total = pre[nm]
+int biter_launch(int op, const BIter* tab, const int64_t* pre, int nm, int64_t total,
+                 hipStream_t s);
 bool batched_supported(int kind, int64_t d, int64_t W);
 void batched_plan(int64_t n1, int64_t n2, int64_t W, int ns, int64_t split_rows, BatchProblem* bp);
 int kv_batched_run(int kind, int dch, int ns, const BatchProblem* dprobs, int np, int64_t ntiles,
