@@ -494,13 +494,16 @@ __global__ void k_col_partial(const float* __restrict__ X, int64_t n, int d, int
   }
 }
 
-__global__ void k_col_finish(const double* __restrict__ part, int nblk, int d, int64_t n,
-                             float* __restrict__ mean) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= d) return;
+// one block per column: fixed-order sum of the block partials
+__global__ void __launch_bounds__(256)
+k_col_finish(const double* __restrict__ part, int nblk, int d, int64_t n,
+             float* __restrict__ mean) {
+  __shared__ double red[4];
+  const int k = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[static_cast<int64_t>(b) * d + k];
-  mean[k] = static_cast<float>(n > 0 ? s / n : 0.0);
+  for (int b = threadIdx.x; b < nblk; b += 256) s += part[static_cast<int64_t>(b) * d + k];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) mean[k] = static_cast<float>(n > 0 ? s / n : 0.0);
 }
 
 struct Plan {
@@ -608,8 +611,8 @@ int column_mean_f32(const float* X, int64_t n, int64_t d, float* mean, double* p
   const int64_t rows_per = ceil_div(n, nblk);
   nblk = ceil_div(n, rows_per);
   k_col_partial<<<static_cast<unsigned>(nblk), 256, 0, s>>>(X, n, static_cast<int>(d), rows_per, part);
-  k_col_finish<<<static_cast<unsigned>(ceil_div(d, 64)), 64, 0, s>>>(part, static_cast<int>(nblk),
-                                                                      static_cast<int>(d), n, mean);
+  k_col_finish<<<static_cast<unsigned>(d), 256, 0, s>>>(part, static_cast<int>(nblk),
+                                                         static_cast<int>(d), n, mean);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
