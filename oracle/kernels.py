@@ -96,3 +96,35 @@ def apply_full_kernel_cn(KX: np.ndarray, v: np.ndarray, C: int) -> np.ndarray:
         return (KX @ v.reshape(N, C)).reshape(-1)
     b = v.shape[1]
     return np.einsum("nm,mcb->ncb", KX, v.reshape(N, C, b)).reshape(N * C, b)
+
+
+# --- one kernel per latent function ------------------------------------------
+
+def kernel_matrices_per_class(X1, X2, kind: str, lengthscales, outputscales):
+    """K_c(X1, X2) for c < C: the same kernel family with class-specific
+    lengthscale and outputscale (independent GPs with their own
+    hyperparameters)."""
+    return [kernel_matrix(X1, X2, kind, l, o) for l, o in zip(lengthscales, outputscales)]
+
+
+def full_kernel_cn_per_class(Ks) -> np.ndarray:
+    """The NC x NC prior covariance in CN-ordering for C independent GPs with
+    kernels K_c: entry (n*C + c, m*C + c') = delta_{c c'} K_c[n, m], i.e.
+    sum_c K_c (x) e_c e_c^T."""
+    C = len(Ks)
+    N, M = Ks[0].shape
+    out = np.zeros((N * C, M * C))
+    for c, K in enumerate(Ks):
+        E = np.zeros((C, C))
+        E[c, c] = 1.0
+        out += np.kron(K, E)
+    return out
+
+
+def apply_kernel_per_class(Ks, v: np.ndarray) -> np.ndarray:
+    """(sum_c K_c (x) e_c e_c^T) v for CN-ordered v of length M*C (or (M*C, b))."""
+    C = len(Ks)
+    N, M = Ks[0].shape
+    V = v.reshape(M, C, -1)
+    out = np.stack([Ks[c] @ V[:, c, :] for c in range(C)], axis=1)   # (N, C, b)
+    return out.reshape(N * C) if v.ndim == 1 else out.reshape(N * C, -1)

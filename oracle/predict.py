@@ -52,6 +52,27 @@ def predictive_var_exact(Xs, X, Khat, C, kind, ell, os_):
     return (os_ - red).reshape(Xs.shape[0], C)
 
 
+def predictive_mean_per_class(Xs, X, v, kind, lengthscales, outputscales):
+    """Mean with one kernel per latent function: mean[s, c] = sum_n k_c(xs, x_n) v[n*C + c]."""
+    C = len(lengthscales)
+    V = v.reshape(X.shape[0], C)
+    return np.stack([kernel_matrix(Xs, X, kind, l, o) @ V[:, c]
+                     for c, (l, o) in enumerate(zip(lengthscales, outputscales))], axis=1)
+
+
+def predictive_var_root_per_class(Xs, X, Q, kind, lengthscales, outputscales):
+    """Marginal variances with C_j = Q Q^T and one kernel per latent function:
+    var[s, c] = k_c(xs, xs) - sum_b (sum_n k_c(xs, x_n) Q[n*C + c, b])^2."""
+    C = len(lengthscales)
+    N, b = X.shape[0], Q.shape[1]
+    Qr = Q.reshape(N, C, b)
+    out = []
+    for c, (l, o) in enumerate(zip(lengthscales, outputscales)):
+        A = kernel_matrix(Xs, X, kind, l, o) @ Qr[:, c, :]
+        out.append(o - (A * A).sum(axis=1))
+    return np.stack(out, axis=1)
+
+
 def probit_probs(mean: np.ndarray, var: np.ndarray) -> np.ndarray:
     z = mean / np.sqrt(1.0 + (math.pi / 8.0) * var)
     z = z - z.max(axis=1, keepdims=True)

@@ -97,3 +97,28 @@ def test_full_kernel_cn_ordering():
                     assert Kf[n * C + c, m * C + c2] == (KX[n, m] if c == c2 else 0.0)
     v = rng.standard_normal(12)
     np.testing.assert_allclose(ok.apply_full_kernel_cn(KX, v, C), Kf @ v, rtol=1e-14)
+
+
+def test_per_class_kernels_dense_definition_and_shared_limit():
+    """One kernel per latent function: the matrix-free apply equals the dense
+    block-diagonal (in NC-ordering) matrix re-indexed to CN-ordering, that
+    matrix is symmetric PSD with the class variances on its diagonal, and equal
+    hyperparameters reduce to the shared-kernel Kronecker form."""
+    rng = np.random.default_rng(21)
+    X = rng.standard_normal((30, 3))
+    ells, oss = [0.7, 1.3, 2.1], [0.5, 1.0, 1.7]
+    Ks = ok.kernel_matrices_per_class(X, X, "matern32", ells, oss)
+    Kf = ok.full_kernel_cn_per_class(Ks)
+    # entry by entry from the definition
+    for (n, c, m, c2) in [(0, 0, 0, 0), (3, 1, 7, 1), (5, 2, 5, 2), (4, 0, 9, 2), (2, 1, 2, 0)]:
+        want = ok.kernel_matrix(X[n:n + 1], X[m:m + 1], "matern32", ells[c], oss[c])[0, 0] \
+            if c == c2 else 0.0
+        assert abs(Kf[n * 3 + c, m * 3 + c2] - want) < 1e-15
+    assert np.allclose(Kf, Kf.T) and np.linalg.eigvalsh(Kf).min() > -1e-10
+    assert np.allclose(np.diag(Kf), np.tile(oss, 30))
+    v = rng.standard_normal((90, 4))
+    np.testing.assert_allclose(ok.apply_kernel_per_class(Ks, v), Kf @ v, rtol=1e-13, atol=1e-13)
+    Ks1 = ok.kernel_matrices_per_class(X, X, "rbf", [0.9] * 3, [1.2] * 3)
+    np.testing.assert_allclose(ok.full_kernel_cn_per_class(Ks1),
+                               ok.full_kernel_cn(ok.kernel_matrix(X, X, "rbf", 0.9, 1.2), 3),
+                               rtol=1e-15, atol=1e-15)

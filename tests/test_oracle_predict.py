@@ -59,3 +59,20 @@ def test_probit_limits():
     np.testing.assert_allclose(p1, 0.25, atol=1e-5)
     ent = lambda p: -(p * np.log(p)).sum(1)
     assert np.all(ent(op.probit_probs(m, np.full_like(m, 3.0))) >= ent(p0) - 1e-12)
+
+
+def test_per_class_predictions_match_dense_definition():
+    rng = np.random.default_rng(22)
+    X, Xs = rng.standard_normal((25, 2)), rng.standard_normal((7, 2))
+    ells, oss = [0.6, 1.4], [0.8, 1.9]
+    C = 2
+    v = rng.standard_normal(25 * C)
+    Q = rng.standard_normal((25 * C, 6))
+    Kx = ok.full_kernel_cn_per_class(ok.kernel_matrices_per_class(Xs, X, "rbf", ells, oss))
+    Kss = ok.full_kernel_cn_per_class(ok.kernel_matrices_per_class(Xs, Xs, "rbf", ells, oss))
+    mean = (Kx @ v).reshape(7, C)
+    var = np.diag(Kss - Kx @ Q @ Q.T @ Kx.T).reshape(7, C)
+    np.testing.assert_allclose(op.predictive_mean_per_class(Xs, X, v, "rbf", ells, oss), mean,
+                               rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(op.predictive_var_root_per_class(Xs, X, Q, "rbf", ells, oss), var,
+                               rtol=1e-12, atol=1e-11)
