@@ -76,8 +76,12 @@ typedef enum igp_precision { IGP_FP64 = 0, IGP_FP32 = 1, IGP_BF16 = 2 } igp_prec
  * i.e. Out[n*C + c + b*ldo] = sum_m k(x1_n, x2_m) V[m*C + c + b*ldv] (+ beta*Out).
  * This is the product w -> K w that Algorithms 1 and 2 take as input (the
  * paper's appendix on matrix-vector products: K is evaluated lazily and
- * never formed; cost quadratic in N).
- *   kp      kernel and hyperparameters.
+ * never formed; cost quadratic in N).  With n_kp == C each latent function
+ * has its own kernel k_c (same family, its own lengthscale and outputscale):
+ * Out[n*C + c] = sum_m k_c(x1_n, x2_m) V[m*C + c] (FP64 and FP32; the
+ * direct-difference kernel evaluates the C kernels on shared distances).
+ *   kp      kernel and hyperparameters: n_kp entries, n_kp == 1 (shared by
+ *           all classes) or n_kp == C (one per class, one kernel family).
  *   X1      n1 x d row-major (device), X2 n2 x d row-major (device).
  *   V       nb vectors of length n2*C, vector b at V + b*ldv (ldv >= n2*C).
  *   Out     nb vectors of length n1*C, vector b at Out + b*ldo (ldo >= n1*C);
@@ -87,12 +91,13 @@ typedef enum igp_precision { IGP_FP64 = 0, IGP_FP32 = 1, IGP_BF16 = 2 } igp_prec
  *   ws      device workspace of at least glm_kernel_matmul_ws_bytes(...) bytes.
  * n1 == 0 or nb == 0 is a no-op; n2 == 0 gives Out = beta*Out.
  * Errors: IGP_EINVAL (NULL pointer with non-zero size, d < 1, C < 1,
- * ld too small, non-positive hyperparameter), IGP_ENOMEM (ws too small),
- * IGP_EDEVICE (launch failure).
+ * ld too small, non-positive hyperparameter, n_kp not 1 or C, mixed kernel
+ * families), IGP_EUNSUPPORTED (n_kp > 1 with IGP_BF16), IGP_ENOMEM (ws too
+ * small), IGP_EDEVICE (launch failure).
  * ====================================================================== */
 size_t glm_kernel_matmul_ws_bytes(int64_t n1, int64_t n2, int64_t d, int64_t C,
                                   int64_t nb, int32_t precision);
-int glm_kernel_matmul(const igp_kernel_params* kp,
+int glm_kernel_matmul(const igp_kernel_params* kp, int32_t n_kp,
                       const void* X1, int64_t n1, const void* X2, int64_t n2, int64_t d,
                       const void* V, int64_t C, int64_t nb, int64_t ldv,
                       void* Out, int64_t ldo, double beta, int32_t precision,
@@ -182,6 +187,10 @@ typedef struct igp_model igp_model;
 size_t itergp_state_bytes(int64_t N, int64_t D, int64_t C, const igp_solver_config* cfg);
 
 /* Create a model with f_0 = m = 0 and empty buffers (Algorithm 1, start).
+ *   kp     n_kp kernel parameter sets: 1 (shared by all latent functions) or
+ *          C (one per latent function, one kernel family; the products then
+ *          run on the direct-difference kernel and the batched form is not
+ *          available; not with IGP_BF16).
  *   X      N x D row-major (double for IGP_FP64, float otherwise); copied
  *          into the arena, the caller may free it after the call returns.
  *   y      observations (see igp_likelihood): N int32 labels in [0, C) for
@@ -191,7 +200,8 @@ size_t itergp_state_bytes(int64_t N, int64_t D, int64_t C, const igp_solver_conf
  *   arena  device memory of >= itergp_state_bytes(...) bytes, 256-byte
  *          aligned, owned by the caller, alive for the model's lifetime.
  * Synchronises `stream`.  The model runs all its work on `stream`. */
-int itergp_init(igp_model** out, const igp_kernel_params* kp, const igp_solver_config* cfg,
+int itergp_init(igp_model** out, const igp_kernel_params* kp, int32_t n_kp,
+                const igp_solver_config* cfg,
                 const void* X, const void* y, int64_t N, int64_t D, int64_t C,
                 void* arena, size_t arena_bytes, hipStream_t stream);
 

@@ -71,13 +71,13 @@ SIGNATURES = {
     "igp_last_error": (ct.c_char_p, []),
     "igp_version": (ct.c_char_p, []),
     "glm_kernel_matmul_ws_bytes": (_SZ, [_I64, _I64, _I64, _I64, _I64, _I32]),
-    "glm_kernel_matmul": (ct.c_int, [ct.POINTER(KernelParams), _P, _I64, _P, _I64, _I64, _P,
+    "glm_kernel_matmul": (ct.c_int, [ct.POINTER(KernelParams), _I32, _P, _I64, _P, _I64, _I64, _P,
                                      _I64, _I64, _I64, _P, _I64, ct.c_double, _I32, _P, _SZ,
                                      _P]),
     "glm_softmax_hessian_apply": (ct.c_int, [_P, _I64, _I64, _P, _I64, _I64, _P, _I64, _I32,
                                              _I32, _P]),
     "itergp_state_bytes": (_SZ, [_I64, _I64, _I64, ct.POINTER(SolverConfig)]),
-    "itergp_init": (ct.c_int, [ct.POINTER(_P), ct.POINTER(KernelParams),
+    "itergp_init": (ct.c_int, [ct.POINTER(_P), ct.POINTER(KernelParams), _I32,
                                ct.POINTER(SolverConfig), _P, _P, _I64, _I64, _I64, _P, _SZ, _P]),
     "itergp_set_user_actions": (ct.c_int, [_P, _P, _I64, _I64]),
     "itergp_newton_step": (ct.c_int, [_P, ct.POINTER(StepInfo)]),

@@ -41,8 +41,22 @@ def _need(t: torch.Tensor, dtype, name):
         raise ValueError(f"{name} must be contiguous")
 
 
-def kernel_params(kind, lengthscale, outputscale) -> L.KernelParams:
-    return L.KernelParams(_kind(kind), 0, float(lengthscale), float(outputscale))
+def kernel_params(kind, lengthscale, outputscale, C: int = 1):
+    """(array of KernelParams, n_kp): one set shared by all classes, or one per
+    class when lengthscale or outputscale is a sequence of C values."""
+    per = [isinstance(a, (list, tuple)) or (hasattr(a, "__len__") and not isinstance(a, str))
+           for a in (lengthscale, outputscale)]
+    if not any(per):
+        arr = (L.KernelParams * 1)(L.KernelParams(_kind(kind), 0, float(lengthscale),
+                                                  float(outputscale)))
+        return arr, 1
+    ls = list(lengthscale) if per[0] else [lengthscale] * C
+    os_ = list(outputscale) if per[1] else [outputscale] * C
+    if len(ls) != C or len(os_) != C:
+        raise ValueError(f"per-class hyperparameters need {C} values")
+    arr = (L.KernelParams * C)(*[L.KernelParams(_kind(kind), 0, float(a), float(b))
+                                 for a, b in zip(ls, os_)])
+    return arr, C
 
 
 def glm_kernel_matmul(X1: torch.Tensor, X2: torch.Tensor, V: torch.Tensor, C: int, kind,
@@ -70,8 +84,8 @@ def glm_kernel_matmul(X1: torch.Tensor, X2: torch.Tensor, V: torch.Tensor, C: in
     O2 = out.view(nb, n1 * C)
     wsb = lib.glm_kernel_matmul_ws_bytes(n1, n2, d, C, nb, p)
     ws = torch.empty(max(int(wsb), 1), dtype=torch.uint8, device=X1.device)
-    kp = kernel_params(kind, lengthscale, outputscale)
-    L.check(lib.glm_kernel_matmul(ct.byref(kp), _ptr(X1), n1, _ptr(X2), n2, d, _ptr(V2), C, nb,
+    kp, n_kp = kernel_params(kind, lengthscale, outputscale, C)
+    L.check(lib.glm_kernel_matmul(kp, n_kp, _ptr(X1), n1, _ptr(X2), n2, d, _ptr(V2), C, nb,
                                   n2 * C, _ptr(O2), n1 * C, float(beta), p, _ptr(ws), wsb,
                                   _stream()))
     return out.view(-1) if vec else out
@@ -136,14 +150,14 @@ class IterNCGP:
         self.N, self.D = X.shape
         self.C = int(C)
         self.y = y                       # kept alive: the model reads it every step
-        self.kp = kernel_params(kind, lengthscale, outputscale)
+        self.kp, self.n_kp = kernel_params(kind, lengthscale, outputscale, self.C)
         nbytes = self.lib.itergp_state_bytes(self.N, self.D, self.C, ct.byref(self.cfg))
         if nbytes == 0:
             raise ValueError("invalid model configuration")
         self.arena = torch.empty(int(nbytes), dtype=torch.uint8, device=X.device)
         self.stream = torch.cuda.current_stream()   # the model runs all its work here
         self.handle = ct.c_void_p()
-        L.check(self.lib.itergp_init(ct.byref(self.handle), ct.byref(self.kp),
+        L.check(self.lib.itergp_init(ct.byref(self.handle), self.kp, self.n_kp,
                                      ct.byref(self.cfg), _ptr(X), _ptr(y), self.N, self.D,
                                      self.C, _ptr(self.arena), nbytes, _stream()))
         self._user = None

@@ -13,9 +13,9 @@ int newton_step_batched(igp_model* const* models, int n, igp_step_info* infos, v
                         size_t ws_bytes);
 std::string batched_tuning_json();
 size_t state_bytes(int64_t N, int64_t D, int64_t C, const igp_solver_config* cfg);
-int model_init(igp_model** out, const igp_kernel_params* kp, const igp_solver_config* cfg,
-               const void* X, const void* y, int64_t N, int64_t D, int64_t C, void* arena,
-               size_t arena_bytes, hipStream_t stream);
+int model_init(igp_model** out, const igp_kernel_params* kp, int n_kp,
+               const igp_solver_config* cfg, const void* X, const void* y, int64_t N, int64_t D,
+               int64_t C, void* arena, size_t arena_bytes, hipStream_t stream);
 
 namespace {
 thread_local std::string g_error;
@@ -71,13 +71,18 @@ size_t glm_kernel_matmul_ws_bytes(int64_t n1, int64_t n2, int64_t d, int64_t C, 
   return kv_ws_bytes(n1, n2, d, C, nb, precision);
 }
 
-int glm_kernel_matmul(const igp_kernel_params* kp, const void* X1, int64_t n1, const void* X2,
-                      int64_t n2, int64_t d, const void* V, int64_t C, int64_t nb, int64_t ldv,
-                      void* Out, int64_t ldo, double beta, int32_t precision, void* ws,
-                      size_t ws_bytes, hipStream_t stream) {
+int glm_kernel_matmul(const igp_kernel_params* kp, int32_t n_kp, const void* X1, int64_t n1,
+                      const void* X2, int64_t n2, int64_t d, const void* V, int64_t C,
+                      int64_t nb, int64_t ldv, void* Out, int64_t ldo, double beta,
+                      int32_t precision, void* ws, size_t ws_bytes, hipStream_t stream) {
   return guarded([&]() -> int {
     clear_error();
-    IGP_TRY(check_kp(kp));
+    IGP_REQUIRE(n_kp == 1 || (n_kp == C && C <= 64), "n_kp must be 1 or C (<= 64), got %d",
+                n_kp);
+    for (int c = 0; c < n_kp; ++c) {
+      IGP_TRY(check_kp(kp ? kp + c : nullptr));
+      IGP_REQUIRE(kp[c].kind == kp[0].kind, "per-class kernels must share one kernel family");
+    }
     IGP_REQUIRE(n1 >= 0 && n2 >= 0 && nb >= 0, "negative size");
     IGP_REQUIRE(d >= 1 && C >= 1, "d and C must be >= 1");
     IGP_REQUIRE(precision >= IGP_FP64 && precision <= IGP_BF16, "unknown precision %d", precision);
@@ -93,6 +98,10 @@ int glm_kernel_matmul(const igp_kernel_params* kp, const void* X1, int64_t n1, c
     }
     KVProblem p{};
     p.kp = *kp;
+    if (n_kp > 1) {
+      p.kpc = kp;
+      p.n_kp = n_kp;
+    }
     p.precision = precision;
     p.X1 = X1;
     p.X2 = X2;
@@ -136,12 +145,12 @@ size_t itergp_state_bytes(int64_t N, int64_t D, int64_t C, const igp_solver_conf
   return state_bytes(N, D, C, cfg);
 }
 
-int itergp_init(igp_model** out, const igp_kernel_params* kp, const igp_solver_config* cfg,
-                const void* X, const void* y, int64_t N, int64_t D, int64_t C, void* arena,
-                size_t arena_bytes, hipStream_t stream) {
+int itergp_init(igp_model** out, const igp_kernel_params* kp, int32_t n_kp,
+                const igp_solver_config* cfg, const void* X, const void* y, int64_t N,
+                int64_t D, int64_t C, void* arena, size_t arena_bytes, hipStream_t stream) {
   return guarded([&]() -> int {
     clear_error();
-    return model_init(out, kp, cfg, X, y, N, D, C, arena, arena_bytes, stream);
+    return model_init(out, kp, n_kp, cfg, X, y, N, D, C, arena, arena_bytes, stream);
   });
 }
 

@@ -99,6 +99,9 @@ Layout<T> carve(Carver& cv, int64_t N, int64_t D, int64_t C, const igp_solver_co
 template <typename T>
 struct Model final : igp_model {
   igp_kernel_params kp{};
+  std::vector<igp_kernel_params> kps;   // one per class when n_kp == C > 1
+  int n_kp = 1;
+  std::vector<double> prior_var;        // k_c(x, x) per class
   igp_solver_config cfg{};
   int64_t N = 0, D = 0, C = 0, n = 0, ld = 0;
   const void* y = nullptr;       // observations (igp_likelihood decides the type)
@@ -180,6 +183,10 @@ struct Model final : igp_model {
       p.norm2 = L.nrm;
     }
     p.kp = kp;
+    if (n_kp > 1) {
+      p.kpc = kps.data();
+      p.n_kp = n_kp;
+    }
     p.precision = cfg.precision;
     p.X1 = X1;
     p.X2 = L.X;
@@ -597,7 +604,7 @@ struct Model final : igp_model {
         pv.fixed_split = true;
         IGP_TRY(kv_launch(pv, ws2, w2, s));
       }
-      IGP_TRY(predict_epilogue<T>(A, Ns * C, Ns * C, ncols, kp.outputscale, mean, Ns, C,
+      IGP_TRY(predict_epilogue<T>(A, Ns * C, Ns * C, ncols, prior_var.data(), mean, Ns, C,
                                   static_cast<T*>(var_), static_cast<T*>(probs_), s));
     }
     return IGP_OK;
@@ -964,13 +971,20 @@ __global__ void k_check_labels(const int32_t* y, int64_t N, int C, int* bad) {
     if (y[i] < 0 || y[i] >= C) atomicAdd(bad, 1);
 }
 
-int validate_common(const igp_kernel_params* kp, const igp_solver_config* cfg, int64_t N,
-                    int64_t D, int64_t C) {
+int validate_common(const igp_kernel_params* kp, int n_kp, const igp_solver_config* cfg,
+                    int64_t N, int64_t D, int64_t C) {
   IGP_REQUIRE(kp && cfg, "NULL kernel params or config");
-  IGP_REQUIRE(kp->kind >= IGP_RBF && kp->kind <= IGP_MATERN52, "unknown kernel kind %d", kp->kind);
-  IGP_REQUIRE(std::isfinite(kp->lengthscale) && kp->lengthscale > 0 &&
-                  std::isfinite(kp->outputscale) && kp->outputscale > 0,
-              "kernel hyperparameters must be finite and positive");
+  IGP_REQUIRE(n_kp == 1 || n_kp == C, "n_kp must be 1 or C, got %d", n_kp);
+  for (int c = 0; c < n_kp; ++c) {
+    IGP_REQUIRE(kp[c].kind >= IGP_RBF && kp[c].kind <= IGP_MATERN52, "unknown kernel kind %d",
+                kp[c].kind);
+    IGP_REQUIRE(kp[c].kind == kp[0].kind, "per-class kernels must share one kernel family");
+    IGP_REQUIRE(std::isfinite(kp[c].lengthscale) && kp[c].lengthscale > 0 &&
+                    std::isfinite(kp[c].outputscale) && kp[c].outputscale > 0,
+                "kernel hyperparameters must be finite and positive");
+  }
+  IGP_REQUIRE(n_kp == 1 || cfg->precision != IGP_BF16,
+              "one kernel per class is not supported in BF16 mode");
   IGP_REQUIRE(N >= 1 && D >= 1 && C >= 1, "N, D, C must be >= 1");
   IGP_REQUIRE(C <= 64, "C must be <= 64");
   IGP_REQUIRE(cfg->policy >= IGP_POLICY_CG && cfg->policy <= IGP_POLICY_USER, "unknown policy");
@@ -992,18 +1006,25 @@ int validate_common(const igp_kernel_params* kp, const igp_solver_config* cfg, i
   return IGP_OK;
 }
 
+// prepared (centred, padded) rows feed the matrix-core products; one kernel per
+// class runs on the direct-difference kernel instead
+bool model_prepared(int precision, int kind, int64_t D, int n_kp) {
+  return n_kp == 1 && kv_uses_prepared(precision, kind, D);
+}
+
 template <typename T>
-size_t state_bytes_t(int64_t N, int64_t D, int64_t C, const igp_solver_config& cfg, int kind) {
+size_t state_bytes_t(int64_t N, int64_t D, int64_t C, const igp_solver_config& cfg, int kind,
+                     int n_kp = 1) {
   Carver cv(nullptr, 0);
-  carve<T>(cv, N, D, C, cfg, kv_uses_prepared(cfg.precision, kind, D));
+  carve<T>(cv, N, D, C, cfg, model_prepared(cfg.precision, kind, D, n_kp));
   return cv.used + 256;
 }
 
 template <typename T>
-int init_t(igp_model** out, const igp_kernel_params* kp, const igp_solver_config* cfg,
+int init_t(igp_model** out, const igp_kernel_params* kp, int n_kp, const igp_solver_config* cfg,
            const void* X, const void* y, int64_t N, int64_t D, int64_t C, void* arena,
            size_t arena_bytes, hipStream_t stream) {
-  const size_t need = state_bytes_t<T>(N, D, C, *cfg, kp->kind);
+  const size_t need = state_bytes_t<T>(N, D, C, *cfg, kp->kind, n_kp);
   if (arena_bytes < need) {
     set_error("arena too small: need %zu bytes, have %zu", need, arena_bytes);
     return IGP_ENOMEM;
@@ -1011,6 +1032,9 @@ int init_t(igp_model** out, const igp_kernel_params* kp, const igp_solver_config
   IGP_REQUIRE(reinterpret_cast<uintptr_t>(arena) % 256 == 0, "arena must be 256-byte aligned");
   auto m = std::make_unique<Model<T>>();
   m->kp = *kp;
+  m->n_kp = n_kp;
+  m->kps.assign(kp, kp + n_kp);
+  for (int64_t c = 0; c < C; ++c) m->prior_var.push_back(kp[n_kp > 1 ? c : 0].outputscale);
   m->cfg = *cfg;
   m->N = N;
   m->D = D;
@@ -1020,7 +1044,7 @@ int init_t(igp_model** out, const igp_kernel_params* kp, const igp_solver_config
   m->y = y;
   m->stream = stream;
   Carver cv(arena, arena_bytes);
-  m->prepared = kv_uses_prepared(cfg->precision, kp->kind, D);
+  m->prepared = model_prepared(cfg->precision, kp->kind, D, n_kp);
   m->L = carve<T>(cv, N, D, C, *cfg, m->prepared);
   IGP_CHECK_HIP(hipMemcpyAsync(m->L.X, X, N * D * sizeof(T), hipMemcpyDeviceToDevice, stream));
   if (m->prepared) {
@@ -1062,16 +1086,16 @@ size_t state_bytes(int64_t N, int64_t D, int64_t C, const igp_solver_config* cfg
                   state_bytes_t<float>(N, D, C, *cfg, IGP_MATERN12));
 }
 
-int model_init(igp_model** out, const igp_kernel_params* kp, const igp_solver_config* cfg,
-               const void* X, const void* y, int64_t N, int64_t D, int64_t C, void* arena,
-               size_t arena_bytes, hipStream_t stream) {
+int model_init(igp_model** out, const igp_kernel_params* kp, int n_kp,
+               const igp_solver_config* cfg, const void* X, const void* y, int64_t N, int64_t D,
+               int64_t C, void* arena, size_t arena_bytes, hipStream_t stream) {
   IGP_REQUIRE(out, "NULL output handle");
   *out = nullptr;
-  IGP_TRY(validate_common(kp, cfg, N, D, C));
+  IGP_TRY(validate_common(kp, n_kp, cfg, N, D, C));
   IGP_REQUIRE(X && y && arena, "NULL X, y or arena");
   if (cfg->precision == IGP_FP64)
-    return init_t<double>(out, kp, cfg, X, y, N, D, C, arena, arena_bytes, stream);
-  return init_t<float>(out, kp, cfg, X, y, N, D, C, arena, arena_bytes, stream);
+    return init_t<double>(out, kp, n_kp, cfg, X, y, N, D, C, arena, arena_bytes, stream);
+  return init_t<float>(out, kp, n_kp, cfg, X, y, N, D, C, arena, arena_bytes, stream);
 }
 
 }  // namespace igp

@@ -9,6 +9,7 @@
 // staged in LDS.  Partial sums per split are reduced in a fixed order by
 // kv_reduce, so results do not depend on scheduling.
 #include <algorithm>
+#include <type_traits>
 
 #include "ops.hpp"
 
@@ -19,11 +20,18 @@ constexpr int TM = 64;    // rows of X1 per workgroup
 constexpr int TN = 64;    // columns of X2 per tile
 constexpr int DC = 32;    // feature chunk staged in LDS
 
-template <typename T, int KIND, int WC>
+// class-specific 1/l^2 and outputscale, passed by value (C <= 64)
+template <typename T>
+struct ClassParams {
+  T il2[64];
+  T os[64];
+};
+
+template <typename T, int KIND, int WC, bool PC = false>
 __global__ void __launch_bounds__(256)
 kv_valu(const T* __restrict__ X1, const T* __restrict__ X2, int64_t n1, int64_t n2, int d,
         const T* __restrict__ V, int C, int W, int64_t ldv, T* __restrict__ P,
-        int64_t cols_per_split, T inv_l2, const int* skip) {
+        int64_t cols_per_split, T inv_l2, const int* skip, ClassParams<T> cp) {
   if (skip && *skip) return;
   constexpr int TILE_BYTES = 2 * TM * (DC + 1) * sizeof(T);
   constexpr int RED_BYTES = 4 * TM * WC * sizeof(T);
@@ -42,6 +50,16 @@ kv_valu(const T* __restrict__ X1, const T* __restrict__ X2, int64_t n1, int64_t 
   T acc[WC];
 #pragma unroll
   for (int w = 0; w < WC; ++w) acc[w] = T(0);
+  // one kernel per class: column w belongs to class (w0 + w) % C
+  T il2w[PC ? WC : 1], osw[PC ? WC : 1];
+  if constexpr (PC) {
+#pragma unroll
+    for (int w = 0; w < WC; ++w) {
+      const int c = (w0 + w) % C;
+      il2w[w] = cp.il2[c];
+      osw[w] = cp.os[c];
+    }
+  }
 
   for (int64_t m0 = m_begin; m0 < m_end; m0 += TN) {
     T r2[16];
@@ -76,9 +94,15 @@ kv_valu(const T* __restrict__ X1, const T* __restrict__ X2, int64_t n1, int64_t 
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
-      const T kv = kfun<KIND>(r2[c] * inv_l2);
+      if constexpr (PC) {
 #pragma unroll
-      for (int w = 0; w < WC; ++w) acc[w] += kv * sV[wv * 16 + c][w];
+        for (int w = 0; w < WC; ++w)
+          acc[w] += osw[w] * kfun<KIND>(r2[c] * il2w[w]) * sV[wv * 16 + c][w];
+      } else {
+        const T kv = kfun<KIND>(r2[c] * inv_l2);
+#pragma unroll
+        for (int w = 0; w < WC; ++w) acc[w] += kv * sV[wv * 16 + c][w];
+      }
     }
     __syncthreads();
   }
@@ -156,15 +180,26 @@ void launch_valu_kind(const KVProblem& p, const SplitPlan& sp, T* P, hipStream_t
   const T* X2 = static_cast<const T*>(p.X2);
   const T* V = static_cast<const T*>(p.V);
   const int d = static_cast<int>(p.d), C = static_cast<int>(p.C);
-  if (sp.wc == 4)
-    kv_valu<T, KIND, 4><<<grid, 256, 0, s>>>(X1, X2, p.n1, p.n2, d, V, C, W, p.ldv, P,
-                                             sp.cols_per_split, inv_l2, p.skip);
-  else if (sp.wc == 8)
-    kv_valu<T, KIND, 8><<<grid, 256, 0, s>>>(X1, X2, p.n1, p.n2, d, V, C, W, p.ldv, P,
-                                             sp.cols_per_split, inv_l2, p.skip);
-  else
-    kv_valu<T, KIND, 16><<<grid, 256, 0, s>>>(X1, X2, p.n1, p.n2, d, V, C, W, p.ldv, P,
-                                              sp.cols_per_split, inv_l2, p.skip);
+  ClassParams<T> cp{};
+  const bool pc = p.n_kp > 1;
+  if (pc)
+    for (int c = 0; c < C; ++c) {
+      cp.il2[c] = static_cast<T>(1.0 / (p.kpc[c].lengthscale * p.kpc[c].lengthscale));
+      cp.os[c] = static_cast<T>(p.kpc[c].outputscale);
+    }
+  auto go = [&](auto wc, auto pcv) {
+    kv_valu<T, KIND, decltype(wc)::value, decltype(pcv)::value><<<grid, 256, 0, s>>>(
+        X1, X2, p.n1, p.n2, d, V, C, W, p.ldv, P, sp.cols_per_split, inv_l2, p.skip, cp);
+  };
+  using F = std::false_type;
+  using Tr = std::true_type;
+  if (sp.wc == 4) {
+    if (pc) go(std::integral_constant<int, 4>{}, Tr{}); else go(std::integral_constant<int, 4>{}, F{});
+  } else if (sp.wc == 8) {
+    if (pc) go(std::integral_constant<int, 8>{}, Tr{}); else go(std::integral_constant<int, 8>{}, F{});
+  } else {
+    if (pc) go(std::integral_constant<int, 16>{}, Tr{}); else go(std::integral_constant<int, 16>{}, F{});
+  }
 }
 
 template <typename T>
@@ -190,10 +225,11 @@ int launch_valu(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t s) {
   int blocks = static_cast<int>(ceil_div(total, 256));
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
+  // with one kernel per class the outputscales are applied inside the product
+  const T os = p.n_kp > 1 ? T(1) : static_cast<T>(p.kp.outputscale);
   kv_reduce<T><<<blocks, 256, 0, s>>>(P, sp.nsplit, p.n1, static_cast<int>(W),
-                                      static_cast<int>(p.C), static_cast<T*>(p.Out), p.ldo,
-                                      static_cast<T>(p.kp.outputscale), static_cast<T>(p.beta),
-                                      p.skip);
+                                      static_cast<int>(p.C), static_cast<T*>(p.Out), p.ldo, os,
+                                      static_cast<T>(p.beta), p.skip);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
@@ -305,6 +341,20 @@ int launch_mfma_path(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t 
 
 int kv_launch(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t s) {
   if (p.n1 == 0 || p.nb == 0) return IGP_OK;
+  if (p.n_kp > 1) {
+    // one kernel per class: the direct-difference kernel evaluates each class's
+    // kernel on the shared distances (FP64 and FP32)
+    IGP_REQUIRE(p.kpc && p.n_kp == p.C && p.C <= 64,
+                "one kernel per class needs n_kp == C <= 64 parameter sets");
+    for (int c = 0; c < p.n_kp; ++c)
+      IGP_REQUIRE(p.kpc[c].kind == p.kp.kind, "per-class kernels must share one kernel family");
+    if (p.precision == IGP_BF16) {
+      set_error("one kernel per class is not supported in BF16 mode");
+      return IGP_EUNSUPPORTED;
+    }
+    if (p.precision == IGP_FP64) return launch_valu<double>(p, ws, ws_bytes, s);
+    return launch_valu<float>(p, ws, ws_bytes, s);
+  }
   if (p.precision == IGP_FP64) return launch_valu<double>(p, ws, ws_bytes, s);
   if (kv_uses_prepared(p.precision, p.kp.kind, p.d)) return launch_mfma_path(p, ws, ws_bytes, s);
   return launch_valu<float>(p, ws, ws_bytes, s);

@@ -239,9 +239,13 @@ k_newton_stats(const T* __restrict__ fnew, const T* __restrict__ f, const T* __r
   s = block_sum(gv, red); if (threadIdx.x == 0) part[3 * nb + blockIdx.x] = s;
 }
 
+struct PriorVar {
+  double v[64];   // k_c(x, x) per class
+};
+
 template <typename T>
 __global__ void k_predict_epilogue(const T* __restrict__ A, int64_t lda, int64_t nrows,
-                                   int ncols, double os, const T* __restrict__ mean, int64_t Ns,
+                                   int ncols, PriorVar os, const T* __restrict__ mean, int64_t Ns,
                                    int C, T* __restrict__ var, T* __restrict__ probs) {
   const int64_t s = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (s >= Ns) return;
@@ -254,7 +258,7 @@ __global__ void k_predict_epilogue(const T* __restrict__ A, int64_t lda, int64_t
       const double a = static_cast<double>(A[static_cast<int64_t>(b) * lda + row]);
       acc += a * a;
     }
-    const double vv = os - acc;
+    const double vv = os.v[c] - acc;
     if (var) var[row] = static_cast<T>(vv);
     if (probs) {
       const double vz = vv > 0.0 ? vv : 0.0;
@@ -440,12 +444,15 @@ int newton_stats(const T* fnew, const T* f, const T* v, const int32_t* y, int64_
 }
 
 template <typename T>
-int predict_epilogue(const T* A, int64_t lda, int64_t nrows, int ncols, double os, const T* mean,
-                     int64_t Ns, int64_t C, T* var, T* probs, hipStream_t s) {
+int predict_epilogue(const T* A, int64_t lda, int64_t nrows, int ncols, const double* os_c,
+                     const T* mean, int64_t Ns, int64_t C, T* var, T* probs, hipStream_t s) {
   (void)nrows;
   if (Ns == 0) return IGP_OK;
+  IGP_REQUIRE(C <= 64, "C must be <= 64");
+  PriorVar pv{};
+  for (int c = 0; c < C; ++c) pv.v[c] = os_c[c];
   k_predict_epilogue<T><<<static_cast<unsigned>(ceil_div(Ns, 128)), 128, 0, s>>>(
-      A, lda, nrows, ncols, os, mean, Ns, static_cast<int>(C), var, probs);
+      A, lda, nrows, ncols, pv, mean, Ns, static_cast<int>(C), var, probs);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
@@ -473,7 +480,7 @@ int predict_epilogue(const T* A, int64_t lda, int64_t nrows, int ncols, double o
                             const double*, T*, int64_t, hipStream_t);                          \
   template int newton_stats<T>(const T*, const T*, const T*, const int32_t*, int64_t, int64_t, \
                                double*, double*, hipStream_t);                                 \
-  template int predict_epilogue<T>(const T*, int64_t, int64_t, int, double, const T*, int64_t, \
+  template int predict_epilogue<T>(const T*, int64_t, int64_t, int, const double*, const T*, int64_t, \
                                    int64_t, T*, T*, hipStream_t);
 IGP_INST(float)
 IGP_INST(double)

@@ -41,6 +41,10 @@ struct KVProblem {
   const float* norm1 = nullptr;
   const float* norm2 = nullptr;
   const int* skip = nullptr;
+  // one kernel per latent function (same family, class-specific lengthscale and
+  // outputscale): kpc[c] for c < C when n_kp == C > 1
+  const igp_kernel_params* kpc = nullptr;
+  int n_kp = 1;
   // split the X2 rows into fixed 4096-row ranges regardless of n1, so that each
   // output row is summed in the same order whatever rows share the launch
   bool fixed_split = false;
@@ -219,8 +223,9 @@ template <typename T>
 int newton_stats(const T* fnew, const T* f, const T* v, const int32_t* y, int64_t N,
                  int64_t C, double* partials, double* scal, hipStream_t s);
 // predict epilogue: var = os - sum_b A_b^2 ; probs = softmax(mean / sqrt(1 + pi/8 var))
+// os_c: the prior variance k_c(x, x) of each class (C values, host)
 template <typename T>
-int predict_epilogue(const T* A, int64_t lda, int64_t nrows, int ncols, double os,
+int predict_epilogue(const T* A, int64_t lda, int64_t nrows, int ncols, const double* os_c,
                      const T* mean, int64_t Ns, int64_t C, T* var, T* probs, hipStream_t s);
 
 // ---- host FP64 symmetric eigensolver ---------------------------------------------

@@ -56,31 +56,41 @@ def test_state_bytes_queries():
 def test_argument_errors_without_device_work():
     lib = L.load()
     kp = L.KernelParams(L.IGP_RBF, 0, -1.0, 1.0)
-    rc = lib.glm_kernel_matmul(ct.byref(kp), None, 4, None, 4, 2, None, 1, 1, 4, None, 4, 0.0,
+    rc = lib.glm_kernel_matmul(ct.byref(kp), 1, None, 4, None, 4, 2, None, 1, 1, 4, None, 4, 0.0,
                                L.IGP_FP32, None, 0, None)
     assert rc == L.IGP_EINVAL
     assert b"hyperparameters" in lib.igp_last_error()
     kp = L.KernelParams(7, 0, 1.0, 1.0)
-    assert lib.glm_kernel_matmul(ct.byref(kp), None, 4, None, 4, 2, None, 1, 1, 4, None, 4, 0.0,
+    assert lib.glm_kernel_matmul(ct.byref(kp), 1, None, 4, None, 4, 2, None, 1, 1, 4, None, 4, 0.0,
                                  L.IGP_FP32, None, 0, None) == L.IGP_EINVAL
     kp = L.KernelParams(L.IGP_RBF, 0, 1.0, 1.0)
     # empty problems are no-ops that touch nothing
-    assert lib.glm_kernel_matmul(ct.byref(kp), None, 0, None, 4, 2, None, 1, 1, 4, None, 4, 0.0,
+    assert lib.glm_kernel_matmul(ct.byref(kp), 1, None, 0, None, 4, 2, None, 1, 1, 4, None, 4, 0.0,
                                  L.IGP_FP32, None, 0, None) == L.IGP_OK
     assert lib.glm_softmax_hessian_apply(None, 0, 3, None, 1, 0, None, 0, L.IGP_W_PINV,
                                          L.IGP_FP32, None) == L.IGP_OK
     assert lib.glm_softmax_hessian_apply(None, 4, 3, None, 1, 12, None, 12, 5, L.IGP_FP32,
                                          None) == L.IGP_EINVAL
+    # one kernel per class: n_kp must be 1 or C, one kernel family
+    kp3 = (L.KernelParams * 3)(L.KernelParams(L.IGP_RBF, 0, 1.0, 1.0),
+                               L.KernelParams(L.IGP_RBF, 0, 2.0, 1.0),
+                               L.KernelParams(L.IGP_MATERN32, 0, 1.0, 1.0))
+    assert lib.glm_kernel_matmul(kp3, 2, None, 4, None, 4, 2, None, 3, 1, 12, None, 12, 0.0,
+                                 L.IGP_FP32, None, 0, None) == L.IGP_EINVAL
+    assert b"n_kp" in lib.igp_last_error()
+    assert lib.glm_kernel_matmul(kp3, 3, None, 4, None, 4, 2, None, 3, 1, 12, None, 12, 0.0,
+                                 L.IGP_FP32, None, 0, None) == L.IGP_EINVAL
+    assert b"family" in lib.igp_last_error()
     h = ct.c_void_p()
     cfg = L.SolverConfig(0, 10, -1, 1, 1e-5, 1e-5, L.IGP_FP32, 0, 5, 0)   # max_buffer < j_max
-    assert lib.itergp_init(ct.byref(h), ct.byref(kp), ct.byref(cfg), ct.c_void_p(1),
+    assert lib.itergp_init(ct.byref(h), ct.byref(kp), 1, ct.byref(cfg), ct.c_void_p(1),
                            ct.c_void_p(1), 10, 2, 3, ct.c_void_p(256), 1 << 30,
                            None) == L.IGP_EINVAL
     assert b"max_buffer" in lib.igp_last_error()
     for lik, noise, msg in ((7, 1.0, b"likelihood"), (L.IGP_LIK_GAUSSIAN, 0.0, b"noise_var"),
                             (L.IGP_LIK_GAUSSIAN, float("nan"), b"noise_var")):
         cfg = L.SolverConfig(0, 10, -1, 1, 1e-5, 1e-5, L.IGP_FP32, 0, 20, lik, noise)
-        assert lib.itergp_init(ct.byref(h), ct.byref(kp), ct.byref(cfg), ct.c_void_p(1),
+        assert lib.itergp_init(ct.byref(h), ct.byref(kp), 1, ct.byref(cfg), ct.c_void_p(1),
                                ct.c_void_p(1), 10, 2, 1, ct.c_void_p(256), 1 << 30,
                                None) == L.IGP_EINVAL
         assert msg in lib.igp_last_error()
