@@ -43,7 +43,8 @@ KV_INSTANCE = None
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors read off a 256 MiB device
 # copy in the same run; profiles/kv_matern52_N20000_D16_C5_fp32.md).  Keyed by
 # the kernel instance it was measured on; any other instance reports null.
-MEASURED_TRAFFIC = {("kv_mfma_f32_narrow<3,1,5,2>", "fp32"): 46.23e6}
+MEASURED_TRAFFIC = {("kv_mfma_f32_narrow<3,1,5,2>", "fp32"): 46.23e6,
+                    ("kv_bf16_kernel<0>", "bf16"): 24.00e9}
 
 
 def valu_slots_per_eval(kind: str, W: int) -> int:
@@ -400,7 +401,8 @@ def bench_image(args):
                    "lengthscale": w.lengthscale, "zero_frac": w.meta.get("zero_frac"),
                    "precision": prec, "residual": args.residual},
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": BF16_MFMA_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": tflops / BF16_MFMA_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": tflops / BF16_MFMA_PEAK_TFLOPS,
+                     "traffic": MEASURED_TRAFFIC.get(("kv_bf16_kernel<0>", prec)),
                      "kernel": "fused K.v, BF16 distance GEMM (2 N^2 (D + C) flops per product)",
                      "avg_launch_us": kv_avg_s * 1e6},
         "kv_error_vs_fp64": {"rel_l2_64_rows": kv_err},
@@ -490,6 +492,12 @@ def bench_serving(args):
                      "newton_steps_per_s": 2 * n_fit / span})
         if frac == args.load[0]:
             first = tk
+            slow = sorted((t for t in tk if t.kind == "predict"), key=lambda t: -t.latency)[:5]
+            runs[-1]["slowest_predicts"] = [
+                {"rows": t.rows, "latency_ms": round(t.latency * 1e3, 2),
+                 "queued_ms": round((t.t_start - t.t_arrive) * 1e3, 2),
+                 "fits_running": sum(1 for f in tk if f.kind == "fit" and f.t_start <= t.t_done
+                                     and f.t_done >= t.t_start)} for t in slow]
     # alone vs in the mix, on a few of the served queries (tolerance: bitwise)
     mism = 0
     for t in [t for t in first if t.kind == "predict"][:8]:
