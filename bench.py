@@ -39,10 +39,11 @@ VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes x clock
 KV_INSTANCE = None
 
 
-# HBM bytes per launch of the solver product, from two rocprofv3 --pmc runs
+# Bytes beyond L2 per launch of the product, from two rocprofv3 --pmc runs
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors read off a 256 MiB device
-# copy in the same run; profiles/kv_matern52_N20000_D16_C5_fp32.md).  Keyed by
-# the kernel instance it was measured on; any other instance reports null.
+# copy in the same run; profiles/kv_matern52_N20000_D16_C5_fp32.md and
+# profiles/kv_bf16_rbf_N60000_D784_C10.md).  Keyed by the kernel instance it
+# was measured on; any other instance reports null.
 MEASURED_TRAFFIC = {("kv_mfma_f32_narrow<3,1,5,2>", "fp32"): 46.23e6,
                     ("kv_bf16_kernel<0>", "bf16"): 24.00e9}
 
