@@ -217,6 +217,21 @@ int itergp_set_user_actions(igp_model* m, const void* actions, int64_t ncols, in
  * Host control flow; synchronises the model's stream.  info may be NULL. */
 int itergp_newton_step(igp_model* m, igp_step_info* info);
 
+/* The same Newton step in three calls, so that a caller (a scheduler sharing
+ * the GPU, a progress monitor) can do other work between solver iterations:
+ *   itergp_newton_step_begin    pseudo-targets, Algorithm 3, v_0 and r_0;
+ *   itergp_newton_step_iterate  up to max_iters iterations of Algorithm 2;
+ *                               done (nullable) = 1 once the solver has stopped
+ *                               (tolerance, j_max, breakdown, actions used up);
+ *   itergp_newton_step_end      f = K v + m and the step record (info nullable);
+ *                               IGP_EINVAL unless the solver has stopped.
+ * Between the calls itergp_predict gives the IterGP posterior at the current
+ * iteration; itergp_compress and the batched step refuse a model in a step.
+ * Each call synchronises the model's stream. */
+int itergp_newton_step_begin(igp_model* m);
+int itergp_newton_step_iterate(igp_model* m, int64_t max_iters, int32_t* done);
+int itergp_newton_step_end(igp_model* m, igp_step_info* info);
+
 /* Compression of the fitted state for serving (Algorithm 3 alone): the
  * virtual solver run over the stored buffer S, T with W(f)^+ at the current
  * iterate f, keeping at most rank_limit eigendirections (-1: all above the

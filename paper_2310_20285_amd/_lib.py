@@ -82,6 +82,9 @@ SIGNATURES = {
     "itergp_set_user_actions": (ct.c_int, [_P, _P, _I64, _I64]),
     "itergp_newton_step": (ct.c_int, [_P, ct.POINTER(StepInfo)]),
     "itergp_compress": (ct.c_int, [_P, _I32, ct.POINTER(_I32)]),
+    "itergp_newton_step_begin": (ct.c_int, [_P]),
+    "itergp_newton_step_iterate": (ct.c_int, [_P, _I64, ct.POINTER(_I32)]),
+    "itergp_newton_step_end": (ct.c_int, [_P, ct.POINTER(StepInfo)]),
     "itergp_predict_ws_bytes": (_SZ, [_P, _I64]),
     "itergp_predict": (ct.c_int, [_P, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
     "itergp_get_view": (ct.c_int, [_P, _I32, ct.POINTER(_P), ct.POINTER(_I64),

@@ -173,6 +173,22 @@ class IterNCGP:
         L.check(self.lib.itergp_newton_step(self.handle, ct.byref(info)))
         return info.as_dict()
 
+    def step_begin(self) -> None:
+        """itergp_newton_step_begin: the start of a Newton step."""
+        L.check(self.lib.itergp_newton_step_begin(self.handle))
+
+    def step_iterate(self, max_iters: int = 1) -> bool:
+        """Up to max_iters solver iterations; True once the solver has stopped."""
+        done = ct.c_int32()
+        L.check(self.lib.itergp_newton_step_iterate(self.handle, int(max_iters), ct.byref(done)))
+        return bool(done.value)
+
+    def step_end(self) -> dict:
+        """itergp_newton_step_end: f = K v + m and the step record."""
+        info = L.StepInfo()
+        L.check(self.lib.itergp_newton_step_end(self.handle, ct.byref(info)))
+        return info.as_dict()
+
     def set_profiling(self, enable: bool = True):
         L.check(self.lib.itergp_set_profiling(self.handle, 1 if enable else 0))
 

@@ -169,6 +169,27 @@ int itergp_newton_step(igp_model* m, igp_step_info* info) {
   });
 }
 
+int itergp_newton_step_begin(igp_model* m) {
+  return guarded([&]() -> int {
+    IGP_REQUIRE(m, "NULL model");
+    return m->step_begin();
+  });
+}
+
+int itergp_newton_step_iterate(igp_model* m, int64_t max_iters, int32_t* done) {
+  return guarded([&]() -> int {
+    IGP_REQUIRE(m, "NULL model");
+    return m->step_iterate(max_iters, done);
+  });
+}
+
+int itergp_newton_step_end(igp_model* m, igp_step_info* info) {
+  return guarded([&]() -> int {
+    IGP_REQUIRE(m, "NULL model");
+    return m->step_end(info);
+  });
+}
+
 int itergp_compress(igp_model* m, int32_t rank_limit, int32_t* kept) {
   return guarded([&]() -> int {
     IGP_REQUIRE(m, "NULL model");

@@ -3,6 +3,7 @@
 // operation running in the library's HIP kernels and only B x B algebra and
 // scalar control on the host.
 #include <algorithm>
+#include <cstdint>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -501,8 +502,15 @@ struct Model final : igp_model {
   KVProblem product_action() const { return kv_problem(L.X, N, s_col(), 1, n, t_col(), n); }
   KVProblem product_update() const { return kv_problem(L.X, N, L.v, 1, n, L.fnew, n); }
 
-  int newton_step(igp_step_info* info_out) override {
+  // A Newton step in three parts, so that a caller can interleave other work
+  // between solver iterations: begin (pseudo-targets, Algorithm 3, v_0, r_0),
+  // iterate (up to max_iters iterations of Algorithm 2), end (f = K v + m and
+  // the step's statistics).  newton_step runs the three back to back.
+  bool in_step = false;
+
+  int step_begin() override {
     clear_error();
+    IGP_REQUIRE(!in_step, "a Newton step is already in progress");
     IGP_TRY(phase_begin());
     IGP_TRY(phase_vsr_gram());
     IGP_TRY(phase_vsr_fetch());
@@ -511,7 +519,15 @@ struct Model final : igp_model {
     IGP_TRY(phase_v0());
     IGP_TRY(read_scalars(sc));
     phase_start_iterations();
-    for (;;) {
+    in_step = true;
+    return IGP_OK;
+  }
+
+  int step_iterate(int64_t max_iters, int32_t* done) override {
+    clear_error();
+    IGP_REQUIRE(in_step, "no Newton step in progress");
+    IGP_REQUIRE(max_iters >= 0, "max_iters must be >= 0");
+    for (int64_t k = 0; k < max_iters; ++k) {
       IGP_TRY(phase_can_act());
       if (!st.active) break;
       IGP_TRY(phase_action());
@@ -520,10 +536,29 @@ struct Model final : igp_model {
       IGP_TRY(read_scalars(sc));
       phase_consume();
     }
+    if (done) {
+      IGP_TRY(phase_can_act());
+      *done = st.active ? 0 : 1;
+    }
+    return IGP_OK;
+  }
+
+  int step_end(igp_step_info* info_out) override {
+    clear_error();
+    IGP_REQUIRE(in_step, "no Newton step in progress");
+    IGP_TRY(phase_can_act());
+    IGP_REQUIRE(!st.active, "the solver has not finished: iterate until done");
+    in_step = false;
     IGP_TRY(apply_K(L.v, L.fnew));
     IGP_TRY(phase_stats());
     IGP_TRY(read_scalars(sc));
     return phase_finish(info_out);
+  }
+
+  int newton_step(igp_step_info* info_out) override {
+    IGP_TRY(step_begin());
+    IGP_TRY(step_iterate(INT64_MAX, nullptr));
+    return step_end(info_out);
   }
 
   // Algorithm 3 on its own: the virtual solver run over the stored buffer with
@@ -531,6 +566,7 @@ struct Model final : igp_model {
   // at), keeping at most rank_limit directions; v and f are left as they are.
   int compress(int32_t rank_limit, int32_t* kept) override {
     clear_error();
+    IGP_REQUIRE(!in_step, "compress during a Newton step");
     IGP_REQUIRE(rank_limit >= -1, "rank_limit must be >= -1");
     // W at f; the pseudo-targets it also forms go to scratch (rhs is kept)
     IGP_TRY(likelihood_terms(L.wv));
@@ -893,6 +929,7 @@ int batch_models(igp_model* const* models, int n, std::vector<Model<float>*>* ou
                 "model %d: all models of a batch share kernel family, feature count class and "
                 "stream", i);
     for (auto* o : *out) IGP_REQUIRE(o != m, "model %d appears twice", i);
+    IGP_REQUIRE(!m->in_step, "model %d is in the middle of a Newton step", i);
     out->push_back(m);
   }
   return IGP_OK;

@@ -15,6 +15,9 @@ struct igp_model {
   virtual int set_profiling(int enable) = 0;
   virtual int get_profile(igp_profile* out) const = 0;
   virtual int compress(int32_t rank_limit, int32_t* kept) = 0;
+  virtual int step_begin() = 0;
+  virtual int step_iterate(int64_t max_iters, int32_t* done) = 0;
+  virtual int step_end(igp_step_info* info) = 0;
 };
 
 namespace igp {

@@ -13,7 +13,10 @@ Device work:
   soon as a slot frees up.  A query larger than a batch is served in pieces.
 * Fits (Algorithm 1 on new training data) run in worker threads, each on its
   own stream with its own model, and overlap the prediction batches on the
-  device.  The library releases the interpreter lock inside its calls.
+  device.  The library releases the interpreter lock inside its calls.  A fit
+  advances a few solver iterations at a time and, between them, waits while
+  prediction batches are queued or running (at most ``fit_yield_ms`` per
+  slice), so that queries do not queue behind a fit's products.
 
 Admission: the resident model and the prediction slots are charged to the HBM
 budget when the server starts.  A fit is charged its model arena plus its
@@ -170,10 +173,13 @@ class Server:
     fit_workers     fits running at a time
     fit_config      solver configuration of fits (api.solver_config keywords),
                     plus "steps" (Newton steps per fit)
+    fit_slice       solver iterations a fit runs between checks for queries
+    fit_yield_ms    longest a fit waits for queries per slice (0: no yielding)
     """
 
     def __init__(self, model: api.IterNCGP, budget_bytes: int, max_batch_rows: int = 8192,
-                 slots: int = 2, fit_workers: int = 2, fit_config: Optional[dict] = None):
+                 slots: int = 2, fit_workers: int = 2, fit_config: Optional[dict] = None,
+                 fit_slice: int = 2, fit_yield_ms: float = 25.0):
         self.model = model
         self.device = model.arena.device
         self.budget = HBMBudget(budget_bytes)
@@ -194,6 +200,8 @@ class Server:
         self.fit_streams = [torch.cuda.Stream(device=self.device) for _ in range(fit_workers)]
         self.fit_config = dict(fit_config or {})
         self.fit_steps = int(self.fit_config.pop("steps", 2))
+        self.fit_slice = max(int(fit_slice), 1)
+        self.fit_yield_s = max(float(fit_yield_ms), 0.0) / 1e3
         self.tickets: List[Ticket] = []
         self._running = 0
         self._lock = threading.Lock()
@@ -293,7 +301,14 @@ class Server:
                 y = torch.from_numpy(p["y"]).to(self.device)
                 m = api.IterNCGP(X, y, p["C"], p["kind"], p["lengthscale"], p["outputscale"],
                                  **self.fit_config)
-                infos = [m.newton_step() for _ in range(self.fit_steps)]
+                infos = []
+                for _ in range(self.fit_steps):
+                    m.step_begin()
+                    while True:
+                        self._yield_to_queries()
+                        if m.step_iterate(self.fit_slice):
+                            break
+                    infos.append(m.step_end())
                 f = m.view(L.IGP_VIEW_F).cpu().numpy().reshape(t.rows, p["C"])
             t.result = {"f": f, "steps": infos}
             t.status = "done"
@@ -306,6 +321,15 @@ class Server:
             with self._lock:
                 self._running -= 1
                 self.fit_streams.append(s)
+
+    def _yield_to_queries(self) -> None:
+        """Called by fit workers between solver slices: wait while prediction
+        batches are queued or on the device, for at most fit_yield_ms."""
+        if self.fit_yield_s <= 0.0:
+            return
+        t_end = time.perf_counter() + self.fit_yield_s
+        while (self.pq or self.inflight) and time.perf_counter() < t_end:
+            time.sleep(5e-5)
 
     def _admit_fits(self) -> bool:
         with self._lock:

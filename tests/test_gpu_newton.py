@@ -143,3 +143,34 @@ def test_fp32_user_replay_matches_fp64_oracle(gpu_lib, residual):
     mean, var, _ = m.predict(Xs, probs=False)
     mref = op.predictive_mean(w.Xs, w.X, recs[-1].v, w.C, w.kernel, w.lengthscale, w.outputscale)
     assert _rel(mean.double().cpu().numpy(), mref) <= 1e-4
+
+
+def test_step_in_parts_equals_whole_step(gpu_lib):
+    """itergp_newton_step_begin / _iterate / _end give bitwise the iterates of
+    itergp_newton_step; the order of the calls is enforced."""
+    w = datagen.config2(N=1500, Ns=10)
+    kw = dict(policy="cg", j_max=40, rank_limit=20, recycle=True, precision="fp32",
+              residual_mode="recurrence")
+    a, _ = _model(w, w.X, **kw)
+    b, _ = _model(w, w.X, **kw)
+    from paper_2310_20285_amd._lib import IterGPError
+    for step in range(3):
+        ia = a.newton_step()
+        b.step_begin()
+        with pytest.raises(IterGPError):
+            b.step_begin()
+        with pytest.raises(IterGPError):
+            b.compress(5)
+        parts = 0
+        while not b.step_iterate(3):
+            parts += 1
+            if parts == 1:
+                # the posterior at the current iteration is available mid-step
+                mean, _, _ = b.predict(torch.tensor(w.Xs, dtype=torch.float32, device="cuda"),
+                                       var=False, probs=False)
+                assert torch.isfinite(mean).all()
+        ib = b.step_end()
+        with pytest.raises(IterGPError):
+            b.step_end()
+        assert ia["iters"] == ib["iters"]
+        assert torch.equal(a.view(0), b.view(0)) and torch.equal(a.view(2), b.view(2))
