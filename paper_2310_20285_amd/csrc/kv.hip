@@ -315,7 +315,14 @@ int launch_mfma_path(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t 
     IGP_TRY(column_mean_f32(static_cast<const float*>(p.X2), p.n2, p.d, centre, part,
                             MEAN_PART_BLOCKS * p.d, s));
     IGP_TRY(prep_rows_any(p.precision, static_cast<const float*>(p.X1), p.n1, p.d, centre, b1, m1, s));
-    IGP_TRY(prep_rows_any(p.precision, static_cast<const float*>(p.X2), p.n2, p.d, centre, b2, m2, s));
+    if (p.X1 == p.X2 && p.n1 == p.n2) {
+      // one point set on both sides: one prepared copy (the products may then
+      // use the symmetric kernel)
+      b2 = b1;
+      m2 = m1;
+    } else {
+      IGP_TRY(prep_rows_any(p.precision, static_cast<const float*>(p.X2), p.n2, p.d, centre, b2, m2, s));
+    }
     X1p = b1; n1p = m1; X2p = b2; n2p = m2;
   }
   if (!cv.fits() || !ws) {

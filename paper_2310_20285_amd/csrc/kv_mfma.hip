@@ -388,6 +388,273 @@ kv_mfma_f32_narrow(const float* __restrict__ X1p, const float* __restrict__ nrm1
                                  cdot);
 }
 
+// ---- symmetric product K(X, X) V ----------------------------------------------
+// When both row sets are the same points, each kernel value k(x_n, x_m) serves
+// two outputs, Out[n] += k V[m] and Out[m] += k V[n], so every unordered pair
+// of rows is evaluated once.  The rows are cut into I-blocks of 64 NS rows (one
+// workgroup pass: four waves x NS strips of 16) and super-blocks of G I-blocks;
+// the workgroups take the pairs (s, u), u >= s, of super-blocks.  A workgroup
+// runs one pass per I-block of super-block s, streaming the rows of super-block
+// u through LDS (on the pair u == s only the rows from the I-block itself on,
+// and inside the I-block -- the 128 x 128 diagonal tile -- only the direct sum).
+//
+// The distance MFMA is issued with the register rows as A, so lane (r, g) holds
+// k(n = 16 st + 4g + v, m = r) in accumulator register v of strip st -- the
+// B-operand layout of an MFMA whose k-index runs over n:
+//   direct      acc[st][v][w] += k V[m][w] on VALU FMAs (summed over the 16
+//               lanes r of a lane row once per pass);
+//   transposed  D[w][m] += V[n][w] k(n, m) on v_mfma_f32_16x16x4f32, one per
+//               (st, v), with lane (r, g) supplying V[16 st + 4g + v][w = r] as
+//               A; lanes (r, g < WX / 4) add their four D values (w = 4g ..
+//               4g + 3, m = r) to this wave's slice of an LDS slab [m][w] with
+//               one 128-bit read and write (the four slices are added in wave
+//               order when the slab is written out).
+// Partials: slot u of row n in super-block s holds the direct sum of the pair
+// (s, u); slot s of row m in super-block u > s holds the transposed sum of the
+// pair (s, u); on the pair (s, s) the slab is added to the direct sum of each
+// I-block when it is written.  Every row thus has exactly Q slots, each written
+// once, and kv_reduce adds them in slot order: the product is deterministic.
+constexpr int SYM_NS = 2;                 // strips per wave: I-blocks of 128 rows
+constexpr int SYM_MAX_Q = 128;            // super-blocks (partial slots per row)
+constexpr size_t SYM_MAX_LDS = 48 * 1024;
+
+__device__ inline float row16_sum(float x) {
+  // sum over the 16 lanes of a lane row (rotations by 8, 4, 2, 1, each one
+  // v_add_f32 with a DPP source); every lane holds the sum, each lane always
+  // in the same order
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xF, 0xF, true));
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x124, 0xF, 0xF, true));
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x122, 0xF, 0xF, true));
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x121, 0xF, 0xF, true));
+  return x;
+}
+
+template <int DCH, int WX>
+struct SymLayout {
+  static constexpr int DP = DCH * 16;
+  static constexpr int XS = DP + 4;       // LDS row stride of the X2 tile
+  static constexpr int VS = TN + 1;       // LDS row stride of the V tile, stored [w][m]
+  static constexpr int FIXED = 2 * TN * XS + 2 * TN + 2 * WX * VS;   // floats before the slab
+  static constexpr int SW = WX <= 4 ? 4 : 8;   // slab row: the output columns, padded
+};
+
+template <int KIND, int DCH, int WX>
+__global__ void __launch_bounds__(256)
+kv_mfma_f32_sym(const float* __restrict__ Xp, const float* __restrict__ nrm, int64_t n,
+                const float* __restrict__ V, int C, int64_t ldv, float* __restrict__ P, int G,
+                int Q, float cnorm, float cdot, const int* skip) {
+  if (skip && *skip) return;
+  using L = SymLayout<DCH, WX>;
+  constexpr int NS = SYM_NS;
+  constexpr int DP = L::DP, XS = L::XS, VS = L::VS;
+  constexpr int XQT = TN * DP / 4 / 256;   // float4 of X2 per thread per tile (= DCH)
+  constexpr int VT = TN * WX;
+  constexpr int VE = (VT + 255) / 256;
+  constexpr int IB = 64 * NS;
+  extern __shared__ __align__(16) float smem[];
+  float* sX = smem;                        // [2][TN * XS]
+  float* sN = sX + 2 * TN * XS;            // [2][TN]
+  float* sV = sN + 2 * TN;                 // [2][WX * VS]
+  constexpr int SW = L::SW;
+  const int64_t ST = static_cast<int64_t>(G) * IB;
+  float* slab = smem + L::FIXED;           // [4 waves][ST][SW]
+  const int SLICE = static_cast<int>(ST) * SW;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, r = lane & 15;
+
+  // workgroup -> pair (s, u): items s Q - s (s - 1) / 2 ... precede super-block s
+  const int t = static_cast<int>(blockIdx.x);
+  int lo = 0, hi = Q - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (mid * Q - mid * (mid - 1) / 2 <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  const int s = lo;
+  const int u = s + (t - (s * Q - s * (s - 1) / 2));
+  const bool diag_item = u == s;
+  const int64_t j_lo = u * ST;
+  const int64_t j_hi = (u + 1) * ST < n ? (u + 1) * ST : n;
+
+  for (int e = tid; e < 4 * SLICE; e += 256) slab[e] = 0.0f;
+  float* myslab = slab + wave * SLICE;
+
+  int vm[VE], vdst[VE];
+  int64_t voff[VE];
+#pragma unroll
+  for (int q = 0; q < VE; ++q) {
+    const int e = tid + q * 256;
+    const int w = e % WX;
+    vm[q] = e < VT ? e / WX : TN;   // TN marks an unused slot
+    vdst[q] = w * VS + (e < VT ? e / WX : 0);
+    voff[q] = static_cast<int64_t>(w / C) * ldv + (w % C);
+  }
+
+  f4 px[XQT];
+  float pv[VE];
+  float pn = 0.0f;
+  auto fetch = [&](int64_t m0, int64_t m_end) {
+#pragma unroll
+    for (int q = 0; q < XQT; ++q) {
+      const int e = tid + q * 256;
+      const int row = e / (DP / 4), col = e % (DP / 4);
+      const int64_t m = m0 + row;
+      px[q] = m < m_end ? *reinterpret_cast<const f4*>(Xp + m * DP + col * 4) : f4{0, 0, 0, 0};
+    }
+    if (tid < TN) {
+      const int64_t m = m0 + tid;
+      pn = m < m_end ? nrm[m] * cnorm : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < VE; ++q) {
+      const int64_t gm = m0 + vm[q];
+      pv[q] = (vm[q] < TN && gm < m_end) ? V[voff[q] + gm * C] : 0.0f;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < XQT; ++q) {
+      const int e = tid + q * 256;
+      const int row = e / (DP / 4), col = e % (DP / 4);
+      *reinterpret_cast<f4*>(&sX[buf * TN * XS + row * XS + col * 4]) = px[q];
+    }
+    if (tid < TN) sN[buf * TN + tid] = pn;
+#pragma unroll
+    for (int q = 0; q < VE; ++q)
+      if (vm[q] < TN) sV[buf * WX * VS + vdst[q]] = pv[q];
+  };
+
+  for (int k = 0; k < G; ++k) {
+    const int64_t ib0 = s * ST + static_cast<int64_t>(k) * IB;
+    if (ib0 >= n) break;
+    const int64_t row0 = ib0 + wave * (16 * NS);
+    // this wave's rows: A operand (row 16 st + r), norms and V of rows 16 st + 4g + v
+    f4 xa[NS][DCH];
+    float n1v[NS][4];
+    float a1[NS][4];   // V[16 st + 4g + v][w = r]: A operand of the transposed MFMA
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+      const int64_t na = row0 + st * 16 + r;
+#pragma unroll
+      for (int c = 0; c < DCH; ++c)
+        xa[st][c] = na < n ? *reinterpret_cast<const f4*>(Xp + na * DP + 16 * c + 4 * g)
+                           : f4{0, 0, 0, 0};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t nb = row0 + st * 16 + 4 * g + v;
+        const bool ok = nb < n;
+        n1v[st][v] = ok ? nrm[nb] * cnorm : 0.0f;
+        a1[st][v] = (ok && r < WX) ? V[static_cast<int64_t>(r / C) * ldv + (r % C) + nb * C] : 0.0f;
+      }
+    }
+    float acc[NS][4][WX];
+#pragma unroll
+    for (int st = 0; st < NS; ++st)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int w = 0; w < WX; ++w) acc[st][v][w] = 0.0f;
+
+    const int64_t m_begin = diag_item ? ib0 : j_lo;
+    const int64_t m_end = j_hi;
+    const int64_t direct_only_end = diag_item ? ib0 + IB : m_begin;
+    fetch(m_begin, m_end);
+    stash(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t m0 = m_begin; m0 < m_end; m0 += TN) {
+      const bool more = m0 + TN < m_end;
+      if (more) fetch(m0 + TN, m_end);
+      const bool both = m0 >= direct_only_end;
+      const float* bX = sX + buf * TN * XS;
+      const float* bN = sN + buf * TN;
+      const float* bV = sV + buf * WX * VS;
+#pragma unroll 1
+      for (int mb = 0; mb < TN / 16; ++mb) {
+        f4 dd[NS];
+#pragma unroll
+        for (int st = 0; st < NS; ++st) dd[st] = f4{0, 0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < DCH; ++c) {
+          const f4 b = *reinterpret_cast<const f4*>(&bX[(mb * 16 + r) * XS + 16 * c + 4 * g]);
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int st = 0; st < NS; ++st)
+              dd[st] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[st][c][kk], b[kk], dd[st], 0, 0, 0);
+        }
+        const float n2v = bN[mb * 16 + r];
+        float vm2[WX];
+#pragma unroll
+        for (int w = 0; w < WX; ++w) vm2[w] = bV[w * VS + mb * 16 + r];
+        f4 kk[NS];
+#pragma unroll
+        for (int st = 0; st < NS; ++st)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            kk[st][v] = ktransform<KIND>(__builtin_fmaf(dd[st][v], cdot, n1v[st][v] + n2v));
+#pragma unroll
+            for (int w = 0; w < WX; ++w)
+              acc[st][v][w] = __builtin_fmaf(kk[st][v], vm2[w], acc[st][v][w]);
+          }
+        if (both) {
+          // lane (r, g) receives D[w = 4g + j][m = r], j < 4
+          f4* dst = reinterpret_cast<f4*>(myslab + ((m0 - j_lo) + mb * 16 + r) * SW + 4 * g);
+          const bool mine = 4 * g < SW;
+          f4 old = {0, 0, 0, 0};
+          if (mine) old = *dst;
+          f4 tr = {0, 0, 0, 0};
+#pragma unroll
+          for (int st = 0; st < NS; ++st)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              tr = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[st][v], kk[st][v], tr, 0, 0, 0);
+          if (mine) *dst = old + tr;
+        }
+      }
+      if (more) stash(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+    // direct sums of this I-block -> slot u (plus, on the diagonal pair, the
+    // transposed sums its rows received from the earlier I-blocks)
+#pragma unroll
+    for (int st = 0; st < NS; ++st)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int w = 0; w < WX; ++w) acc[st][v][w] = row16_sum(acc[st][v][w]);
+    // lane r of the row writes output column w = r
+#pragma unroll
+    for (int st = 0; st < NS; ++st)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float x = acc[st][v][0];
+#pragma unroll
+        for (int w = 1; w < WX; ++w) x = r == w ? acc[st][v][w] : x;
+        const int64_t nb = row0 + st * 16 + 4 * g + v;
+        if (r < WX && nb < n) {
+          if (diag_item) {
+            const int o = static_cast<int>(nb - j_lo) * SW + r;
+            x += (slab[o] + slab[SLICE + o]) + (slab[2 * SLICE + o] + slab[3 * SLICE + o]);
+          }
+          P[(static_cast<int64_t>(u) * n + nb) * WX + r] = x;
+        }
+      }
+  }
+  if (!diag_item) {
+    // transposed sums of super-block u -> slot s (every pass ended with a barrier)
+    const int64_t rows = j_hi - j_lo;
+    for (int64_t e = tid; e < rows * WX; e += 256) {
+      const int ml = static_cast<int>(e / WX), w = static_cast<int>(e % WX);
+      const int o = ml * SW + w;
+      P[(static_cast<int64_t>(s) * n + j_lo + ml) * WX + w] =
+          (slab[o] + slab[SLICE + o]) + (slab[2 * SLICE + o] + slab[3 * SLICE + o]);
+    }
+  }
+}
+
 // ---- persistent batched launch -------------------------------------------------
 // Every product of a batch (independent problems of different sizes, output
 // widths and hyperparameters; same kernel family and feature count) is cut
@@ -534,6 +801,65 @@ Plan plan_mfma(int64_t n1, int64_t n2, int64_t d, int64_t W, bool fixed = false)
   return p;
 }
 
+// Symmetric plan: G I-blocks per super-block, Q super-blocks, Q (Q + 1) / 2
+// workgroups.  G grows with n so that there are about 4000 workgroups, within
+// 48 KB of LDS for the slab; beyond SYM_MAX_Q super-blocks the partial slots
+// would outgrow the plain plan's and the plain kernel is used.
+struct SymPlan {
+  bool ok;
+  int G, Q;
+  size_t lds;
+};
+
+size_t sym_lds_bytes(int dch, int64_t W, int G) {
+  const int64_t fixed = 2 * TN * (dch * 16 + 4) + 2 * TN + 2 * W * (TN + 1);
+  const int64_t sw = W <= 4 ? 4 : 8;
+  return sizeof(float) *
+         static_cast<size_t>(fixed + 4 * static_cast<int64_t>(G) * 64 * SYM_NS * sw);
+}
+
+SymPlan plan_sym(int64_t n, int64_t d, int64_t W) {
+  SymPlan sp{};
+  const int dch = static_cast<int>(ceil_div(d, 16));
+  if (n < 1 || W < 1 || W > WV || dch > 2) return sp;
+  const int64_t IB = 64 * SYM_NS;
+  int G = static_cast<int>(std::min<int64_t>(std::max<int64_t>(ceil_div(n, IB * 90), 1), 4));
+  while (G > 1 && sym_lds_bytes(dch, W, G) > SYM_MAX_LDS) --G;
+  sp.G = G;
+  sp.Q = static_cast<int>(ceil_div(n, G * IB));
+  sp.lds = sym_lds_bytes(dch, W, G);
+  sp.ok = sp.Q <= SYM_MAX_Q && sp.lds <= SYM_MAX_LDS;
+  return sp;
+}
+
+template <int KIND, int DCH>
+int launch_sym_dch(const SymPlan& sp, const float* Xp, const float* np_, int64_t n,
+                   const float* V, int C, int W, int64_t ldv, float* P, float cnorm, float cdot,
+                   const int* skip, hipStream_t s) {
+  const unsigned items = static_cast<unsigned>(sp.Q * (sp.Q + 1) / 2);
+  switch (W) {
+#define IGP_SW(K)                                                                              \
+  case K:                                                                                      \
+    kv_mfma_f32_sym<KIND, DCH, K><<<items, 256, sp.lds, s>>>(Xp, np_, n, V, C, ldv, P, sp.G,   \
+                                                             sp.Q, cnorm, cdot, skip);         \
+    break;
+    IGP_SW(1) IGP_SW(2) IGP_SW(3) IGP_SW(4) IGP_SW(5) IGP_SW(6) IGP_SW(7) IGP_SW(8)
+#undef IGP_SW
+    default: break;
+  }
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template <int KIND>
+int launch_sym(const SymPlan& sp, int dch, const float* Xp, const float* np_, int64_t n,
+               const float* V, int C, int W, int64_t ldv, float* P, float cnorm, float cdot,
+               const int* skip, hipStream_t s) {
+  if (dch == 1)
+    return launch_sym_dch<KIND, 1>(sp, Xp, np_, n, V, C, W, ldv, P, cnorm, cdot, skip, s);
+  return launch_sym_dch<KIND, 2>(sp, Xp, np_, n, V, C, W, ldv, P, cnorm, cdot, skip, s);
+}
+
 template <int KIND, int DCH>
 int launch_kind_dch(const Plan& pl, const float* X1p, const float* n1p, const float* X2p,
                     const float* n2p, int64_t n1, int64_t n2, const float* V, int C, int W,
@@ -595,7 +921,12 @@ bool mfma_f32_supported(int kind, int64_t d) {
 
 size_t mfma_f32_partial_bytes(int64_t n1, int64_t n2, int64_t d, int64_t W, bool fixed) {
   Plan pl = plan_mfma(n1, n2, d, W, fixed);
-  return static_cast<size_t>(pl.nsplit) * n1 * W * sizeof(float);
+  size_t b = static_cast<size_t>(pl.nsplit) * n1 * W * sizeof(float);
+  if (!fixed && n1 == n2) {
+    const SymPlan sp = plan_sym(n1, d, W);
+    if (sp.ok) b = std::max(b, static_cast<size_t>(sp.Q) * n1 * W * sizeof(float));
+  }
+  return b;
 }
 
 int64_t padded_dim(int64_t d) { return ceil_div(d, 16) * 16; }
@@ -641,6 +972,31 @@ int kv_mfma_f32_launch(const KVProblem& p, const float* X1p, const float* n1p,
   const double inv_l2 = 1.0 / (p.kp.lengthscale * p.kp.lengthscale);
   const float* V = static_cast<const float*>(p.V);
   const int C = static_cast<int>(p.C), Wi = static_cast<int>(W);
+  // the same prepared rows on both sides: each pair of rows evaluated once
+  const SymPlan sp = (X1p == X2p && n1p == n2p && p.n1 == p.n2 && !p.fixed_split)
+                         ? plan_sym(p.n1, p.d, W) : SymPlan{};
+  if (sp.ok) {
+    if (static_cast<size_t>(sp.Q) * p.n1 * W * sizeof(float) > P_bytes) {
+      set_error("kernel-product workspace too small for the symmetric partials");
+      return IGP_ENOMEM;
+    }
+    *nsplit_out = sp.Q;
+    const int dch = static_cast<int>(ceil_div(p.d, 16));
+    const float k = kv_kappa(p.kp.kind);
+    const float cn = static_cast<float>(k * inv_l2), cd = static_cast<float>(-2.0 * k * inv_l2);
+    switch (p.kp.kind) {
+      case IGP_RBF:
+        return launch_sym<IGP_RBF>(sp, dch, X1p, n1p, p.n1, V, C, Wi, p.ldv, P, cn, cd, p.skip, s);
+      case IGP_MATERN32:
+        return launch_sym<IGP_MATERN32>(sp, dch, X1p, n1p, p.n1, V, C, Wi, p.ldv, P, cn, cd,
+                                        p.skip, s);
+      case IGP_MATERN52:
+        return launch_sym<IGP_MATERN52>(sp, dch, X1p, n1p, p.n1, V, C, Wi, p.ldv, P, cn, cd,
+                                        p.skip, s);
+      default:
+        break;
+    }
+  }
   switch (p.kp.kind) {
     case IGP_RBF: {
       const float k = kappa<IGP_RBF>();

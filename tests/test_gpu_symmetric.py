@@ -1,0 +1,87 @@
+"""K(X, X) V with the same point set on both sides (the solver products of a
+Newton step): the library evaluates each pair of rows once and adds k(x_n, x_m)
+to both outputs.  Checked against the FP64 oracle:
+
+* every entry within the FP32 product tolerance 8 eps32 (8 + sqrt n) (K|v|)
+  over kernel families, feature counts of one and two 16-wide chunks, output
+  widths 1..8 and ragged sizes (a single row, partial I-blocks and tiles);
+* at sizes with several I-blocks per super-block (n = 13000, 24001) on 48
+  sampled rows, including the last row;
+* against the one-sided kernel on a copy of the points (same arithmetic up to
+  FP32 summation order);
+* beyond the symmetric plan's range (n = 70000, W = 8) the one-sided kernel
+  serves the call: sampled rows against the oracle.
+"""
+import math
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import kernels as ok
+from paper_2310_20285_amd import api
+
+pytestmark = pytest.mark.gpu
+EPS32 = float(np.finfo(np.float32).eps)
+
+
+def _case(n, d, C, nb, seed):
+    rng = np.random.default_rng(seed)
+    X = torch.tensor(rng.standard_normal((n, d)), dtype=torch.float32, device="cuda")
+    V = torch.tensor(rng.standard_normal((nb, n * C)), dtype=torch.float32, device="cuda")
+    return X, V
+
+
+def _check_rows(out, X, V, rows, C, kind, ell, os_):
+    n = X.shape[0]
+    Xh = X.double().cpu().numpy()
+    Vh = V.double().cpu().numpy().reshape(V.shape[0], n, C)
+    K = ok.kernel_matrix(Xh[rows], Xh, kind, ell, os_)
+    tol = 8 * EPS32 * (8 + math.sqrt(n))
+    o = out.double().cpu().numpy().reshape(V.shape[0], n, C)
+    for b in range(V.shape[0]):
+        ref, scale = K @ Vh[b], K @ np.abs(Vh[b])
+        err = np.abs(o[b][rows] - ref)
+        assert np.all(err <= tol * scale + 1e-300), (b, (err / scale).max())
+
+
+@pytest.mark.parametrize("kind", ["rbf", "matern32", "matern52"])
+@pytest.mark.parametrize("n,d,C,nb", [(1, 3, 2, 1), (130, 3, 5, 1), (257, 20, 1, 1), (1000, 16, 8, 1),
+                                      (3001, 7, 3, 2), (2049, 32, 4, 2)])
+def test_symmetric_product_all_entries(gpu_lib, kind, n, d, C, nb):
+    X, V = _case(n, d, C, nb, zlib.crc32(f"{kind}{n}{d}{C}{nb}".encode()))
+    out = api.glm_kernel_matmul(X, X, V, C, kind, 1.7, 1.2, "fp32")
+    _check_rows(out.view(nb, -1), X, V, np.arange(n), C, kind, 1.7, 1.2)
+
+
+@pytest.mark.parametrize("n,d,C", [(13000, 16, 5), (24001, 20, 4)])
+def test_symmetric_product_multi_block_sampled(gpu_lib, n, d, C):
+    X, V = _case(n, d, C, 1, n)
+    out = api.glm_kernel_matmul(X, X, V, C, "matern52", 2.0, 1.0, "fp32")
+    rows = np.sort(np.random.default_rng(n).choice(n, size=48, replace=False))
+    rows[-1] = n - 1
+    _check_rows(out.view(1, -1), X, V, rows, C, "matern52", 2.0, 1.0)
+
+
+def test_symmetric_matches_one_sided(gpu_lib):
+    X, V = _case(13000, 16, 5, 2, 7)
+    sym = api.glm_kernel_matmul(X, X, V, 5, "rbf", 1.5, 1.0, "fp32")
+    one = api.glm_kernel_matmul(X, X.clone(), V, 5, "rbf", 1.5, 1.0, "fp32")
+    rel = ((sym - one).norm() / one.norm()).item()
+    assert rel <= 1e-5, rel
+
+
+def test_symmetric_repeatable(gpu_lib):
+    X, V = _case(13000, 16, 3, 1, 8)
+    a = api.glm_kernel_matmul(X, X, V, 3, "matern32", 1.0, 1.0, "fp32")
+    b = api.glm_kernel_matmul(X, X, V, 3, "matern32", 1.0, 1.0, "fp32")
+    assert torch.equal(a, b)
+
+
+def test_beyond_symmetric_range_sampled(gpu_lib):
+    X, V = _case(70000, 8, 8, 1, 9)
+    out = api.glm_kernel_matmul(X, X, V, 8, "matern32", 1.0, 1.0, "fp32")
+    rows = np.sort(np.random.default_rng(9).choice(70000, size=16, replace=False))
+    rows[-1] = 69999
+    _check_rows(out.view(1, -1), X, V, rows, 8, "matern32", 1.0, 1.0)
