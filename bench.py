@@ -29,13 +29,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# ALU roofline of the fused product at small D (derivation in the design doc):
-# VALU issue slots per kernel evaluation -- the kernel transform (full-rate
-# ops count 1, the quarter-rate transcendentals v_sqrt_f32 / v_exp_f32 count
-# 4) plus, when the output is at most 8 wide, the W contraction FMAs; the
-# distance dot products are priced as free (matrix cores).
-TRANSFORM_SLOTS = {"rbf": 6, "matern12": 11, "matern32": 13, "matern52": 14}
-VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes x clock
+# Issue-bound ("alu") roofline of the fused FP32 product at small D (derivation
+# in the design doc).  FP32 MFMA and VALU work never execute at the same time on a
+# SIMD, so one 16 x 16 block of kernel values on one wave costs the sum of its
+# issue cycles:
+#   full-rate FP32 VALU op   4 cycles (16 lanes per cycle, wave64; no packed FP32)
+#   v_exp_f32 / v_sqrt_f32   8 cycles (measured: half the full rate)
+#   v_mfma_f32_16x16x4f32   32 cycles (2048 flops at the 157.3 TFLOP/s FP32 matrix peak)
+# A block is 4 values per lane x (transform + W multiply-adds) on VALU and the
+# distance on 4 ceil(D/16) MFMAs; the symmetric kernel adds 4 MFMAs for the
+# transposed sum, and then each evaluation serves two outputs.
+SIMDS, CLOCK_HZ = 256 * 4, 2.4e9
+VALU_CYCLES, TRANS_CYCLES, MFMA_F32_CYCLES = 4.0, 8.0, 32.0
+TRANSFORM_OPS = {"rbf": (2, 1), "matern12": (3, 2), "matern32": (5, 2), "matern52": (6, 2)}
 KV_INSTANCE = None
 
 
@@ -44,12 +50,19 @@ KV_INSTANCE = None
 # copy in the same run; profiles/kv_matern52_N20000_D16_C5_fp32.md and
 # profiles/kv_bf16_rbf_N60000_D784_C10.md).  Keyed by the kernel instance it
 # was measured on; any other instance reports null.
-MEASURED_TRAFFIC = {("kv_mfma_f32_narrow<3,1,5,2>", "fp32"): 46.23e6,
-                    ("kv_bf16_kernel<0>", "bf16"): 24.00e9}
+MEASURED_TRAFFIC = {("kv_mfma_f32_sym<3,1,5>", "fp32"): 45.82e6,
+                    ("kv_bf16_sym<0>", "bf16"): 12.92e9}
 
 
-def valu_slots_per_eval(kind: str, W: int) -> int:
-    return TRANSFORM_SLOTS[kind] + (W if W <= 8 else 0)
+def block_cycles(kind: str, W: int, D: int, symmetric: bool) -> float:
+    full, trans = TRANSFORM_OPS[kind]
+    valu = 4 * ((full + W) * VALU_CYCLES + trans * TRANS_CYCLES)
+    mfma = (4 * math.ceil(D / 16) + (4 if symmetric else 0)) * MFMA_F32_CYCLES
+    return valu + mfma
+
+
+def peak_evals_per_s(kind: str, W: int, D: int, symmetric: bool) -> float:
+    return SIMDS * CLOCK_HZ * 256 / block_cycles(kind, W, D, symmetric)
 
 
 def cpu_baseline(w, k_products_per_step: float):
@@ -121,7 +134,7 @@ def main():
     if args.workload == "poisson":
         return bench_poisson(args)
     args.precision = args.precision or "fp32"
-    KV_INSTANCE = "kv_mfma_f32_narrow<3,1,5,2>"   # Matern-5/2, D <= 16, W = 5, 2 strips
+    KV_INSTANCE = "kv_mfma_f32_sym<3,1,5>"   # Matern-5/2, D <= 16, W = 5
     w = datagen.config2()
     dt = torch.float64 if args.precision == "fp64" else torch.float32
     X = torch.tensor(w.X, dtype=dt, device=dev)
@@ -166,9 +179,10 @@ def main():
     elapsed = t1 - t0
     value = args.steps / elapsed
     kv_avg_s = prof["kv_ms"] / max(prof["kv_launches"], 1) / 1e3
-    evals_per_launch = float(w.N) * w.N
+    symmetric = prof["kv_symmetric"] == prof["kv_launches"] > 0
+    evals_per_launch = prof["kv_evals"] / max(prof["kv_launches"], 1)
     achieved_evals = evals_per_launch / kv_avg_s
-    peak_evals = VALU_LANE_OPS_PER_S / valu_slots_per_eval(w.kernel, w.C)
+    peak_evals = peak_evals_per_s(w.kernel, w.C, w.D, symmetric)
     kv_tflops = prof["kv_flops"] / max(prof["kv_launches"], 1) / kv_avg_s / 1e12
     k_per_step = prof["kv_launches"] / max(prof["steps"], 1)
 
@@ -195,7 +209,9 @@ def main():
                      "peak": peak_evals / 1e9, "unit": "Geval/s",
                      "frac": achieved_evals / peak_evals,
                      "traffic": MEASURED_TRAFFIC.get((KV_INSTANCE, args.precision)),
-                     "kernel": "fused K.v (kernel evaluation + contraction)",
+                     "kernel": ("symmetric fused K.v: N(N+1)/2 kernel evaluations per launch, "
+                                "each serving both outputs" if symmetric else
+                                "fused K.v: N^2 kernel evaluations per launch"),
                      "avg_launch_us": kv_avg_s * 1e6},
         "kv": {"launches": prof["kv_launches"], "avg_us": kv_avg_s * 1e6,
                "tflops_algorithmic": kv_tflops, "k_products_per_step": k_per_step,
@@ -376,8 +392,12 @@ def bench_image(args):
     t1 = time.perf_counter()
     prof = m.profile()
     kv_avg_s = prof["kv_ms"] / max(prof["kv_launches"], 1) / 1e3
-    flops = 2.0 * w.N * w.N * (w.D + w.C)
+    # algorithmic flops of the method that ran: n(n+1) D + 2 n^2 C for the
+    # symmetric product (each pair of rows once), 2 n^2 (D + C) one-sided
+    symmetric = prof["kv_symmetric"] == prof["kv_launches"] > 0
+    flops = prof["kv_flops"] / max(prof["kv_launches"], 1)
     tflops = flops / kv_avg_s / 1e12
+    dense_tflops = 2.0 * w.N * w.N * (w.D + w.C) / kv_avg_s / 1e12
     # error of one product against the FP64 oracle on sampled rows
     from oracle import kernels as ok
     rng = np.random.default_rng(0)
@@ -403,9 +423,13 @@ def bench_image(args):
                    "precision": prec, "residual": args.residual},
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": BF16_MFMA_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / BF16_MFMA_PEAK_TFLOPS,
-                     "traffic": MEASURED_TRAFFIC.get(("kv_bf16_kernel<0>", prec)),
-                     "kernel": "fused K.v, BF16 distance GEMM (2 N^2 (D + C) flops per product)",
-                     "avg_launch_us": kv_avg_s * 1e6},
+                     "traffic": MEASURED_TRAFFIC.get(
+                         ("kv_bf16_sym<0>" if symmetric else "kv_bf16_kernel<0>", prec)),
+                     "kernel": ("symmetric fused K.v, BF16 distance GEMM (N(N+1) D + 2 N^2 C "
+                                "flops per product)" if symmetric else
+                                "fused K.v, BF16 distance GEMM (2 N^2 (D + C) flops per product)"),
+                     "avg_launch_us": kv_avg_s * 1e6,
+                     "dense_equivalent_tflops": dense_tflops},
         "kv_error_vs_fp64": {"rel_l2_64_rows": kv_err},
         "newton": [{k: (round(v_, 6) if isinstance(v_, float) else v_) for k, v_ in i.items()
                     if k in ("iters", "buffer_cols", "rel_change", "psi")} for i in infos],

@@ -274,10 +274,13 @@ int itergp_get_view(const igp_model* m, int32_t which, const void** ptr,
 typedef struct igp_profile {
   int64_t kv_launches;   /* products timed */
   double kv_ms;          /* sum of their device durations, milliseconds */
-  double kv_evals;       /* kernel evaluations, sum of n1*n2 */
-  double kv_flops;       /* algorithmic flops, sum of 2*n1*n2*(d + C*nb) */
+  double kv_evals;       /* kernel evaluations performed: n1*n2, or n(n+1)/2 for a
+                            symmetric product (same rows on both sides, each pair once) */
+  double kv_flops;       /* algorithmic flops of the method that ran: 2*n1*n2*(d + C*nb),
+                            or n(n+1)*d + 2*n*n*C*nb for a symmetric product */
   double step_ms;        /* device time of whole Newton steps (first to last kernel) */
   int64_t steps;         /* Newton steps timed */
+  int64_t kv_symmetric;  /* products among kv_launches that ran symmetric */
 } igp_profile;
 int itergp_set_profiling(igp_model* m, int32_t enable);   /* enables/disables and resets */
 int itergp_get_profile(const igp_model* m, igp_profile* out);

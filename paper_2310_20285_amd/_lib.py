@@ -56,7 +56,8 @@ class StepInfo(ct.Structure):
 
 class Profile(ct.Structure):
     _fields_ = [("kv_launches", ct.c_int64), ("kv_ms", ct.c_double), ("kv_evals", ct.c_double),
-                ("kv_flops", ct.c_double), ("step_ms", ct.c_double), ("steps", ct.c_int64)]
+                ("kv_flops", ct.c_double), ("step_ms", ct.c_double), ("steps", ct.c_int64),
+                ("kv_symmetric", ct.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

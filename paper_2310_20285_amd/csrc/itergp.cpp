@@ -119,6 +119,7 @@ struct Model final : igp_model {
   size_t evused = 0;
   igp_profile pstat{};
   double pending_evals = 0.0, pending_flops = 0.0;
+  int64_t pending_sym = 0;
 
   ~Model() override {
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
@@ -153,7 +154,9 @@ struct Model final : igp_model {
     }
     pstat.kv_evals += pending_evals;
     pstat.kv_flops += pending_flops;
+    pstat.kv_symmetric += pending_sym;
     pending_evals = pending_flops = 0.0;
+    pending_sym = 0;
     evused = 0;
     return IGP_OK;
   }
@@ -163,6 +166,7 @@ struct Model final : igp_model {
     pstat = igp_profile{};
     evused = 0;
     pending_evals = pending_flops = 0.0;
+    pending_sym = 0;
     return IGP_OK;
   }
 
@@ -212,11 +216,21 @@ struct Model final : igp_model {
       IGP_TRY(event_pair(&a, &b));
       IGP_CHECK_HIP(hipEventRecord(a, stream));
     }
-    IGP_TRY(kv_launch(kv_problem(L.X, N, V, 1, n, Out, n), L.kvws, L.kvws_bytes, stream));
+    int sym = 0;
+    KVProblem p = kv_problem(L.X, N, V, 1, n, Out, n);
+    p.symmetric_out = &sym;
+    IGP_TRY(kv_launch(p, L.kvws, L.kvws_bytes, stream));
     if (prof) {
       IGP_CHECK_HIP(hipEventRecord(b, stream));
-      pending_evals += static_cast<double>(N) * N;
-      pending_flops += 2.0 * N * N * (D + C);
+      const double Nd = static_cast<double>(N);
+      if (sym) {
+        pending_evals += Nd * (Nd + 1.0) / 2.0;
+        pending_flops += Nd * (Nd + 1.0) * D + 2.0 * Nd * Nd * C;
+        pending_sym += 1;
+      } else {
+        pending_evals += Nd * Nd;
+        pending_flops += 2.0 * Nd * Nd * (D + C);
+      }
     }
     return IGP_OK;
   }

@@ -74,6 +74,76 @@ constexpr int MB = TMW / 16, NB = TNW / 16;
 constexpr int VS = BM + 8;             // LDS row stride of the transposed V tile (bf16)
 constexpr int QA = BM * 4 / NT, QB = BN * 4 / NT;   // 16-byte pieces staged per thread
 
+// D^T of one (X2 tile, X1 block) pair for this wave: acc[mb][nb][v] =
+// sum_k X2[m0 + wm TMW + mb 16 + 4g + v][k] X1[n0 + wn TNW + nb 16 + r][k].
+// Feature chunks of KC stream through the double-buffered LDS tiles sA / sB
+// ([2][BM RS] and [2][BN RS]); chunk ks+1 (loaded during the previous
+// iteration) goes to the other buffer before the products of chunk ks, so its
+// LDS writes overlap them, and the loads of chunk ks+2 are issued right after.
+// Rows past the end are clamped to the last row (their products meet V = 0 or
+// are never stored).  Ends with a barrier: the buffers may be reused.
+__device__ __forceinline__ void dist_tile(f4 (&acc)[MB][NB], __bf16* __restrict__ sA,
+                                          __bf16* __restrict__ sB,
+                                          const __bf16* __restrict__ X1b,
+                                          const __bf16* __restrict__ X2b, int64_t n0, int64_t n1,
+                                          int64_t m0, int64_t m_end, int DPB, int tid, int wm,
+                                          int wn, int g, int r) {
+  u4 pa[QA], pb[QB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int e = tid + q * NT;
+      const int64_t m = m0 + (e >> 2) < m_end ? m0 + (e >> 2) : m_end - 1;
+      pa[q] = *reinterpret_cast<const u4*>(X2b + m * DPB + k0 + (e & 3) * 8);
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int e = tid + q * NT;
+      const int64_t n = n0 + (e >> 2) < n1 ? n0 + (e >> 2) : n1 - 1;
+      pb[q] = *reinterpret_cast<const u4*>(X1b + n * DPB + k0 + (e & 3) * 8);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int e = tid + q * NT;
+      *reinterpret_cast<u4*>(&sA[buf * BM * RS + (e >> 2) * RS + (e & 3) * 8]) = pa[q];
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int e = tid + q * NT;
+      *reinterpret_cast<u4*>(&sB[buf * BN * RS + (e >> 2) * RS + (e & 3) * 8]) = pb[q];
+    }
+  };
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f4{0, 0, 0, 0};
+  const int nks = DPB / KC;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  if (nks > 1) fetch(KC);
+  int buf = 0;
+  for (int ks = 0; ks < nks; ++ks) {
+    if (ks + 1 < nks) stash(buf ^ 1);
+    if (ks + 2 < nks) fetch((ks + 2) * KC);
+    bf8 b[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+      b[nb] = *reinterpret_cast<const bf8*>(&sB[buf * BN * RS + (wn * TNW + nb * 16 + r) * RS + g * 8]);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const bf8 a = *reinterpret_cast<const bf8*>(&sA[buf * BM * RS + (wm * TMW + mb * 16 + r) * RS + g * 8]);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[mb][nb], 0, 0, 0);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+}
+
 template <int KIND>
 __global__ void __launch_bounds__(NT)
 kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
@@ -105,8 +175,6 @@ kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
   const int w0 = bz * VT;
   const int64_t m_begin = static_cast<int64_t>(by) * cols_per_split;
   const int64_t m_end = m_begin + cols_per_split < n2 ? m_begin + cols_per_split : n2;
-  const int nks = DPB / KC;
-
   // this lane's X1 norms: n = n0 + wn*TNW + nb*16 + r
   float n1v[NB];
 #pragma unroll
@@ -117,35 +185,6 @@ kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
   f4 out[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) out[nb] = f4{0, 0, 0, 0};
-
-  // staging: piece e = tid + q*NT is (row e / 4, 16-byte piece e % 4) of a chunk
-  u4 pa[QA], pb[QB];
-  auto fetch = [&](int64_t m0, int k0) {
-#pragma unroll
-    for (int q = 0; q < QA; ++q) {
-      const int e = tid + q * NT;
-      const int64_t m = m0 + (e >> 2) < m_end ? m0 + (e >> 2) : m_end - 1;
-      pa[q] = *reinterpret_cast<const u4*>(X2b + m * DPB + k0 + (e & 3) * 8);
-    }
-#pragma unroll
-    for (int q = 0; q < QB; ++q) {
-      const int e = tid + q * NT;
-      const int64_t n = n0 + (e >> 2) < n1 ? n0 + (e >> 2) : n1 - 1;
-      pb[q] = *reinterpret_cast<const u4*>(X1b + n * DPB + k0 + (e & 3) * 8);
-    }
-  };
-  auto stash = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < QA; ++q) {
-      const int e = tid + q * NT;
-      *reinterpret_cast<u4*>(&sA[buf][(e >> 2) * RS + (e & 3) * 8]) = pa[q];
-    }
-#pragma unroll
-    for (int q = 0; q < QB; ++q) {
-      const int e = tid + q * NT;
-      *reinterpret_cast<u4*>(&sB[buf][(e >> 2) * RS + (e & 3) * 8]) = pb[q];
-    }
-  };
 
   for (int64_t m0 = m_begin; m0 < m_end; m0 += BM) {
     // V^T tile (hi / lo) and X2 norms of this m tile; V = 0 past the end
@@ -164,37 +203,7 @@ kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
       sN2[e] = gm < m_end ? nrm2[gm] * cnorm : 0.0f;
     }
     f4 acc[MB][NB];
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f4{0, 0, 0, 0};
-
-    // chunk ks+1 (loaded during the previous iteration) goes to the other
-    // buffer before the products of chunk ks, so its LDS writes overlap them;
-    // the loads of chunk ks+2 are issued right after
-    fetch(m0, 0);
-    stash(0);
-    __syncthreads();
-    if (nks > 1) fetch(m0, KC);
-    int buf = 0;
-    for (int ks = 0; ks < nks; ++ks) {
-      if (ks + 1 < nks) stash(buf ^ 1);
-      if (ks + 2 < nks) fetch(m0, (ks + 2) * KC);
-      bf8 b[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        b[nb] = *reinterpret_cast<const bf8*>(&sB[buf][(wn * TNW + nb * 16 + r) * RS + g * 8]);
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const bf8 a =
-            *reinterpret_cast<const bf8*>(&sA[buf][(wm * TMW + mb * 16 + r) * RS + g * 8]);
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[mb][nb], 0, 0, 0);
-      }
-      __syncthreads();
-      buf ^= 1;
-    }
+    dist_tile(acc, &sA[0][0], &sB[0][0], X1b, X2b, n0, n1, m0, m_end, DPB, tid, wm, wn, g, r);
     // kernel transform + contraction: acc[mb][nb][v] = D^T[m = wm*TMW + mb*16 + 4g + v][n = .. + r]
 #pragma unroll
     for (int p = 0; p < MB / 2; ++p) {
@@ -259,6 +268,203 @@ kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
   }
 }
 
+// ---- symmetric product K(X, X) V -------------------------------------------
+// With the same rows on both sides every kernel value serves Out[n] += k V[m]
+// and Out[m] += k V[n], so each unordered pair (s, u >= s) of 256-row blocks is
+// one workgroup and the distance tile -- the bulk of the work at hundreds of
+// features -- is computed once.  After the tile and the kernel transform:
+//   direct      as in kv_bf16_kernel (K in the A-operand layout, V of the
+//               u rows as B), partial of rows in block s -> slot u;
+//   transposed  Out[m][w] = sum_n V[n][w] K[n][m]: the MFMA needs 8
+//               consecutive n per lane at fixed m, the transpose of the
+//               accumulator layout, so each wave writes the hi / lo parts of
+//               its K values for one pair of m-blocks to a private LDS scratch
+//               [m][n] and reads them back as the B operand (V of the s rows,
+//               stored [w][n], is A); the four waves that share the m rows
+//               are added in wave order; partial of rows in block u -> slot s.
+// The pair (s, s) takes only the direct sum.  Every row thus has exactly Q
+// slots, each written once, reduced in slot order by kv_reduce.
+constexpr int TS = TNW + 8;               // row stride (bf16) of the transpose scratch [m][n]
+constexpr int TWAVE = 2 * 32 * TS;        // scratch per wave: hi and lo of 32 m rows
+static_assert(WM == 2, "the direct reduction adds the second wave row to the first");
+static_assert(WM * WN * TWAVE <= 2 * (BM + BN) * RS, "transpose scratch fits in the chunk buffers");
+static_assert(WM * WN * MB * 64 * 16 + WN * NB * 64 * 16 <= 2 * (BM + BN) * RS * 2,
+              "reduction buffers fit in the chunk buffers");
+
+template <int KIND>
+__global__ void __launch_bounds__(NT)
+kv_bf16_sym(const __bf16* __restrict__ Xb, const float* __restrict__ nrm, int64_t n, int DPB,
+            const float* __restrict__ V, int C, int W, int64_t ldv, float* __restrict__ P, int Q,
+            float cnorm, float cdot, const int* skip) {
+  if (skip && *skip) return;
+  __shared__ __align__(16) __bf16 sAB[2 * (BM + BN) * RS];   // chunks, then scratch
+  __shared__ __align__(16) __bf16 sVh[VT * VS];     // V^T of the u rows (m), high part
+  __shared__ __align__(16) __bf16 sVl[VT * VS];     // ... low part
+  __shared__ __align__(16) __bf16 sUh[VT * VS];     // V^T of the s rows (n), high part
+  __shared__ __align__(16) __bf16 sUl[VT * VS];     // ... low part
+  __shared__ __align__(16) float sN2[BM];
+
+  // ids congruent mod 8 run on one XCD: give each XCD a contiguous range of pairs
+  const int nwg = gridDim.x, bid = blockIdx.x;
+  const int xcd = bid & 7, loc = bid >> 3;
+  const int per = (nwg + 7) >> 3, rem = nwg & 7;
+  const int lin = (rem == 0 || xcd < rem) ? xcd * per + loc
+                                          : rem * per + (xcd - rem) * (per - 1) + loc;
+  // pair index -> (s, u): the pairs of blocks before s number s Q - s (s - 1) / 2
+  int lo = 0, hi = Q - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (mid * Q - mid * (mid - 1) / 2 <= lin) lo = mid;
+    else hi = mid - 1;
+  }
+  const int sb = lo;
+  const int ub = sb + (lin - (sb * Q - sb * (sb - 1) / 2));
+  const bool diag = ub == sb;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  const int wn = wave % WN, wm = wave / WN;
+  const int64_t n0 = static_cast<int64_t>(sb) * BN;
+  const int64_t m0 = static_cast<int64_t>(ub) * BM;
+  const int64_t m_end = m0 + BM < n ? m0 + BM : n;
+
+  float n1v[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int64_t row = n0 + wn * TNW + nb * 16 + r;
+    n1v[nb] = row < n ? nrm[row] * cnorm : 0.0f;
+  }
+  // V^T tiles (hi / lo) of the u rows and, off the diagonal, of the s rows;
+  // the X2 norms of the u rows; V = 0 past the end
+  for (int e = tid; e < BM * VT; e += NT) {
+    const int m = e / VT, w = e % VT;
+    float v = 0.0f, x = 0.0f;
+    if (m0 + m < n && w < W) v = V[static_cast<int64_t>(w / C) * ldv + (m0 + m) * C + (w % C)];
+    if (!diag && n0 + m < n && w < W)
+      x = V[static_cast<int64_t>(w / C) * ldv + (n0 + m) * C + (w % C)];
+    const __bf16 vh = to_bf(v), xh = to_bf(x);
+    sVh[w * VS + m] = vh;
+    sVl[w * VS + m] = to_bf(v - from_bf(vh));
+    sUh[w * VS + m] = xh;
+    sUl[w * VS + m] = to_bf(x - from_bf(xh));
+  }
+  for (int e = tid; e < BM; e += NT) sN2[e] = m0 + e < n ? nrm[m0 + e] * cnorm : 0.0f;
+
+  f4 acc[MB][NB];
+  dist_tile(acc, sAB, sAB + 2 * BM * RS, Xb, Xb, n0, n, m0, m_end, DPB, tid, wm, wn, g, r);
+
+  __bf16* Th = sAB + wave * TWAVE;     // this wave's transpose scratch, [32 m][TS]
+  __bf16* Tl = Th + 32 * TS;
+  f4 out[NB], out2[MB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) out[nb] = f4{0, 0, 0, 0};
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) out2[mb] = f4{0, 0, 0, 0};
+  // acc[mb][nb][v] = D^T[m = wm*TMW + mb*16 + 4g + v][n = wn*TNW + nb*16 + r]
+#pragma unroll
+  for (int p = 0; p < MB / 2; ++p) {
+    const int mba = 2 * p, mbb = 2 * p + 1;
+    const int ma = wm * TMW + mba * 16 + 4 * g, mbm = wm * TMW + mbb * 16 + 4 * g;
+    const f4 na = *reinterpret_cast<const f4*>(&sN2[ma]);
+    const f4 nbv = *reinterpret_cast<const f4*>(&sN2[mbm]);
+    bf8 vh, vl;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      vh[t] = sVh[r * VS + ma + t];
+      vl[t] = sVl[r * VS + ma + t];
+      vh[4 + t] = sVh[r * VS + mbm + t];
+      vl[4 + t] = sVl[r * VS + mbm + t];
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      bf8 kh, kl;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float ka = kt_bf<KIND>(__builtin_fmaf(acc[mba][nb][t], cdot, n1v[nb] + na[t]));
+        const float kb = kt_bf<KIND>(__builtin_fmaf(acc[mbb][nb][t], cdot, n1v[nb] + nbv[t]));
+        const __bf16 ha = to_bf(ka), hb = to_bf(kb);
+        kh[t] = ha;
+        kh[4 + t] = hb;
+        kl[t] = to_bf(ka - from_bf(ha));
+        kl[4 + t] = to_bf(kb - from_bf(hb));
+      }
+      out[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vh, out[nb], 0, 0, 0);
+      out[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vl, out[nb], 0, 0, 0);
+      out[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kl, vh, out[nb], 0, 0, 0);
+      if (!diag) {
+        // K[n = nb*16 + r][m = sub*16 + 4g + t] -> scratch row m, column n
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int row = (t >> 2) * 16 + 4 * g + (t & 3);
+          Th[row * TS + nb * 16 + r] = kh[t];
+          Tl[row * TS + nb * 16 + r] = kl[t];
+        }
+      }
+    }
+    if (!diag) {
+#pragma unroll
+      for (int sub = 0; sub < 2; ++sub)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          const int col = ks * 32 + 8 * g;
+          const bf8 bh = *reinterpret_cast<const bf8*>(&Th[(sub * 16 + r) * TS + col]);
+          const bf8 bl = *reinterpret_cast<const bf8*>(&Tl[(sub * 16 + r) * TS + col]);
+          const bf8 ah = *reinterpret_cast<const bf8*>(&sUh[r * VS + wn * TNW + col]);
+          const bf8 al = *reinterpret_cast<const bf8*>(&sUl[r * VS + wn * TNW + col]);
+          f4& o = out2[2 * p + sub];
+          o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, o, 0, 0, 0);
+          o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, o, 0, 0, 0);
+          o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, o, 0, 0, 0);
+        }
+    }
+  }
+  // out[nb][j]  = direct sum for n = n0 + wn*TNW + nb*16 + 4g + j, w = r (add the WM wave rows);
+  // out2[mb][j] = transposed sum for w = 4g + j, m = m0 + wm*TMW + mb*16 + r (add the WN wave
+  // columns).  Both reductions go through the chunk buffers.
+  f4* red2 = reinterpret_cast<f4*>(sAB);                       // [wave][mb][lane]
+  f4* red1 = red2 + WM * WN * MB * 64;                         // [wn][nb][lane]
+  __syncthreads();
+  if (!diag) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) red2[(wave * MB + mb) * 64 + lane] = out2[mb];
+  }
+  if (wm == 1) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) red1[(wn * NB + nb) * 64 + lane] = out[nb];
+  }
+  __syncthreads();
+  if (!diag) {
+    // wave (wm, wn) writes m-blocks 2 wn and 2 wn + 1 of its wm rows
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int mb = 2 * wn + q;
+      f4 x = red2[((wm * WN + 0) * MB + mb) * 64 + lane];
+#pragma unroll
+      for (int k = 1; k < WN; ++k) x += red2[((wm * WN + k) * MB + mb) * 64 + lane];
+      const int64_t m = m0 + wm * TMW + mb * 16 + r;
+      if (m < n) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int w = 4 * g + j;
+          if (w < W) P[(static_cast<int64_t>(sb) * n + m) * W + w] = x[j];
+        }
+      }
+    }
+  }
+  if (wm == 0) {
+    const int w = r;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const f4 x = out[nb] + red1[(wn * NB + nb) * 64 + lane];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t row = n0 + wn * TNW + nb * 16 + 4 * g + j;
+        if (row < n && w < W) P[(static_cast<int64_t>(ub) * n + row) * W + w] = x[j];
+      }
+    }
+  }
+}
+
 // Centred rows rounded to BF16 (zero-padded to DPB features) and the squared
 // norms of the rounded rows.
 __global__ void k_prep_rows_bf16(const float* __restrict__ X, int64_t n, int d, int DPB,
@@ -309,9 +515,23 @@ PlanB plan_bf16(int64_t n1, int64_t n2, int64_t W, bool fixed = false) {
 
 int64_t bf16_padded_dim(int64_t d) { return ceil_div(d, KC) * KC; }
 
+namespace {
+// blocks of the symmetric launch (partial slots per row); beyond the cap the
+// slots would take several times the one-sided plan's memory and that plan runs
+constexpr int64_t SYM_BF_MAX_Q = 256;
+
+int64_t sym_blocks(int64_t n, int64_t W) {
+  const int64_t q = ceil_div(n, BN);
+  return (W >= 1 && W <= VT && q >= 1 && q <= SYM_BF_MAX_Q) ? q : 0;
+}
+}  // namespace
+
 size_t bf16_partial_bytes(int64_t n1, int64_t n2, int64_t W, bool fixed) {
   PlanB pl = plan_bf16(n1, n2, W, fixed);
-  return static_cast<size_t>(pl.nsplit) * n1 * W * sizeof(float);
+  size_t b = static_cast<size_t>(pl.nsplit) * n1 * W * sizeof(float);
+  if (!fixed && n1 == n2)
+    b = std::max(b, static_cast<size_t>(sym_blocks(n1, W)) * n1 * W * sizeof(float));
+  return b;
 }
 
 int prep_rows_bf16(const float* X, int64_t n, int64_t d, const float* centre, void* Xb,
@@ -327,13 +547,21 @@ int prep_rows_bf16(const float* X, int64_t n, int64_t d, const float* centre, vo
 int kv_bf16_launch(const KVProblem& p, const void* X1b, const float* n1p, const void* X2b,
                    const float* n2p, float* P, size_t P_bytes, hipStream_t s, int* nsplit_out) {
   const int64_t W = p.C * p.nb;
+  // the same prepared rows on both sides: each pair of 256-row blocks once
+  const int64_t Q = (X1b == X2b && n1p == n2p && p.n1 == p.n2 && !p.fixed_split)
+                        ? sym_blocks(p.n1, W) : 0;
   PlanB pl = plan_bf16(p.n1, p.n2, W, p.fixed_split);
-  *nsplit_out = pl.nsplit;
-  if (static_cast<size_t>(pl.nsplit) * p.n1 * W * sizeof(float) > P_bytes) {
+  *nsplit_out = Q > 0 ? static_cast<int>(Q) : pl.nsplit;
+  if (p.symmetric_out) *p.symmetric_out = Q > 0 ? 1 : 0;
+  if (Q > 0 && static_cast<size_t>(Q) * p.n1 * W * sizeof(float) > P_bytes) {
+    set_error("kernel-product workspace too small for the symmetric partials");
+    return IGP_ENOMEM;
+  }
+  if (Q == 0 && static_cast<size_t>(pl.nsplit) * p.n1 * W * sizeof(float) > P_bytes) {
     set_error("kernel-product workspace too small for the split partials");
     return IGP_ENOMEM;
   }
-  if (pl.nsplit == 0 || pl.gx == 0 || pl.gz == 0) return IGP_OK;
+  if (Q == 0 && (pl.nsplit == 0 || pl.gx == 0 || pl.gz == 0)) return IGP_OK;
   const double inv_l2 = 1.0 / (p.kp.lengthscale * p.kp.lengthscale);
   float kap;
   switch (p.kp.kind) {
@@ -355,10 +583,15 @@ int kv_bf16_launch(const KVProblem& p, const void* X1b, const float* n1p, const 
   const __bf16* A2 = static_cast<const __bf16*>(X2b);
   const float* V = static_cast<const float*>(p.V);
   const int C = static_cast<int>(p.C), Wi = static_cast<int>(W);
+  const unsigned sym_grid = static_cast<unsigned>(Q * (Q + 1) / 2);
   auto go = [&](auto kind) {
-    kv_bf16_kernel<decltype(kind)::value><<<grid, NT, 0, s>>>(
-        A1, n1p, A2, n2p, p.n1, p.n2, DPB, V, C, Wi, p.ldv, P, pl.cols_per_split, pl.gx,
-        pl.nsplit, cnorm, cdot, p.skip);
+    if (Q > 0)
+      kv_bf16_sym<decltype(kind)::value><<<sym_grid, NT, 0, s>>>(
+          A1, n1p, p.n1, DPB, V, C, Wi, p.ldv, P, static_cast<int>(Q), cnorm, cdot, p.skip);
+    else
+      kv_bf16_kernel<decltype(kind)::value><<<grid, NT, 0, s>>>(
+          A1, n1p, A2, n2p, p.n1, p.n2, DPB, V, C, Wi, p.ldv, P, pl.cols_per_split, pl.gx,
+          pl.nsplit, cnorm, cdot, p.skip);
   };
   switch (p.kp.kind) {
     case IGP_RBF: go(std::integral_constant<int, IGP_RBF>{}); break;

@@ -975,6 +975,7 @@ int kv_mfma_f32_launch(const KVProblem& p, const float* X1p, const float* n1p,
   // the same prepared rows on both sides: each pair of rows evaluated once
   const SymPlan sp = (X1p == X2p && n1p == n2p && p.n1 == p.n2 && !p.fixed_split)
                          ? plan_sym(p.n1, p.d, W) : SymPlan{};
+  if (p.symmetric_out) *p.symmetric_out = sp.ok ? 1 : 0;
   if (sp.ok) {
     if (static_cast<size_t>(sp.Q) * p.n1 * W * sizeof(float) > P_bytes) {
       set_error("kernel-product workspace too small for the symmetric partials");

@@ -44,6 +44,9 @@ struct KVProblem {
   const float* norm1 = nullptr;
   const float* norm2 = nullptr;
   const int* skip = nullptr;
+  // set by the launcher when non-null: 1 if the product evaluated each pair of
+  // rows once (same prepared rows on both sides), else 0
+  int* symmetric_out = nullptr;
   // one kernel per latent function (same family, class-specific lengthscale and
   // outputscale): kpc[c] for c < C when n_kp == C > 1
   const igp_kernel_params* kpc = nullptr;

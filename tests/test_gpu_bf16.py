@@ -70,6 +70,39 @@ def test_bf16_kernel_matmul_within_rounding_bound(gpu_lib, kind, shape):
     assert np.all(err <= 2.0 * bound.reshape(-1)), (err / bound.reshape(-1)).max()
 
 
+@pytest.mark.parametrize("kind", ["rbf", "matern52"])
+@pytest.mark.parametrize("shape", [(1, 8, 2), (300, 784, 10), (513, 40, 3), (257, 100, 16),
+                                   (300, 20, 17)])
+def test_bf16_symmetric_within_rounding_bound(gpu_lib, kind, shape):
+    """Same rows on both sides: each pair of 256-row blocks evaluated once (a
+    ragged last block, up to W = 16 output columns; W = 17 takes the one-sided
+    kernel), same bound as the one-sided product."""
+    n, d, C = shape
+    rng = np.random.default_rng(n + d + C)
+    X = rng.uniform(0.0, 1.0, size=(n, d)) * (rng.uniform(size=(n, d)) < 0.3)
+    V = rng.standard_normal(n * C)
+    ell = math.sqrt(0.3 * d)
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    Vd = torch.tensor(V, dtype=torch.float32, device="cuda")
+    Xh, Vh = (t.double().cpu().numpy() for t in (Xd, Vd))
+    out = api.glm_kernel_matmul(Xd, Xd, Vd, C, kind, ell, 0.8, "bf16").double().cpu().numpy()
+    bound, K = _bound(Xh, Xh, Vh, C, kind, ell, 0.8)
+    ref = (K @ Vh.reshape(n, C)).reshape(-1)
+    err = np.abs(out - ref)
+    assert np.all(err <= 2.0 * bound.reshape(-1)), (err / bound.reshape(-1)).max()
+
+
+def test_bf16_symmetric_matches_one_sided(gpu_lib):
+    rng = np.random.default_rng(5)
+    X = torch.tensor(rng.uniform(0.0, 1.0, size=(2600, 784)), dtype=torch.float32, device="cuda")
+    V = torch.tensor(rng.standard_normal((2, 2600 * 10)), dtype=torch.float32, device="cuda")
+    sym = api.glm_kernel_matmul(X, X, V, 10, "rbf", 12.0, 1.0, "bf16")
+    one = api.glm_kernel_matmul(X, X.clone(), V, 10, "rbf", 12.0, 1.0, "bf16")
+    assert ((sym - one).norm() / one.norm()).item() <= 1e-5
+    again = api.glm_kernel_matmul(X, X, V, 10, "rbf", 12.0, 1.0, "bf16")
+    assert torch.equal(sym, again)
+
+
 def test_bf16_model_error_vs_fp64_oracle(gpu_lib):
     """IterNCGP on an image-shaped problem in BF16 mode with the oracle's
     actions replayed: the error against FP64 is reported and bounded."""
