@@ -13,7 +13,10 @@
  * - Pointers named X*, V, Out, F, mean, var, probs, y, arena and ws are DEVICE
  *   pointers owned by the caller.  The library never allocates device memory:
  *   calls that need scratch space take a caller-provided workspace whose size
- *   is given by the matching *_ws_bytes / *_state_bytes query.
+ *   is given by the matching *_ws_bytes / *_state_bytes query.  (A model keeps
+ *   two HIP events and a 224-byte pinned host buffer for reading the solver's
+ *   scalars back, created on its first Newton step and freed by
+ *   itergp_destroy.)
  * - Vectors in R^{NC} use CN-ordering (the paper's appendix on orderings):
  *   entry n*C + c belongs to point n and latent function c.  A set of nb such
  *   vectors is stored column by column: vector b starts at element b*ld.

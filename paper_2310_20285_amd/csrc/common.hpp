@@ -72,6 +72,20 @@ struct Carver {
 };
 
 // ---- device helpers --------------------------------------------------------
+// The solver's gate (and its iteration record) are written by kernels and read
+// by later kernels of the same stream: read them with device-coherent vector
+// loads, never through the scalar cache.
+__device__ inline int coherent_load(const int* p) {
+  return __hip_atomic_load(const_cast<int*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double coherent_load(const double* p) {
+  const unsigned long long u = __hip_atomic_load(
+      reinterpret_cast<unsigned long long*>(const_cast<double*>(p)), __ATOMIC_RELAXED,
+      __HIP_MEMORY_SCOPE_AGENT);
+  return __longlong_as_double(static_cast<long long>(u));
+}
+__device__ inline bool gate_closed(const int* g) { return g && coherent_load(g) != 0; }
+
 template <typename T>
 __device__ inline T wave_sum(T v) {
 #pragma unroll

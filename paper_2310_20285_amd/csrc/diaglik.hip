@@ -45,7 +45,9 @@ k_diag_begin(int lik, const T* __restrict__ f, const void* __restrict__ y, int64
 template <typename T>
 __global__ void __launch_bounds__(NTD)
 k_diag_apply(const T* __restrict__ winv, int64_t n, const T* __restrict__ V, int64_t ldv,
-             const T* __restrict__ Add, int64_t lda, T* __restrict__ Out, int64_t ldo) {
+             const T* __restrict__ Add, int64_t lda, T* __restrict__ Out, int64_t ldo,
+             const int* gate) {
+  if (gate_closed(gate)) return;
   const int64_t i = blockIdx.x * static_cast<int64_t>(NTD) + threadIdx.x;
   if (i >= n) return;
   iter::winv_diag<T>(winv, i, V, blockIdx.y, ldv, Add, lda, Out, ldo);
@@ -123,10 +125,10 @@ int diag_begin(int lik, const T* f, const void* y, int64_t n, double s2, T* winv
 
 template <typename T>
 int diag_apply(const T* winv, int64_t n, const T* V, int64_t nb, int64_t ldv, const T* Add,
-               int64_t lda, T* Out, int64_t ldo, hipStream_t s) {
+               int64_t lda, T* Out, int64_t ldo, hipStream_t s, const int* gate) {
   if (n == 0 || nb == 0) return IGP_OK;
   dim3 grid(static_cast<unsigned>(ceil_div(n, NTD)), static_cast<unsigned>(nb));
-  k_diag_apply<T><<<grid, NTD, 0, s>>>(winv, n, V, ldv, Add, lda, Out, ldo);
+  k_diag_apply<T><<<grid, NTD, 0, s>>>(winv, n, V, ldv, Add, lda, Out, ldo, gate);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
@@ -156,7 +158,7 @@ int diag_check_targets(int lik, const void* y, int64_t n, int* flag, hipStream_t
 #define IGP_DIAG_INST(T)                                                                      \
   template int diag_begin<T>(int, const T*, const void*, int64_t, double, T*, T*, hipStream_t); \
   template int diag_apply<T>(const T*, int64_t, const T*, int64_t, int64_t, const T*, int64_t, \
-                             T*, int64_t, hipStream_t);                                       \
+                             T*, int64_t, hipStream_t, const int*);                           \
   template int diag_stats<T>(int, double, const T*, const T*, const T*, const void*, int64_t, \
                              double*, double*, hipStream_t);                                  \
   template int diag_check_targets<T>(int, const void*, int64_t, int*, hipStream_t);

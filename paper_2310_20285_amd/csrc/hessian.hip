@@ -51,7 +51,8 @@ template <typename T, int CMAX>
 __global__ void __launch_bounds__(256)
 k_winv_apply(const T* __restrict__ pi, int logits, int mode, int64_t N, int C,
              const T* __restrict__ V, int64_t nb, int64_t ldv, const T* __restrict__ Add,
-             int64_t lda, T* __restrict__ Out, int64_t ldo) {
+             int64_t lda, T* __restrict__ Out, int64_t ldo, const int* gate) {
+  if (gate_closed(gate)) return;
   const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   const int64_t b = blockIdx.y;
   if (n >= N || b >= nb) return;
@@ -95,14 +96,14 @@ int softmax_pi_rhs(const T* F, const int32_t* y, int64_t N, int64_t C, T* pi, T*
 template <typename T>
 int winv_apply(const T* pi, bool pi_is_logits, int mode, int64_t N, int64_t C, const T* V,
                int64_t nb, int64_t ldv, const T* Add, int64_t lda, T* Out, int64_t ldo,
-               hipStream_t s) {
+               hipStream_t s, const int* gate) {
   if (C > 64) {
     set_error("C = %lld classes exceeds the supported maximum of 64", (long long)C);
     return IGP_EUNSUPPORTED;
   }
   if (N == 0 || nb == 0) return IGP_OK;
   dim3 grid(static_cast<unsigned>(ceil_div(N, 256)), static_cast<unsigned>(nb));
-  IGP_DISPATCH_C(C, (k_winv_apply<T, CM><<<grid, 256, 0, s>>>(pi, pi_is_logits ? 1 : 0, mode, N, (int)C, V, nb, ldv, Add, lda, Out, ldo)));
+  IGP_DISPATCH_C(C, (k_winv_apply<T, CM><<<grid, 256, 0, s>>>(pi, pi_is_logits ? 1 : 0, mode, N, (int)C, V, nb, ldv, Add, lda, Out, ldo, gate)));
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
@@ -112,9 +113,10 @@ template int softmax_pi_rhs<float>(const float*, const int32_t*, int64_t, int64_
 template int softmax_pi_rhs<double>(const double*, const int32_t*, int64_t, int64_t, double*,
                                     double*, double*, int*, hipStream_t);
 template int winv_apply<float>(const float*, bool, int, int64_t, int64_t, const float*, int64_t,
-                               int64_t, const float*, int64_t, float*, int64_t, hipStream_t);
+                               int64_t, const float*, int64_t, float*, int64_t, hipStream_t,
+                               const int*);
 template int winv_apply<double>(const double*, bool, int, int64_t, int64_t, const double*,
                                 int64_t, int64_t, const double*, int64_t, double*, int64_t,
-                                hipStream_t);
+                                hipStream_t, const int*);
 
 }  // namespace igp

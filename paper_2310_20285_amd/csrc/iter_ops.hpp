@@ -12,7 +12,7 @@ namespace igp {
 namespace iter {
 
 constexpr int NT = 256;
-constexpr int GV_ROWS = 4096;        // rows per wave of the Q^T z pass
+constexpr int GV_ROWS = QTZ_ROWS;    // rows per wave of the Q^T z pass
 constexpr int MAXCOLS_LDS = 4096;    // y staged in LDS by the direction update
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -64,7 +64,7 @@ __device__ inline void dot(const T* __restrict__ a, const T* __restrict__ b, int
 template <typename T>
 __device__ inline void action_cg(const T* __restrict__ r, const double* __restrict__ rr,
                                  T* __restrict__ s, int64_t n, int64_t bid, int64_t nblk) {
-  const double inv = 1.0 / sqrt(*rr);
+  const double inv = 1.0 / sqrt(coherent_load(rr));
   for (int64_t i = bid * NT + threadIdx.x; i < n; i += nblk * NT)
     s[i] = static_cast<T>(static_cast<double>(r[i]) * inv);
 }
@@ -95,7 +95,7 @@ __device__ inline void gemv_t(const T* __restrict__ Q, int64_t ldq, int64_t n, i
   const int64_t r0 = chunk * GV_ROWS;
   const T* q = Q + static_cast<int64_t>(b) * ldq;
   double acc0 = 0.0, acc1 = 0.0;
-#pragma unroll 4
+#pragma unroll
   for (int k = 0; k < GV_ROWS / 64; k += 2) {
     const int64_t i0 = r0 + k * 64 + lane, i1 = i0 + 64;
     if (i0 < n) acc0 += static_cast<double>(q[i0]) * static_cast<double>(z[i0]);
@@ -170,10 +170,10 @@ __device__ inline void append_step(const T* __restrict__ d, const double* __rest
                                    T* __restrict__ qcol, T* __restrict__ v, int64_t n,
                                    const T* __restrict__ kd, T* __restrict__ kqcol,
                                    T* __restrict__ kv, int64_t bid, int64_t nblk) {
-  const double eta = scal[SC_ETA];
+  const double eta = coherent_load(scal + SC_ETA);
   if (!(eta > 0.0)) return;
   const double qs = 1.0 / sqrt(eta);
-  const double step = scal[SC_ALPHA] / eta;
+  const double step = coherent_load(scal + SC_ALPHA) / eta;
   for (int64_t i = bid * NT + threadIdx.x; i < n; i += nblk * NT) {
     const double di = static_cast<double>(d[i]);
     qcol[i] = static_cast<T>(di * qs);

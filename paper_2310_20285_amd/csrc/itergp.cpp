@@ -33,6 +33,8 @@ struct Layout {
   void* kvws;
   size_t kvws_bytes;
   int* flags;
+  int* gate;      // closed (1) once the solver has stopped: later iteration kernels return
+  double* rec;    // device record of the iterations (IterRecord)
   // matrix-core paths: common centre, centred zero-padded rows (float or
   // BF16), squared norms of those rows
   float* centre;
@@ -72,7 +74,7 @@ Layout<T> carve(Carver& cv, int64_t N, int64_t D, int64_t C, const igp_solver_co
     L.kd = cv.take<T>(n);
   }
   int64_t npart = PARTIAL_DOUBLES;
-  const int64_t gemv_need = (ceil_div(n, 2048) + 1) * std::max<int64_t>(B, 1);
+  const int64_t gemv_need = (ceil_div(n, QTZ_ROWS) + 1) * std::max<int64_t>(B, 1);
   npart = std::max(npart, gemv_need);
   npart = std::max(npart, 4 * ceil_div(N, 256) + 64);
   L.part = cv.take<double>(npart);
@@ -87,6 +89,8 @@ Layout<T> carve(Carver& cv, int64_t N, int64_t D, int64_t C, const igp_solver_co
                           : kv_ws_bytes(N, N, D, C, 1, cfg.precision);
   L.kvws = cv.take<char>(L.kvws_bytes);
   L.flags = cv.take<int>(64);
+  L.gate = cv.take<int>(1);
+  L.rec = cv.take<double>(REC_COUNT);
   if (prepared) {
     L.centre = cv.take<float>(D);
     L.Xp = cfg.precision == IGP_BF16 ? static_cast<void*>(cv.take<uint16_t>(N * bf16_padded_dim(D)))
@@ -120,9 +124,22 @@ struct Model final : igp_model {
   igp_profile pstat{};
   double pending_evals = 0.0, pending_flops = 0.0;
   int64_t pending_sym = 0;
+  std::vector<char> pair_skipped;   // per event pair
+  // products of iterations enqueued ahead of their convergence test: counted
+  // once the iteration is known to have run
+  struct SpecProduct {
+    size_t pair;
+    double evals, flops;
+    bool sym;
+    int iter;
+  };
+  std::vector<SpecProduct> spec_products;
 
   ~Model() override {
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : win_ev)
+      if (e) (void)hipEventDestroy(e);
+    if (win_host) (void)hipHostFree(win_host);
   }
 
   int event_pair(hipEvent_t* a, hipEvent_t* b) {
@@ -134,6 +151,8 @@ struct Model final : igp_model {
     *a = evpool[evused];
     *b = evpool[evused + 1];
     evused += 2;
+    pair_skipped.resize(evused / 2, 0);
+    pair_skipped[evused / 2 - 1] = 0;
     return IGP_OK;
   }
 
@@ -142,6 +161,7 @@ struct Model final : igp_model {
     if (!prof) return IGP_OK;
     // pair 0 brackets the whole step; the rest bracket products with K
     for (size_t i = 0; i + 1 < evused; i += 2) {
+      if (pair_skipped[i / 2]) continue;   // a product of an iteration that did not run
       float ms = 0.f;
       IGP_CHECK_HIP(hipEventElapsedTime(&ms, evpool[i], evpool[i + 1]));
       if (i == 0) {
@@ -210,7 +230,8 @@ struct Model final : igp_model {
 
   bool recurrence() const { return cfg.residual_mode == IGP_RESIDUAL_RECURRENCE; }
 
-  int apply_K(const T* V, T* Out) {
+  // Out = K V; with a gate, part of solver iteration `iter`, skipped once the gate closes
+  int apply_K(const T* V, T* Out, const int* gate = nullptr, int iter = 0) {
     hipEvent_t a = nullptr, b = nullptr;
     if (prof) {
       IGP_TRY(event_pair(&a, &b));
@@ -219,20 +240,43 @@ struct Model final : igp_model {
     int sym = 0;
     KVProblem p = kv_problem(L.X, N, V, 1, n, Out, n);
     p.symmetric_out = &sym;
+    p.skip = gate;
     IGP_TRY(kv_launch(p, L.kvws, L.kvws_bytes, stream));
     if (prof) {
       IGP_CHECK_HIP(hipEventRecord(b, stream));
       const double Nd = static_cast<double>(N);
-      if (sym) {
-        pending_evals += Nd * (Nd + 1.0) / 2.0;
-        pending_flops += Nd * (Nd + 1.0) * D + 2.0 * Nd * Nd * C;
-        pending_sym += 1;
+      const double evals = sym ? Nd * (Nd + 1.0) / 2.0 : Nd * Nd;
+      const double flops = sym ? Nd * (Nd + 1.0) * D + 2.0 * Nd * Nd * C
+                               : 2.0 * Nd * Nd * (D + C);
+      if (gate) {
+        spec_products.push_back({evused / 2 - 1, evals, flops, sym != 0, iter});
       } else {
-        pending_evals += Nd * Nd;
-        pending_flops += 2.0 * Nd * Nd * (D + C);
+        pending_evals += evals;
+        pending_flops += flops;
+        pending_sym += sym;
       }
     }
     return IGP_OK;
+  }
+
+  // after a window of iterations: count the products of those that ran
+  // (iteration number <= last_run), drop the rest from the profile
+  // after iterations lo..hi were consumed: count the products of those that
+  // ran (iteration <= last_run), drop the rest from the profile
+  void settle_products(int lo, int hi, int last_run) {
+    std::vector<SpecProduct> keep;
+    for (const SpecProduct& sp : spec_products) {
+      if (sp.iter < lo || sp.iter > hi) {
+        keep.push_back(sp);
+      } else if (sp.iter <= last_run) {
+        pending_evals += sp.evals;
+        pending_flops += sp.flops;
+        pending_sym += sp.sym ? 1 : 0;
+      } else {
+        pair_skipped[sp.pair] = 1;
+      }
+    }
+    spec_products.swap(keep);
   }
 
   int read_scalars(double* out) {
@@ -270,10 +314,11 @@ struct Model final : igp_model {
 
   // Out[:, b] = W^+ V[:, b] (+ Add[:, b]) for b < nb
   int apply_winv(const T* V, int64_t nb, int64_t ldv, const T* Add, int64_t lda, T* Out,
-                 int64_t ldo) {
+                 int64_t ldo, const int* gate = nullptr) {
     if (softmax())
-      return winv_apply<T>(L.pi, false, IGP_W_PINV, N, C, V, nb, ldv, Add, lda, Out, ldo, stream);
-    return diag_apply<T>(L.pi, n, V, nb, ldv, Add, lda, Out, ldo, stream);
+      return winv_apply<T>(L.pi, false, IGP_W_PINV, N, C, V, nb, ldv, Add, lda, Out, ldo, stream,
+                           gate);
+    return diag_apply<T>(L.pi, n, V, nb, ldv, Add, lda, Out, ldo, stream, gate);
   }
 
   // pseudo-targets yhat - m = g + W^+ (onehot(y) - pi), m = 0 (softmax), or
@@ -287,6 +332,7 @@ struct Model final : igp_model {
       IGP_TRY(event_pair(&a, &st.step_b));
       IGP_CHECK_HIP(hipEventRecord(a, stream));
     }
+    spec_products.clear();
     IGP_TRY(likelihood_terms(L.rhs));
     IGP_TRY(dot_into<T>(L.rhs, L.rhs, n, L.part, L.scal + SC_RHS2, stream));
     const bool recycle = cfg.recycle && cfg.policy != IGP_POLICY_UNIT;
@@ -374,12 +420,18 @@ struct Model final : igp_model {
   }
 
   // r = (yhat - m) - K v - W^+ v with K v formed (explicit) or carried (recurrence)
-  int enqueue_residual() {
+  // r = rhs - K v - W^+ v (K v from the recurrence or a product); within a
+  // solver iteration (iter > 0) behind the gate, ending the iteration
+  int enqueue_residual(int iter = 0) {
+    int* gate = iter > 0 ? L.gate : nullptr;
     if (!recurrence()) {
-      IGP_TRY(apply_K(L.v, L.kv));
-      ++st.kprod;
+      IGP_TRY(apply_K(L.v, L.kv, gate, iter));
+      if (!gate) ++st.kprod;
     }
-    IGP_TRY(apply_winv(L.v, 1, n, nullptr, 0, L.wv, n));
+    IGP_TRY(apply_winv(L.v, 1, n, nullptr, 0, L.wv, n, gate));
+    if (gate)
+      return residual_consume<T>(L.rhs, L.kv, L.wv, L.r, n, L.part, L.scal, st.thresh, gate,
+                                 L.rec, stream);
     return residual<T>(L.rhs, L.kv, L.wv, L.r, n, L.part, L.scal + SC_RR, stream);
   }
 
@@ -433,39 +485,11 @@ struct Model final : igp_model {
     t.scal = L.scal; t.part = L.part; t.yb = L.yb;
     t.n = n; t.N = N; t.ld = ld; t.unit_idx = st.j - 1;
     t.C = static_cast<int>(C); t.ncols = ncols; t.lik = cfg.likelihood; t.policy = cfg.policy;
-    t.nchunks = static_cast<int>(ceil_div(n, 4096));
+    t.nchunks = static_cast<int>(ceil_div(n, QTZ_ROWS));
     return t;
   }
 
-  // s_j (policy) and alpha_j = s_j^T r_{j-1}
-  int phase_action() {
-    host_action();
-    if (cfg.policy == IGP_POLICY_CG) {
-      IGP_TRY(action_cg<T>(L.r, L.scal + SC_RR, s_col(), n, stream));
-    } else if (cfg.policy == IGP_POLICY_UNIT) {
-      IGP_TRY(fill_unit<T>(s_col(), n, st.j - 1, stream));
-    } else {
-      IGP_TRY(copy_vec<T>(user + static_cast<int64_t>(st.j - 1) * user_ld, s_col(), n, stream));
-    }
-    return dot_into<T>(s_col(), L.r, n, L.part, L.scal + SC_ALPHA, stream);
-  }
-
-  // after t_j = K s_j: z_j, Q^T z_j, d_j, eta_j, guarded append, next residual
-  int phase_after_product() {
-    host_after_product();
-    IGP_TRY(apply_winv(s_col(), 1, n, t_col(), n, L.z, n));
-    IGP_TRY(gemv_t<T>(L.Q, ld, n, ncols, L.z, L.part, L.yb, stream));
-    IGP_TRY(dir_update<T>(s_col(), L.Q, ld, n, ncols, L.yb, L.z, L.d, L.part, L.scal + SC_ETA,
-                          stream, t_col(), recurrence() ? L.KQ : nullptr, L.kd));
-    IGP_TRY(append_and_step<T>(L.d, L.scal, L.Q + static_cast<int64_t>(ncols) * ld, L.v, n,
-                               stream, recurrence() ? L.kd : nullptr,
-                               recurrence() ? L.KQ + static_cast<int64_t>(ncols) * ld : nullptr,
-                               L.kv));
-    if (st.next_r) IGP_TRY(enqueue_residual());
-    return IGP_OK;
-  }
-
-  // after the iteration's scalars are on the host
+  // after the iteration's scalars are on the host (batched driver)
   void phase_consume() {
     const double eta = sc[SC_ETA];
     if (!(eta > 0.0)) {
@@ -516,6 +540,114 @@ struct Model final : igp_model {
   KVProblem product_action() const { return kv_problem(L.X, N, s_col(), 1, n, t_col(), n); }
   KVProblem product_update() const { return kv_problem(L.X, N, L.v, 1, n, L.fnew, n); }
 
+  // Solver iteration jj (1-based) with its action in buffer column col, behind
+  // the gate: the action, alpha, t = K s, z, Q^T z, d and eta, the guarded
+  // append, the next residual when next_r, and iter_consume (Algorithm 2).
+  int enqueue_iteration(int jj, int col, bool next_r) {
+    int* gate = L.gate;
+    T* sv = L.S + static_cast<int64_t>(col) * ld;
+    T* tv = L.Tb + static_cast<int64_t>(col) * ld;
+    if (cfg.policy == IGP_POLICY_CG) {
+      IGP_TRY(action_cg_dot<T>(L.r, L.scal + SC_RR, sv, n, L.part, L.scal + SC_ALPHA, gate,
+                               stream));
+    } else {
+      if (cfg.policy == IGP_POLICY_UNIT)
+        IGP_TRY(fill_unit<T>(sv, n, jj - 1, stream, gate));
+      else
+        IGP_TRY(copy_vec<T>(user + static_cast<int64_t>(jj - 1) * user_ld, sv, n, stream, gate));
+      IGP_TRY(dot_into<T>(sv, L.r, n, L.part, L.scal + SC_ALPHA, stream, gate));
+    }
+    IGP_TRY(apply_K(sv, tv, gate, jj));
+    IGP_TRY(apply_winv(sv, 1, n, tv, n, L.z, n, gate));
+    IGP_TRY(gemv_t<T>(L.Q, ld, n, col, L.z, L.part, L.yb, stream, gate));
+    IGP_TRY(dir_update<T>(sv, L.Q, ld, n, col, L.yb, L.z, L.d, L.part, L.scal + SC_ETA, stream,
+                          tv, recurrence() ? L.KQ : nullptr, L.kd, gate));
+    IGP_TRY(append_and_step<T>(L.d, L.scal, L.Q + static_cast<int64_t>(col) * ld, L.v, n,
+                               stream, recurrence() ? L.kd : nullptr,
+                               recurrence() ? L.KQ + static_cast<int64_t>(col) * ld : nullptr,
+                               L.kv, gate));
+    if (next_r) return enqueue_residual(jj);   // its last block ends the iteration
+    return iter_consume(L.scal, st.thresh, 0, L.gate, L.rec, stream);
+  }
+
+  // Iterations go to the stream in windows of up to SPEC_WINDOW, each followed by
+  // an asynchronous copy of the scalars and the iteration record to pinned host
+  // memory and an event; the next window is enqueued (assuming every iteration
+  // of this one appends) before the host waits for this one, so the device is
+  // not left idle while the host reads and plans.
+  static constexpr int64_t SPEC_WINDOW = 4;
+  struct Window {
+    int j0 = 0, col0 = 0, w = 0, slot = 0;
+  };
+  double rec_h[REC_COUNT] = {};     // record as of the last consumed window
+  double* win_host = nullptr;       // pinned: 2 x (SC_COUNT + REC_COUNT) doubles
+  hipEvent_t win_ev[2] = {nullptr, nullptr};
+
+  int window_buffers() {
+    if (!win_host) {
+      IGP_CHECK_HIP(hipHostMalloc(reinterpret_cast<void**>(&win_host),
+                                  2 * (SC_COUNT + REC_COUNT) * sizeof(double)));
+    }
+    for (hipEvent_t& e : win_ev)
+      if (!e) IGP_CHECK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return IGP_OK;
+  }
+
+  // how many iterations may follow iteration j0 with ncols0 buffer columns
+  int64_t window_size(int j0, int ncols0, int64_t budget) const {
+    int64_t w = std::min<int64_t>(SPEC_WINDOW, budget);
+    w = std::min<int64_t>(w, cfg.j_max - j0);
+    w = std::min<int64_t>(w, cfg.max_buffer - ncols0);
+    if (cfg.policy == IGP_POLICY_USER) w = std::min<int64_t>(w, user_cols - j0);
+    return std::max<int64_t>(w, 0);
+  }
+
+  int enqueue_window(const Window& win) {
+    for (int i = 0; i < win.w; ++i) {
+      const int jj = win.j0 + i + 1;
+      IGP_TRY(enqueue_iteration(jj, win.col0 + i, jj < cfg.j_max));
+    }
+    double* h = win_host + win.slot * (SC_COUNT + REC_COUNT);
+    IGP_CHECK_HIP(hipMemcpyAsync(h, L.scal, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                                 stream));
+    IGP_CHECK_HIP(hipMemcpyAsync(h + SC_COUNT, L.rec, REC_COUNT * sizeof(double),
+                                 hipMemcpyDeviceToHost, stream));
+    IGP_CHECK_HIP(hipEventRecord(win_ev[win.slot], stream));
+    return IGP_OK;
+  }
+
+  // wait for a window and fold its iterations into the host state; returns the
+  // number of iterations that ran (0 when the solver had stopped before it)
+  int consume_window(const Window& win, int* ran_out) {
+    IGP_CHECK_HIP(hipEventSynchronize(win_ev[win.slot]));
+    const double* h = win_host + win.slot * (SC_COUNT + REC_COUNT);
+    const double* rec = h + SC_COUNT;
+    std::copy(h, h + SC_COUNT, sc);
+    const int ran = static_cast<int>(rec[REC_EXEC] - rec_h[REC_EXEC]);
+    const int appended = static_cast<int>(rec[REC_APPEND] - rec_h[REC_APPEND]);
+    std::copy(rec, rec + REC_COUNT, rec_h);
+    IGP_REQUIRE(ran >= 0 && ran <= win.w && appended <= ran && appended >= ran - 1 &&
+                    (ran == 0 || (win.j0 == st.j && win.col0 == ncols)),
+                "solver iteration record out of step with the host");
+    for (int i = 1; i <= ran; ++i)
+      st.kprod += 1 + (!recurrence() && win.j0 + i < cfg.j_max ? 1 : 0);
+    settle_products(win.j0 + 1, win.j0 + win.w, win.j0 + ran);
+    *ran_out = ran;
+    if (ran == 0) return IGP_OK;
+    st.j = win.j0 + appended;
+    ncols += appended;
+    st.info.eta_min = std::min(st.info.eta_min, rec[REC_ETAMIN]);
+    if (appended > 0 && win.j0 + 1 < cfg.j_max) st.info.res_norm = std::sqrt(rec[REC_RR]);
+    if (rec[REC_BREAK] != 0.0) {   // s_j and t_j of the last iteration are dropped
+      st.info.breakdown = 1;
+      st.active = false;
+    } else if (rec[REC_CONV] != 0.0) {
+      st.info.converged = 1;
+      st.active = false;
+    }
+    return IGP_OK;
+  }
+
   // A Newton step in three parts, so that a caller can interleave other work
   // between solver iterations: begin (pseudo-targets, Algorithm 3, v_0, r_0),
   // iterate (up to max_iters iterations of Algorithm 2), end (f = K v + m and
@@ -533,6 +665,8 @@ struct Model final : igp_model {
     IGP_TRY(phase_v0());
     IGP_TRY(read_scalars(sc));
     phase_start_iterations();
+    IGP_TRY(iter_gate_init(L.gate, L.rec, stream));
+    for (double& x : rec_h) x = 0.0;
     in_step = true;
     return IGP_OK;
   }
@@ -541,14 +675,40 @@ struct Model final : igp_model {
     clear_error();
     IGP_REQUIRE(in_step, "no Newton step in progress");
     IGP_REQUIRE(max_iters >= 0, "max_iters must be >= 0");
-    for (int64_t k = 0; k < max_iters; ++k) {
-      IGP_TRY(phase_can_act());
-      if (!st.active) break;
-      IGP_TRY(phase_action());
-      IGP_TRY(apply_K(s_col(), t_col()));
-      IGP_TRY(phase_after_product());
-      IGP_TRY(read_scalars(sc));
-      phase_consume();
+    IGP_TRY(window_buffers());
+    int64_t k = 0;        // iterations run
+    int64_t queued = 0;   // iterations enqueued, not yet consumed
+    Window cur, nxt;
+    bool have_cur = false;
+    int slot = 0;
+    while (k < max_iters) {
+      if (!have_cur) {
+        IGP_TRY(phase_can_act());
+        if (!st.active) break;
+        cur = Window{st.j, ncols, static_cast<int>(window_size(st.j, ncols, max_iters - k)), slot};
+        IGP_TRY(enqueue_window(cur));
+        queued = cur.w;
+        have_cur = true;
+      }
+      // the following window, as if every iteration of this one appends
+      const int64_t wn = window_size(cur.j0 + cur.w, cur.col0 + cur.w, max_iters - k - queued);
+      const bool have_nxt = wn > 0;
+      if (have_nxt) {
+        nxt = Window{cur.j0 + cur.w, cur.col0 + cur.w, static_cast<int>(wn), cur.slot ^ 1};
+        IGP_TRY(enqueue_window(nxt));
+      }
+      int ran = 0;
+      IGP_TRY(consume_window(cur, &ran));
+      k += ran;
+      queued = have_nxt ? nxt.w : 0;
+      if (!st.active) {
+        if (have_nxt) IGP_TRY(consume_window(nxt, &ran));   // runs nothing: the gate is closed
+        have_cur = false;
+        break;
+      }
+      have_cur = have_nxt;
+      if (have_nxt) cur = nxt;
+      slot = cur.slot ^ (have_cur ? 0 : 1);
     }
     if (done) {
       IGP_TRY(phase_can_act());

@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(256)
 kv_valu(const T* __restrict__ X1, const T* __restrict__ X2, int64_t n1, int64_t n2, int d,
         const T* __restrict__ V, int C, int W, int64_t ldv, T* __restrict__ P,
         int64_t cols_per_split, T inv_l2, const int* skip, ClassParams<T> cp) {
-  if (skip && *skip) return;
+  if (gate_closed(skip)) return;
   constexpr int TILE_BYTES = 2 * TM * (DC + 1) * sizeof(T);
   constexpr int RED_BYTES = 4 * TM * WC * sizeof(T);
   constexpr int U_BYTES = TILE_BYTES > RED_BYTES ? TILE_BYTES : RED_BYTES;
@@ -124,7 +124,7 @@ kv_valu(const T* __restrict__ X1, const T* __restrict__ X2, int64_t n1, int64_t 
 template <typename T>
 __global__ void kv_reduce(const T* __restrict__ P, int nsplit, int64_t n1, int W, int C,
                           T* __restrict__ Out, int64_t ldo, T os, T beta, const int* skip) {
-  if (skip && *skip) return;
+  if (gate_closed(skip)) return;
   const int64_t total = n1 * W;
   for (int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; idx < total;
        idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {

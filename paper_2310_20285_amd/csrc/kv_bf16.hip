@@ -151,7 +151,7 @@ kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
                int64_t n2, int DPB, const float* __restrict__ V, int C, int W, int64_t ldv,
                float* __restrict__ P, int64_t cols_per_split, int gx, int nsplit, float cnorm,
                float cdot, const int* skip) {
-  if (skip && *skip) return;
+  if (gate_closed(skip)) return;
   __shared__ __align__(16) __bf16 sA[2][BM * RS];   // X2 chunk (m rows)
   __shared__ __align__(16) __bf16 sB[2][BN * RS];   // X1 chunk (n rows)
   __shared__ __align__(16) __bf16 sVh[VT * VS];     // V^T tile, high part
@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(NT)
 kv_bf16_sym(const __bf16* __restrict__ Xb, const float* __restrict__ nrm, int64_t n, int DPB,
             const float* __restrict__ V, int C, int W, int64_t ldv, float* __restrict__ P, int Q,
             float cnorm, float cdot, const int* skip) {
-  if (skip && *skip) return;
+  if (gate_closed(skip)) return;
   __shared__ __align__(16) __bf16 sAB[2 * (BM + BN) * RS];   // chunks, then scratch
   __shared__ __align__(16) __bf16 sVh[VT * VS];     // V^T of the u rows (m), high part
   __shared__ __align__(16) __bf16 sVl[VT * VS];     // ... low part

@@ -69,7 +69,7 @@ kv_mfma_f32(const float* __restrict__ X1p, const float* __restrict__ nrm1,
             int64_t n2, const float* __restrict__ V, int C, int W, int64_t ldv,
             float* __restrict__ P, int64_t cols_per_split, float cnorm, float cdot,
             const int* skip) {
-  if (skip && *skip) return;
+  if (gate_closed(skip)) return;
   constexpr int DP = DCH * 16;        // padded feature count
   constexpr int XS = DP + 4;          // LDS row stride of the X2 tile (floats)
   constexpr int WT = WCH * 16;        // output columns per workgroup
@@ -378,7 +378,7 @@ kv_mfma_f32_narrow(const float* __restrict__ X1p, const float* __restrict__ nrm1
                    int64_t n2, const float* __restrict__ V, int C, int64_t ldv,
                    float* __restrict__ P, int64_t cols_per_split, float cnorm, float cdot,
                    const int* skip) {
-  if (skip && *skip) return;
+  if (gate_closed(skip)) return;
   __shared__ __align__(16) NarrowSmem<DCH, WX> sm;
   const int64_t m_begin = static_cast<int64_t>(blockIdx.y) * cols_per_split;
   const int64_t m_end = m_begin + cols_per_split < n2 ? m_begin + cols_per_split : n2;
@@ -443,7 +443,7 @@ __global__ void __launch_bounds__(256)
 kv_mfma_f32_sym(const float* __restrict__ Xp, const float* __restrict__ nrm, int64_t n,
                 const float* __restrict__ V, int C, int64_t ldv, float* __restrict__ P, int G,
                 int Q, float cnorm, float cdot, const int* skip) {
-  if (skip && *skip) return;
+  if (gate_closed(skip)) return;
   using L = SymLayout<DCH, WX>;
   constexpr int NS = SYM_NS;
   constexpr int DP = L::DP, XS = L::XS, VS = L::VS;

@@ -16,34 +16,90 @@ using iter::MAXCOLS_LDS;
 using iter::NT;
 using iter::grid_for;
 
-__global__ void k_finish_sum(const double* __restrict__ part, int nblk, double* __restrict__ out) {
+__global__ void k_finish_sum(const double* __restrict__ part, int nblk, double* __restrict__ out,
+                             const int* gate) {
+  if (gate_closed(gate)) return;
   __shared__ double red[NT / 64];
   iter::finish_sum(part, nblk, out, red);
+}
+
+// end of a solver iteration (one thread): unless the gate is closed, count it,
+// close the gate on a breakdown (eta <= 0) or convergence, keep min eta and rr
+__device__ inline void consume_iteration(const double* __restrict__ scal, double thresh,
+                                         int next_r, int* gate, double* rec) {
+  if (gate_closed(gate)) return;
+  rec[REC_EXEC] = coherent_load(rec + REC_EXEC) + 1.0;
+  const double eta = coherent_load(scal + SC_ETA);
+  if (!(eta > 0.0)) {   // breakdown: the iteration's column was not appended
+    rec[REC_BREAK] = 1.0;
+    __hip_atomic_store(gate, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  rec[REC_APPEND] = coherent_load(rec + REC_APPEND) + 1.0;
+  rec[REC_ETAMIN] = fmin(coherent_load(rec + REC_ETAMIN), eta);
+  if (next_r) {
+    const double rr = coherent_load(scal + SC_RR);
+    rec[REC_RR] = rr;
+    if (!(sqrt(rr) >= thresh)) {
+      rec[REC_CONV] = 1.0;
+      __hip_atomic_store(gate, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(NT)
 k_residual(const T* __restrict__ rhs, const T* __restrict__ kv, const T* __restrict__ wv,
-           T* __restrict__ r, int64_t n, double* __restrict__ part) {
+           T* __restrict__ r, int64_t n, double* __restrict__ part, const int* gate) {
+  if (gate_closed(gate)) return;
   __shared__ double red[NT / 64];
   iter::residual<T>(rhs, kv, wv, r, n, part, blockIdx.x, gridDim.x, red);
 }
 
+// rr = sum of the residual partials, then the end of the solver iteration
+__global__ void k_finish_rr_consume(const double* __restrict__ part, int nblk,
+                                    double* __restrict__ scal, double thresh, int* gate,
+                                    double* rec) {
+  if (gate_closed(gate)) return;
+  __shared__ double red[NT / 64];
+  iter::finish_sum(part, nblk, scal + SC_RR, red);
+  if (threadIdx.x == 0) consume_iteration(scal, thresh, 1, gate, rec);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(NT)
-k_dot(const T* __restrict__ a, const T* __restrict__ b, int64_t n, double* __restrict__ part) {
+k_dot(const T* __restrict__ a, const T* __restrict__ b, int64_t n, double* __restrict__ part,
+      const int* gate) {
+  if (gate_closed(gate)) return;
   __shared__ double red[NT / 64];
   iter::dot<T>(a, b, n, part, blockIdx.x, gridDim.x, red);
 }
 
+// CG action s = r / sqrt(r^T r) and the partials of alpha = s^T r in one pass
+// (the partials of a separate k_dot over s and r)
 template <typename T>
 __global__ void __launch_bounds__(NT)
-k_action_cg(const T* __restrict__ r, const double* __restrict__ rr, T* __restrict__ s, int64_t n) {
-  iter::action_cg<T>(r, rr, s, n, blockIdx.x, gridDim.x);
+k_action_cg_dot(const T* __restrict__ r, const double* __restrict__ rr, T* __restrict__ s,
+                int64_t n, double* __restrict__ part, const int* gate) {
+  if (gate_closed(gate)) return;
+  __shared__ double red[NT / 64];
+  const double inv = 1.0 / sqrt(coherent_load(rr));
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(NT) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * NT) {
+    const T ri = r[i];
+    const T si = static_cast<T>(static_cast<double>(ri) * inv);
+    s[i] = si;
+    acc += static_cast<double>(si) * static_cast<double>(ri);
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
 template <typename T>
-__global__ void __launch_bounds__(NT) k_fill_unit(T* __restrict__ s, int64_t n, int64_t idx) {
+__global__ void __launch_bounds__(NT) k_fill_unit(T* __restrict__ s, int64_t n, int64_t idx,
+                                                  const int* gate) {
+  if (gate_closed(gate)) return;
   iter::fill_unit<T>(s, n, idx, blockIdx.x, gridDim.x);
 }
 
@@ -55,7 +111,9 @@ __global__ void k_fill_zero(T* __restrict__ a, int64_t n) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(NT) k_copy(const T* __restrict__ a, T* __restrict__ b, int64_t n) {
+__global__ void __launch_bounds__(NT) k_copy(const T* __restrict__ a, T* __restrict__ b, int64_t n,
+                                             const int* gate) {
+  if (gate_closed(gate)) return;
   iter::copy<T>(a, b, n, blockIdx.x, gridDim.x);
 }
 
@@ -73,12 +131,14 @@ __global__ void k_add(const T* __restrict__ a, const T* __restrict__ b, T* __res
 template <typename T>
 __global__ void __launch_bounds__(NT)
 k_gemv_t(const T* __restrict__ Q, int64_t ldq, int64_t n, int ncols, const T* __restrict__ z,
-         double* __restrict__ part, int nchunks) {
+         double* __restrict__ part, int nchunks, const int* gate) {
+  if (gate_closed(gate)) return;
   iter::gemv_t<T>(Q, ldq, n, ncols, z, part, nchunks, blockIdx.x);
 }
 
 __global__ void k_finish_cols(const double* __restrict__ part, int nrow_blocks, int ncols,
-                              double* __restrict__ y) {
+                              double* __restrict__ y, const int* gate) {
+  if (gate_closed(gate)) return;
   iter::finish_col(part, nrow_blocks, ncols, blockIdx.x * blockDim.x + threadIdx.x, y);
 }
 
@@ -88,7 +148,8 @@ __global__ void __launch_bounds__(NT)
 k_dir_update(const T* __restrict__ sv, const T* __restrict__ Q, int64_t ldq, int64_t n,
              int ncols, const double* __restrict__ y, const T* __restrict__ z,
              T* __restrict__ d, double* __restrict__ part, const T* __restrict__ tv,
-             const T* __restrict__ KQm, T* __restrict__ kd) {
+             const T* __restrict__ KQm, T* __restrict__ kd, const int* gate) {
+  if (gate_closed(gate)) return;
   __shared__ double sy[MAXCOLS_LDS];
   __shared__ double red[NT / 64];
   iter::dir_update<T, KQ>(sv, Q, ldq, n, ncols, y, z, d, part, tv, KQm, kd, blockIdx.x, sy, red);
@@ -111,7 +172,8 @@ template <typename T, bool KQ>
 __global__ void __launch_bounds__(NT)
 k_append_step(const T* __restrict__ d, const double* __restrict__ scal, T* __restrict__ qcol,
               T* __restrict__ v, int64_t n, const T* __restrict__ kd, T* __restrict__ kqcol,
-              T* __restrict__ kv) {
+              T* __restrict__ kv, const int* gate) {
+  if (gate_closed(gate)) return;
   iter::append_step<T, KQ>(d, scal, qcol, v, n, kd, kqcol, kv, blockIdx.x, gridDim.x);
 }
 
@@ -276,39 +338,78 @@ __global__ void k_predict_epilogue(const T* __restrict__ A, int64_t lda, int64_t
   }
 }
 
+__global__ void k_iter_gate_init(int* gate, double* rec) {
+  if (threadIdx.x != 0) return;
+  *gate = 0;
+  for (int k = 0; k < REC_COUNT; ++k) rec[k] = 0.0;
+  rec[REC_ETAMIN] = INFINITY;
+}
+
+__global__ void k_iter_consume(const double* __restrict__ scal, double thresh, int next_r,
+                               int* gate, double* rec) {
+  if (threadIdx.x == 0) consume_iteration(scal, thresh, next_r, gate, rec);
+}
+
 }  // namespace
 
 // ------------------------------ launchers ---------------------------------------
 
+int iter_gate_init(int* gate, double* rec, hipStream_t s) {
+  k_iter_gate_init<<<1, 64, 0, s>>>(gate, rec);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+int iter_consume(const double* scal, double thresh, int next_r, int* gate, double* rec,
+                 hipStream_t s) {
+  k_iter_consume<<<1, 64, 0, s>>>(scal, thresh, next_r, gate, rec);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
 template <typename T>
 int residual(const T* rhs, const T* kv, const T* wv, T* r, int64_t n, double* part,
-             double* out, hipStream_t s) {
+             double* out, hipStream_t s, const int* gate) {
   const int g = grid_for(n);
-  k_residual<T><<<g, NT, 0, s>>>(rhs, kv, wv, r, n, part);
-  k_finish_sum<<<1, NT, 0, s>>>(part, g, out);
+  k_residual<T><<<g, NT, 0, s>>>(rhs, kv, wv, r, n, part, gate);
+  k_finish_sum<<<1, NT, 0, s>>>(part, g, out, gate);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
 
 template <typename T>
-int dot_into(const T* a, const T* b, int64_t n, double* part, double* out, hipStream_t s) {
+int dot_into(const T* a, const T* b, int64_t n, double* part, double* out, hipStream_t s,
+             const int* gate) {
   const int g = grid_for(n);
-  k_dot<T><<<g, NT, 0, s>>>(a, b, n, part);
-  k_finish_sum<<<1, NT, 0, s>>>(part, g, out);
+  k_dot<T><<<g, NT, 0, s>>>(a, b, n, part, gate);
+  k_finish_sum<<<1, NT, 0, s>>>(part, g, out, gate);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
 
 template <typename T>
-int action_cg(const T* r, const double* rr, T* sv, int64_t n, hipStream_t s) {
-  k_action_cg<T><<<grid_for(n), NT, 0, s>>>(r, rr, sv, n);
+int action_cg_dot(const T* r, const double* rr, T* sv, int64_t n, double* part, double* alpha,
+                  const int* gate, hipStream_t s) {
+  const int g = grid_for(n);
+  k_action_cg_dot<T><<<g, NT, 0, s>>>(r, rr, sv, n, part, gate);
+  k_finish_sum<<<1, NT, 0, s>>>(part, g, alpha, gate);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
 
 template <typename T>
-int fill_unit(T* sv, int64_t n, int64_t idx, hipStream_t s) {
-  k_fill_unit<T><<<grid_for(n), NT, 0, s>>>(sv, n, idx);
+int residual_consume(const T* rhs, const T* kv, const T* wv, T* r, int64_t n, double* part,
+                     double* scal, double thresh, int* gate, double* rec, hipStream_t s) {
+  const int g = grid_for(n);
+  k_residual<T><<<g, NT, 0, s>>>(rhs, kv, wv, r, n, part, gate);
+  k_finish_rr_consume<<<1, NT, 0, s>>>(part, g, scal, thresh, gate, rec);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template <typename T>
+int fill_unit(T* sv, int64_t n, int64_t idx, hipStream_t s, const int* gate) {
+  k_fill_unit<T><<<grid_for(n), NT, 0, s>>>(sv, n, idx, gate);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
@@ -321,8 +422,8 @@ int fill_zero(T* a, int64_t n, hipStream_t s) {
 }
 
 template <typename T>
-int copy_vec(const T* a, T* b, int64_t n, hipStream_t s) {
-  k_copy<T><<<grid_for(n), NT, 0, s>>>(a, b, n);
+int copy_vec(const T* a, T* b, int64_t n, hipStream_t s, const int* gate) {
+  k_copy<T><<<grid_for(n), NT, 0, s>>>(a, b, n, gate);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
@@ -336,13 +437,14 @@ int add_vec(const T* a, const T* b, T* o, int64_t n, hipStream_t s) {
 
 template <typename T>
 int gemv_t(const T* Q, int64_t ldq, int64_t n, int ncols, const T* z, double* part, double* y,
-           hipStream_t s) {
+           hipStream_t s, const int* gate) {
   if (ncols == 0) return IGP_OK;
   const int nchunks = static_cast<int>(ceil_div(n, GV_ROWS));
   const int64_t waves = static_cast<int64_t>(nchunks) * ncols;
   k_gemv_t<T><<<static_cast<unsigned>(ceil_div(waves, NT / 64)), NT, 0, s>>>(Q, ldq, n, ncols, z,
-                                                                             part, nchunks);
-  k_finish_cols<<<static_cast<unsigned>(ceil_div(ncols, 64)), 64, 0, s>>>(part, nchunks, ncols, y);
+                                                                             part, nchunks, gate);
+  k_finish_cols<<<static_cast<unsigned>(ceil_div(ncols, 64)), 64, 0, s>>>(part, nchunks, ncols, y,
+                                                                          gate);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
@@ -350,30 +452,31 @@ int gemv_t(const T* Q, int64_t ldq, int64_t n, int ncols, const T* z, double* pa
 template <typename T>
 int dir_update(const T* sv, const T* Q, int64_t ldq, int64_t n, int ncols, const double* y,
                const T* z, T* d, double* part, double* eta_out, hipStream_t s, const T* tv,
-               const T* KQm, T* kd) {
+               const T* KQm, T* kd, const int* gate) {
   if (ncols > MAXCOLS_LDS) {
     set_error("buffer of %d columns exceeds %d", ncols, MAXCOLS_LDS);
     return IGP_EUNSUPPORTED;
   }
   const int g = static_cast<int>(ceil_div(n, NT));
   if (KQm)
-    k_dir_update<T, true><<<g, NT, 0, s>>>(sv, Q, ldq, n, ncols, y, z, d, part, tv, KQm, kd);
+    k_dir_update<T, true><<<g, NT, 0, s>>>(sv, Q, ldq, n, ncols, y, z, d, part, tv, KQm, kd,
+                                           gate);
   else
     k_dir_update<T, false><<<g, NT, 0, s>>>(sv, Q, ldq, n, ncols, y, z, d, part, nullptr,
-                                            nullptr, nullptr);
-  k_finish_sum<<<1, NT, 0, s>>>(part, g, eta_out);
+                                            nullptr, nullptr, gate);
+  k_finish_sum<<<1, NT, 0, s>>>(part, g, eta_out, gate);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
 
 template <typename T>
 int append_and_step(const T* d, const double* scal, T* qcol, T* v, int64_t n, hipStream_t s,
-                    const T* kd, T* kqcol, T* kv) {
+                    const T* kd, T* kqcol, T* kv, const int* gate) {
   if (kd)
-    k_append_step<T, true><<<grid_for(n), NT, 0, s>>>(d, scal, qcol, v, n, kd, kqcol, kv);
+    k_append_step<T, true><<<grid_for(n), NT, 0, s>>>(d, scal, qcol, v, n, kd, kqcol, kv, gate);
   else
     k_append_step<T, false><<<grid_for(n), NT, 0, s>>>(d, scal, qcol, v, n, nullptr, nullptr,
-                                                       nullptr);
+                                                       nullptr, gate);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
@@ -435,10 +538,10 @@ int newton_stats(const T* fnew, const T* f, const T* v, const int32_t* y, int64_
   const int g = static_cast<int>(ceil_div(N, NT));
   if (g == 0) return IGP_OK;
   k_newton_stats<T><<<g, NT, 0, s>>>(fnew, f, v, y, N, static_cast<int>(C), part);
-  k_finish_sum<<<1, NT, 0, s>>>(part + 0 * g, g, scal + SC_DIFF2);
-  k_finish_sum<<<1, NT, 0, s>>>(part + 1 * g, g, scal + SC_FNEW2);
-  k_finish_sum<<<1, NT, 0, s>>>(part + 2 * g, g, scal + SC_LOGLIK);
-  k_finish_sum<<<1, NT, 0, s>>>(part + 3 * g, g, scal + SC_GV);
+  k_finish_sum<<<1, NT, 0, s>>>(part + 0 * g, g, scal + SC_DIFF2, nullptr);
+  k_finish_sum<<<1, NT, 0, s>>>(part + 1 * g, g, scal + SC_FNEW2, nullptr);
+  k_finish_sum<<<1, NT, 0, s>>>(part + 2 * g, g, scal + SC_LOGLIK, nullptr);
+  k_finish_sum<<<1, NT, 0, s>>>(part + 3 * g, g, scal + SC_GV, nullptr);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
@@ -459,20 +562,25 @@ int predict_epilogue(const T* A, int64_t lda, int64_t nrows, int ncols, const do
 
 #define IGP_INST(T)                                                                             \
   template int residual<T>(const T*, const T*, const T*, T*, int64_t, double*, double*,        \
-                           hipStream_t);                                                       \
-  template int dot_into<T>(const T*, const T*, int64_t, double*, double*, hipStream_t);        \
-  template int action_cg<T>(const T*, const double*, T*, int64_t, hipStream_t);                \
-  template int fill_unit<T>(T*, int64_t, int64_t, hipStream_t);                                \
-  template int copy_vec<T>(const T*, T*, int64_t, hipStream_t);                                \
+                           hipStream_t, const int*);                                           \
+  template int residual_consume<T>(const T*, const T*, const T*, T*, int64_t, double*,         \
+                                   double*, double, int*, double*, hipStream_t);               \
+  template int dot_into<T>(const T*, const T*, int64_t, double*, double*, hipStream_t,         \
+                           const int*);                                                        \
+  template int action_cg_dot<T>(const T*, const double*, T*, int64_t, double*, double*,        \
+                                const int*,                                                    \
+                                hipStream_t);                                                  \
+  template int fill_unit<T>(T*, int64_t, int64_t, hipStream_t, const int*);                    \
+  template int copy_vec<T>(const T*, T*, int64_t, hipStream_t, const int*);                    \
   template int fill_zero<T>(T*, int64_t, hipStream_t);                                         \
   template int add_vec<T>(const T*, const T*, T*, int64_t, hipStream_t);                       \
   template int gemv_t<T>(const T*, int64_t, int64_t, int, const T*, double*, double*,         \
-                         hipStream_t);                                                         \
+                         hipStream_t, const int*);                                             \
   template int dir_update<T>(const T*, const T*, int64_t, int64_t, int, const double*,         \
                              const T*, T*, double*, double*, hipStream_t, const T*, const T*,  \
-                             T*);                                                              \
+                             T*, const int*);                                                  \
   template int append_and_step<T>(const T*, const double*, T*, T*, int64_t, hipStream_t,      \
-                                  const T*, T*, T*);                                           \
+                                  const T*, T*, T*, const int*);                               \
   template int gemv_n<T>(const T*, int64_t, int64_t, int, const double*, T*, hipStream_t);     \
   template int gram<T>(const T*, const T*, int64_t, int64_t, int, double*, size_t, double*,   \
                        hipStream_t);                                                           \

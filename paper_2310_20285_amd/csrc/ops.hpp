@@ -56,6 +56,8 @@ struct KVProblem {
   bool fixed_split = false;
 };
 constexpr int64_t FIXED_SPLIT_ROWS = 4096;
+// rows per wave of the Q^T z pass of a solver iteration (partials per column: n / QTZ_ROWS)
+constexpr int QTZ_ROWS = 1024;
 
 size_t kv_ws_bytes(int64_t n1, int64_t n2, int64_t d, int64_t C, int64_t nb, int precision,
                    bool fixed_split = false);
@@ -150,7 +152,7 @@ int softmax_pi_rhs(const T* F, const int32_t* y, int64_t N, int64_t C, T* pi, T*
 template <typename T>
 int winv_apply(const T* pi, bool pi_is_logits, int mode, int64_t N, int64_t C,
                const T* V, int64_t nb, int64_t ldv, const T* Add, int64_t lda,
-               T* Out, int64_t ldo, hipStream_t s);
+               T* Out, int64_t ldo, hipStream_t s, const int* gate = nullptr);
 
 // ---- reductions and projections (FP64 accumulation) ---------------------------
 constexpr int RED_THREADS = 256;
@@ -168,18 +170,28 @@ enum Scalar {
   SC_COUNT
 };
 
+// The launchers below that take `gate` skip their work (every kernel returns at
+// once) while *gate != 0: the solver enqueues iterations ahead of their
+// convergence test and the test closes the gate (iter_consume).
 template <typename T>
 int residual(const T* rhs, const T* kv, const T* wv, T* r, int64_t n, double* partials,
-             double* out_scalar, hipStream_t s);
+             double* out_scalar, hipStream_t s, const int* gate = nullptr);
+// the residual of a solver iteration, its norm finished together with the
+// iteration's end (iter_consume with next_r = 1)
+template <typename T>
+int residual_consume(const T* rhs, const T* kv, const T* wv, T* r, int64_t n, double* partials,
+                     double* scal, double thresh, int* gate, double* rec, hipStream_t s);
 template <typename T>
 int dot_into(const T* a, const T* b, int64_t n, double* partials, double* out_scalar,
-             hipStream_t s);
+             hipStream_t s, const int* gate = nullptr);
+// s = r / sqrt(rr) and alpha = s^T r (one pass over r, then the finishing sum)
 template <typename T>
-int action_cg(const T* r, const double* rr, T* s_out, int64_t n, hipStream_t s);
+int action_cg_dot(const T* r, const double* rr, T* s_out, int64_t n, double* partials,
+                  double* alpha, const int* gate, hipStream_t s);
 template <typename T>
-int fill_unit(T* s_out, int64_t n, int64_t idx, hipStream_t s);
+int fill_unit(T* s_out, int64_t n, int64_t idx, hipStream_t s, const int* gate = nullptr);
 template <typename T>
-int copy_vec(const T* src, T* dst, int64_t n, hipStream_t s);
+int copy_vec(const T* src, T* dst, int64_t n, hipStream_t s, const int* gate = nullptr);
 template <typename T>
 int fill_zero(T* a, int64_t n, hipStream_t s);
 template <typename T>
@@ -187,17 +199,27 @@ int add_vec(const T* a, const T* b, T* out, int64_t n, hipStream_t s);
 // y[b] = sum_i Q[b*ldq + i] z[i], b < ncols
 template <typename T>
 int gemv_t(const T* Q, int64_t ldq, int64_t n, int ncols, const T* z, double* partials,
-           double* y, hipStream_t s);
+           double* y, hipStream_t s, const int* gate = nullptr);
 // d = s - Q y ; eta partials of z^T d ; with KQ: also kd = t - KQ y (= K d)
 template <typename T>
 int dir_update(const T* sv, const T* Q, int64_t ldq, int64_t n, int ncols, const double* y,
                const T* z, T* d, double* partials, double* eta_out, hipStream_t s,
-               const T* tv = nullptr, const T* KQ = nullptr, T* kd = nullptr);
+               const T* tv = nullptr, const T* KQ = nullptr, T* kd = nullptr,
+               const int* gate = nullptr);
 // Q[:, col] = d / sqrt(eta); v += (alpha/eta) d   (no-op when eta <= 0)
 // with kd: also KQ[:, col] = kd / sqrt(eta); kv += (alpha/eta) kd
 template <typename T>
 int append_and_step(const T* d, const double* scal, T* qcol, T* v, int64_t n, hipStream_t s,
-                    const T* kd = nullptr, T* kqcol = nullptr, T* kv = nullptr);
+                    const T* kd = nullptr, T* kqcol = nullptr, T* kv = nullptr,
+                    const int* gate = nullptr);
+// Device-side end of a solver iteration (after its eta and, when next_r, its
+// residual norm are in scal): unless the gate is already closed, count the
+// iteration in rec, close the gate on a breakdown (eta <= 0) or when
+// sqrt(rr) < thresh, and keep the smallest eta and the last rr.
+enum IterRecord { REC_EXEC = 0, REC_APPEND, REC_BREAK, REC_CONV, REC_ETAMIN, REC_RR, REC_COUNT };
+int iter_gate_init(int* gate, double* rec, hipStream_t s);
+int iter_consume(const double* scal, double thresh, int next_r, int* gate, double* rec,
+                 hipStream_t s);
 // v = Q y
 template <typename T>
 int gemv_n(const T* Q, int64_t ldq, int64_t n, int ncols, const double* y, T* out,
@@ -218,7 +240,7 @@ int diag_begin(int lik, const T* f, const void* y, int64_t n, double s2, T* winv
                hipStream_t s);
 template <typename T>
 int diag_apply(const T* winv, int64_t n, const T* V, int64_t nb, int64_t ldv, const T* Add,
-               int64_t lda, T* Out, int64_t ldo, hipStream_t s);
+               int64_t lda, T* Out, int64_t ldo, hipStream_t s, const int* gate = nullptr);
 template <typename T>
 int diag_stats(int lik, double s2, const T* fnew, const T* f, const T* v, const void* y,
                int64_t n, double* part, double* scal, hipStream_t s);
