@@ -58,7 +58,8 @@ kb_iter(const BIter* __restrict__ tab, const int64_t* __restrict__ pre, int nm) 
   } else if constexpr (OP == BOP_GEMV) {
     iter::gemv_t<float>(t.Q, t.ld, t.n, t.ncols, t.z, t.part, t.nchunks, bid);
   } else if constexpr (OP == BOP_FIN_COLS) {
-    iter::finish_col(t.part, t.nchunks, t.ncols, static_cast<int>(bid * NT + threadIdx.x), t.yb);
+    iter::finish_col(t.part, t.nchunks, t.ncols,
+                     static_cast<int>(bid * (NT / 64) + (threadIdx.x >> 6)), t.yb);
   } else if constexpr (OP == BOP_DIR) {
     __shared__ double sy[iter::MAXCOLS_LDS];
     __shared__ double red[NT / 64];
@@ -83,7 +84,7 @@ int64_t biter_blocks(int op, const BIter& t, bool residual) {
     case BOP_FIN_ETA: return 1;
     case BOP_WINV_Z: return ceil_div(t.lik == IGP_LIK_SOFTMAX ? t.N : t.n, NT);
     case BOP_GEMV: return t.ncols == 0 ? 0 : ceil_div(static_cast<int64_t>(t.nchunks) * t.ncols, NT / 64);
-    case BOP_FIN_COLS: return t.ncols == 0 ? 0 : ceil_div(t.ncols, NT);
+    case BOP_FIN_COLS: return t.ncols == 0 ? 0 : ceil_div(t.ncols, NT / 64);
     case BOP_DIR: return ceil_div(t.n, NT);
     case BOP_WINV_V: return residual ? ceil_div(t.lik == IGP_LIK_SOFTMAX ? t.N : t.n, NT) : 0;
     case BOP_RESID: return residual ? iter::grid_for(t.n) : 0;

@@ -102,23 +102,21 @@ __device__ inline void gemv_t(const T* __restrict__ Q, int64_t ldq, int64_t n, i
     if (i1 < n) acc1 += static_cast<double>(q[i1]) * static_cast<double>(z[i1]);
   }
   const double s = wave_sum(acc0 + acc1);
-  if (lane == 0) part[chunk * ncols + b] = s;
+  if (lane == 0) part[static_cast<int64_t>(b) * nchunks + chunk] = s;   // column-major
 }
 
 // y[b] = fixed-order sum of the chunk partials of column b (one thread per column)
-__device__ inline void finish_col(const double* __restrict__ part, int nrow_blocks, int ncols,
+__device__ inline void finish_col(const double* __restrict__ part, int nchunks, int ncols,
                                   int b, double* __restrict__ y) {
+  // one wave per column b: lane l adds the chunk partials l, l + 64, ..., then
+  // a fixed butterfly over the wave
   if (b >= ncols) return;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int r = 0;
-  for (; r + 4 <= nrow_blocks; r += 4) {
-    s0 += part[static_cast<int64_t>(r) * ncols + b];
-    s1 += part[static_cast<int64_t>(r + 1) * ncols + b];
-    s2 += part[static_cast<int64_t>(r + 2) * ncols + b];
-    s3 += part[static_cast<int64_t>(r + 3) * ncols + b];
-  }
-  for (; r < nrow_blocks; ++r) s0 += part[static_cast<int64_t>(r) * ncols + b];
-  y[b] = (s0 + s1) + (s2 + s3);
+  const int lane = threadIdx.x & 63;
+  const double* p = part + static_cast<int64_t>(b) * nchunks;
+  double s = 0.0;
+  for (int r = lane; r < nchunks; r += 64) s += p[r];
+  s = wave_sum(s);
+  if (lane == 0) y[b] = s;
 }
 
 // d = s - Q y (and kd = t - KQ y) ; part[bid] = z^T d over this block's rows.

@@ -136,10 +136,11 @@ k_gemv_t(const T* __restrict__ Q, int64_t ldq, int64_t n, int ncols, const T* __
   iter::gemv_t<T>(Q, ldq, n, ncols, z, part, nchunks, blockIdx.x);
 }
 
-__global__ void k_finish_cols(const double* __restrict__ part, int nrow_blocks, int ncols,
-                              double* __restrict__ y, const int* gate) {
+__global__ void __launch_bounds__(NT)
+k_finish_cols(const double* __restrict__ part, int nrow_blocks, int ncols,
+              double* __restrict__ y, const int* gate) {
   if (gate_closed(gate)) return;
-  iter::finish_col(part, nrow_blocks, ncols, blockIdx.x * blockDim.x + threadIdx.x, y);
+  iter::finish_col(part, nrow_blocks, ncols, blockIdx.x * (NT / 64) + (threadIdx.x >> 6), y);
 }
 
 // d = s - Q y ; eta partial = z^T d.  One row per thread; y staged in LDS.
@@ -443,8 +444,8 @@ int gemv_t(const T* Q, int64_t ldq, int64_t n, int ncols, const T* z, double* pa
   const int64_t waves = static_cast<int64_t>(nchunks) * ncols;
   k_gemv_t<T><<<static_cast<unsigned>(ceil_div(waves, NT / 64)), NT, 0, s>>>(Q, ldq, n, ncols, z,
                                                                              part, nchunks, gate);
-  k_finish_cols<<<static_cast<unsigned>(ceil_div(ncols, 64)), 64, 0, s>>>(part, nchunks, ncols, y,
-                                                                          gate);
+  k_finish_cols<<<static_cast<unsigned>(ceil_div(ncols, NT / 64)), NT, 0, s>>>(part, nchunks,
+                                                                              ncols, y, gate);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
