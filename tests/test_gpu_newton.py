@@ -174,3 +174,42 @@ def test_step_in_parts_equals_whole_step(gpu_lib):
             b.step_end()
         assert ia["iters"] == ib["iters"]
         assert torch.equal(a.view(0), b.view(0)) and torch.equal(a.view(2), b.view(2))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("residual", ["explicit", "recurrence"])
+def test_free_running_cg_repeatable(gpu_lib, cfg1, prec, residual):
+    """The solver enqueues iterations ahead of their convergence test and a
+    device gate stops the ones past it: three fresh fits give bitwise the same
+    iteration counts, buffers and iterates (the gate and the scalars the
+    iteration kernels read must never be read stale)."""
+    w = cfg1
+    kw = dict(policy="cg", j_max=60, rank_limit=40, recycle=True, tol_abs=1e-5, tol_rel=1e-5)
+    runs = []
+    for _ in range(3):
+        m, _ = _model(w, w.X, precision=prec, max_buffer=100, residual_mode=residual, **kw)
+        infos = [m.newton_step() for _ in range(4)]
+        runs.append(([(i["iters"], i["buffer_cols"], i["converged"]) for i in infos],
+                     m.view(0).clone(), m.view(2).clone()))
+    for r in runs[1:]:
+        assert r[0] == runs[0][0]
+        assert torch.equal(r[1], runs[0][1]) and torch.equal(r[2], runs[0][2])
+
+
+def test_window_boundaries_match_single_iterations(gpu_lib):
+    """Slices of 1..5 iterations (windows cut at every size) give bitwise the
+    iterates of the whole step."""
+    w = datagen.config2(N=1200, Ns=10)
+    kw = dict(policy="cg", j_max=23, rank_limit=20, recycle=True, precision="fp32",
+              residual_mode="recurrence")
+    ref, _ = _model(w, w.X, **kw)
+    ir = [ref.newton_step() for _ in range(2)]
+    for sl in (1, 2, 3, 5):
+        m, _ = _model(w, w.X, **kw)
+        for step in range(2):
+            m.step_begin()
+            while not m.step_iterate(sl):
+                pass
+            info = m.step_end()
+            assert info["iters"] == ir[step]["iters"], (sl, step)
+        assert torch.equal(m.view(0), ref.view(0)) and torch.equal(m.view(2), ref.view(2)), sl
