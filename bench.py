@@ -29,8 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Issue-bound ("alu") roofline of the fused FP32 product at small D (derivation
-# in the design doc).  FP32 MFMA and VALU work never execute at the same time on a
+# Issue-bound ("alu") roofline of the fused FP32 product at small D.  FP32 MFMA
+# and VALU work never execute at the same time on a
 # SIMD, so one 16 x 16 block of kernel values on one wave costs the sum of its
 # issue cycles:
 #   full-rate FP32 VALU op   4 cycles (16 lanes per cycle, wave64; no packed FP32)

@@ -6,7 +6,7 @@ notation: actions s_j, products t_j = K s_j, buffers S and T, root Q of the
 approximate precision C_j = Q Q^T, search direction d_j, normaliser eta_j,
 observation alpha_j, representer weights v_j.
 
-Readings of points the paper leaves open (each also listed in the design doc):
+Readings of points the paper leaves open:
 
 * The inner stopping test uses ||r_{j-1}|| right after it is formed, before
   an action is chosen; the iteration cap is tested before the residual is

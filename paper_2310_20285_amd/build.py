@@ -25,9 +25,22 @@ SOURCES = ["kv.hip", "kv_mfma.hip", "kv_bf16.hip", "hessian.hip", "diaglik.hip",
 ARCH = "gfx950"
 COMMON = [*os.environ.get("IGP_EXTRA_FLAGS", "").split(), "-O3", "-fPIC", "-std=c++17", f"-I{INCLUDE}", "-Wall", "-Wno-unused-function",
           "-Wno-unused-parameter"]
-# Packed FP32 instructions stay disabled on this target (see DESIGN.md).
+# Packed FP32 instructions stay disabled on this target.
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
+
+
+# host-only sources (no HIP kernels), built with the host C++ compiler against
+# the HIP host headers
+HOST_ONLY = {"eigh.cpp"}
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+
+
+def host_cxx() -> str:
+    for c in (os.environ.get("CXX"), shutil.which("g++"), shutil.which("c++")):
+        if c and os.path.exists(c):
+            return c
+    raise RuntimeError("no host C++ compiler found")
 
 
 def hipcc() -> str:
@@ -51,8 +64,11 @@ def _compile(src: str, force: bool) -> str:
     if (not force and os.path.exists(obj)
             and os.path.getmtime(obj) > max(os.path.getmtime(path), _headers_mtime())):
         return obj
-    host_simd = ["-Xarch_host", "-mavx2", "-Xarch_host", "-mfma"] if src == "eigh.cpp" else []
-    cmd = [hipcc(), "-x", "hip", *COMMON, *DEVICE, *host_simd, "-c", path, "-o", obj]
+    if src in HOST_ONLY:
+        cmd = [host_cxx(), *COMMON, "-mavx2", "-mfma", f"-I{ROCM}/include",
+               "-D__HIP_PLATFORM_AMD__", "-c", path, "-o", obj]
+    else:
+        cmd = [hipcc(), "-x", "hip", *COMMON, *DEVICE, "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

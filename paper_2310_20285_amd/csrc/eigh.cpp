@@ -10,17 +10,35 @@
 //     bulge with Givens rotations that are accumulated into Z;
 //  3. deflation when |e_i| <= eps (|d_i| + |d_{i+1}|).
 // Z is kept column-major so that every rotation and reflector update runs
-// over contiguous columns.
+// over contiguous columns.  Host-only code (built with the host C++ compiler):
+// the dot products run with four partial sums so that they vectorise.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
 #include <vector>
 
-#include "ops.hpp"
+#include "itergp.h"
 
 namespace igp {
 
+void set_error(const char* fmt, ...);
+int eigh_desc(int n, const double* A, double* w_out, double* Z_out);
+
 namespace {
+
+// sum_i a[i] b[i] in four interleaved partial sums, added in a fixed order
+inline double dot4(const double* a, const double* b, int m) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int i = 0;
+  for (; i + 4 <= m; i += 4) {
+    s0 += a[i] * b[i];
+    s1 += a[i + 1] * b[i + 1];
+    s2 += a[i + 2] * b[i + 2];
+    s3 += a[i + 3] * b[i + 3];
+  }
+  for (; i < m; ++i) s0 += a[i] * b[i];
+  return (s0 + s1) + (s2 + s3);
+}
 
 void tridiagonalize(int n, std::vector<double>& a, std::vector<double>& Z, std::vector<double>& d,
                     std::vector<double>& e) {
@@ -32,29 +50,20 @@ void tridiagonalize(int n, std::vector<double>& a, std::vector<double>& Z, std::
     const int m = n - k - 1;
     std::vector<double>& v = vs[k];
     v.assign(m, 0.0);
-    double sig = 0.0;
-    for (int i = 0; i < m; ++i) {
-      v[i] = a[static_cast<size_t>(k + 1 + i) * n + k];
-      sig += v[i] * v[i];
-    }
+    for (int i = 0; i < m; ++i) v[i] = a[static_cast<size_t>(k + 1 + i) * n + k];
+    const double sig = dot4(v.data(), v.data(), m);
     const double xnorm = std::sqrt(sig);
     if (xnorm == 0.0) continue;
     const double alpha = v[0] >= 0.0 ? -xnorm : xnorm;   // H x = alpha e_1
     v[0] -= alpha;
-    double vtv = 0.0;
-    for (int i = 0; i < m; ++i) vtv += v[i] * v[i];
+    const double vtv = dot4(v.data(), v.data(), m);
     if (vtv == 0.0) continue;
     const double beta = 2.0 / vtv;
     betas[k] = beta;
     // p = beta * A22 v
-    for (int i = 0; i < m; ++i) {
-      const double* row = &a[static_cast<size_t>(k + 1 + i) * n + (k + 1)];
-      double s = 0.0;
-      for (int j = 0; j < m; ++j) s += row[j] * v[j];
-      p[i] = beta * s;
-    }
-    double ptv = 0.0;
-    for (int i = 0; i < m; ++i) ptv += p[i] * v[i];
+    for (int i = 0; i < m; ++i)
+      p[i] = beta * dot4(&a[static_cast<size_t>(k + 1 + i) * n + (k + 1)], v.data(), m);
+    const double ptv = dot4(p.data(), v.data(), m);
     const double c = 0.5 * beta * ptv;
     for (int i = 0; i < m; ++i) w[i] = p[i] - c * v[i];
     // A22 -= v w^T + w v^T
@@ -83,9 +92,7 @@ void tridiagonalize(int n, std::vector<double>& a, std::vector<double>& Z, std::
     const int m = n - k - 1;
     for (int j = k + 1; j < n; ++j) {
       double* col = &Z[static_cast<size_t>(j) * n + (k + 1)];
-      double s = 0.0;
-      for (int i = 0; i < m; ++i) s += v[i] * col[i];
-      s *= betas[k];
+      const double s = betas[k] * dot4(v.data(), col, m);
       for (int i = 0; i < m; ++i) col[i] -= s * v[i];
     }
   }
@@ -104,7 +111,7 @@ void qr_step(int n, int l, int m, std::vector<double>& d, std::vector<double>& e
              std::vector<double>& Z) {
   const double dd = 0.5 * (d[m - 1] - d[m]);
   const double em = e[m - 1];
-  const double den = dd + std::copysign(std::hypot(dd, em), dd == 0.0 ? 1.0 : dd);
+  const double den = dd + std::copysign(std::sqrt(dd * dd + em * em), dd == 0.0 ? 1.0 : dd);
   const double mu = den != 0.0 ? d[m] - em * em / den : d[m] - std::fabs(em);
   double x = d[l] - mu, z = e[l];
   double bulge = 0.0;
@@ -113,7 +120,7 @@ void qr_step(int n, int l, int m, std::vector<double>& d, std::vector<double>& e
       x = e[k - 1];
       z = bulge;
     }
-    const double r = std::hypot(x, z);
+    const double r = std::sqrt(x * x + z * z);   // entries far from overflow
     double c = 1.0, s = 0.0;
     if (r != 0.0) {
       c = x / r;

@@ -1,7 +1,7 @@
 """GPU parity of the two standalone boundary calls against the FP64 oracle:
 glm_kernel_matmul and glm_softmax_hessian_apply.
 
-Tolerances (derived in DESIGN.md, "Parity tolerances"):
+Tolerances (rounding bounds of each precision):
   FP64: |got - ref| <= 1e-12 * (K |V|)            (rounding of ~n2 FP64 terms)
   FP32: |got - ref| <= 8 eps32 (8 + sqrt(n2)) * (K |V|)
 where K |V| is the oracle product with |V|, the natural scale of each entry.
