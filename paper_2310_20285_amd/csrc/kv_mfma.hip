@@ -463,16 +463,24 @@ kv_mfma_f32_sym(const float* __restrict__ Xp, const float* __restrict__ nrm, int
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, r = lane & 15;
 
-  // workgroup -> pair (s, u): items s Q - s (s - 1) / 2 ... precede super-block s
+  // workgroup -> pair (s, u): the Q (Q - 1) / 2 pairs u > s first (those of
+  // super-blocks before s number s (Q - 1) - s (s - 1) / 2), then the Q
+  // diagonal pairs, which take about half the work, at the end of the grid
   const int t = static_cast<int>(blockIdx.x);
-  int lo = 0, hi = Q - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (mid * Q - mid * (mid - 1) / 2 <= t) lo = mid;
-    else hi = mid - 1;
+  const int noff = Q * (Q - 1) / 2;
+  int s, u;
+  if (t >= noff) {
+    s = u = t - noff;
+  } else {
+    int lo = 0, hi = Q - 2;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (mid * (Q - 1) - mid * (mid - 1) / 2 <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    s = lo;
+    u = s + 1 + (t - (s * (Q - 1) - s * (s - 1) / 2));
   }
-  const int s = lo;
-  const int u = s + (t - (s * Q - s * (s - 1) / 2));
   const bool diag_item = u == s;
   const int64_t j_lo = u * ST;
   const int64_t j_hi = (u + 1) * ST < n ? (u + 1) * ST : n;
