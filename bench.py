@@ -41,7 +41,10 @@ if ROOT not in sys.path:
 # transposed sum, and then each evaluation serves two outputs.
 SIMDS, CLOCK_HZ = 256 * 4, 2.4e9
 VALU_CYCLES, TRANS_CYCLES, MFMA_F32_CYCLES = 4.0, 8.0, 32.0
-TRANSFORM_OPS = {"rbf": (2, 1), "matern12": (3, 2), "matern32": (5, 2), "matern52": (6, 2)}
+# transform (full-rate, transcendental) per value, the distance add and scale
+# included: Matern-3/2 and -5/2 take |t| into the square root as a free operand
+# modifier, Matern-1/2 clamps t at 0 with one max
+TRANSFORM_OPS = {"rbf": (2, 1), "matern12": (3, 2), "matern32": (4, 2), "matern52": (5, 2)}
 KV_INSTANCE = None
 
 
@@ -50,7 +53,7 @@ KV_INSTANCE = None
 # copy in the same run; profiles/kv_matern52_N20000_D16_C5_fp32.md and
 # profiles/kv_bf16_rbf_N60000_D784_C10.md).  Keyed by the kernel instance it
 # was measured on; any other instance reports null.
-MEASURED_TRAFFIC = {("kv_mfma_f32_sym<3,1,5>", "fp32"): 45.82e6,
+MEASURED_TRAFFIC = {("kv_mfma_f32_sym<3,1,5>", "fp32"): 46.04e6,
                     ("kv_bf16_sym<0>", "bf16"): 12.92e9}
 
 

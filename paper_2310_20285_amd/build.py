@@ -30,6 +30,11 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
           "-munsafe-fp-atomics"]
 
 
+# per-source device flags: the FP32 matrix-core kernels keep their MFMA
+# accumulators in ordinary VGPRs (no accumulator-register copies before the
+# kernel transform reads the distances)
+SOURCE_FLAGS = {"kv_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
 # host-only sources (no HIP kernels), built with the host C++ compiler against
 # the HIP host headers
 HOST_ONLY = {"eigh.cpp"}
@@ -68,7 +73,8 @@ def _compile(src: str, force: bool) -> str:
         cmd = [host_cxx(), *COMMON, "-mavx2", "-mfma", f"-I{ROCM}/include",
                "-D__HIP_PLATFORM_AMD__", "-c", path, "-o", obj]
     else:
-        cmd = [hipcc(), "-x", "hip", *COMMON, *DEVICE, "-c", path, "-o", obj]
+        cmd = [hipcc(), "-x", "hip", *COMMON, *DEVICE, *SOURCE_FLAGS.get(src, []), "-c", path,
+               "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

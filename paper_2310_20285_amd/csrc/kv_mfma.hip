@@ -47,7 +47,10 @@ __device__ inline float ktransform(float t) {
   if constexpr (KIND == IGP_RBF) {
     return __builtin_amdgcn_exp2f(-t);
   } else {
-    const float a = __builtin_amdgcn_sqrtf(fmaxf(t, 0.0f));
+    // Matern-3/2 and -5/2 are flat at r = 0 (k = 1 - O(r^2)), so a slightly
+    // negative t from rounding may enter through its magnitude (a free operand
+    // modifier); Matern-1/2 has slope at 0 and clamps instead
+    const float a = __builtin_amdgcn_sqrtf(KIND == IGP_MATERN12 ? fmaxf(t, 0.0f) : fabsf(t));
     const float e = __builtin_amdgcn_exp2f(-a);
     if constexpr (KIND == IGP_MATERN12) {
       return e;
