@@ -271,9 +271,13 @@ int itergp_get_view(const igp_model* m, int32_t which, const void** ptr,
                     int64_t* rows, int64_t* cols, int64_t* ld);
 
 /* Tracing: device time of the kernel-matrix products inside Newton steps,
- * measured with HIP events recorded on the model's stream around each
- * product (kernel evaluation, reduction of split partials).  Counters cover
- * every itergp_newton_step since the last itergp_set_profiling call. */
+ * measured with HIP events recorded on the model's stream around a product
+ * (kernel evaluation, reduction of split partials).  Each event adds a few
+ * microseconds of stream time, so the products may be sampled: with
+ * enable = k > 0 every k-th product of the model is timed (k = 1: all of them);
+ * products of solver iterations that did not run are never counted.
+ * Counters cover every itergp_newton_step since the last itergp_set_profiling
+ * call; enable = 0 turns tracing off. */
 typedef struct igp_profile {
   int64_t kv_launches;   /* products timed */
   double kv_ms;          /* sum of their device durations, milliseconds */
@@ -285,7 +289,7 @@ typedef struct igp_profile {
   int64_t steps;         /* Newton steps timed */
   int64_t kv_symmetric;  /* products among kv_launches that ran symmetric */
 } igp_profile;
-int itergp_set_profiling(igp_model* m, int32_t enable);   /* enables/disables and resets */
+int itergp_set_profiling(igp_model* m, int32_t enable);   /* 0: off; k > 0: time every k-th product; resets */
 int itergp_get_profile(const igp_model* m, igp_profile* out);
 
 /* Batched form: one Newton step of n independent models together.  Every

@@ -189,8 +189,9 @@ class IterNCGP:
         L.check(self.lib.itergp_newton_step_end(self.handle, ct.byref(info)))
         return info.as_dict()
 
-    def set_profiling(self, enable: bool = True):
-        L.check(self.lib.itergp_set_profiling(self.handle, 1 if enable else 0))
+    def set_profiling(self, enable: bool = True, every: int = 1):
+        """Turn product tracing on (timing every ``every``-th product) or off; resets."""
+        L.check(self.lib.itergp_set_profiling(self.handle, int(every) if enable else 0))
 
     def profile(self) -> dict:
         p = L.Profile()

@@ -235,6 +235,7 @@ int itergp_set_profiling(igp_model* m, int32_t enable) {
   return guarded([&]() -> int {
     clear_error();
     IGP_REQUIRE(m, "NULL model");
+    IGP_REQUIRE(enable >= 0, "profiling: enable must be 0 (off) or a sampling stride >= 1");
     return m->set_profiling(enable);
   });
 }

@@ -117,8 +117,10 @@ struct Model final : igp_model {
   int64_t user_cols = 0, user_ld = 0;
   int steps_done = 0;
   std::vector<double> hM, hMs, hU, hlam, hscale;
-  // tracing
+  // tracing: every prof_every-th product is timed (prof_seq counts them)
   bool prof = false;
+  int prof_every = 1;
+  int64_t prof_seq = 0;
   std::vector<hipEvent_t> evpool;
   size_t evused = 0;
   igp_profile pstat{};
@@ -182,7 +184,9 @@ struct Model final : igp_model {
   }
 
   int set_profiling(int enable) override {
-    prof = enable != 0;
+    prof = enable > 0;
+    prof_every = enable > 0 ? enable : 1;
+    prof_seq = 0;
     pstat = igp_profile{};
     evused = 0;
     pending_evals = pending_flops = 0.0;
@@ -233,7 +237,8 @@ struct Model final : igp_model {
   // Out = K V; with a gate, part of solver iteration `iter`, skipped once the gate closes
   int apply_K(const T* V, T* Out, const int* gate = nullptr, int iter = 0) {
     hipEvent_t a = nullptr, b = nullptr;
-    if (prof) {
+    const bool timed = prof && (prof_seq++ % prof_every == 0);
+    if (timed) {
       IGP_TRY(event_pair(&a, &b));
       IGP_CHECK_HIP(hipEventRecord(a, stream));
     }
@@ -242,7 +247,7 @@ struct Model final : igp_model {
     p.symmetric_out = &sym;
     p.skip = gate;
     IGP_TRY(kv_launch(p, L.kvws, L.kvws_bytes, stream));
-    if (prof) {
+    if (timed) {
       IGP_CHECK_HIP(hipEventRecord(b, stream));
       const double Nd = static_cast<double>(N);
       const double evals = sym ? Nd * (Nd + 1.0) / 2.0 : Nd * Nd;

@@ -213,3 +213,30 @@ def test_window_boundaries_match_single_iterations(gpu_lib):
             info = m.step_end()
             assert info["iters"] == ir[step]["iters"], (sl, step)
         assert torch.equal(m.view(0), ref.view(0)) and torch.equal(m.view(2), ref.view(2)), sl
+
+
+def test_profiling_stride(gpu_lib, cfg1):
+    """Product tracing: stride 1 times every product of the steps that ran,
+    stride 3 a subset, with the same evaluations per timed product (the
+    symmetric count n(n+1)/2); the iterates do not depend on tracing; a negative
+    stride is refused."""
+    w = cfg1
+    kw = dict(policy="cg", j_max=30, rank_limit=20, recycle=True, precision="fp32",
+              residual_mode="recurrence", max_buffer=90)
+    out = {}
+    for every in (1, 3):
+        m, _ = _model(w, w.X, **kw)
+        m.set_profiling(True, every=every)
+        infos = [m.newton_step() for _ in range(3)]
+        prof = m.profile()
+        total = sum(i["k_products"] for i in infos)
+        if every == 1:
+            assert prof["kv_launches"] == total
+        else:
+            assert 1 <= prof["kv_launches"] < total
+        assert prof["kv_evals"] / prof["kv_launches"] == pytest.approx(w.N * (w.N + 1) / 2)
+        assert prof["kv_ms"] > 0.0 and prof["steps"] == 3
+        out[every] = m.view(0).double().cpu().numpy()
+    assert np.array_equal(out[1], out[3])
+    with pytest.raises(Exception):
+        m.set_profiling(True, every=-1)
