@@ -164,14 +164,13 @@ __device__ inline void dir_update(const T* __restrict__ sv, const T* __restrict_
 
 // eta > 0: Q column = d / sqrt(eta), v += (alpha / eta) d (and the K Q / K v twins)
 template <typename T, bool KQ>
-__device__ inline void append_step(const T* __restrict__ d, const double* __restrict__ scal,
-                                   T* __restrict__ qcol, T* __restrict__ v, int64_t n,
-                                   const T* __restrict__ kd, T* __restrict__ kqcol,
-                                   T* __restrict__ kv, int64_t bid, int64_t nblk) {
-  const double eta = coherent_load(scal + SC_ETA);
+__device__ inline void append_step_vals(const T* __restrict__ d, double alpha, double eta,
+                                        T* __restrict__ qcol, T* __restrict__ v, int64_t n,
+                                        const T* __restrict__ kd, T* __restrict__ kqcol,
+                                        T* __restrict__ kv, int64_t bid, int64_t nblk) {
   if (!(eta > 0.0)) return;
   const double qs = 1.0 / sqrt(eta);
-  const double step = coherent_load(scal + SC_ALPHA) / eta;
+  const double step = alpha / eta;
   for (int64_t i = bid * NT + threadIdx.x; i < n; i += nblk * NT) {
     const double di = static_cast<double>(d[i]);
     qcol[i] = static_cast<T>(di * qs);
@@ -182,6 +181,16 @@ __device__ inline void append_step(const T* __restrict__ d, const double* __rest
       kv[i] = static_cast<T>(static_cast<double>(kv[i]) + step * ki);
     }
   }
+}
+
+// the same with alpha and eta read from scal
+template <typename T, bool KQ>
+__device__ inline void append_step(const T* __restrict__ d, const double* __restrict__ scal,
+                                   T* __restrict__ qcol, T* __restrict__ v, int64_t n,
+                                   const T* __restrict__ kd, T* __restrict__ kqcol,
+                                   T* __restrict__ kv, int64_t bid, int64_t nblk) {
+  append_step_vals<T, KQ>(d, coherent_load(scal + SC_ALPHA), coherent_load(scal + SC_ETA), qcol,
+                          v, n, kd, kqcol, kv, bid, nblk);
 }
 
 // ---- softmax-Hessian blocks (one thread per data point) ----------------------

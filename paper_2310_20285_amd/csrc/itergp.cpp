@@ -29,6 +29,7 @@ struct Layout {
   T *S, *Tb, *Q, *S2, *T2;
   T *KQ, *kd;   // recurrence mode: K Q and K d
   double *part, *scal, *yb, *M, *U, *lamscale, *gram_part;
+  double* apart;  // partials of a solver iteration's alpha (finished by the append step)
   size_t gram_cap;
   void* kvws;
   size_t kvws_bytes;
@@ -91,6 +92,7 @@ Layout<T> carve(Carver& cv, int64_t N, int64_t D, int64_t C, const igp_solver_co
   L.flags = cv.take<int>(64);
   L.gate = cv.take<int>(1);
   L.rec = cv.take<double>(REC_COUNT);
+  L.apart = cv.take<double>(RED_BLOCKS);
   if (prepared) {
     L.centre = cv.take<float>(D);
     L.Xp = cfg.precision == IGP_BF16 ? static_cast<void*>(cv.take<uint16_t>(N * bf16_padded_dim(D)))
@@ -552,22 +554,24 @@ struct Model final : igp_model {
     int* gate = L.gate;
     T* sv = L.S + static_cast<int64_t>(col) * ld;
     T* tv = L.Tb + static_cast<int64_t>(col) * ld;
+    // alpha and eta stay as partials (L.apart, L.part) until the append step
+    // finishes them
     if (cfg.policy == IGP_POLICY_CG) {
-      IGP_TRY(action_cg_dot<T>(L.r, L.scal + SC_RR, sv, n, L.part, L.scal + SC_ALPHA, gate,
-                               stream));
+      IGP_TRY(action_cg_dot<T>(L.r, L.scal + SC_RR, sv, n, L.apart, nullptr, gate, stream));
     } else {
       if (cfg.policy == IGP_POLICY_UNIT)
         IGP_TRY(fill_unit<T>(sv, n, jj - 1, stream, gate));
       else
         IGP_TRY(copy_vec<T>(user + static_cast<int64_t>(jj - 1) * user_ld, sv, n, stream, gate));
-      IGP_TRY(dot_into<T>(sv, L.r, n, L.part, L.scal + SC_ALPHA, stream, gate));
+      IGP_TRY(dot_into<T>(sv, L.r, n, L.apart, nullptr, stream, gate));
     }
     IGP_TRY(apply_K(sv, tv, gate, jj));
     IGP_TRY(apply_winv(sv, 1, n, tv, n, L.z, n, gate));
     IGP_TRY(gemv_t<T>(L.Q, ld, n, col, L.z, L.part, L.yb, stream, gate));
-    IGP_TRY(dir_update<T>(sv, L.Q, ld, n, col, L.yb, L.z, L.d, L.part, L.scal + SC_ETA, stream,
-                          tv, recurrence() ? L.KQ : nullptr, L.kd, gate));
-    IGP_TRY(append_and_step<T>(L.d, L.scal, L.Q + static_cast<int64_t>(col) * ld, L.v, n,
+    IGP_TRY(dir_update<T>(sv, L.Q, ld, n, col, L.yb, L.z, L.d, L.part, nullptr, stream, tv,
+                          recurrence() ? L.KQ : nullptr, L.kd, gate));
+    IGP_TRY(append_and_step<T>(L.d, L.apart, L.part, L.scal,
+                               L.Q + static_cast<int64_t>(col) * ld, L.v, n,
                                stream, recurrence() ? L.kd : nullptr,
                                recurrence() ? L.KQ + static_cast<int64_t>(col) * ld : nullptr,
                                L.kv, gate));

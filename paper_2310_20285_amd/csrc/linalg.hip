@@ -169,13 +169,26 @@ __global__ void k_gemv_n(const T* __restrict__ Q, int64_t ldq, int64_t n, int nc
   out[i] = static_cast<T>(acc);
 }
 
+// every block finishes alpha and eta from their partials (the fixed-order sum
+// of k_finish_sum, so all blocks hold the same values); block 0 stores them
 template <typename T, bool KQ>
 __global__ void __launch_bounds__(NT)
-k_append_step(const T* __restrict__ d, const double* __restrict__ scal, T* __restrict__ qcol,
-              T* __restrict__ v, int64_t n, const T* __restrict__ kd, T* __restrict__ kqcol,
-              T* __restrict__ kv, const int* gate) {
+k_append_step(const T* __restrict__ d, const double* __restrict__ apart, int anblk,
+              const double* __restrict__ epart, int enblk, double* __restrict__ scal,
+              T* __restrict__ qcol, T* __restrict__ v, int64_t n, const T* __restrict__ kd,
+              T* __restrict__ kqcol, T* __restrict__ kv, const int* gate) {
   if (gate_closed(gate)) return;
-  iter::append_step<T, KQ>(d, scal, qcol, v, n, kd, kqcol, kv, blockIdx.x, gridDim.x);
+  __shared__ double red[NT / 64];
+  double a = 0.0, e = 0.0;
+  for (int i = threadIdx.x; i < anblk; i += NT) a += apart[i];
+  a = block_sum(a, red);
+  for (int i = threadIdx.x; i < enblk; i += NT) e += epart[i];
+  e = block_sum(e, red);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal[SC_ALPHA] = a;
+    scal[SC_ETA] = e;
+  }
+  iter::append_step_vals<T, KQ>(d, a, e, qcol, v, n, kd, kqcol, kv, blockIdx.x, gridDim.x);
 }
 
 // Gram matrix M = A^T B over a chunk of rows; 32 x 32 output tile per block,
@@ -383,7 +396,7 @@ int dot_into(const T* a, const T* b, int64_t n, double* part, double* out, hipSt
              const int* gate) {
   const int g = grid_for(n);
   k_dot<T><<<g, NT, 0, s>>>(a, b, n, part, gate);
-  k_finish_sum<<<1, NT, 0, s>>>(part, g, out, gate);
+  if (out) k_finish_sum<<<1, NT, 0, s>>>(part, g, out, gate);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
@@ -393,7 +406,7 @@ int action_cg_dot(const T* r, const double* rr, T* sv, int64_t n, double* part, 
                   const int* gate, hipStream_t s) {
   const int g = grid_for(n);
   k_action_cg_dot<T><<<g, NT, 0, s>>>(r, rr, sv, n, part, gate);
-  k_finish_sum<<<1, NT, 0, s>>>(part, g, alpha, gate);
+  if (alpha) k_finish_sum<<<1, NT, 0, s>>>(part, g, alpha, gate);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
@@ -465,19 +478,22 @@ int dir_update(const T* sv, const T* Q, int64_t ldq, int64_t n, int ncols, const
   else
     k_dir_update<T, false><<<g, NT, 0, s>>>(sv, Q, ldq, n, ncols, y, z, d, part, nullptr,
                                             nullptr, nullptr, gate);
-  k_finish_sum<<<1, NT, 0, s>>>(part, g, eta_out, gate);
+  if (eta_out) k_finish_sum<<<1, NT, 0, s>>>(part, g, eta_out, gate);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
 
 template <typename T>
-int append_and_step(const T* d, const double* scal, T* qcol, T* v, int64_t n, hipStream_t s,
-                    const T* kd, T* kqcol, T* kv, const int* gate) {
+int append_and_step(const T* d, const double* apart, const double* epart, double* scal, T* qcol,
+                    T* v, int64_t n, hipStream_t s, const T* kd, T* kqcol, T* kv,
+                    const int* gate) {
+  const int anblk = grid_for(n), enblk = static_cast<int>(ceil_div(n, NT));
   if (kd)
-    k_append_step<T, true><<<grid_for(n), NT, 0, s>>>(d, scal, qcol, v, n, kd, kqcol, kv, gate);
+    k_append_step<T, true><<<grid_for(n), NT, 0, s>>>(d, apart, anblk, epart, enblk, scal, qcol,
+                                                      v, n, kd, kqcol, kv, gate);
   else
-    k_append_step<T, false><<<grid_for(n), NT, 0, s>>>(d, scal, qcol, v, n, nullptr, nullptr,
-                                                       nullptr, gate);
+    k_append_step<T, false><<<grid_for(n), NT, 0, s>>>(d, apart, anblk, epart, enblk, scal, qcol,
+                                                       v, n, nullptr, nullptr, nullptr, gate);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
@@ -580,8 +596,8 @@ int predict_epilogue(const T* A, int64_t lda, int64_t nrows, int ncols, const do
   template int dir_update<T>(const T*, const T*, int64_t, int64_t, int, const double*,         \
                              const T*, T*, double*, double*, hipStream_t, const T*, const T*,  \
                              T*, const int*);                                                  \
-  template int append_and_step<T>(const T*, const double*, T*, T*, int64_t, hipStream_t,      \
-                                  const T*, T*, T*, const int*);                               \
+  template int append_and_step<T>(const T*, const double*, const double*, double*, T*, T*,   \
+                                  int64_t, hipStream_t, const T*, T*, T*, const int*);         \
   template int gemv_n<T>(const T*, int64_t, int64_t, int, const double*, T*, hipStream_t);     \
   template int gram<T>(const T*, const T*, int64_t, int64_t, int, double*, size_t, double*,   \
                        hipStream_t);                                                           \

@@ -181,10 +181,13 @@ int residual(const T* rhs, const T* kv, const T* wv, T* r, int64_t n, double* pa
 template <typename T>
 int residual_consume(const T* rhs, const T* kv, const T* wv, T* r, int64_t n, double* partials,
                      double* scal, double thresh, int* gate, double* rec, hipStream_t s);
+// a^T b: grid_for(n) block partials, then (when out_scalar is non-null) their
+// fixed-order sum into out_scalar
 template <typename T>
 int dot_into(const T* a, const T* b, int64_t n, double* partials, double* out_scalar,
              hipStream_t s, const int* gate = nullptr);
-// s = r / sqrt(rr) and alpha = s^T r (one pass over r, then the finishing sum)
+// s = r / sqrt(rr) and the grid_for(n) partials of alpha = s^T r in one pass
+// over r, then (when alpha is non-null) their sum into alpha
 template <typename T>
 int action_cg_dot(const T* r, const double* rr, T* s_out, int64_t n, double* partials,
                   double* alpha, const int* gate, hipStream_t s);
@@ -200,18 +203,23 @@ int add_vec(const T* a, const T* b, T* out, int64_t n, hipStream_t s);
 template <typename T>
 int gemv_t(const T* Q, int64_t ldq, int64_t n, int ncols, const T* z, double* partials,
            double* y, hipStream_t s, const int* gate = nullptr);
-// d = s - Q y ; eta partials of z^T d ; with KQ: also kd = t - KQ y (= K d)
+// d = s - Q y ; the ceil(n / 256) partials of eta = z^T d, summed into eta_out
+// when it is non-null ; with KQ: also kd = t - KQ y (= K d)
 template <typename T>
 int dir_update(const T* sv, const T* Q, int64_t ldq, int64_t n, int ncols, const double* y,
                const T* z, T* d, double* partials, double* eta_out, hipStream_t s,
                const T* tv = nullptr, const T* KQ = nullptr, T* kd = nullptr,
                const int* gate = nullptr);
+// alpha and eta from their partials (alpha_part: the grid_for(n) partials of
+// dot_into / action_cg_dot; eta_part: the ceil(n / 256) partials of
+// dir_update), summed in the same fixed order as the finishing kernel by every
+// block and stored in scal[SC_ALPHA], scal[SC_ETA]; then
 // Q[:, col] = d / sqrt(eta); v += (alpha/eta) d   (no-op when eta <= 0)
 // with kd: also KQ[:, col] = kd / sqrt(eta); kv += (alpha/eta) kd
 template <typename T>
-int append_and_step(const T* d, const double* scal, T* qcol, T* v, int64_t n, hipStream_t s,
-                    const T* kd = nullptr, T* kqcol = nullptr, T* kv = nullptr,
-                    const int* gate = nullptr);
+int append_and_step(const T* d, const double* alpha_part, const double* eta_part, double* scal,
+                    T* qcol, T* v, int64_t n, hipStream_t s, const T* kd = nullptr,
+                    T* kqcol = nullptr, T* kv = nullptr, const int* gate = nullptr);
 // Device-side end of a solver iteration (after its eta and, when next_r, its
 // residual norm are in scal): unless the gate is already closed, count the
 // iteration in rec, close the gate on a breakdown (eta <= 0) or when
