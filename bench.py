@@ -235,9 +235,21 @@ def main():
     if not args.no_plain:
         out["plain_fp32"] = plain_comparison(w, X, y, Xs, args.steps, jmax, R, elapsed / args.steps,
                                              float(np.percentile(pred_ms, 99)))
+        out["dense_k_fp32"] = dense_k(w, X, kv_avg_s)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, k_per_step)
     print(json.dumps(out))
+
+
+def dense_k(w, X, fused_s):
+    """Dense-K-in-HBM FP32 product (K formed once, then one GEMM per product)
+    beside the fused product's time."""
+    from plain_fp32 import dense_k_comparison
+    r = dense_k_comparison(X, w.C, w.kernel, w.lengthscale, w.outputscale)
+    if "product_ms" in r:
+        r["fused_product_ms"] = fused_s * 1e3
+        r["dense_over_fused"] = r["product_ms"] / (fused_s * 1e3)
+    return r
 
 
 def plain_comparison(w, X, y, Xs, steps, jmax, R, ours_s_per_step, ours_p99_ms):
@@ -441,6 +453,7 @@ def bench_image(args):
                      "avg_launch_us": kv_avg_s * 1e6,
                      "dense_equivalent_tflops": dense_tflops},
         "kv_error_vs_fp64": {"rel_l2_64_rows": kv_err},
+        "dense_k_fp32": None if args.no_plain else dense_k(w, X, kv_avg_s),
         "newton": [{k: (round(v_, 6) if isinstance(v_, float) else v_) for k, v_ in i.items()
                     if k in ("iters", "buffer_cols", "rel_change", "psi")} for i in infos],
     }

@@ -132,6 +132,46 @@ class PlainIterNCGP:
         return mean, var, probs
 
 
+def dense_k_comparison(X: torch.Tensor, C: int, kind: str, lengthscale: float,
+                       outputscale: float, reps: int = 5, block: int = 4096) -> dict:
+    """Dense-K-in-HBM FP32 form of the product: K(X, X) formed once (blockwise
+    |x|^2 + |x'|^2 - 2 X X^T -> kernel, TF32 off) and kept in HBM as N^2 FP32
+    values; each product K V with V of N x C is then one GEMM that streams K.
+    Reported beside the fused product where K fits in free device memory."""
+    torch.backends.cuda.matmul.allow_tf32 = False
+    N = X.shape[0]
+    kbytes = N * N * 4
+    free, _ = torch.cuda.mem_get_info()
+    if kbytes + 4 * block * N * 4 > 0.8 * free:
+        return {"skipped": f"K needs {kbytes / 1e9:.1f} GB, {free / 1e9:.1f} GB free"}
+    pm = PlainIterNCGP(X.float(), torch.zeros(N, dtype=torch.int32, device=X.device), C, kind,
+                       lengthscale, outputscale, block=block)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    K = torch.empty(N, N, device=X.device)
+    for i0 in range(0, N, block):
+        xb = pm.X[i0:i0 + block]
+        r2 = pm.sq[i0:i0 + block, None] + pm.sq[None, :] - 2.0 * (xb @ pm.X.T)
+        K[i0:i0 + block] = pm.kfun(r2)
+    e1.record()
+    torch.cuda.synchronize()
+    form_ms = e0.elapsed_time(e1)
+    V = torch.randn(N, C, device=X.device)
+    out = K @ V
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        out = K @ V
+    e1.record()
+    torch.cuda.synchronize()
+    prod_ms = e0.elapsed_time(e1) / reps
+    del K, out
+    torch.cuda.empty_cache()
+    return {"k_bytes": kbytes, "form_ms": form_ms, "product_ms": prod_ms,
+            "k_stream_tb_per_s": kbytes / (prod_ms * 1e-3) / 1e12}
+
+
 def fifo_replay(served: PlainIterNCGP, requests, fit_config: dict, steps: int,
                 realtime: bool = True):
     """Serve a request stream one request at a time in arrival order (no
