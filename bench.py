@@ -76,7 +76,7 @@ def peak_evals_per_s(kind: str, W: int, D: int, symmetric: bool) -> float:
 def cpu_baseline(w, k_products_per_step: float):
     """Time the oracle's FP64 K.v product on a bounded slice of the workload."""
     import numpy as np
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import kernels as ok
     rows = 4000
@@ -88,13 +88,23 @@ def cpu_baseline(w, k_products_per_step: float):
     per_product = dt * (w.N / rows)
     per_step = per_product * k_products_per_step
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    # the same on one thread (BLAS pool limited to 1), on a quarter of the rows
+    rows1 = rows // 4
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        ok.kernel_matvec(w.X[:rows1], w.X, v, w.kernel, w.lengthscale, w.outputscale)
+        dt1 = time.perf_counter() - t0
+    per_product1 = dt1 * (w.N / rows1)
     return {"value": 1.0 / per_step, "unit": "Newton steps/s", "cores": threads,
             "kind": "oracle",
             "sample": (f"oracle.kernels.kernel_matvec (FP64 numpy) on {rows} of the {w.N} rows "
                        f"of one K.v product ({dt:.1f} s), scaled to a full product "
                        f"({per_product:.1f} s) and to {k_products_per_step:.0f} products per "
                        f"Newton step as measured on the GPU; elementwise numpy runs on one "
-                       f"thread, its matrix products on the BLAS pool")}
+                       f"thread, its matrix products on the BLAS pool"),
+            "single_thread": {"value": 1.0 / (per_product1 * k_products_per_step),
+                              "unit": "Newton steps/s", "cores": 1,
+                              "sample": f"{rows1} rows ({dt1:.1f} s), scaled the same way"}}
 
 
 def main():
