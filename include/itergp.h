@@ -146,11 +146,19 @@ typedef enum igp_residual_mode {
  * its pseudo-inverse).  Poisson (log link) and Gaussian: one observation per
  * latent value, y with N*C entries in CN-ordering (int32 counts >= 0 for
  * Poisson; finite targets of the model's element type for Gaussian), W^{-1}
- * diagonal: exp(-f) (appendix on the Poisson log likelihood) or noise_var. */
+ * diagonal: exp(-f) (appendix on the Poisson log likelihood) or noise_var.
+ * Block: any likelihood that factorises over the N points, supplied by the
+ * caller before each Newton step (and before itergp_compress) through
+ * itergp_set_block_likelihood as the gradient of log p at the current f and
+ * the per-point C x C blocks W_n of its negative Hessian (symmetric positive
+ * definite); the step uses yhat - m = f + W^{-1} grad (section 3.1 with m = 0)
+ * and per-point C x C solves; y is unused (may be NULL) and psi is NaN (log p
+ * at the new iterate is the caller's). */
 typedef enum igp_likelihood {
   IGP_LIK_SOFTMAX = 0,
   IGP_LIK_POISSON = 1,
-  IGP_LIK_GAUSSIAN = 2
+  IGP_LIK_GAUSSIAN = 2,
+  IGP_LIK_BLOCK = 3
 } igp_likelihood;
 
 typedef struct igp_solver_config {
@@ -289,6 +297,20 @@ typedef struct igp_profile {
   int64_t steps;         /* Newton steps timed */
   int64_t kv_symmetric;  /* products among kv_launches that ran symmetric */
 } igp_profile;
+/* Block likelihood (IGP_LIK_BLOCK): gradient and negative-Hessian blocks at the
+ * model's current f (Algorithm 1, the per-step W and pseudo-targets), for the
+ * next itergp_newton_step or itergp_compress, which consume them.
+ *   grad  N*C values, CN-ordering (grad[n*C + c] = d log p / d f_{n,c}).
+ *   W     N*C*C values: W[(n*C + a)*C + b] = -d^2 log p / d f_{n,a} d f_{n,b};
+ *         each block symmetric positive definite.
+ * Device pointers of the model's element type; read on the model's stream
+ * before the call returns (the call synchronises it), then free.  Each block
+ * is inverted on the device (Gauss-Jordan in FP64, one wave per point) and
+ * f + W^{-1} grad formed.  Errors: IGP_EINVAL for a model of another
+ * likelihood, NULL pointers, or a block whose pivots are not all positive
+ * (not positive definite), with the count in the message. */
+int itergp_set_block_likelihood(igp_model* m, const void* grad, const void* W);
+
 int itergp_set_profiling(igp_model* m, int32_t enable);   /* 0: off; k > 0: time every k-th product; resets */
 int itergp_get_profile(const igp_model* m, igp_profile* out);
 

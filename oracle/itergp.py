@@ -27,7 +27,9 @@ Readings of points the paper leaves open:
   without recycling (the paper's Cholesky runs are without recycling).
 
 Likelihoods with a diagonal negative Hessian (Poisson with log link,
-Gaussian) run the same loop with W^{-1} diagonal (iterncgp_diag).
+Gaussian) run the same loop with W^{-1} diagonal (iterncgp_diag); any
+likelihood that factorises over the points, given as its gradient and C x C
+negative-Hessian blocks, with W^{-1} block diagonal (iterncgp_block).
 
 Pins (tests/test_oracle_itergp.py): full-budget IterGP equals the dense
 Cholesky solve; C_j = S (S^T Khat S)^{-1} S^T equals Q Q^T; the unit policy
@@ -264,6 +266,43 @@ def iterncgp_diag(apply_K: Apply, y: np.ndarray, steps: int, likelihood: str = "
         rel = float(np.linalg.norm(f_new - f) / nn) if nn > 0 else float("inf")
         recs.append(NewtonRecord(f_new[:, None], v, Q, rhs, info, rel, S, T))
         f = f_new
+        if outer_tol is not None and rel <= outer_tol:
+            break
+    return recs
+
+
+def iterncgp_block(apply_K: Apply, terms: Callable, N: int, C: int, steps: int,
+                   policy: str = "cg", j_max: int = 100, rank_limit: Optional[int] = None,
+                   recycle: bool = True, tol_abs: float = 1e-5, tol_rel: float = 1e-5,
+                   outer_tol: Optional[float] = None,
+                   user_actions: Optional[List[np.ndarray]] = None,
+                   F0: Optional[np.ndarray] = None):
+    """Algorithm 1 for a likelihood that factorises over the N points, m = 0,
+    f_0 = m.  ``terms(F)`` returns the gradient of log p at F, shape (N, C),
+    and the negative-Hessian blocks W_n, shape (N, C, C), each symmetric
+    positive definite.  The Newton step of section 3.1 as GP regression:
+    yhat - m = f + W^{-1} grad, then (K + W^{-1}) v = yhat - m by IterGP with
+    W^{-1} block diagonal (each block inverted by numpy.linalg.inv),
+    f_{i+1} = K v.  Returns the list of NewtonRecord."""
+    n = N * C
+    F = np.zeros((N, C)) if F0 is None else np.array(F0, dtype=np.float64)
+    S, T = np.zeros((n, 0)), np.zeros((n, 0))
+    recs = []
+    for i in range(steps):
+        grad, W = terms(F)
+        Winv = np.linalg.inv(np.asarray(W, dtype=np.float64))
+        apply_Winv = (lambda B: (lambda V: lik.apply_blocks(B, V)))(Winv)
+        rhs = F.reshape(-1) + lik.apply_blocks(Winv, np.asarray(grad, dtype=np.float64).reshape(-1))
+        ua = None if user_actions is None else user_actions[i]
+        v, Q, S, T, info = itergp(apply_K, apply_Winv, rhs, S, T, policy, j_max,
+                                  tol_abs, tol_rel, rank_limit,
+                                  recycle and policy != "unit", ua)
+        F_new = apply_K(v).reshape(N, C)
+        g_old, g_new = F.reshape(-1), F_new.reshape(-1)
+        nn = float(np.linalg.norm(g_new))
+        rel = float(np.linalg.norm(g_new - g_old) / nn) if nn > 0 else float("inf")
+        recs.append(NewtonRecord(F_new, v, Q, rhs, info, rel, S, T))
+        F = F_new
         if outer_tol is not None and rel <= outer_tol:
             break
     return recs

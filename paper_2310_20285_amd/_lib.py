@@ -31,7 +31,7 @@ class KernelParams(ct.Structure):
                 ("lengthscale", ct.c_double), ("outputscale", ct.c_double)]
 
 
-IGP_LIK_SOFTMAX, IGP_LIK_POISSON, IGP_LIK_GAUSSIAN = 0, 1, 2
+IGP_LIK_SOFTMAX, IGP_LIK_POISSON, IGP_LIK_GAUSSIAN, IGP_LIK_BLOCK = 0, 1, 2, 3
 
 
 class SolverConfig(ct.Structure):
@@ -81,6 +81,7 @@ SIGNATURES = {
     "itergp_init": (ct.c_int, [ct.POINTER(_P), ct.POINTER(KernelParams), _I32,
                                ct.POINTER(SolverConfig), _P, _P, _I64, _I64, _I64, _P, _SZ, _P]),
     "itergp_set_user_actions": (ct.c_int, [_P, _P, _I64, _I64]),
+    "itergp_set_block_likelihood": (ct.c_int, [_P, _P, _P]),
     "itergp_newton_step": (ct.c_int, [_P, ct.POINTER(StepInfo)]),
     "itergp_compress": (ct.c_int, [_P, _I32, ct.POINTER(_I32)]),
     "itergp_newton_step_begin": (ct.c_int, [_P]),

@@ -112,7 +112,7 @@ def glm_softmax_hessian_apply(F: torch.Tensor, V: torch.Tensor, mode="pinv",
 
 
 _LIK = {"softmax": L.IGP_LIK_SOFTMAX, "poisson": L.IGP_LIK_POISSON,
-        "gaussian": L.IGP_LIK_GAUSSIAN}
+        "gaussian": L.IGP_LIK_GAUSSIAN, "block": L.IGP_LIK_BLOCK}
 
 
 def solver_config(policy="cg", j_max=100, rank_limit=-1, recycle=True, tol_abs=1e-5,
@@ -146,7 +146,8 @@ class IterNCGP:
         self.dtype = _DTYPE[self.precision]
         _need(X, self.dtype, "X")
         gaussian = self.cfg.likelihood == L.IGP_LIK_GAUSSIAN
-        _need(y, self.dtype if gaussian else torch.int32, "y")
+        if self.cfg.likelihood != L.IGP_LIK_BLOCK or y is not None:
+            _need(y, self.dtype if gaussian else torch.int32, "y")
         self.N, self.D = X.shape
         self.C = int(C)
         self.y = y                       # kept alive: the model reads it every step
@@ -158,7 +159,8 @@ class IterNCGP:
         self.stream = torch.cuda.current_stream()   # the model runs all its work here
         self.handle = ct.c_void_p()
         L.check(self.lib.itergp_init(ct.byref(self.handle), self.kp, self.n_kp,
-                                     ct.byref(self.cfg), _ptr(X), _ptr(y), self.N, self.D,
+                                     ct.byref(self.cfg), _ptr(X),
+                                     None if y is None else _ptr(y), self.N, self.D,
                                      self.C, _ptr(self.arena), nbytes, _stream()))
         self._user = None
 
@@ -188,6 +190,14 @@ class IterNCGP:
         info = L.StepInfo()
         L.check(self.lib.itergp_newton_step_end(self.handle, ct.byref(info)))
         return info.as_dict()
+
+    def set_block_likelihood(self, grad: torch.Tensor, W: torch.Tensor) -> None:
+        """itergp_set_block_likelihood: grad (N*C,) and W (N, C, C) at the current f."""
+        _need(grad, self.dtype, "grad")
+        _need(W, self.dtype, "W")
+        if grad.numel() != self.N * self.C or W.numel() != self.N * self.C * self.C:
+            raise ValueError("grad must hold N*C values and W N*C*C")
+        L.check(self.lib.itergp_set_block_likelihood(self.handle, _ptr(grad), _ptr(W)))
 
     def set_profiling(self, enable: bool = True, every: int = 1):
         """Turn product tracing on (timing every ``every``-th product) or off; resets."""

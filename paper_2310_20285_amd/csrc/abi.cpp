@@ -231,6 +231,14 @@ int igp_host_eigh(int32_t n, const double* A, double* w, double* Z) {
   });
 }
 
+int itergp_set_block_likelihood(igp_model* m, const void* grad, const void* W) {
+  return guarded([&]() -> int {
+    clear_error();
+    IGP_REQUIRE(m, "NULL model");
+    return m->set_block_likelihood(grad, W);
+  });
+}
+
 int itergp_set_profiling(igp_model* m, int32_t enable) {
   return guarded([&]() -> int {
     clear_error();

@@ -9,7 +9,8 @@
 //     log p = -(y - f)^2 / (2 s2) - log(2 pi s2) / 2
 //
 // The Newton step's pseudo-targets are yhat - m = f + W^{-1} grad (section 3.1
-// with m = 0): f + y exp(-f) - 1 for Poisson, y for Gaussian.
+// with m = 0): f + y exp(-f) - 1 for Poisson, y for Gaussian.  The update
+// statistics below also serve the block likelihood (no y; log p left NaN).
 #include "iter_ops.hpp"
 
 namespace igp {
@@ -64,15 +65,17 @@ k_diag_stats(int lik, double s2, const T* __restrict__ fnew, const T* __restrict
   if (i < n) {
     const double a = static_cast<double>(fnew[i]);
     const double b = static_cast<double>(f[i]);
-    const double yi = target<T>(lik, y, i);
     dd = (a - b) * (a - b);
     ff = a * a;
     gv = a * static_cast<double>(v[i]);
     if (lik == IGP_LIK_POISSON) {
+      const double yi = target<T>(lik, y, i);
       ll = yi * a - exp(a) - lgamma(yi + 1.0);
-    } else {
-      const double r = yi - a;
+    } else if (lik == IGP_LIK_GAUSSIAN) {
+      const double r = target<T>(lik, y, i) - a;
       ll = -0.5 * r * r / s2 - 0.5 * log(2.0 * 3.14159265358979323846 * s2);
+    } else {
+      ll = __builtin_nan("");   // block likelihood: log p is the caller's
     }
   }
   const int nb = gridDim.x;

@@ -28,6 +28,7 @@ struct Layout {
   T *X, *f, *fnew, *pi, *rhs, *v, *r, *z, *d, *kv, *wv;
   T *S, *Tb, *Q, *S2, *T2;
   T *KQ, *kd;   // recurrence mode: K Q and K d
+  T* wblk;      // block likelihood: the inverted C x C blocks W_n^{-1}
   double *part, *scal, *yb, *M, *U, *lamscale, *gram_part;
   double* apart;  // partials of a solver iteration's alpha (finished by the append step)
   size_t gram_cap;
@@ -74,6 +75,7 @@ Layout<T> carve(Carver& cv, int64_t N, int64_t D, int64_t C, const igp_solver_co
     L.KQ = cv.take<T>(ld * B);
     L.kd = cv.take<T>(n);
   }
+  if (cfg.likelihood == IGP_LIK_BLOCK) L.wblk = cv.take<T>(n * C);
   int64_t npart = PARTIAL_DOUBLES;
   const int64_t gemv_need = (ceil_div(n, QTZ_ROWS) + 1) * std::max<int64_t>(B, 1);
   npart = std::max(npart, gemv_need);
@@ -307,10 +309,20 @@ struct Model final : igp_model {
   double sc[SC_COUNT];
 
   bool softmax() const { return cfg.likelihood == IGP_LIK_SOFTMAX; }
+  bool block() const { return cfg.likelihood == IGP_LIK_BLOCK; }
+  bool block_set = false;   // blocks given for the current f, not yet consumed
 
-  // W at f (pi for softmax, the diagonal of W^{-1} otherwise, both kept in
-  // L.pi) and the pseudo-targets yhat - m = f + W^{-1} grad into rhs
+  // W at f (pi for softmax, the diagonal of W^{-1} for Poisson and Gaussian,
+  // both kept in L.pi) and the pseudo-targets yhat - m = f + W^{-1} grad into
+  // rhs; for the block likelihood both were formed by set_block_likelihood
+  // (the blocks are consumed here)
   int likelihood_terms(T* rhs) {
+    if (block()) {
+      IGP_REQUIRE(block_set, "block likelihood: itergp_set_block_likelihood must give the "
+                             "blocks at the current f before each Newton step or compress");
+      block_set = false;
+      return IGP_OK;
+    }
     if (softmax()) {
       int nblk = 0;
       return softmax_pi_rhs<T>(L.f, static_cast<const int32_t*>(y), N, C, L.pi, rhs, L.part,
@@ -325,6 +337,8 @@ struct Model final : igp_model {
     if (softmax())
       return winv_apply<T>(L.pi, false, IGP_W_PINV, N, C, V, nb, ldv, Add, lda, Out, ldo, stream,
                            gate);
+    if (block())
+      return block_apply<T>(L.wblk, N, C, V, nb, ldv, Add, lda, Out, ldo, stream, gate);
     return diag_apply<T>(L.pi, n, V, nb, ldv, Add, lda, Out, ldo, stream, gate);
   }
 
@@ -850,6 +864,26 @@ struct Model final : igp_model {
     return IGP_OK;
   }
 
+  int set_block_likelihood(const void* grad, const void* W) override {
+    clear_error();
+    IGP_REQUIRE(block(), "itergp_set_block_likelihood needs a model with IGP_LIK_BLOCK");
+    IGP_REQUIRE(!in_step, "itergp_set_block_likelihood during a Newton step");
+    IGP_REQUIRE(grad && W, "block likelihood: NULL gradient or blocks");
+    IGP_CHECK_HIP(hipMemsetAsync(L.flags, 0, sizeof(int), stream));
+    IGP_TRY(block_begin<T>(static_cast<const T*>(W), static_cast<const T*>(grad), L.f, N, C,
+                           L.wblk, L.rhs, L.flags, stream));
+    int bad = 0;
+    IGP_CHECK_HIP(hipMemcpyAsync(&bad, L.flags, sizeof(int), hipMemcpyDeviceToHost, stream));
+    IGP_CHECK_HIP(hipStreamSynchronize(stream));
+    block_set = bad == 0;
+    if (bad) {
+      set_error("block likelihood: %d of %lld blocks are not positive definite", bad,
+                (long long)N);
+      return IGP_EINVAL;
+    }
+    return IGP_OK;
+  }
+
   int set_user_actions(const void* a, int64_t nc, int64_t l) override {
     IGP_REQUIRE(nc >= 0 && (nc == 0 || (a && l >= n)), "user actions: bad pointer or stride");
     user = static_cast<const T*>(a);
@@ -1101,6 +1135,7 @@ int batch_models(igp_model* const* models, int n, std::vector<Model<float>*>* ou
     IGP_REQUIRE(m->prepared && m->cfg.precision == IGP_FP32,
                 "model %d: batched steps need the FP32 matrix-core path", i);
     IGP_REQUIRE(m->recurrence(), "model %d: batched steps need the recurrence residual", i);
+    IGP_REQUIRE(!m->block(), "model %d: batched steps do not take the block likelihood", i);
     IGP_REQUIRE(batched_supported(m->kp.kind, m->D, m->C), "model %d: kernel, D <= 32 and C <= 8 "
                 "are required for the batched launch", i);
     if (i == 0) {
@@ -1218,7 +1253,7 @@ int validate_common(const igp_kernel_params* kp, int n_kp, const igp_solver_conf
   IGP_REQUIRE(std::isfinite(cfg->tol_abs) && std::isfinite(cfg->tol_rel) && cfg->tol_abs >= 0 &&
                   cfg->tol_rel >= 0,
               "tolerances must be finite and >= 0");
-  IGP_REQUIRE(cfg->likelihood >= IGP_LIK_SOFTMAX && cfg->likelihood <= IGP_LIK_GAUSSIAN,
+  IGP_REQUIRE(cfg->likelihood >= IGP_LIK_SOFTMAX && cfg->likelihood <= IGP_LIK_BLOCK,
               "unknown likelihood %d", cfg->likelihood);
   IGP_REQUIRE(cfg->likelihood != IGP_LIK_GAUSSIAN ||
                   (std::isfinite(cfg->noise_var) && cfg->noise_var > 0),
@@ -1279,7 +1314,7 @@ int init_t(igp_model** out, const igp_kernel_params* kp, int n_kp, const igp_sol
     k_check_labels<T><<<256, 256, 0, stream>>>(static_cast<const int32_t*>(y), N,
                                                static_cast<int>(C), m->L.flags);
     IGP_CHECK_LAUNCH();
-  } else {
+  } else if (cfg->likelihood != IGP_LIK_BLOCK) {
     IGP_TRY(diag_check_targets<T>(cfg->likelihood, y, m->n, m->L.flags, stream));
   }
   int bad = 0;
@@ -1312,7 +1347,8 @@ int model_init(igp_model** out, const igp_kernel_params* kp, int n_kp,
   IGP_REQUIRE(out, "NULL output handle");
   *out = nullptr;
   IGP_TRY(validate_common(kp, n_kp, cfg, N, D, C));
-  IGP_REQUIRE(X && y && arena, "NULL X, y or arena");
+  IGP_REQUIRE(X && arena, "NULL X or arena");
+  IGP_REQUIRE(y || cfg->likelihood == IGP_LIK_BLOCK, "NULL y");
   if (cfg->precision == IGP_FP64)
     return init_t<double>(out, kp, n_kp, cfg, X, y, N, D, C, arena, arena_bytes, stream);
   return init_t<float>(out, kp, n_kp, cfg, X, y, N, D, C, arena, arena_bytes, stream);

@@ -13,6 +13,7 @@ struct igp_model {
                    int64_t* ld) const = 0;
   virtual int set_user_actions(const void* a, int64_t ncols, int64_t ld) = 0;
   virtual int set_profiling(int enable) = 0;
+  virtual int set_block_likelihood(const void* grad, const void* W) = 0;
   virtual int get_profile(igp_profile* out) const = 0;
   virtual int compress(int32_t rank_limit, int32_t* kept) = 0;
   virtual int step_begin() = 0;
@@ -254,6 +255,17 @@ int diag_stats(int lik, double s2, const T* fnew, const T* f, const T* v, const 
                int64_t n, double* part, double* scal, hipStream_t s);
 template <typename T>
 int diag_check_targets(int lik, const void* y, int64_t n, int* flag, hipStream_t s);
+// Block likelihood (per-point C x C negative-Hessian blocks, C <= 64):
+// winv[n] = W_n^{-1} (Gauss-Jordan in FP64, one wave per point; a point with a
+// pivot <= 0 counts in *bad and leaves NaN) and rhs[n] = f[n] + W_n^{-1} grad[n]
+template <typename T>
+int block_begin(const T* W, const T* grad, const T* f, int64_t N, int64_t C, T* winv, T* rhs,
+                int* bad, hipStream_t s);
+// Out[:, b] = W^{-1} V[:, b] (+ Add[:, b]) with the inverted blocks, b < nb
+template <typename T>
+int block_apply(const T* winv, int64_t N, int64_t C, const T* V, int64_t nb, int64_t ldv,
+                const T* Add, int64_t lda, T* Out, int64_t ldo, hipStream_t s,
+                const int* gate = nullptr);
 // Newton update bookkeeping: ||fnew - f||^2, ||fnew||^2, loglik(fnew), fnew^T v
 template <typename T>
 int newton_stats(const T* fnew, const T* f, const T* v, const int32_t* y, int64_t N,
