@@ -134,6 +134,9 @@ __global__ void kv_reduce(const T* __restrict__ P, int nsplit, int64_t n1, int W
     const int64_t stride = n1 * W;
     const T* p = P + n * W + w;
     int sp = 0;
+    // unrolled for loads in flight; each accumulator keeps its order (slots
+    // 4k + j go to s_j in increasing k), so the sum does not change
+#pragma unroll 4
     for (; sp + 4 <= nsplit; sp += 4) {
       s0 += p[sp * stride];
       s1 += p[(sp + 1) * stride];
