@@ -59,6 +59,40 @@ k_winv_apply(const T* __restrict__ pi, int logits, int mode, int64_t N, int C,
   iter::winv_point<T, CMAX>(pi, logits, mode, n, C, V, b, ldv, Add, lda, Out, ldo);
 }
 
+// The residual of a solver iteration with the W^+ v it needs, one thread per
+// point: wv = W^+ v (kept), r = rhs - kv - wv, and the block partials of r^T r
+template <typename T, int CMAX>
+__global__ void __launch_bounds__(256)
+k_winv_residual(const T* __restrict__ pi, int64_t N, int C, const T* __restrict__ v,
+                const T* __restrict__ rhs, const T* __restrict__ kv, T* __restrict__ wv,
+                T* __restrict__ r, double* __restrict__ part, const int* gate) {
+  if (gate_closed(gate)) return;
+  __shared__ double red[4];
+  const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  double acc = 0.0;
+  if (n < N) {
+    T p[CMAX], u[CMAX];
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c)
+      if (c < C) {
+        p[c] = pi[n * C + c];
+        u[c] = v[n * C + c];
+      }
+    iter::apply_block<T, CMAX>(IGP_W_PINV, C, p, u);
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c)
+      if (c < C) {
+        const int64_t i = n * C + c;
+        wv[i] = u[c];
+        const T ri = rhs[i] - kv[i] - u[c];
+        r[i] = ri;
+        acc += static_cast<double>(ri) * static_cast<double>(ri);
+      }
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
 }  // namespace
 
 #define IGP_DISPATCH_C(C, BODY)                    \
@@ -108,6 +142,27 @@ int winv_apply(const T* pi, bool pi_is_logits, int mode, int64_t N, int64_t C, c
   return IGP_OK;
 }
 
+template <typename T>
+int winv_residual(const T* pi, int64_t N, int64_t C, const T* v, const T* rhs, const T* kv,
+                  T* wv, T* r, double* part, int* nblk_out, hipStream_t s, const int* gate) {
+  if (C > 64) {
+    set_error("C = %lld classes exceeds the supported maximum of 64", (long long)C);
+    return IGP_EUNSUPPORTED;
+  }
+  const int blocks = static_cast<int>(ceil_div(N, 256));
+  *nblk_out = blocks;
+  if (blocks == 0) return IGP_OK;
+  IGP_DISPATCH_C(C, (k_winv_residual<T, CM><<<blocks, 256, 0, s>>>(pi, N, (int)C, v, rhs, kv, wv, r, part, gate)));
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template int winv_residual<float>(const float*, int64_t, int64_t, const float*, const float*,
+                                  const float*, float*, float*, double*, int*, hipStream_t,
+                                  const int*);
+template int winv_residual<double>(const double*, int64_t, int64_t, const double*,
+                                   const double*, const double*, double*, double*, double*,
+                                   int*, hipStream_t, const int*);
 template int softmax_pi_rhs<float>(const float*, const int32_t*, int64_t, int64_t, float*,
                                    float*, double*, int*, hipStream_t);
 template int softmax_pi_rhs<double>(const double*, const int32_t*, int64_t, int64_t, double*,

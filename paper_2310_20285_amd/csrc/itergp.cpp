@@ -449,6 +449,12 @@ struct Model final : igp_model {
       IGP_TRY(apply_K(L.v, L.kv, gate, iter));
       if (!gate) ++st.kprod;
     }
+    if (gate && softmax()) {   // W^+ v and the residual in one pass over the points
+      int g = 0;
+      IGP_TRY(winv_residual<T>(L.pi, N, C, L.v, L.rhs, L.kv, L.wv, L.r, L.part, &g, stream,
+                               gate));
+      return rr_consume(L.part, g, L.scal, st.thresh, gate, L.rec, stream);
+    }
     IGP_TRY(apply_winv(L.v, 1, n, nullptr, 0, L.wv, n, gate));
     if (gate)
       return residual_consume<T>(L.rhs, L.kv, L.wv, L.r, n, L.part, L.scal, st.thresh, gate,

@@ -411,6 +411,13 @@ int action_cg_dot(const T* r, const double* rr, T* sv, int64_t n, double* part, 
   return IGP_OK;
 }
 
+int rr_consume(const double* part, int nblk, double* scal, double thresh, int* gate, double* rec,
+               hipStream_t s) {
+  k_finish_rr_consume<<<1, NT, 0, s>>>(part, nblk, scal, thresh, gate, rec);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
 template <typename T>
 int residual_consume(const T* rhs, const T* kv, const T* wv, T* r, int64_t n, double* part,
                      double* scal, double thresh, int* gate, double* rec, hipStream_t s) {

@@ -179,6 +179,16 @@ int residual(const T* rhs, const T* kv, const T* wv, T* r, int64_t n, double* pa
              double* out_scalar, hipStream_t s, const int* gate = nullptr);
 // the residual of a solver iteration, its norm finished together with the
 // iteration's end (iter_consume with next_r = 1)
+// rr = the fixed-order sum of nblk residual partials into scal[SC_RR], then
+// the end of the solver iteration as in residual_consume
+int rr_consume(const double* partials, int nblk, double* scal, double thresh, int* gate,
+               double* rec, hipStream_t s);
+// softmax: wv = W^+ v, r = rhs - kv - wv and ceil(N / 256) partials of r^T r
+// (one thread per point), *nblk_out = their count
+template <typename T>
+int winv_residual(const T* pi, int64_t N, int64_t C, const T* v, const T* rhs, const T* kv,
+                  T* wv, T* r, double* partials, int* nblk_out, hipStream_t s,
+                  const int* gate = nullptr);
 template <typename T>
 int residual_consume(const T* rhs, const T* kv, const T* wv, T* r, int64_t n, double* partials,
                      double* scal, double thresh, int* gate, double* rec, hipStream_t s);
