@@ -207,6 +207,7 @@ k_gram(const T* __restrict__ A, const T* __restrict__ B, int64_t ld, int64_t n, 
   const int ta = tid % 16, tb = tid / 16;   // outputs (a0+ta+16*u, b0+tb+16*v)
   double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
   for (int64_t i0 = i_begin; i0 < i_end; i0 += GT) {
+#pragma unroll 4
     for (int e = tid; e < GT * GT; e += NT) {
       const int col = e / GT, row = e % GT;     // column-major: rows contiguous
       const int64_t gi = i0 + row;
@@ -273,6 +274,7 @@ k_right_mul(const T* __restrict__ A, int64_t lda, int64_t n, int ncols,
   double acc[RM_COLS];
 #pragma unroll
   for (int rr = 0; rr < RM_COLS; ++rr) acc[rr] = 0.0;
+#pragma unroll 4
   for (int b = 0; b < ncols; ++b) {
     const double a = static_cast<double>(A[static_cast<int64_t>(b) * lda + i]);
 #pragma unroll
@@ -522,7 +524,9 @@ int gram(const T* A, const T* B, int64_t ld, int64_t n, int ncols, double* part,
          size_t part_cap, double* M, hipStream_t s) {
   if (ncols == 0) return IGP_OK;
   const int tiles = static_cast<int>(ceil_div(ncols, GT));
-  int64_t nchunks = std::min<int64_t>(64, ceil_div(2048, static_cast<int64_t>(tiles) * tiles));
+  // enough row chunks (each a block per output tile) to keep every CU busy: the
+  // kernel is bound by the latency of its 32-row passes, not by bandwidth
+  int64_t nchunks = std::min<int64_t>(256, ceil_div(4096, static_cast<int64_t>(tiles) * tiles));
   const size_t per = static_cast<size_t>(ncols) * ncols;
   if (nchunks * per > part_cap) nchunks = static_cast<int64_t>(part_cap / per);
   if (nchunks < 1) {
