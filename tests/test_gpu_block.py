@@ -3,7 +3,7 @@ Hessian blocks given by the caller) on the GPU path, against the FP64 oracle
 (oracle.itergp.iterncgp_block):
 
 * correlated Gaussian observations, one full-budget step: the GP regression
-  mean K (K + I (x) Sigma)^{-1} y within 1e-9 (FP64);
+  mean K (K + I (x) Sigma)^{-1} y within 1e-9 (FP64), for C = 3, 6 and 20;
 * softmax plus a ridge on f (non-diagonal, positive definite blocks), the
   oracle's CG actions replayed for three Newton steps: iterates within 1e-10
   (FP64) / 1e-4 (FP32) of the oracle, the grad and blocks computed on the host
@@ -59,8 +59,8 @@ def _model(X, C, prec, **kw):
     return m, dt
 
 
-def test_correlated_gaussian_full_budget_is_regression(gpu_lib):
-    N, C = 60, 3
+@pytest.mark.parametrize("N,C", [(60, 3), (30, 6), (12, 20)])   # the 4-, 16- and 64-wide inverses
+def test_correlated_gaussian_full_budget_is_regression(gpu_lib, N, C):
     rng, X, Kf = _data(0, N, C)
     A = rng.standard_normal((N, C, C))
     Sigma = np.einsum("nij,nkj->nik", A, A) / C + 0.3 * np.eye(C)
