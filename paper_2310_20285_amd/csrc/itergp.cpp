@@ -120,7 +120,7 @@ struct Model final : igp_model {
   const T* user = nullptr;
   int64_t user_cols = 0, user_ld = 0;
   int steps_done = 0;
-  std::vector<double> hM, hMs, hU, hlam, hscale;
+  std::vector<double> hM, hMs, hU, hlam, hscale, hL, hx;
   // tracing: every prof_every-th product is timed (prof_seq counts them)
   bool prof = false;
   int prof_every = 1;
@@ -305,6 +305,7 @@ struct Model final : igp_model {
     bool next_r = false;      // the last iteration enqueued a residual
     hipEvent_t step_b = nullptr;
     int keep = 0, dropped = 0;
+    bool chol = false;        // the virtual solver run took the Cholesky form
   } st;
   double sc[SC_COUNT];
 
@@ -378,6 +379,63 @@ struct Model final : igp_model {
     return IGP_OK;
   }
 
+  // Untruncated form of Algorithm 3.  Only Q_0 Q_0^T = S M^{-1} S^T enters C_0,
+  // so when no direction would be dropped any factor F with F F^T = M^{-1}
+  // serves: F = L^{-T} from the Cholesky factor M = L L^T (B^3/3 flops instead
+  // of an eigendecomposition, and S, T keep their basis).  It is taken only
+  // when it provably changes nothing: the rank limit keeps all B columns, and
+  // lambda_max <= tr(M), lambda_min >= 1 / tr(M^{-1}) = 1 / ||L^{-1}||_F^2 put
+  // every eigenvalue above the floor lambda_max B eps whenever
+  // tr(M) tr(M^{-1}) B eps < 1.  On success hU holds L^{-T} in the layout of
+  // an eigenvector block (column r of F at hU[r B ...]).
+  static double dot4(const double* a, const double* b, int m) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int k = 0;
+    for (; k + 4 <= m; k += 4) {
+      s0 += a[k] * b[k];
+      s1 += a[k + 1] * b[k + 1];
+      s2 += a[k + 2] * b[k + 2];
+      s3 += a[k + 3] * b[k + 3];
+    }
+    for (; k < m; ++k) s0 += a[k] * b[k];
+    return (s0 + s1) + (s2 + s3);
+  }
+
+  bool chol_untruncated(int B) {
+    if (cfg.rank_limit >= 0 && cfg.rank_limit < B) return false;
+    hL.assign(static_cast<size_t>(B) * B, 0.0);   // row-major lower factor
+    double trace = 0.0;
+    for (int i = 0; i < B; ++i) {
+      const double* Mi = hMs.data() + static_cast<size_t>(i) * B;
+      double* Li = hL.data() + static_cast<size_t>(i) * B;
+      trace += Mi[i];
+      for (int j = 0; j <= i; ++j) {
+        const double* Lj = hL.data() + static_cast<size_t>(j) * B;
+        const double sum = Mi[j] - dot4(Li, Lj, j);
+        if (j < i) {
+          Li[j] = sum / Lj[j];
+        } else {
+          if (!(sum > 0.0)) return false;
+          Li[i] = std::sqrt(sum);
+        }
+      }
+    }
+    // column j of L^{-1} solves L x = e_j (x_i = 0 for i < j); it is row j of
+    // F = L^{-T}, so F[j][i] = x_i, stored at hU[i B + j]
+    hx.resize(B);
+    double trinv = 0.0;
+    std::fill(hU.begin(), hU.end(), 0.0);
+    for (int j = 0; j < B; ++j) {
+      for (int i = j; i < B; ++i) {
+        const double* Li = hL.data() + static_cast<size_t>(i) * B;
+        hx[i] = ((i == j ? 1.0 : 0.0) - dot4(Li + j, hx.data() + j, i - j)) / Li[i];
+        trinv += hx[i] * hx[i];
+        hU[static_cast<size_t>(i) * B + j] = hx[i];
+      }
+    }
+    return std::isfinite(trinv) && trace * trinv * B * 2.220446049250313e-16 < 1.0;
+  }
+
   // host part: M = U Lambda U^T (descending), tiny-eigenvalue floor, keep <= R.
   // Touches only this model's host buffers (safe to run concurrently).
   int phase_vsr_host() {
@@ -388,8 +446,14 @@ struct Model final : igp_model {
       for (int k = 0; k < B; ++k)
         hMs[static_cast<size_t>(i) * B + k] =
             0.5 * (hM[static_cast<size_t>(i) * B + k] + hM[static_cast<size_t>(k) * B + i]);
-    hlam.resize(B);
     hU.resize(static_cast<size_t>(B) * B);
+    st.chol = chol_untruncated(B);
+    if (st.chol) {
+      st.dropped = 0;
+      st.keep = B;
+      return IGP_OK;
+    }
+    hlam.resize(B);
     IGP_TRY(eigh_desc(B, hMs.data(), hlam.data(), hU.data()));
     int keep = 0;
     const double floor = hlam[0] > 0.0 ? hlam[0] * B * 2.220446049250313e-16 : INFINITY;
@@ -407,7 +471,13 @@ struct Model final : igp_model {
     const int B = ncols;
     if (B == 0) return IGP_OK;
     const int keep = st.keep;
-    if (keep > 0) {
+    if (st.chol) {
+      // Q_0 = S L^{-T}, K Q_0 = T L^{-T}; S and T stay as they are
+      IGP_CHECK_HIP(hipMemcpyAsync(L.U, hU.data(), static_cast<size_t>(B) * B * sizeof(double),
+                                   hipMemcpyHostToDevice, stream));
+      IGP_TRY(right_mul<T>(L.S, ld, n, B, L.U, B, nullptr, L.Q, ld, stream));
+      if (recurrence()) IGP_TRY(right_mul<T>(L.Tb, ld, n, B, L.U, B, nullptr, L.KQ, ld, stream));
+    } else if (keep > 0) {
       IGP_CHECK_HIP(hipMemcpyAsync(L.U, hU.data(), static_cast<size_t>(B) * keep * sizeof(double),
                                    hipMemcpyHostToDevice, stream));
       IGP_CHECK_HIP(hipMemcpyAsync(L.lamscale, hscale.data(), keep * sizeof(double),
