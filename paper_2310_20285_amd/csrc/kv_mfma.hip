@@ -104,29 +104,45 @@ kv_mfma_f32(const float* __restrict__ X1p, const float* __restrict__ nrm1,
 #pragma unroll
   for (int wc = 0; wc < WCH; ++wc) out[wc] = f4{0, 0, 0, 0};
 
-  // register staging of one tile
+  // register staging of one tile.  A thread stages one V column, w = w0 +
+  // tid % WT, at rows tid / WT + q MSTEP, through one base pointer; a column
+  // past W reads column W - 1 instead (it only feeds outputs that are not
+  // stored).  Whole tiles skip the row checks.
+  constexpr int MSTEP = 256 / WT;
+  const int wl_t = tid % WT, m_t = tid / WT;
+  const int w_t = w0 + wl_t < W ? w0 + wl_t : W - 1;
+  const float* vbase = V + static_cast<int64_t>(w_t / C) * ldv + (w_t % C) +
+                       static_cast<int64_t>(m_t) * C;
   f4 px[XQT];
   float pv[VE];
   float pn = 0.0f;
   auto fetch = [&](int64_t m0) {
+    const float* vt = vbase + m0 * C;
+    if (m0 + TN <= m_end) {
 #pragma unroll
-    for (int q = 0; q < XQT; ++q) {
-      const int e = tid + q * 256;
-      const int row = e / (DP / 4), col = e % (DP / 4);
-      const int64_t m = m0 + row;
-      px[q] = m < m_end ? *reinterpret_cast<const f4*>(X2p + m * DP + col * 4) : f4{0, 0, 0, 0};
-    }
-    if (tid < TN) {
-      const int64_t m = m0 + tid;
-      pn = m < m_end ? nrm2[m] * cnorm : 0.0f;
-    }
+      for (int q = 0; q < XQT; ++q) {
+        const int e = tid + q * 256;
+        const int row = e / (DP / 4), col = e % (DP / 4);
+        px[q] = *reinterpret_cast<const f4*>(X2p + (m0 + row) * DP + col * 4);
+      }
+      if (tid < TN) pn = nrm2[m0 + tid];   // scaled at the LDS store (no wait here)
 #pragma unroll
-    for (int q = 0; q < VE; ++q) {
-      const int e = tid + q * 256;
-      const int m = e / WT, wl = e % WT;
-      const int64_t gm = m0 + m;
-      const int w = w0 + wl;
-      pv[q] = (gm < m_end && w < W) ? V[(w / C) * ldv + gm * C + (w % C)] : 0.0f;
+      for (int q = 0; q < VE; ++q) pv[q] = vt[static_cast<int64_t>(q) * MSTEP * C];
+    } else {
+#pragma unroll
+      for (int q = 0; q < XQT; ++q) {
+        const int e = tid + q * 256;
+        const int row = e / (DP / 4), col = e % (DP / 4);
+        const int64_t m = m0 + row;
+        px[q] = m < m_end ? *reinterpret_cast<const f4*>(X2p + m * DP + col * 4) : f4{0, 0, 0, 0};
+      }
+      if (tid < TN) {
+        const int64_t m = m0 + tid;
+        pn = m < m_end ? nrm2[m] : 0.0f;
+      }
+#pragma unroll
+      for (int q = 0; q < VE; ++q)
+        pv[q] = m0 + m_t + q * MSTEP < m_end ? vt[static_cast<int64_t>(q) * MSTEP * C] : 0.0f;
     }
   };
   auto stash = [&](int buf) {
@@ -136,13 +152,9 @@ kv_mfma_f32(const float* __restrict__ X1p, const float* __restrict__ nrm1,
       const int row = e / (DP / 4), col = e % (DP / 4);
       *reinterpret_cast<f4*>(&sX[buf][row * XS + col * 4]) = px[q];
     }
-    if (tid < TN) sN[buf][tid] = pn;
+    if (tid < TN) sN[buf][tid] = pn * cnorm;
 #pragma unroll
-    for (int q = 0; q < VE; ++q) {
-      const int e = tid + q * 256;
-      const int m = e / WT, wl = e % WT;
-      sV[buf][wl * VS + m] = pv[q];
-    }
+    for (int q = 0; q < VE; ++q) sV[buf][wl_t * VS + m_t + q * MSTEP] = pv[q];
   };
 
   if (m_begin < m_end) {
@@ -166,17 +178,22 @@ kv_mfma_f32(const float* __restrict__ X1p, const float* __restrict__ nrm1,
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], xb[c][3], acc, 0, 0, 0);
       }
       const f4 n2v = *reinterpret_cast<const f4*>(&sN[buf][mb * 16 + 4 * g]);
+      // this block's V fragments, read before the transform so that their
+      // LDS latency hides behind it
+      f4 vb[WCH];
+#pragma unroll
+      for (int wc = 0; wc < WCH; ++wc)
+        vb[wc] = *reinterpret_cast<const f4*>(&sV[buf][(wc * 16 + r) * VS + mb * 16 + 4 * g]);
       f4 kv;
 #pragma unroll
       for (int v = 0; v < 4; ++v)
         kv[v] = ktransform<KIND>(__builtin_fmaf(acc[v], cdot, n1v + n2v[v]));
 #pragma unroll
       for (int wc = 0; wc < WCH; ++wc) {
-        const f4 vb = *reinterpret_cast<const f4*>(&sV[buf][(wc * 16 + r) * VS + mb * 16 + 4 * g]);
-        out[wc] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[0], vb[0], out[wc], 0, 0, 0);
-        out[wc] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[1], vb[1], out[wc], 0, 0, 0);
-        out[wc] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[2], vb[2], out[wc], 0, 0, 0);
-        out[wc] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[3], vb[3], out[wc], 0, 0, 0);
+        out[wc] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[0], vb[wc][0], out[wc], 0, 0, 0);
+        out[wc] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[1], vb[wc][1], out[wc], 0, 0, 0);
+        out[wc] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[2], vb[wc][2], out[wc], 0, 0, 0);
+        out[wc] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[3], vb[wc][3], out[wc], 0, 0, 0);
       }
     }
     if (more) stash(buf ^ 1);
@@ -285,7 +302,7 @@ __device__ inline void narrow_tile(NarrowSmem<DCH, WX>& sm, const float* __restr
     }
     if (tid < TN) {
       const int64_t m = m0 + tid;
-      pn = m < m_end ? nrm2[m] * cnorm : 0.0f;
+      pn = m < m_end ? nrm2[m] : 0.0f;   // scaled at the LDS store (no wait here)
     }
 #pragma unroll
     for (int q = 0; q < VE; ++q) {
@@ -300,7 +317,7 @@ __device__ inline void narrow_tile(NarrowSmem<DCH, WX>& sm, const float* __restr
       const int row = e / (DP / 4), col = e % (DP / 4);
       *reinterpret_cast<f4*>(&sX[buf][row * XS + col * 4]) = px[q];
     }
-    if (tid < TN) sN[buf][tid] = pn;
+    if (tid < TN) sN[buf][tid] = pn * cnorm;
 #pragma unroll
     for (int q = 0; q < VE; ++q) sV[buf][tid + q * 256] = pv[q];
   };
@@ -515,7 +532,7 @@ kv_mfma_f32_sym(const float* __restrict__ Xp, const float* __restrict__ nrm, int
     }
     if (tid < TN) {
       const int64_t m = m0 + tid;
-      pn = m < m_end ? nrm[m] * cnorm : 0.0f;
+      pn = m < m_end ? nrm[m] : 0.0f;   // scaled at the LDS store (no wait here)
     }
 #pragma unroll
     for (int q = 0; q < VE; ++q) {
@@ -530,7 +547,7 @@ kv_mfma_f32_sym(const float* __restrict__ Xp, const float* __restrict__ nrm, int
       const int row = e / (DP / 4), col = e % (DP / 4);
       *reinterpret_cast<f4*>(&sX[buf * TN * XS + row * XS + col * 4]) = px[q];
     }
-    if (tid < TN) sN[buf * TN + tid] = pn;
+    if (tid < TN) sN[buf * TN + tid] = pn * cnorm;
 #pragma unroll
     for (int q = 0; q < VE; ++q)
       if (vm[q] < TN) sV[buf * WX * VS + vdst[q]] = pv[q];
