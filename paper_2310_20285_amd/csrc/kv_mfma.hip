@@ -824,7 +824,10 @@ Plan plan_mfma(int64_t n1, int64_t n2, int64_t d, int64_t W, bool fixed = false)
   int64_t want = ceil_div(8192, static_cast<int64_t>(p.gx) * p.gz);
   if (want < 1) want = 1;
   if (want > tiles) want = tiles;
-  p.cols_per_split = fixed ? FIXED_SPLIT_ROWS : ceil_div(tiles, want) * TN;
+  // a fixed split depends on the output width only, never on n1: narrow
+  // outputs (a predictive mean) have few workgroups per split and split finer
+  p.cols_per_split = fixed ? (W <= 16 ? FIXED_SPLIT_ROWS_NARROW : FIXED_SPLIT_ROWS)
+                           : ceil_div(tiles, want) * TN;
   p.nsplit = static_cast<int>(ceil_div(n2, p.cols_per_split));
   return p;
 }

@@ -52,11 +52,13 @@ struct KVProblem {
   // outputscale): kpc[c] for c < C when n_kp == C > 1
   const igp_kernel_params* kpc = nullptr;
   int n_kp = 1;
-  // split the X2 rows into fixed 4096-row ranges regardless of n1, so that each
-  // output row is summed in the same order whatever rows share the launch
+  // split the X2 rows into fixed ranges regardless of n1 (4096 rows; 512 for
+  // outputs at most 16 wide on the FP32 matrix cores), so that each output row
+  // is summed in the same order whatever rows share the launch
   bool fixed_split = false;
 };
 constexpr int64_t FIXED_SPLIT_ROWS = 4096;
+constexpr int64_t FIXED_SPLIT_ROWS_NARROW = 512;
 // rows per wave of the Q^T z pass of a solver iteration (partials per column: n / QTZ_ROWS)
 constexpr int QTZ_ROWS = 1024;
 
