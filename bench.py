@@ -179,7 +179,7 @@ def main():
     torch.cuda.synchronize()
     m.set_profiling(True, every=KV_SAMPLE)
     infos = []
-    pred_ms = []
+    pred_ev = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         infos.append(m.newton_step())
@@ -188,10 +188,10 @@ def main():
         a.record()
         m.predict(Xs)
         b.record()
-        b.synchronize()
-        pred_ms.append(a.elapsed_time(b))
+        pred_ev.append((a, b))   # read after the loop: the next step queues behind it
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    pred_ms = [a.elapsed_time(b) for a, b in pred_ev]
     prof = m.profile()
 
     elapsed = t1 - t0

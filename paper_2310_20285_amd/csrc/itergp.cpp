@@ -120,7 +120,7 @@ struct Model final : igp_model {
   const T* user = nullptr;
   int64_t user_cols = 0, user_ld = 0;
   int steps_done = 0;
-  std::vector<double> hM, hMs, hU, hlam, hscale, hL, hx;
+  std::vector<double> hM, hMs, hU, hlam, hscale, hL;
   // tracing: every prof_every-th product is timed (prof_seq counts them)
   bool prof = false;
   int prof_every = 1;
@@ -386,8 +386,8 @@ struct Model final : igp_model {
   // when it provably changes nothing: the rank limit keeps all B columns, and
   // lambda_max <= tr(M), lambda_min >= 1 / tr(M^{-1}) = 1 / ||L^{-1}||_F^2 put
   // every eigenvalue above the floor lambda_max B eps whenever
-  // tr(M) tr(M^{-1}) B eps < 1.  On success hU holds L^{-T} in the layout of
-  // an eigenvector block (column r of F at hU[r B ...]).
+  // tr(M) tr(M^{-1}) B eps < 1.  On success hU holds F = L^{-T} in the layout
+  // of an eigenvector block (column r of F at hU[r B ...]).
   static double dot4(const double* a, const double* b, int m) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int k = 0;
@@ -403,34 +403,41 @@ struct Model final : igp_model {
 
   bool chol_untruncated(int B) {
     if (cfg.rank_limit >= 0 && cfg.rank_limit < B) return false;
-    hL.assign(static_cast<size_t>(B) * B, 0.0);   // row-major lower factor
+    // M = L L^T column by column (row-major L): the entries below the diagonal
+    // of one column are independent dot products
+    hL.assign(static_cast<size_t>(B) * B, 0.0);
     double trace = 0.0;
-    for (int i = 0; i < B; ++i) {
-      const double* Mi = hMs.data() + static_cast<size_t>(i) * B;
-      double* Li = hL.data() + static_cast<size_t>(i) * B;
-      trace += Mi[i];
-      for (int j = 0; j <= i; ++j) {
-        const double* Lj = hL.data() + static_cast<size_t>(j) * B;
-        const double sum = Mi[j] - dot4(Li, Lj, j);
-        if (j < i) {
-          Li[j] = sum / Lj[j];
-        } else {
-          if (!(sum > 0.0)) return false;
-          Li[i] = std::sqrt(sum);
-        }
+    for (int j = 0; j < B; ++j) {
+      double* Lj = hL.data() + static_cast<size_t>(j) * B;
+      const double* Mj = hMs.data() + static_cast<size_t>(j) * B;
+      trace += Mj[j];
+      const double dj = Mj[j] - dot4(Lj, Lj, j);
+      if (!(dj > 0.0)) return false;
+      Lj[j] = std::sqrt(dj);
+      const double inv = 1.0 / Lj[j];
+      for (int i = j + 1; i < B; ++i) {
+        double* Li = hL.data() + static_cast<size_t>(i) * B;
+        Li[j] = (hMs[static_cast<size_t>(i) * B + j] - dot4(Li, Lj, j)) * inv;
       }
     }
-    // column j of L^{-1} solves L x = e_j (x_i = 0 for i < j); it is row j of
-    // F = L^{-T}, so F[j][i] = x_i, stored at hU[i B + j]
-    hx.resize(B);
-    double trinv = 0.0;
+    // X = L^{-1} by rows, X_i = (e_i - sum_{k<i} L_ik X_k) / L_ii (contiguous
+    // row updates).  F = L^{-T} has F[b][r] = X[r][b], so the row-major X is
+    // already the eigenvector-block layout hU[r B + b].
     std::fill(hU.begin(), hU.end(), 0.0);
-    for (int j = 0; j < B; ++j) {
-      for (int i = j; i < B; ++i) {
-        const double* Li = hL.data() + static_cast<size_t>(i) * B;
-        hx[i] = ((i == j ? 1.0 : 0.0) - dot4(Li + j, hx.data() + j, i - j)) / Li[i];
-        trinv += hx[i] * hx[i];
-        hU[static_cast<size_t>(i) * B + j] = hx[i];
+    double trinv = 0.0;
+    for (int i = 0; i < B; ++i) {
+      double* __restrict__ Xi = hU.data() + static_cast<size_t>(i) * B;
+      const double* __restrict__ Li = hL.data() + static_cast<size_t>(i) * B;
+      Xi[i] = 1.0;
+      for (int k = 0; k < i; ++k) {
+        const double a = Li[k];
+        const double* __restrict__ Xk = hU.data() + static_cast<size_t>(k) * B;
+        for (int c = 0; c <= k; ++c) Xi[c] -= a * Xk[c];
+      }
+      const double inv = 1.0 / Li[i];
+      for (int c = 0; c <= i; ++c) {
+        Xi[c] *= inv;
+        trinv += Xi[c] * Xi[c];
       }
     }
     return std::isfinite(trinv) && trace * trinv * B * 2.220446049250313e-16 < 1.0;
