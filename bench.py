@@ -58,7 +58,7 @@ KV_SAMPLE = 3
 # copy in the same run; profiles/kv_matern52_N20000_D16_C5_fp32.md and
 # profiles/kv_bf16_rbf_N60000_D784_C10.md).  Keyed by the kernel instance it
 # was measured on; any other instance reports null.
-MEASURED_TRAFFIC = {("kv_mfma_f32_sym<3,1,5>", "fp32"): 46.04e6,
+MEASURED_TRAFFIC = {("kv_mfma_f32_sym<3,1,5>", "fp32"): 46.03e6,
                     ("kv_bf16_sym<0>", "bf16"): 12.92e9}
 
 
