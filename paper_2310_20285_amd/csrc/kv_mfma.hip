@@ -824,10 +824,14 @@ Plan plan_mfma(int64_t n1, int64_t n2, int64_t d, int64_t W, bool fixed = false)
   int64_t want = ceil_div(8192, static_cast<int64_t>(p.gx) * p.gz);
   if (want < 1) want = 1;
   if (want > tiles) want = tiles;
-  // a fixed split depends on the output width only, never on n1: narrow
-  // outputs (a predictive mean) have few workgroups per split and split finer
-  p.cols_per_split = fixed ? (W <= 16 ? FIXED_SPLIT_ROWS_NARROW : FIXED_SPLIT_ROWS)
-                           : ceil_div(tiles, want) * TN;
+  // a fixed split depends on n2 and the output width only, never on n1:
+  // narrow outputs (a predictive mean) split at 512 rows, widths up to 512
+  // into about 20 ranges of at least 1024 rows (enough workgroups for a few
+  // thousand test rows, partial sums bounded by 20 outputs), wider at 4096
+  int64_t fixed_rows = FIXED_SPLIT_ROWS;
+  if (W <= 16) fixed_rows = FIXED_SPLIT_ROWS_NARROW;
+  else if (W <= 512) fixed_rows = std::max<int64_t>(1024, ceil_div(ceil_div(n2, 20), TN) * TN);
+  p.cols_per_split = fixed ? fixed_rows : ceil_div(tiles, want) * TN;
   p.nsplit = static_cast<int>(ceil_div(n2, p.cols_per_split));
   return p;
 }

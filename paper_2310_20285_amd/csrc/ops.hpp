@@ -52,9 +52,10 @@ struct KVProblem {
   // outputscale): kpc[c] for c < C when n_kp == C > 1
   const igp_kernel_params* kpc = nullptr;
   int n_kp = 1;
-  // split the X2 rows into fixed ranges regardless of n1 (4096 rows; 512 for
-  // outputs at most 16 wide on the FP32 matrix cores), so that each output row
-  // is summed in the same order whatever rows share the launch
+  // split the X2 rows into fixed ranges regardless of n1 (4096 rows; on the
+  // FP32 matrix cores 512 rows for outputs at most 16 wide and about n2 / 20
+  // rows, at least 1024, for outputs at most 512 wide), so that each output
+  // row is summed in the same order whatever rows share the launch
   bool fixed_split = false;
 };
 constexpr int64_t FIXED_SPLIT_ROWS = 4096;
