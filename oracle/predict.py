@@ -15,8 +15,10 @@ softmax(mean / sqrt(1 + pi/8 var)) (appendix on the large-scale experiment).
 Pins (tests/test_oracle_predict.py): at full budget the IterGP variance equals
 the exact variance; the variance is non-increasing in j (Proposition "The
 Uncertainty Decreases in the Inner Loop"); probit with var = 0 is the softmax
-of the mean and the binary probit approximation is within its known error of
-numerical quadrature.
+of the mean; in the binary case the scale applied to the mean equals the
+exact Gaussian smoothing of the cdf Phi(lam x) whose slope at 0 matches the
+sigmoid's (checked by adaptive quadrature), and the result is within twice
+the sigmoid-to-cdf substitution error of the logistic-normal integral.
 """
 from __future__ import annotations
 

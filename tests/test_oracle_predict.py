@@ -76,3 +76,63 @@ def test_per_class_predictions_match_dense_definition():
                                rtol=1e-12, atol=1e-12)
     np.testing.assert_allclose(op.predictive_var_root_per_class(Xs, X, Q, "rbf", ells, oss), var,
                                rtol=1e-12, atol=1e-11)
+
+
+# The probit approximation of the predictive class probabilities (appendix on
+# the large-scale experiment) replaces the logistic sigmoid by the Gaussian cdf
+# Phi(lam x) whose slope at 0 equals the sigmoid's (1/4), i.e.
+# lam = sqrt(2 pi) / 4, and uses the exact Gaussian integral of that cdf:
+#     int Phi(lam x) N(x; m, v) dx = Phi(lam m / sqrt(1 + lam^2 v)).
+# In the binary case (C = 2, logits [m, 0], variances [v, 0]) the softmax of
+# the scaled logits is sigmoid(kappa(v) m), so the scale kappa(v) that
+# probit_probs applies can be read back and checked against that integral,
+# computed here by adaptive quadrature; the constant lam is derived from
+# the slope condition, not taken from the function under test.
+
+def _adaptive_expect(fn, m, v):
+    """E[fn(x)] for x ~ N(m, v) by adaptive quadrature (fn may vary on a scale
+    much finer than sqrt(v), where Gauss-Hermite is not accurate)."""
+    from scipy.integrate import quad
+    if v == 0.0:
+        return float(fn(np.float64(m)))
+    sd = np.sqrt(v)
+    dens = lambda x: np.exp(-0.5 * ((x - m) / sd) ** 2) / (sd * np.sqrt(2.0 * np.pi))
+    lo, hi = m - 40.0 * sd, m + 40.0 * sd
+    pts = sorted({min(max(p, lo), hi) for p in (-10.0, -3.0, 0.0, 3.0, 10.0)})
+    val, err = quad(lambda x: fn(x) * dens(x), lo, hi, points=pts, epsabs=1e-14,
+                    epsrel=1e-13, limit=400)
+    return float(val)
+
+
+def _binary_probit(m, v):
+    return op.probit_probs(np.array([[m, 0.0]]), np.array([[v, 0.0]]))[0, 0]
+
+
+def test_probit_scale_is_the_exact_gaussian_smoothing_of_the_slope_matched_cdf():
+    from scipy.special import logit, ndtr, ndtri
+    lam = np.sqrt(2.0 * np.pi) / 4.0                 # Phi'(0) lam = sigmoid'(0) = 1/4
+    for v in [0.0, 0.05, 0.3, 1.0, 2.5, 7.0, 30.0, 400.0]:
+        for m in [0.4, -1.3, 2.2]:
+            kappa = logit(_binary_probit(m, v)) / m
+            # the quadrature of the probit-link integral, mapped back to the
+            # scale of its argument: Phi(lam m kappa_ref) = E[Phi(lam x)]
+            kappa_ref = ndtri(_adaptive_expect(lambda x: ndtr(lam * x), m, v)) / (lam * m)
+            assert abs(kappa - kappa_ref) <= 1e-9 * kappa_ref, (m, v, kappa, kappa_ref)
+
+
+def test_binary_probit_within_its_error_of_the_logistic_normal_integral():
+    from scipy.special import expit, ndtr
+    lam = np.sqrt(2.0 * np.pi) / 4.0
+    # two substitutions of sigmoid by Phi(lam .), each off by at most this much
+    t = np.linspace(-30.0, 30.0, 600001)
+    sub_err = float(np.abs(expit(t) - ndtr(lam * t)).max())
+    assert 0.017 < sub_err < 0.018
+    worst = 0.0
+    for v in np.concatenate([np.linspace(0.0, 4.0, 21), np.geomspace(4.0, 1e3, 15)]):
+        for m in np.linspace(-8.0, 8.0, 41):
+            exact = _adaptive_expect(expit, m, v)
+            worst = max(worst, abs(_binary_probit(m, v) - exact))
+    assert worst <= 2.0 * sub_err
+    # measured maximum over this grid for the slope-matched constant: 0.0150
+    # (3/pi^2 in place of pi/8 gives 0.023, 8/pi 0.20, no square root 0.27)
+    assert worst <= 0.016
