@@ -1,10 +1,14 @@
 """O-method: IterNCGP (Algorithm 1), IterGP (Algorithm 2) and the virtual
 solver run with compression (Algorithm 3), FP64, matrix-free.
 
-Written from the paper's description of the algorithms, in its order and
-notation: actions s_j, products t_j = K s_j, buffers S and T, root Q of the
-approximate precision C_j = Q Q^T, search direction d_j, normaliser eta_j,
-observation alpha_j, representer weights v_j.
+Written from the paper's statement of the method in its notation: actions
+s_j, products t_j = K s_j, buffers S and T, the approximate precision matrix
+C_j = S_j (S_j^T Khat S_j)^{-1} S_j^T (eq. C_j) with root Q, representer
+weights v_j = C_j (yhat - m), normaliser eta_j and observation alpha_j.  The
+inner solve is written from the definition of C_j (a Cholesky factor of the
+Gram matrix of the actions, grown by one row per action), not from the
+recurrence for the search direction that Algorithm 2 uses to update it; the
+two agree in exact arithmetic, and the library implements the recurrence.
 
 Readings of points the paper leaves open:
 
@@ -16,9 +20,9 @@ Readings of points the paper leaves open:
 * CG actions are stored normalised, s_j = r_{j-1} / ||r_{j-1}||.  All outputs
   are invariant to the scale of an action (C_j depends only on span S); the
   invariance is pinned by a test.
-* eta_j <= 0 ends the solve (appendix on stopping criteria); the action and
-  its product, already appended, are removed again so that the recycled M of
-  the next Newton step stays nonsingular.
+* eta_j <= 0 ends the solve (appendix on stopping criteria); that action and
+  its product are not kept in S and T (Algorithm 2 appends them before eta_j
+  is known), so the recycled M of the next Newton step stays nonsingular.
 * Algorithm 3 takes M = S^T (T + W^+ S), symmetrised as (M + M^T)/2, and its
   eigenpairs sorted by decreasing eigenvalue.  Eigenpairs with
   lambda <= lambda_max * B * eps_64 are dropped before truncation to R
@@ -46,6 +50,7 @@ import dataclasses
 from typing import Callable, List, Optional
 
 import numpy as np
+import scipy.linalg as sla
 
 from . import likelihood as lik
 from .newton import pseudo_target_offset
@@ -103,13 +108,43 @@ def virtual_solver_run(S: np.ndarray, T: np.ndarray, apply_Winv: Apply,
     return Q0, S, T, VSRInfo(lam, n_floor, n_rank)
 
 
+def _choose_action(policy: str, r: np.ndarray, rn: float, j: int,
+                   user_actions: Optional[np.ndarray], normalize: bool) -> np.ndarray:
+    """The policy's j-th action (1-based) given the current residual r."""
+    if policy == "cg":                     # residual actions: CG in exact arithmetic
+        return r / rn if normalize else r.copy()
+    if policy == "unit":                   # unit vectors: partial Cholesky / subset of data
+        e = np.zeros(r.shape[0])
+        e[j - 1] = 1.0
+        return e
+    if policy == "user":
+        return np.array(user_actions[:, j - 1], dtype=np.float64)
+    raise ValueError(policy)
+
+
 def itergp(apply_K: Apply, apply_Winv: Apply, rhs: np.ndarray,
            S: np.ndarray, T: np.ndarray, policy: str = "cg", j_max: int = 100,
            tol_abs: float = 1e-5, tol_rel: float = 1e-5,
            rank_limit: Optional[int] = None, recycle: bool = True,
            user_actions: Optional[np.ndarray] = None,
            normalize_actions: bool = True):
-    """Algorithm 2 for the system Khat v = rhs (rhs = yhat - m).
+    """IterGP (Algorithm 2) for the system Khat v = rhs (rhs = yhat - m), with
+    Khat = K + W^{-1}.
+
+    The method's state after j actions is the approximate precision matrix of
+    eq. C_j, C_j = S_j (S_j^T Khat S_j)^{-1} S_j^T, and the representer
+    weights v_j = C_j rhs.  This function writes that definition out: the
+    Gram matrix M_j = S_j^T Khat S_j = S_j^T (T_j + W^{-1} S_j) (T_j = K S_j,
+    kept beside S_j) is grown by one row and column per action, factored
+    M_j = L_j L_j^T, and v_j = S_j M_j^{-1} S_j^T rhs.  The new action is chosen
+    from the residual r_{j-1} = rhs - Khat v_{j-1}.  The last pivot of L_j,
+    eta_j = (M_j)_{jj} - |L_{j-1}^{-1} (M_j)_{1:j-1, j}|^2, is the Schur
+    complement of the new action against the previous ones (the normaliser of
+    the search direction in Algorithm 2); eta_j <= 0 means the action adds no
+    direction in the Khat geometry, which ends the solve.  The returned root Q
+    of C_j is S_j L_j^{-T}.  With recycling, S_0 and T_0 come from the virtual
+    solver run (Algorithm 3) and C_0 = S_0 (S_0^T Khat S_0)^{-1} S_0^T is the
+    initial precision matrix of the step.
 
     Returns (v, Q, S, T, info).  ``policy`` is "cg" (s_j = r_{j-1}), "unit"
     (s_j = e_j) or "user" (s_j = user_actions[:, j-1]; the solve ends when the
@@ -117,55 +152,68 @@ def itergp(apply_K: Apply, apply_Winv: Apply, rhs: np.ndarray,
     """
     n = rhs.shape[0]
     if recycle:
-        Q, S, T, vinfo = virtual_solver_run(S, T, apply_Winv, rank_limit)
+        _, S, T, vinfo = virtual_solver_run(S, T, apply_Winv, rank_limit)
     else:
-        Q, S, T, vinfo = np.zeros((n, 0)), np.zeros((n, 0)), np.zeros((n, 0)), None
+        S, T, vinfo = np.zeros((n, 0)), np.zeros((n, 0)), None
     info = SolveInfo(vsr=vinfo)
-    v = Q @ (Q.T @ rhs)                                  # v_0 = C_0 (yhat - m)
+    cols_S, cols_T = [S[:, k] for k in range(S.shape[1])], [T[:, k] for k in range(T.shape[1])]
+    b0 = len(cols_S)
+    M = S.T @ (T + apply_Winv(S)) if b0 else np.zeros((0, 0))
+    M = 0.5 * (M + M.T)
+    L = np.linalg.cholesky(M) if b0 else np.zeros((0, 0))
+    proj = S.T @ rhs                                     # S_j^T rhs
+
+    def weights():
+        """v_j = S_j M_j^{-1} S_j^T rhs through the factor L_j."""
+        if not cols_S:
+            return np.zeros(n)
+        w = sla.solve_triangular(L, proj, lower=True)
+        w = sla.solve_triangular(L.T, w, lower=False)
+        return np.stack(cols_S, axis=1) @ w
+
+    v = weights()
     rhs_norm = float(np.linalg.norm(rhs))
     info.rhs_norm = rhs_norm
     thresh = max(tol_abs, tol_rel * rhs_norm)
     j = 0
     while j < j_max:
-        r = rhs - apply_K(v) - apply_Winv(v)             # r_{j-1}
+        r = rhs - apply_K(v) - apply_Winv(v)
         rn = float(np.linalg.norm(r))
         info.res_norms.append(rn)
         if rn < thresh:
             info.converged = True
             break
         if policy == "user" and j >= user_actions.shape[1]:
-            break                                        # supplied actions used up
-        j += 1
-        if policy == "cg":
-            s = r / rn if normalize_actions else r.copy()
-        elif policy == "unit":
-            s = np.zeros(n)
-            s[j - 1] = 1.0
-        elif policy == "user":
-            s = np.array(user_actions[:, j - 1], dtype=np.float64)
-        else:
-            raise ValueError(policy)
-        S = np.concatenate([S, s[:, None]], axis=1)      # append s_j to S
-        alpha = float(s @ r)                             # alpha_j = s_j^T r_{j-1}
-        t = apply_K(s)                                   # t_j = K s_j
-        T = np.concatenate([T, t[:, None]], axis=1)      # append t_j to T
-        z = t + apply_Winv(s)                            # z_j = Khat s_j
-        d = s - Q @ (Q.T @ z)                            # d_j = s_j - C_{j-1} z_j
-        eta = float(z @ d)                               # eta_j = z_j^T d_j
-        info.etas.append(eta)
-        info.alphas.append(alpha)
-        info.actions.append(s)
-        if eta <= 0.0:
-            info.breakdown = True
-            S, T = S[:, :-1], T[:, :-1]
-            info.actions.pop()
-            info.etas.pop()
-            info.alphas.pop()
-            j -= 1
             break
-        Q = np.concatenate([Q, (d / np.sqrt(eta))[:, None]], axis=1)
-        v = v + (alpha / eta) * d
+        s = _choose_action(policy, r, rn, j + 1, user_actions, normalize_actions)
+        t = apply_K(s)
+        ks = t + apply_Winv(s)                           # Khat s
+        # new row/column of the Gram matrix and the Schur complement of s
+        m_new = np.array([c @ ks for c in cols_S])
+        mu = float(s @ ks)
+        l_new = (sla.solve_triangular(L, m_new, lower=True) if cols_S else np.zeros(0))
+        eta = mu - float(l_new @ l_new)
+        if eta <= 0.0:
+            info.breakdown = True                        # s is dropped again
+            break
+        j += 1
+        info.alphas.append(float(s @ r))
+        info.etas.append(eta)
+        info.actions.append(s)
+        cols_S.append(s)
+        cols_T.append(t)
+        k = L.shape[0]
+        L2 = np.zeros((k + 1, k + 1))
+        L2[:k, :k] = L
+        L2[k, :k] = l_new
+        L2[k, k] = np.sqrt(eta)
+        L = L2
+        proj = np.append(proj, s @ rhs)
+        v = weights()
     info.iters = j
+    S = np.stack(cols_S, axis=1) if cols_S else np.zeros((n, 0))
+    T = np.stack(cols_T, axis=1) if cols_T else np.zeros((n, 0))
+    Q = sla.solve_triangular(L, S.T, lower=True).T if cols_S else np.zeros((n, 0))
     return v, Q, S, T, info
 
 
