@@ -67,6 +67,32 @@ def kernel_matrix(X1, X2, kind: str, lengthscale: float, outputscale: float,
     return out
 
 
+def kernel_matrix_gram(X1, X2, kind: str, lengthscale: float, outputscale: float,
+                       out: np.ndarray = None, block: int = 4096) -> np.ndarray:
+    """K_X[n, m] = k(x1_n, x2_m) with the squared distance expanded as
+    |x1|^2 + |x2|^2 - 2 x1.x2 (FP64, one matrix product per row block, clamped
+    at 0).  For many features (hundreds), where the explicit differences of
+    ``kernel_matrix`` cost one pass over the block per feature.  The expansion
+    changes r^2 by at most about 2 D eps_64 (|x1|^2 + |x2|^2) / l^2 (pinned
+    against ``kernel_matrix``).  ``out`` may be a preallocated (N1, N2) array."""
+    X1 = np.asarray(X1, dtype=np.float64)
+    X2 = np.asarray(X2, dtype=np.float64)
+    if out is None:
+        out = np.empty((X1.shape[0], X2.shape[0]))
+    n2 = (X2 * X2).sum(axis=1)
+    inv_l2 = 1.0 / (lengthscale * lengthscale)
+    for i0 in range(0, X1.shape[0], block):
+        A = X1[i0:i0 + block]
+        r2 = A @ X2.T
+        r2 *= -2.0
+        r2 += (A * A).sum(axis=1)[:, None]
+        r2 += n2[None, :]
+        np.maximum(r2, 0.0, out=r2)
+        r2 *= inv_l2
+        out[i0:i0 + block] = kernel_of_r2(r2, kind, outputscale)
+    return out
+
+
 def kernel_matvec(X1, X2, V, kind: str, lengthscale: float, outputscale: float,
                   block: int = 1024) -> np.ndarray:
     """Out = K_X(X1, X2) @ V for V of shape (N2, W), blockwise over rows of X1

@@ -122,3 +122,26 @@ def test_per_class_kernels_dense_definition_and_shared_limit():
     np.testing.assert_allclose(ok.full_kernel_cn_per_class(Ks1),
                                ok.full_kernel_cn(ok.kernel_matrix(X, X, "rbf", 0.9, 1.2), 3),
                                rtol=1e-15, atol=1e-15)
+
+
+@pytest.mark.parametrize("kind", ["rbf", "matern32", "matern52"])
+def test_gram_form_matches_explicit_differences(kind):
+    """The norm-expansion form of the kernel matrix (used for many features)
+    against the explicit-difference definition, within the rounding of the
+    expansion: |dr^2| <= 2 D eps (|x1|^2 + |x2|^2) / l^2 and |dk| <= L |dr^2|
+    with L = max |dk/d(r^2)| / os (1/2 RBF, 3/2 Matern-3/2, 5/6 Matern-5/2)."""
+    rng = np.random.default_rng(41)
+    D = 784
+    X1 = rng.uniform(0.0, 1.0, size=(150, D)) * (rng.uniform(size=(150, D)) < 0.2)
+    X2 = rng.uniform(0.0, 1.0, size=(90, D)) * (rng.uniform(size=(90, D)) < 0.2)
+    X2[:5] = X1[:5]                               # coincident points (r = 0)
+    ell, os_ = 7.5, 1.7
+    ref = ok.kernel_matrix(X1, X2, kind, ell, os_)
+    got = ok.kernel_matrix_gram(X1, X2, kind, ell, os_, block=64)
+    lip = {"rbf": 0.5, "matern32": 1.5, "matern52": 5.0 / 6.0}[kind]
+    eps = np.finfo(np.float64).eps
+    nn = (X1 * X1).sum(1)[:, None] + (X2 * X2).sum(1)[None, :]
+    bound = os_ * lip * 2.0 * D * eps * nn / ell ** 2
+    assert np.all(np.abs(got - ref) <= bound + 4 * eps * os_)
+    # a wrong factor in the expansion is far outside that bound
+    assert np.abs(got - ref).max() < 1e-10
