@@ -106,6 +106,31 @@ int glm_kernel_matmul(const igp_kernel_params* kp, int32_t n_kp,
                       void* Out, int64_t ldo, double beta, int32_t precision,
                       void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ----------------------------------------------------------------------
+ * glm_kernel_matmul_noalloc -- glm_kernel_matmul without a workspace, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, result and errors as glm_kernel_matmul, except that the
+ * scratch space (split partials, centred rows and their norms) comes from a
+ * static device array of glm_kernel_matmul_noalloc_max_bytes() bytes (64 MiB)
+ * that the library holds on each GPU it runs on until the process ends; the
+ * call itself allocates nothing.  The array of the CURRENT device is used, so
+ * `stream` must belong to the current device.  Products whose
+ * glm_kernel_matmul_ws_bytes(...) exceeds the maximum fail with IGP_ENOMEM
+ * before any work is queued (FP32, D = 16, 5 output columns: n1 = n2 = 20000
+ * needs about 33 MiB, n1 = n2 = 30000 about 72 MiB).
+ * All calls on one GPU share its array: calls that overlap in time on one GPU
+ * (different streams, different host threads without ordering) race and give
+ * undefined results; calls ordered on one stream are safe.  The array keeps
+ * the last call's contents; every byte a call reads it has written first.
+ * ---------------------------------------------------------------------- */
+size_t glm_kernel_matmul_noalloc_max_bytes(void);
+int glm_kernel_matmul_noalloc(const igp_kernel_params* kp, int32_t n_kp,
+                              const void* X1, int64_t n1, const void* X2, int64_t n2, int64_t d,
+                              const void* V, int64_t C, int64_t nb, int64_t ldv,
+                              void* Out, int64_t ldo, double beta, int32_t precision,
+                              hipStream_t stream);
+
 /* ======================================================================
  * glm_softmax_hessian_apply -- products with the per-point C x C blocks of
  * the negative Hessian of the softmax log likelihood at logits F.

@@ -75,6 +75,10 @@ SIGNATURES = {
     "glm_kernel_matmul": (ct.c_int, [ct.POINTER(KernelParams), _I32, _P, _I64, _P, _I64, _I64, _P,
                                      _I64, _I64, _I64, _P, _I64, ct.c_double, _I32, _P, _SZ,
                                      _P]),
+    "glm_kernel_matmul_noalloc_max_bytes": (_SZ, []),
+    "glm_kernel_matmul_noalloc": (ct.c_int, [ct.POINTER(KernelParams), _I32, _P, _I64, _P, _I64,
+                                             _I64, _P, _I64, _I64, _I64, _P, _I64, ct.c_double,
+                                             _I32, _P]),
     "glm_softmax_hessian_apply": (ct.c_int, [_P, _I64, _I64, _P, _I64, _I64, _P, _I64, _I32,
                                              _I32, _P]),
     "itergp_state_bytes": (_SZ, [_I64, _I64, _I64, ct.POINTER(SolverConfig)]),

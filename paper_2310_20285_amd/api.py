@@ -91,6 +91,35 @@ def glm_kernel_matmul(X1: torch.Tensor, X2: torch.Tensor, V: torch.Tensor, C: in
     return out.view(-1) if vec else out
 
 
+def glm_kernel_matmul_noalloc(X1: torch.Tensor, X2: torch.Tensor, V: torch.Tensor, C: int, kind,
+                              lengthscale: float, outputscale: float, precision="fp32",
+                              beta: float = 0.0, out: Optional[torch.Tensor] = None
+                              ) -> torch.Tensor:
+    """glm_kernel_matmul through the entry point that allocates no workspace
+    (its scratch is the library's static per-GPU array).  `out` may be given so
+    that the call allocates nothing at all."""
+    lib = L.load()
+    p = _prec(precision)
+    dt = _DTYPE[p]
+    for t, nm in ((X1, "X1"), (X2, "X2"), (V, "V")):
+        _need(t, dt, nm)
+    n1, d = X1.shape
+    n2 = X2.shape[0]
+    vec = V.dim() == 1
+    V2 = V.view(1, -1) if vec else V
+    nb = V2.shape[0]
+    if V2.shape[1] != n2 * C:
+        raise ValueError("V rows must have n2*C entries")
+    if out is None:
+        out = torch.empty((nb, n1 * C), dtype=dt, device=X1.device)
+    O2 = out.view(nb, n1 * C)
+    kp, n_kp = kernel_params(kind, lengthscale, outputscale, C)
+    L.check(lib.glm_kernel_matmul_noalloc(kp, n_kp, _ptr(X1), n1, _ptr(X2), n2, d, _ptr(V2), C,
+                                          nb, n2 * C, _ptr(O2), n1 * C, float(beta), p,
+                                          _stream()))
+    return out.view(-1) if vec else out
+
+
 def glm_softmax_hessian_apply(F: torch.Tensor, V: torch.Tensor, mode="pinv",
                               out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Out_n = W_n V_n (mode "w") or W_n^+ V_n (mode "pinv"); F is (N, C)."""

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libitergp.so")
 
-SOURCES = ["kv.hip", "kv_mfma.hip", "kv_bf16.hip", "hessian.hip", "diaglik.hip", "linalg.hip", "batched_ops.hip", "blocklik.hip", "itergp.cpp", "abi.cpp",
+SOURCES = ["kv.hip", "kv_mfma.hip", "kv_bf16.hip", "hessian.hip", "diaglik.hip", "linalg.hip", "batched_ops.hip", "blocklik.hip", "noalloc.hip", "itergp.cpp", "abi.cpp",
            "eigh.cpp"]
 ARCH = "gfx950"
 COMMON = [*os.environ.get("IGP_EXTRA_FLAGS", "").split(), "-O3", "-fPIC", "-std=c++17", f"-I{INCLUDE}", "-Wall", "-Wno-unused-function",

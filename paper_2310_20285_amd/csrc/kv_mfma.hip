@@ -969,7 +969,8 @@ int64_t padded_dim(int64_t d) { return ceil_div(d, 16) * 16; }
 int column_mean_f32(const float* X, int64_t n, int64_t d, float* mean, double* part,
                     int64_t part_cap, hipStream_t s) {
   if (n == 0) {
-    IGP_CHECK_HIP(hipMemsetAsync(mean, 0, d * sizeof(float), s));
+    // a fill kernel, not a memset node, so that the call can be graph-captured
+    IGP_TRY(fill_zero<float>(mean, d, s));
     return IGP_OK;
   }
   // ~64 rows per block and 256 threads across the columns: short FP64 chains
