@@ -68,8 +68,14 @@ typedef struct igp_kernel_params {
  * IGP_FP64: FP64 throughout.  IGP_FP32: FP32 storage and arithmetic, FP64
  * reductions in the solver.  IGP_BF16: as FP32, but the distance product
  * X1 X2^T runs on BF16 MFMA with FP32 accumulation (inputs rounded to BF16,
- * squared norms taken of the rounded values). */
-typedef enum igp_precision { IGP_FP64 = 0, IGP_FP32 = 1, IGP_BF16 = 2 } igp_precision;
+ * squared norms taken of the rounded values).  IGP_BF16X3: as IGP_BF16 with
+ * each (centred) input split into BF16 high and low parts, x = xh + xl, and
+ * x1.x2 taken as xh1.xh2 + xl1.xh2 + xh1.xl2 (three BF16 products; inputs
+ * kept to about 2^-17 relative instead of 2^-9, at three times the distance
+ * work).  The element type of the BF16 modes is float. */
+typedef enum igp_precision {
+  IGP_FP64 = 0, IGP_FP32 = 1, IGP_BF16 = 2, IGP_BF16X3 = 3
+} igp_precision;
 
 /* ======================================================================
  * glm_kernel_matmul -- the matrix-free product with the prior covariance.
@@ -95,7 +101,7 @@ typedef enum igp_precision { IGP_FP64 = 0, IGP_FP32 = 1, IGP_BF16 = 2 } igp_prec
  * n1 == 0 or nb == 0 is a no-op; n2 == 0 gives Out = beta*Out.
  * Errors: IGP_EINVAL (NULL pointer with non-zero size, d < 1, C < 1,
  * ld too small, non-positive hyperparameter, n_kp not 1 or C, mixed kernel
- * families), IGP_EUNSUPPORTED (n_kp > 1 with IGP_BF16), IGP_ENOMEM (ws too
+ * families), IGP_EUNSUPPORTED (n_kp > 1 in a BF16 mode), IGP_ENOMEM (ws too
  * small), IGP_EDEVICE (launch failure).
  * ====================================================================== */
 size_t glm_kernel_matmul_ws_bytes(int64_t n1, int64_t n2, int64_t d, int64_t C,

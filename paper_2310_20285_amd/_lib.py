@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libitergp.so")
 
 IGP_OK, IGP_EINVAL, IGP_ENOMEM, IGP_EDEVICE, IGP_EUNSUPPORTED = 0, -1, -2, -3, -4
 IGP_RBF, IGP_MATERN12, IGP_MATERN32, IGP_MATERN52 = 0, 1, 2, 3
-IGP_FP64, IGP_FP32, IGP_BF16 = 0, 1, 2
+IGP_FP64, IGP_FP32, IGP_BF16, IGP_BF16X3 = 0, 1, 2, 3
 IGP_W, IGP_W_PINV = 0, 1
 IGP_POLICY_CG, IGP_POLICY_UNIT, IGP_POLICY_USER = 0, 1, 2
 IGP_RESIDUAL_EXPLICIT, IGP_RESIDUAL_RECURRENCE = 0, 1
@@ -23,7 +23,8 @@ IGP_RESIDUAL_EXPLICIT, IGP_RESIDUAL_RECURRENCE = 0, 1
 
 KIND_CODE = {"rbf": IGP_RBF, "matern12": IGP_MATERN12, "matern32": IGP_MATERN32,
              "matern52": IGP_MATERN52}
-PRECISION_CODE = {"fp64": IGP_FP64, "fp32": IGP_FP32, "bf16": IGP_BF16}
+PRECISION_CODE = {"fp64": IGP_FP64, "fp32": IGP_FP32, "bf16": IGP_BF16,
+                  "bf16x3": IGP_BF16X3}
 
 
 class KernelParams(ct.Structure):

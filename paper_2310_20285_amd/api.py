@@ -13,7 +13,8 @@ import torch
 
 from . import _lib as L
 
-_DTYPE = {L.IGP_FP64: torch.float64, L.IGP_FP32: torch.float32, L.IGP_BF16: torch.float32}
+_DTYPE = {L.IGP_FP64: torch.float64, L.IGP_FP32: torch.float32, L.IGP_BF16: torch.float32,
+          L.IGP_BF16X3: torch.float32}
 
 
 def _prec(p) -> int:

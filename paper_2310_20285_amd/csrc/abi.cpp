@@ -85,7 +85,7 @@ int glm_kernel_matmul(const igp_kernel_params* kp, int32_t n_kp, const void* X1,
     }
     IGP_REQUIRE(n1 >= 0 && n2 >= 0 && nb >= 0, "negative size");
     IGP_REQUIRE(d >= 1 && C >= 1, "d and C must be >= 1");
-    IGP_REQUIRE(precision >= IGP_FP64 && precision <= IGP_BF16, "unknown precision %d", precision);
+    IGP_REQUIRE(precision >= IGP_FP64 && precision <= IGP_BF16X3, "unknown precision %d", precision);
     IGP_REQUIRE(std::isfinite(beta), "beta must be finite");
     if (n1 == 0 || nb == 0) return IGP_OK;
     IGP_REQUIRE(X1 && Out, "NULL X1 or Out");

@@ -97,8 +97,9 @@ Layout<T> carve(Carver& cv, int64_t N, int64_t D, int64_t C, const igp_solver_co
   L.apart = cv.take<double>(RED_BLOCKS);
   if (prepared) {
     L.centre = cv.take<float>(D);
-    L.Xp = cfg.precision == IGP_BF16 ? static_cast<void*>(cv.take<uint16_t>(N * bf16_padded_dim(D)))
-                                     : static_cast<void*>(cv.take<float>(N * padded_dim(D)));
+    L.Xp = is_bf16(cfg.precision)
+               ? static_cast<void*>(cv.take<uint16_t>(bf16_rows_elems(cfg.precision, N, D)))
+               : static_cast<void*>(cv.take<float>(N * padded_dim(D)));
     L.nrm = cv.take<float>(N);
     L.meanpart = cv.take<double>(MEAN_BLOCKS * D);
   }
@@ -1321,15 +1322,15 @@ int validate_common(const igp_kernel_params* kp, int n_kp, const igp_solver_conf
                     std::isfinite(kp[c].outputscale) && kp[c].outputscale > 0,
                 "kernel hyperparameters must be finite and positive");
   }
-  IGP_REQUIRE(n_kp == 1 || cfg->precision != IGP_BF16,
-              "one kernel per class is not supported in BF16 mode");
+  IGP_REQUIRE(n_kp == 1 || !is_bf16(cfg->precision),
+              "one kernel per class is not supported in the BF16 modes");
   IGP_REQUIRE(N >= 1 && D >= 1 && C >= 1, "N, D, C must be >= 1");
   IGP_REQUIRE(C <= 64, "C must be <= 64");
   IGP_REQUIRE(cfg->policy >= IGP_POLICY_CG && cfg->policy <= IGP_POLICY_USER, "unknown policy");
   IGP_REQUIRE(cfg->j_max >= 0, "j_max must be >= 0");
   IGP_REQUIRE(cfg->max_buffer >= 1 && cfg->max_buffer <= 4096, "max_buffer must be in [1, 4096]");
   IGP_REQUIRE(cfg->max_buffer >= cfg->j_max, "max_buffer must be >= j_max");
-  IGP_REQUIRE(cfg->precision >= IGP_FP64 && cfg->precision <= IGP_BF16, "unknown precision");
+  IGP_REQUIRE(cfg->precision >= IGP_FP64 && cfg->precision <= IGP_BF16X3, "unknown precision");
   IGP_REQUIRE(cfg->residual_mode == IGP_RESIDUAL_EXPLICIT ||
                   cfg->residual_mode == IGP_RESIDUAL_RECURRENCE,
               "unknown residual mode %d", cfg->residual_mode);

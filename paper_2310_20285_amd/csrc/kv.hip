@@ -240,12 +240,12 @@ int launch_valu(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t s) {
 }  // namespace
 
 bool kv_uses_prepared(int precision, int kind, int64_t d) {
-  return precision == IGP_BF16 || (precision == IGP_FP32 && mfma_f32_supported(kind, d));
+  return is_bf16(precision) || (precision == IGP_FP32 && mfma_f32_supported(kind, d));
 }
 
 size_t prepared_rows_bytes(int precision, int64_t n, int64_t d) {
   Carver cv(nullptr, 0);
-  if (precision == IGP_BF16) cv.take<uint16_t>(n * bf16_padded_dim(d));
+  if (is_bf16(precision)) cv.take<uint16_t>(bf16_rows_elems(precision, n, d));
   else cv.take<float>(n * padded_dim(d));
   cv.take<float>(n);
   return cv.used;
@@ -253,7 +253,7 @@ size_t prepared_rows_bytes(int precision, int64_t n, int64_t d) {
 
 int prep_rows_any(int precision, const float* X, int64_t n, int64_t d, const float* centre,
                   void* rows, float* norms, hipStream_t s) {
-  if (precision == IGP_BF16) return prep_rows_bf16(X, n, d, centre, rows, norms, s);
+  if (is_bf16(precision)) return prep_rows_bf16(precision, X, n, d, centre, rows, norms, s);
   return prep_rows_f32(X, n, d, centre, static_cast<float*>(rows), norms, s);
 }
 
@@ -278,14 +278,14 @@ size_t kv_ws_bytes_prepared(int64_t n1, int64_t n2, int64_t d, int64_t C, int64_
   size_t b = static_cast<size_t>(sp.nsplit) * n1 * W * elt;
   if (precision == IGP_FP32 && d <= 128)
     b = std::max(b, mfma_f32_partial_bytes(n1, n2, d, W, fixed));
-  if (precision == IGP_BF16) b = bf16_partial_bytes(n1, n2, W, fixed);
+  if (is_bf16(precision)) b = bf16_partial_bytes(n1, n2, W, fixed);
   return align_up(b + 256);
 }
 
 size_t kv_ws_bytes(int64_t n1, int64_t n2, int64_t d, int64_t C, int64_t nb, int precision,
                    bool fixed) {
   size_t b = kv_ws_bytes_prepared(n1, n2, d, C, nb, precision, fixed);
-  if (precision == IGP_BF16 || (precision == IGP_FP32 && d <= 128))
+  if (is_bf16(precision) || (precision == IGP_FP32 && d <= 128))
     b += align_up(prep_bytes(precision, n1, n2, d) + 256);
   return b;
 }
@@ -293,7 +293,7 @@ size_t kv_ws_bytes(int64_t n1, int64_t n2, int64_t d, int64_t C, int64_t nb, int
 namespace {
 int launch_mfma_path(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t s) {
   const int64_t W = p.C * p.nb;
-  const bool bf = p.precision == IGP_BF16;
+  const bool bf = is_bf16(p.precision);
   Carver cv(ws, ws_bytes);
   const size_t pbytes = bf ? bf16_partial_bytes(p.n1, p.n2, W, p.fixed_split)
                            : mfma_f32_partial_bytes(p.n1, p.n2, p.d, W, p.fixed_split);
@@ -358,8 +358,8 @@ int kv_launch(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t s) {
                 "one kernel per class needs n_kp == C <= 64 parameter sets");
     for (int c = 0; c < p.n_kp; ++c)
       IGP_REQUIRE(p.kpc[c].kind == p.kp.kind, "per-class kernels must share one kernel family");
-    if (p.precision == IGP_BF16) {
-      set_error("one kernel per class is not supported in BF16 mode");
+    if (is_bf16(p.precision)) {
+      set_error("one kernel per class is not supported in the BF16 modes");
       return IGP_EUNSUPPORTED;
     }
     if (p.precision == IGP_FP64) return launch_valu<double>(p, ws, ws_bytes, s);

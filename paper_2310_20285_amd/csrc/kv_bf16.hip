@@ -20,7 +20,10 @@
 // transposed-tile arrangement), and a pair of m-blocks gives the 8 k-values of
 // one 16x16x32 instruction.  K and V are split into BF16 high and low parts
 // and the contraction takes hi*hi + hi*lo + lo*hi, which keeps about 16
-// significant bits of each factor.
+// significant bits of each factor.  In the split-input mode (X3) the distance
+// loop runs three phases (see dist_tile) and K and V are split into three BF16
+// parts h + m + l (about 24 bits, the FP32 significand); the contraction takes
+// the six products of combined order up to two, hh + hm + mh + hl + mm + lh.
 //
 // The grid is one-dimensional and remapped so that the workgroups the hardware
 // deals to one XCD (ids congruent mod 8) take consecutive tiles: the same X2
@@ -65,6 +68,43 @@ __device__ inline float kt_bf(float t) {
 __device__ inline __bf16 to_bf(float x) { return static_cast<__bf16>(x); }
 __device__ inline float from_bf(__bf16 x) { return static_cast<float>(x); }
 
+// x = h + m + l to about 2^-24 |x| (three BF16 parts)
+__device__ inline void split3(float x, __bf16& h, __bf16& m, __bf16& l) {
+  h = to_bf(x);
+  const float r = x - from_bf(h);
+  m = to_bf(r);
+  l = to_bf(r - from_bf(m));
+}
+// the same into element i of three register vectors
+__device__ inline void split3_at(float x, bf8& h, bf8& m, bf8& l, int i) {
+  const __bf16 a = to_bf(x);
+  const float r = x - from_bf(a);
+  const __bf16 b = to_bf(r);
+  h[i] = a;
+  m[i] = b;
+  l[i] = to_bf(r - from_bf(b));
+}
+
+// out += the product of (kh, km, kl) and (vh, vm, vl) to combined order two;
+// with X3 false only hh + hl + lh of the two-part splits (k*, v* with * = h, l)
+template <bool X3>
+__device__ inline f4 contract(const bf8& kh, const bf8& km, const bf8& kl, const bf8& vh,
+                              const bf8& vm, const bf8& vl, f4 out) {
+  if constexpr (X3) {
+    out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vl, out, 0, 0, 0);
+    out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(km, vm, out, 0, 0, 0);
+    out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kl, vh, out, 0, 0, 0);
+    out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vm, out, 0, 0, 0);
+    out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(km, vh, out, 0, 0, 0);
+    out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vh, out, 0, 0, 0);
+  } else {
+    out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vh, out, 0, 0, 0);
+    out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vl, out, 0, 0, 0);
+    out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kl, vh, out, 0, 0, 0);
+  }
+  return out;
+}
+
 constexpr int WM = 2, WN = 4;          // waves along m and n
 constexpr int TMW = 128, TNW = 64;     // rows of m and n per wave
 constexpr int BM = WM * TMW;           // X2 rows per tile (256)
@@ -76,6 +116,10 @@ constexpr int QA = BM * 4 / NT, QB = BN * 4 / NT;   // 16-byte pieces staged per
 
 // D^T of one (X2 tile, X1 block) pair for this wave: acc[mb][nb][v] =
 // sum_k X2[m0 + wm TMW + mb 16 + 4g + v][k] X1[n0 + wn TNW + nb 16 + r][k].
+// With nph = 3 (inputs split into BF16 high and low parts, X = H + L) the
+// feature loop runs three phases, H2.H1 + H2.L1 + L2.H1: the chunk index
+// selects the phase's pair of row arrays, so the same pipeline streams 3 DPB
+// features.
 // Feature chunks of KC stream through the double-buffered LDS tiles sA / sB
 // ([2][BM RS] and [2][BN RS]); chunk ks+1 (loaded during the previous
 // iteration) goes to the other buffer before the products of chunk ks, so its
@@ -85,22 +129,29 @@ constexpr int QA = BM * 4 / NT, QB = BN * 4 / NT;   // 16-byte pieces staged per
 __device__ __forceinline__ void dist_tile(f4 (&acc)[MB][NB], __bf16* __restrict__ sA,
                                           __bf16* __restrict__ sB,
                                           const __bf16* __restrict__ X1b,
-                                          const __bf16* __restrict__ X2b, int64_t n0, int64_t n1,
-                                          int64_t m0, int64_t m_end, int DPB, int tid, int wm,
-                                          int wn, int g, int r) {
+                                          const __bf16* __restrict__ X2b,
+                                          const __bf16* __restrict__ X1l,
+                                          const __bf16* __restrict__ X2l, int nph, int64_t n0,
+                                          int64_t n1, int64_t m0, int64_t m_end, int DPB, int tid,
+                                          int wm, int wn, int g, int r) {
   u4 pa[QA], pb[QB];
-  auto fetch = [&](int k0) {
+  const int cpp = DPB / KC;   // chunks per phase
+  auto fetch = [&](int kc) {
+    const int ph = kc / cpp;
+    const int k0 = (kc - ph * cpp) * KC;
+    const __bf16* A2 = ph == 2 ? X2l : X2b;   // phase 0: H2.H1, 1: H2.L1, 2: L2.H1
+    const __bf16* B1 = ph == 1 ? X1l : X1b;
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
       const int e = tid + q * NT;
       const int64_t m = m0 + (e >> 2) < m_end ? m0 + (e >> 2) : m_end - 1;
-      pa[q] = *reinterpret_cast<const u4*>(X2b + m * DPB + k0 + (e & 3) * 8);
+      pa[q] = *reinterpret_cast<const u4*>(A2 + m * DPB + k0 + (e & 3) * 8);
     }
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
       const int e = tid + q * NT;
       const int64_t n = n0 + (e >> 2) < n1 ? n0 + (e >> 2) : n1 - 1;
-      pb[q] = *reinterpret_cast<const u4*>(X1b + n * DPB + k0 + (e & 3) * 8);
+      pb[q] = *reinterpret_cast<const u4*>(B1 + n * DPB + k0 + (e & 3) * 8);
     }
   };
   auto stash = [&](int buf) {
@@ -119,15 +170,15 @@ __device__ __forceinline__ void dist_tile(f4 (&acc)[MB][NB], __bf16* __restrict_
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f4{0, 0, 0, 0};
-  const int nks = DPB / KC;
+  const int nks = cpp * nph;
   fetch(0);
   stash(0);
   __syncthreads();
-  if (nks > 1) fetch(KC);
+  if (nks > 1) fetch(1);
   int buf = 0;
   for (int ks = 0; ks < nks; ++ks) {
     if (ks + 1 < nks) stash(buf ^ 1);
-    if (ks + 2 < nks) fetch((ks + 2) * KC);
+    if (ks + 2 < nks) fetch(ks + 2);
     bf8 b[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
@@ -144,11 +195,13 @@ __device__ __forceinline__ void dist_tile(f4 (&acc)[MB][NB], __bf16* __restrict_
   }
 }
 
-template <int KIND>
+template <int KIND, bool X3>
 __global__ void __launch_bounds__(NT)
 kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
-               const __bf16* __restrict__ X2b, const float* __restrict__ nrm2, int64_t n1,
-               int64_t n2, int DPB, const float* __restrict__ V, int C, int W, int64_t ldv,
+               const __bf16* __restrict__ X2b, const float* __restrict__ nrm2,
+               const __bf16* __restrict__ X1l, const __bf16* __restrict__ X2l, int nph,
+               int64_t n1, int64_t n2, int DPB, const float* __restrict__ V, int C, int W,
+               int64_t ldv,
                float* __restrict__ P, int64_t cols_per_split, int gx, int nsplit, float cnorm,
                float cdot, const int* skip) {
   if (gate_closed(skip)) return;
@@ -156,6 +209,7 @@ kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
   __shared__ __align__(16) __bf16 sB[2][BN * RS];   // X1 chunk (n rows)
   __shared__ __align__(16) __bf16 sVh[VT * VS];     // V^T tile, high part
   __shared__ __align__(16) __bf16 sVl[VT * VS];     // V^T tile, low part
+  __shared__ __align__(16) __bf16 sVm[X3 ? VT * VS : 8];   // middle part (X3)
   __shared__ __align__(16) float sN2[BM];
 
   // ids congruent mod 8 run on one XCD: give each XCD a contiguous tile range
@@ -194,16 +248,21 @@ kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
       const int w = w0 + wl;
       float v = 0.0f;
       if (gm < m_end && w < W) v = V[static_cast<int64_t>(w / C) * ldv + gm * C + (w % C)];
-      const __bf16 hi = to_bf(v);
-      sVh[wl * VS + m] = hi;
-      sVl[wl * VS + m] = to_bf(v - from_bf(hi));
+      if constexpr (X3) {
+        split3(v, sVh[wl * VS + m], sVm[wl * VS + m], sVl[wl * VS + m]);
+      } else {
+        const __bf16 hi = to_bf(v);
+        sVh[wl * VS + m] = hi;
+        sVl[wl * VS + m] = to_bf(v - from_bf(hi));
+      }
     }
     for (int e = tid; e < BM; e += NT) {
       const int64_t gm = m0 + e;
       sN2[e] = gm < m_end ? nrm2[gm] * cnorm : 0.0f;
     }
     f4 acc[MB][NB];
-    dist_tile(acc, &sA[0][0], &sB[0][0], X1b, X2b, n0, n1, m0, m_end, DPB, tid, wm, wn, g, r);
+    dist_tile(acc, &sA[0][0], &sB[0][0], X1b, X2b, X1l, X2l, nph, n0, n1, m0, m_end, DPB, tid,
+              wm, wn, g, r);
     // kernel transform + contraction: acc[mb][nb][v] = D^T[m = wm*TMW + mb*16 + 4g + v][n = .. + r]
 #pragma unroll
     for (int p = 0; p < MB / 2; ++p) {
@@ -211,33 +270,40 @@ kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
       const int ma = wm * TMW + mba * 16 + 4 * g, mbm = wm * TMW + mbb * 16 + 4 * g;
       const f4 na = *reinterpret_cast<const f4*>(&sN2[ma]);
       const f4 nbv = *reinterpret_cast<const f4*>(&sN2[mbm]);
-      bf8 vh, vl;
+      bf8 vh, vl, vm;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         vh[t] = sVh[r * VS + ma + t];
         vl[t] = sVl[r * VS + ma + t];
         vh[4 + t] = sVh[r * VS + mbm + t];
         vl[4 + t] = sVl[r * VS + mbm + t];
+        if constexpr (X3) {
+          vm[t] = sVm[r * VS + ma + t];
+          vm[4 + t] = sVm[r * VS + mbm + t];
+        }
       }
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        bf8 kh, kl;
+        bf8 kh, kl, km;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const float ka = kt_bf<KIND>(__builtin_fmaf(acc[mba][nb][t], cdot, n1v[nb] + na[t]));
           const float kb = kt_bf<KIND>(__builtin_fmaf(acc[mbb][nb][t], cdot, n1v[nb] + nbv[t]));
-          const __bf16 ha = to_bf(ka), hb = to_bf(kb);
-          kh[t] = ha;
-          kh[4 + t] = hb;
-          kl[t] = to_bf(ka - from_bf(ha));
-          kl[4 + t] = to_bf(kb - from_bf(hb));
+          if constexpr (X3) {
+            split3_at(ka, kh, km, kl, t);
+            split3_at(kb, kh, km, kl, 4 + t);
+          } else {
+            const __bf16 ha = to_bf(ka), hb = to_bf(kb);
+            kh[t] = ha;
+            kh[4 + t] = hb;
+            kl[t] = to_bf(ka - from_bf(ha));
+            kl[4 + t] = to_bf(kb - from_bf(hb));
+          }
         }
-        out[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vh, out[nb], 0, 0, 0);
-        out[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vl, out[nb], 0, 0, 0);
-        out[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kl, vh, out[nb], 0, 0, 0);
+        out[nb] = contract<X3>(kh, km, kl, vh, vm, vl, out[nb]);
       }
     }
-    __syncthreads();   // sVh / sVl / sN2 / sA / sB are rewritten by the next m tile
+    __syncthreads();   // sV* / sN2 / sA / sB are rewritten by the next m tile
   }
   // out[nb][j] = Out[n = n0 + wn*TNW + nb*16 + 4g + j][w = w0 + r]; add the WM wave rows
   // in LDS (sA is free after the last m tile)
@@ -286,14 +352,17 @@ kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
 // slots, each written once, reduced in slot order by kv_reduce.
 constexpr int TS = TNW + 8;               // row stride (bf16) of the transpose scratch [m][n]
 constexpr int TWAVE = 2 * 32 * TS;        // scratch per wave: hi and lo of 32 m rows
+constexpr int TSF = TNW + 4;              // row stride of the FP32 scratch of the X3 mode
+static_assert(32 * TSF * 2 <= TWAVE, "the FP32 transpose scratch fits in a wave's share");
 static_assert(WM == 2, "the direct reduction adds the second wave row to the first");
 static_assert(WM * WN * TWAVE <= 2 * (BM + BN) * RS, "transpose scratch fits in the chunk buffers");
 static_assert(WM * WN * MB * 64 * 16 + WN * NB * 64 * 16 <= 2 * (BM + BN) * RS * 2,
               "reduction buffers fit in the chunk buffers");
 
-template <int KIND>
+template <int KIND, bool X3>
 __global__ void __launch_bounds__(NT)
-kv_bf16_sym(const __bf16* __restrict__ Xb, const float* __restrict__ nrm, int64_t n, int DPB,
+kv_bf16_sym(const __bf16* __restrict__ Xb, const float* __restrict__ nrm,
+            const __bf16* __restrict__ Xl, int nph, int64_t n, int DPB,
             const float* __restrict__ V, int C, int W, int64_t ldv, float* __restrict__ P, int Q,
             float cnorm, float cdot, const int* skip) {
   if (gate_closed(skip)) return;
@@ -302,6 +371,8 @@ kv_bf16_sym(const __bf16* __restrict__ Xb, const float* __restrict__ nrm, int64_
   __shared__ __align__(16) __bf16 sVl[VT * VS];     // ... low part
   __shared__ __align__(16) __bf16 sUh[VT * VS];     // V^T of the s rows (n), high part
   __shared__ __align__(16) __bf16 sUl[VT * VS];     // ... low part
+  __shared__ __align__(16) __bf16 sVm[X3 ? VT * VS : 8];   // middle parts (X3)
+  __shared__ __align__(16) __bf16 sUm[X3 ? VT * VS : 8];
   __shared__ __align__(16) float sN2[BM];
 
   // ids congruent mod 8 run on one XCD: give each XCD a contiguous range of pairs
@@ -342,19 +413,26 @@ kv_bf16_sym(const __bf16* __restrict__ Xb, const float* __restrict__ nrm, int64_
     if (m0 + m < n && w < W) v = V[static_cast<int64_t>(w / C) * ldv + (m0 + m) * C + (w % C)];
     if (!diag && n0 + m < n && w < W)
       x = V[static_cast<int64_t>(w / C) * ldv + (n0 + m) * C + (w % C)];
-    const __bf16 vh = to_bf(v), xh = to_bf(x);
-    sVh[w * VS + m] = vh;
-    sVl[w * VS + m] = to_bf(v - from_bf(vh));
-    sUh[w * VS + m] = xh;
-    sUl[w * VS + m] = to_bf(x - from_bf(xh));
+    if constexpr (X3) {
+      split3(v, sVh[w * VS + m], sVm[w * VS + m], sVl[w * VS + m]);
+      split3(x, sUh[w * VS + m], sUm[w * VS + m], sUl[w * VS + m]);
+    } else {
+      const __bf16 vh = to_bf(v), xh = to_bf(x);
+      sVh[w * VS + m] = vh;
+      sVl[w * VS + m] = to_bf(v - from_bf(vh));
+      sUh[w * VS + m] = xh;
+      sUl[w * VS + m] = to_bf(x - from_bf(xh));
+    }
   }
   for (int e = tid; e < BM; e += NT) sN2[e] = m0 + e < n ? nrm[m0 + e] * cnorm : 0.0f;
 
   f4 acc[MB][NB];
-  dist_tile(acc, sAB, sAB + 2 * BM * RS, Xb, Xb, n0, n, m0, m_end, DPB, tid, wm, wn, g, r);
+  dist_tile(acc, sAB, sAB + 2 * BM * RS, Xb, Xb, Xl, Xl, nph, n0, n, m0, m_end, DPB, tid, wm,
+            wn, g, r);
 
   __bf16* Th = sAB + wave * TWAVE;     // this wave's transpose scratch, [32 m][TS]
   __bf16* Tl = Th + 32 * TS;
+  float* Tf = reinterpret_cast<float*>(Th);   // X3: K values in FP32, [32 m][TSF]
   f4 out[NB], out2[MB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) out[nb] = f4{0, 0, 0, 0};
@@ -367,37 +445,51 @@ kv_bf16_sym(const __bf16* __restrict__ Xb, const float* __restrict__ nrm, int64_
     const int ma = wm * TMW + mba * 16 + 4 * g, mbm = wm * TMW + mbb * 16 + 4 * g;
     const f4 na = *reinterpret_cast<const f4*>(&sN2[ma]);
     const f4 nbv = *reinterpret_cast<const f4*>(&sN2[mbm]);
-    bf8 vh, vl;
+    bf8 vh, vl, vm;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       vh[t] = sVh[r * VS + ma + t];
       vl[t] = sVl[r * VS + ma + t];
       vh[4 + t] = sVh[r * VS + mbm + t];
       vl[4 + t] = sVl[r * VS + mbm + t];
+      if constexpr (X3) {
+        vm[t] = sVm[r * VS + ma + t];
+        vm[4 + t] = sVm[r * VS + mbm + t];
+      }
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      bf8 kh, kl;
+      bf8 kh, kl, km;
+      float kf[8];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const float ka = kt_bf<KIND>(__builtin_fmaf(acc[mba][nb][t], cdot, n1v[nb] + na[t]));
         const float kb = kt_bf<KIND>(__builtin_fmaf(acc[mbb][nb][t], cdot, n1v[nb] + nbv[t]));
-        const __bf16 ha = to_bf(ka), hb = to_bf(kb);
-        kh[t] = ha;
-        kh[4 + t] = hb;
-        kl[t] = to_bf(ka - from_bf(ha));
-        kl[4 + t] = to_bf(kb - from_bf(hb));
+        kf[t] = ka;
+        kf[4 + t] = kb;
+        if constexpr (X3) {
+          split3_at(ka, kh, km, kl, t);
+          split3_at(kb, kh, km, kl, 4 + t);
+        } else {
+          const __bf16 ha = to_bf(ka), hb = to_bf(kb);
+          kh[t] = ha;
+          kh[4 + t] = hb;
+          kl[t] = to_bf(ka - from_bf(ha));
+          kl[4 + t] = to_bf(kb - from_bf(hb));
+        }
       }
-      out[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vh, out[nb], 0, 0, 0);
-      out[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, vl, out[nb], 0, 0, 0);
-      out[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kl, vh, out[nb], 0, 0, 0);
+      out[nb] = contract<X3>(kh, km, kl, vh, vm, vl, out[nb]);
       if (!diag) {
         // K[n = nb*16 + r][m = sub*16 + 4g + t] -> scratch row m, column n
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
           const int row = (t >> 2) * 16 + 4 * g + (t & 3);
-          Th[row * TS + nb * 16 + r] = kh[t];
-          Tl[row * TS + nb * 16 + r] = kl[t];
+          if constexpr (X3) {
+            Tf[row * TSF + nb * 16 + r] = kf[t];
+          } else {
+            Th[row * TS + nb * 16 + r] = kh[t];
+            Tl[row * TS + nb * 16 + r] = kl[t];
+          }
         }
       }
     }
@@ -407,14 +499,27 @@ kv_bf16_sym(const __bf16* __restrict__ Xb, const float* __restrict__ nrm, int64_
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
           const int col = ks * 32 + 8 * g;
-          const bf8 bh = *reinterpret_cast<const bf8*>(&Th[(sub * 16 + r) * TS + col]);
-          const bf8 bl = *reinterpret_cast<const bf8*>(&Tl[(sub * 16 + r) * TS + col]);
+          f4& o = out2[2 * p + sub];
           const bf8 ah = *reinterpret_cast<const bf8*>(&sUh[r * VS + wn * TNW + col]);
           const bf8 al = *reinterpret_cast<const bf8*>(&sUl[r * VS + wn * TNW + col]);
-          f4& o = out2[2 * p + sub];
-          o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, o, 0, 0, 0);
-          o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, o, 0, 0, 0);
-          o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, o, 0, 0, 0);
+          if constexpr (X3) {
+            const bf8 am = *reinterpret_cast<const bf8*>(&sUm[r * VS + wn * TNW + col]);
+            const f4 k0 = *reinterpret_cast<const f4*>(&Tf[(sub * 16 + r) * TSF + col]);
+            const f4 k1 = *reinterpret_cast<const f4*>(&Tf[(sub * 16 + r) * TSF + col + 4]);
+            bf8 bh, bm, bl;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              split3_at(k0[t], bh, bm, bl, t);
+              split3_at(k1[t], bh, bm, bl, 4 + t);
+            }
+            o = contract<true>(ah, am, al, bh, bm, bl, o);
+          } else {
+            const bf8 bh = *reinterpret_cast<const bf8*>(&Th[(sub * 16 + r) * TS + col]);
+            const bf8 bl = *reinterpret_cast<const bf8*>(&Tl[(sub * 16 + r) * TS + col]);
+            o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, o, 0, 0, 0);
+            o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, o, 0, 0, 0);
+            o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, o, 0, 0, 0);
+          }
         }
     }
   }
@@ -466,10 +571,11 @@ kv_bf16_sym(const __bf16* __restrict__ Xb, const float* __restrict__ nrm, int64_
 }
 
 // Centred rows rounded to BF16 (zero-padded to DPB features) and the squared
-// norms of the rounded rows.
+// norms of the rounded rows.  With Xl (split mode) the low parts
+// l = bf16(x - h) go to Xl and the norms are those of h + l.
 __global__ void k_prep_rows_bf16(const float* __restrict__ X, int64_t n, int d, int DPB,
                                  const float* __restrict__ centre, __bf16* __restrict__ Xb,
-                                 float* __restrict__ norms) {
+                                 __bf16* __restrict__ Xl, float* __restrict__ norms) {
   const int64_t i = blockIdx.x;
   if (i >= n) return;
   __shared__ float red[4];
@@ -479,7 +585,12 @@ __global__ void k_prep_rows_bf16(const float* __restrict__ X, int64_t n, int d, 
     if (k < d) v = X[i * d + k] - (centre ? centre[k] : 0.0f);
     const __bf16 b = static_cast<__bf16>(v);
     Xb[i * DPB + k] = b;
-    const float fb = static_cast<float>(b);
+    float fb = static_cast<float>(b);
+    if (Xl) {
+      const __bf16 l = static_cast<__bf16>(v - fb);
+      Xl[i * DPB + k] = l;
+      fb += static_cast<float>(l);
+    }
     s += fb * fb;
   }
   s = block_sum(s, red);
@@ -534,12 +645,13 @@ size_t bf16_partial_bytes(int64_t n1, int64_t n2, int64_t W, bool fixed) {
   return b;
 }
 
-int prep_rows_bf16(const float* X, int64_t n, int64_t d, const float* centre, void* Xb,
-                   float* norms, hipStream_t s) {
+int prep_rows_bf16(int precision, const float* X, int64_t n, int64_t d, const float* centre,
+                   void* Xb, float* norms, hipStream_t s) {
   if (n == 0) return IGP_OK;
+  __bf16* H = static_cast<__bf16*>(Xb);
+  __bf16* Lo = precision == IGP_BF16X3 ? H + n * bf16_padded_dim(d) : nullptr;
   k_prep_rows_bf16<<<static_cast<unsigned>(n), 256, 0, s>>>(
-      X, n, static_cast<int>(d), static_cast<int>(bf16_padded_dim(d)), centre,
-      static_cast<__bf16*>(Xb), norms);
+      X, n, static_cast<int>(d), static_cast<int>(bf16_padded_dim(d)), centre, H, Lo, norms);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
@@ -581,16 +693,31 @@ int kv_bf16_launch(const KVProblem& p, const void* X1b, const float* n1p, const 
   const int DPB = static_cast<int>(bf16_padded_dim(p.d));
   const __bf16* A1 = static_cast<const __bf16*>(X1b);
   const __bf16* A2 = static_cast<const __bf16*>(X2b);
+  // split mode: the low parts follow the high parts of each prepared set
+  const int nph = p.precision == IGP_BF16X3 ? 3 : 1;
+  const __bf16* L1 = nph == 3 ? A1 + p.n1 * DPB : A1;
+  const __bf16* L2 = nph == 3 ? A2 + p.n2 * DPB : A2;
   const float* V = static_cast<const float*>(p.V);
   const int C = static_cast<int>(p.C), Wi = static_cast<int>(W);
   const unsigned sym_grid = static_cast<unsigned>(Q * (Q + 1) / 2);
   auto go = [&](auto kind) {
-    if (Q > 0)
-      kv_bf16_sym<decltype(kind)::value><<<sym_grid, NT, 0, s>>>(
-          A1, n1p, p.n1, DPB, V, C, Wi, p.ldv, P, static_cast<int>(Q), cnorm, cdot, p.skip);
+    constexpr int K_ = decltype(kind)::value;
+    if (Q > 0 && nph == 3)
+      kv_bf16_sym<K_, true><<<sym_grid, NT, 0, s>>>(
+          A1, n1p, L1, nph, p.n1, DPB, V, C, Wi, p.ldv, P, static_cast<int>(Q), cnorm, cdot,
+          p.skip);
+    else if (Q > 0)
+      kv_bf16_sym<K_, false><<<sym_grid, NT, 0, s>>>(
+          A1, n1p, L1, nph, p.n1, DPB, V, C, Wi, p.ldv, P, static_cast<int>(Q), cnorm, cdot,
+          p.skip);
+    else if (nph == 3)
+      kv_bf16_kernel<K_, true><<<grid, NT, 0, s>>>(
+          A1, n1p, A2, n2p, L1, L2, nph, p.n1, p.n2, DPB, V, C, Wi, p.ldv, P, pl.cols_per_split,
+          pl.gx, pl.nsplit, cnorm, cdot, p.skip);
     else
-      kv_bf16_kernel<decltype(kind)::value><<<grid, NT, 0, s>>>(
-          A1, n1p, A2, n2p, p.n1, p.n2, DPB, V, C, Wi, p.ldv, P, pl.cols_per_split, pl.gx,
+      kv_bf16_kernel<K_, false><<<grid, NT, 0, s>>>(
+          A1, n1p, A2, n2p, L1, L2, nph, p.n1, p.n2, DPB, V, C, Wi, p.ldv, P, pl.cols_per_split,
+          pl.gx,
           pl.nsplit, cnorm, cdot, p.skip);
   };
   switch (p.kp.kind) {

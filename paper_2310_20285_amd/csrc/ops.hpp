@@ -137,8 +137,14 @@ float kv_kappa(int kind);
 // BF16 matrix-core kernel product (kv_bf16.hip): rows rounded to BF16, padded
 // to a multiple of 32 features, norms of the rounded rows.
 int64_t bf16_padded_dim(int64_t d);
+// the BF16 matrix-core modes (plain, and hi/lo split of the inputs)
+inline bool is_bf16(int precision) { return precision == IGP_BF16 || precision == IGP_BF16X3; }
+// BF16 elements of n prepared rows: the high parts, then (IGP_BF16X3) the low parts
+inline int64_t bf16_rows_elems(int precision, int64_t n, int64_t d) {
+  return n * bf16_padded_dim(d) * (precision == IGP_BF16X3 ? 2 : 1);
+}
 size_t bf16_partial_bytes(int64_t n1, int64_t n2, int64_t W, bool fixed = false);
-int prep_rows_bf16(const float* X, int64_t n, int64_t d, const float* centre, void* Xb,
+int prep_rows_bf16(int precision, const float* X, int64_t n, int64_t d, const float* centre, void* Xb,
                    float* norms, hipStream_t s);
 int kv_bf16_launch(const KVProblem& p, const void* X1b, const float* n1p, const void* X2b,
                    const float* n2p, float* P, size_t P_bytes, hipStream_t s, int* nsplit_out);
