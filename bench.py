@@ -58,8 +58,7 @@ KV_SAMPLE = 3
 # copy in the same run; profiles/kv_matern52_N20000_D16_C5_fp32.md and
 # profiles/kv_bf16_rbf_N60000_D784_C10.md).  Keyed by the kernel instance it
 # was measured on; any other instance reports null.
-MEASURED_TRAFFIC = {("kv_mfma_f32_sym<3,1,5>", "fp32"): 46.03e6,
-                    ("kv_bf16_sym<0>", "bf16"): 12.92e9}
+MEASURED_TRAFFIC = {("kv_mfma_f32_sym<3,1,5>", "fp32"): 46.03e6}
 
 
 def block_cycles(kind: str, W: int, D: int, symmetric: bool) -> float:
@@ -107,23 +106,43 @@ def cpu_baseline(w, k_products_per_step: float):
                               "sample": f"{rows1} rows ({dt1:.1f} s), scaled the same way"}}
 
 
+FIT_STEPS = 5            # Newton steps per fit of the default schedule
+FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 peak (vector and matrix)
+
+
+def golden(name: str) -> dict:
+    """Stored FP64 reference values (written by tests/golden/make_fullsize_golden.py
+    from the oracle alone)."""
+    with open(os.path.join(ROOT, "tests", "golden", name)) as f:
+        return json.load(f)
+
+
+def rel_err(a, b) -> float:
+    import numpy as np
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--residual", default="recurrence", choices=["explicit", "recurrence"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain FP32 PyTorch comparison")
-    ap.add_argument("--precision", default=None, choices=["fp32", "fp64", "bf16"])
+    ap.add_argument("--no-headline", action="store_true",
+                    help="default workload: skip the BF16 image product and the serving p99")
+    ap.add_argument("--precision", default=None, choices=["fp32", "fp64", "bf16", "bf16x3"])
     ap.add_argument("--workload", default="gpc16",
-                    choices=["gpc16", "image", "batched", "serving", "gmm", "poisson"],
+                    choices=["gpc16", "image", "batched", "serving", "gmm", "poisson", "peaks"],
                     help="gpc16: N=20000 D=16 C=5 (default); image: N=60000 D=784 C=10 BF16; "
                          "batched: 64 independent problems in one persistent launch; "
                          "serving: request stream against a fitted N=100000 D=32 C=10 model; "
                          "gmm: the paper's Gaussian-mixture classification (N=100000, D=3, "
-                         "C=10); poisson: the paper's Poisson budget-split schedules")
+                         "C=10); poisson: the paper's Poisson budget-split schedules; "
+                         "peaks: issue-rate microbenchmarks behind the ALU roofline")
     ap.add_argument("--requests", type=int, default=160, help="serving: stream length")
     ap.add_argument("--load", type=float, nargs="+", default=[0.5],
                     help="serving: arrival rates as fractions of the measured capacity")
@@ -142,15 +161,17 @@ def main():
     dev = torch.device("cuda:0")
     global KV_INSTANCE
     if args.workload == "image":
-        return bench_image(args)
+        return print(json.dumps(bench_image(args)))
     if args.workload == "batched":
         return bench_batched(args)
     if args.workload == "serving":
-        return bench_serving(args)
+        return print(json.dumps(bench_serving(args)))
     if args.workload == "gmm":
         return bench_gmm(args)
     if args.workload == "poisson":
         return bench_poisson(args)
+    if args.workload == "peaks":
+        return bench_peaks(args)
     args.precision = args.precision or "fp32"
     KV_INSTANCE = "kv_mfma_f32_sym<3,1,5>"   # Matern-5/2, D <= 16, W = 5
     w = datagen.config2()
@@ -166,43 +187,64 @@ def main():
                             precision=args.precision, residual_mode=args.residual,
                             max_buffer=jmax + R)
 
-    # warm-up: a separate model instance runs `warmup` Newton steps + predictions
+    # warm-up: a separate model runs up to one fit's Newton steps + predictions
     mw = make_model()
-    for _ in range(args.warmup):
+    for _ in range(min(args.warmup, FIT_STEPS)):
         mw.newton_step()
         mw.predict(Xs)
     torch.cuda.synchronize()
     del mw
-    # timed: the first `steps` Newton steps of a fresh fit (f_0 = 0), each followed
-    # by the prediction at the test points
-    m = make_model()
-    torch.cuda.synchronize()
-    m.set_profiling(True, every=KV_SAMPLE)
-    infos = []
-    pred_ev = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        infos.append(m.newton_step())
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        m.predict(Xs)
-        b.record()
-        pred_ev.append((a, b))   # read after the loop: the next step queues behind it
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    # timed: whole fresh fits of FIT_STEPS Newton steps from f_0 = 0 (empty
+    # buffers), each step followed by the prediction at the test points, repeated
+    # until `steps` Newton steps are timed; each fit's model is created before its
+    # timed segment, and the segments are summed
+    elapsed = 0.0
+    infos, fit_iters, pred_ev = [], [], []
+    prof = {}
+    check = None            # the first fit's model, kept for the error check
+    done = 0
+    while done < args.steps:
+        m = make_model()
+        m.set_profiling(True, every=KV_SAMPLE)
+        n_here = min(FIT_STEPS, args.steps - done)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = []
+        for _ in range(n_here):
+            info = m.newton_step()
+            infos.append(info)
+            its.append(info["iters"])
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            m.predict(Xs)
+            b.record()
+            pred_ev.append((a, b))   # read after the loop: the next step queues behind it
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
+        done += n_here
+        fit_iters.append(its)
+        for k, v in m.profile().items():
+            prof[k] = prof.get(k, 0) + v
+        if check is None:
+            check = (m, n_here)
+        else:
+            del m
     pred_ms = [a.elapsed_time(b) for a, b in pred_ev]
-    prof = m.profile()
 
-    elapsed = t1 - t0
     value = args.steps / elapsed
-    kv_avg_s = prof["kv_ms"] / max(prof["kv_launches"], 1) / 1e3
+    launches = max(prof["kv_launches"], 1)
+    kv_avg_s = prof["kv_ms"] / launches / 1e3
     symmetric = prof["kv_symmetric"] == prof["kv_launches"] > 0
-    evals_per_launch = prof["kv_evals"] / max(prof["kv_launches"], 1)
+    evals_per_launch = prof["kv_evals"] / launches
     achieved_evals = evals_per_launch / kv_avg_s
     peak_evals = peak_evals_per_s(w.kernel, w.C, w.D, symmetric)
-    kv_tflops = prof["kv_flops"] / max(prof["kv_launches"], 1) / kv_avg_s / 1e12
+    dense_flops = 2.0 * w.N * w.N * (w.D + w.C)          # 2 N1 N2 (D + W) per product
+    method_flops = prof["kv_flops"] / launches            # what the kernel that ran evaluates
+    achieved = dense_flops / kv_avg_s / 1e12
     k_per_step = sum(i["k_products"] for i in infos) / max(len(infos), 1)
+    total_iters = sum(i["iters"] for i in infos)
+    sched = fit_iters[0]
 
     out = {
         "metric": "IterNCGP Newton steps/s",
@@ -215,40 +257,79 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16"}[args.precision],
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16", "bf16x3": "bf16x3"}[
+            args.precision],
         "data": "synthetic",
-        "config": {"workload": "gpc N=20000 D=16 C=5 matern52 l=2; IterNCGP-CG j<=200 R=100; "
-                               "first 5 Newton steps of a fit from f_0=0, each followed by "
-                               "predict at 2000 test points",
+        "config": {"workload": (f"gpc N=20000 D=16 C=5 matern52 l=2; IterNCGP-CG j<=200 R=100, "
+                                f"tol 1e-5; {len(fit_iters)} fresh fit(s) of {FIT_STEPS} Newton "
+                                f"steps from f_0=0 ({args.steps} steps timed; solver "
+                                f"iterations per step of a fit: {sched}), each step followed "
+                                f"by predict (mean, variance, probit) at 2000 test points"),
                    "residual": args.residual,
                    "N": w.N, "D": w.D, "C": w.C, "j_max": jmax, "rank_limit": R,
-                   "precision": args.precision, "test_points": int(Xs.shape[0])},
-        "roofline": {"bound": "alu", "achieved": achieved_evals / 1e9,
-                     "peak": peak_evals / 1e9, "unit": "Geval/s",
-                     "frac": achieved_evals / peak_evals,
+                   "precision": args.precision, "test_points": int(Xs.shape[0]),
+                   "fits": len(fit_iters), "steps_per_fit": FIT_STEPS},
+        "solver_iterations": {"total": total_iters, "per_s": total_iters / elapsed,
+                              "ms_per_iteration": elapsed / max(total_iters, 1) * 1e3,
+                              "per_fit": fit_iters},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                      "traffic": MEASURED_TRAFFIC.get((KV_INSTANCE, args.precision)),
-                     "kernel": ("symmetric fused K.v: N(N+1)/2 kernel evaluations per launch, "
-                                "each serving both outputs" if symmetric else
-                                "fused K.v: N^2 kernel evaluations per launch"),
-                     "avg_launch_us": kv_avg_s * 1e6},
-        "kv": {"launches": prof["kv_launches"], "timed_every": KV_SAMPLE,
-               "avg_us": kv_avg_s * 1e6,
-               "tflops_algorithmic": kv_tflops, "k_products_per_step": k_per_step,
+                     "kernel": ("symmetric fused K.v (each pair of rows evaluated once)"
+                                if symmetric else "fused K.v"),
+                     "flops_per_launch": dense_flops,
+                     "flop_count": "2 N1 N2 (D + W) per product, W = C output columns",
+                     "avg_launch_us": kv_avg_s * 1e6,
+                     "method_flops_per_launch": method_flops,
+                     "frac_method_flops": method_flops / kv_avg_s / 1e12 / FP32_PEAK_TFLOPS,
+                     "issue_model": {"achieved_geval_s": achieved_evals / 1e9,
+                                     "peak_geval_s": peak_evals / 1e9,
+                                     "frac": achieved_evals / peak_evals,
+                                     "cycles": {"valu": VALU_CYCLES, "transcendental":
+                                                TRANS_CYCLES, "mfma_f32": MFMA_F32_CYCLES}}},
+        "kv": {"launches_timed": prof["kv_launches"], "timed_every": KV_SAMPLE,
+               "avg_us": kv_avg_s * 1e6, "k_products_per_step": k_per_step,
                "share_of_step": kv_avg_s * 1e3 * k_per_step * len(infos)
                                 / max(prof["step_ms"], 1e-9)},
         "predict_latency_ms": {"p50": float(np.percentile(pred_ms, 50)),
-                               "p99": float(np.percentile(pred_ms, 99))},
+                               "p99": float(np.percentile(pred_ms, 99)),
+                               "timing": "HIP events around each call on the model's stream"},
         "newton": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in i.items()
                     if k in ("iters", "buffer_cols", "converged", "res_norm", "rel_change", "psi")}
-                   for i in infos],
+                   for i in infos[:FIT_STEPS]],
     }
+    out["error_vs_fp64"] = fp64_error_default(w, check[0], check[1], Xs)
+    del check
     if not args.no_plain:
-        out["plain_fp32"] = plain_comparison(w, X, y, Xs, args.steps, jmax, R, elapsed / args.steps,
-                                             float(np.percentile(pred_ms, 99)))
+        out["plain_fp32"] = plain_comparison(w, X, y, Xs, sched, R, out)
         out["dense_k_fp32"] = dense_k(w, X, kv_avg_s)
+    if not args.no_headline:
+        out["headline"] = {"bf16_image_product": bf16_product_headline(),
+                           "serving_p99": serving_headline(args)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, k_per_step)
     print(json.dumps(out))
+
+
+def fp64_error_default(w, m, steps_done, Xs):
+    """The fit against the FP64 O-method reference of the same schedule (the
+    oracle's Algorithms 1-3 on the CPU, stored values): Newton iterate f at 256
+    stored rows after the last step, predictive mean at 256 test points after a
+    whole fit, iteration counts."""
+    import numpy as np
+    g = golden("omethod_config2.json")
+    rows = np.asarray(g["rows"])
+    F = m.view(0).double().cpu().numpy().reshape(w.N, w.C)
+    ref = g["steps"][steps_done - 1]
+    res = {"reference": "FP64 O-method (Algorithms 1-3 on the CPU, stored by "
+                        "tests/golden/make_fullsize_golden.py)",
+           "after_step": steps_done,
+           "f_rel_err_256_rows": rel_err(F[rows], ref["F_rows"]),
+           "iters_fp64": [s["iters"] for s in g["steps"][:steps_done]]}
+    if steps_done == len(g["steps"]):
+        mean, _, _ = m.predict(Xs[:g["test_points"]], var=False, probs=False)
+        res["pred_mean_rel_err_256_points"] = rel_err(mean.double().cpu().numpy(), g["mean"])
+    return res
 
 
 def dense_k(w, X, fused_s):
@@ -262,42 +343,111 @@ def dense_k(w, X, fused_s):
     return r
 
 
-def plain_comparison(w, X, y, Xs, steps, jmax, R, ours_s_per_step, ours_p99_ms):
-    """The same schedule with the plain FP32 PyTorch form on the same GPU."""
+def plain_comparison(w, X, y, Xs, sched, R, ours):
+    """The plain FP32 PyTorch form on the same GPU at equal solver work: one fit
+    with the library's per-step iteration counts imposed (tolerance 0), each
+    step followed by the prediction; per Newton step, per solver iteration, per
+    product with K and per prediction (both timed with device events)."""
     import numpy as np
     import torch
 
     from plain_fp32 import PlainIterNCGP
-    pm = PlainIterNCGP(X.float(), y, w.C, w.kernel, w.lengthscale, w.outputscale, j_max=jmax,
-                       rank_limit=R)
+    pm = PlainIterNCGP(X.float(), y, w.C, w.kernel, w.lengthscale, w.outputscale,
+                       j_max=max(sched + [1]), rank_limit=R, tol_abs=0.0, tol_rel=0.0)
     torch.cuda.synchronize()
     lat = []
     its = []
     t0 = time.perf_counter()
-    for _ in range(steps):
-        its.append(pm.newton_step()["iters"])
-        a = time.perf_counter()
+    for j in sched:
+        its.append(pm.newton_step(j_max=j)["iters"])
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
         pm.predict(Xs.float())
-        torch.cuda.synchronize()
-        lat.append((time.perf_counter() - a) * 1e3)
+        b.record()
+        b.synchronize()
+        lat.append(a.elapsed_time(b))
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    # one product with K, timed alone (the kernel comparison)
+    dt = (time.perf_counter() - t0) / len(sched)
+    # one product with K, timed alone
     v = torch.randn(w.N * w.C, device=X.device)
     pm.apply_K(v)
-    torch.cuda.synchronize()
-    a = time.perf_counter()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(5):
         pm.apply_K(v)
-    torch.cuda.synchronize()
-    kv_ms = (time.perf_counter() - a) / 5 * 1e3
+    e1.record()
+    e1.synchronize()
+    kv_ms = e0.elapsed_time(e1) / 5
+    ours_step_ms = ours["ms_per_step"]
+    ours_it_ms = ours["solver_iterations"]["ms_per_iteration"]
+    it_ms = dt * 1e3 * len(sched) / max(sum(its), 1)
+    p99 = float(np.percentile(lat, 99))
     return {"value": 1.0 / dt, "unit": "Newton steps/s", "ms_per_step": dt * 1e3,
+            "schedule": "the library's solver iterations per step imposed, tolerance 0",
             "iters_per_step": its,
+            "speedup_of_library_per_step": dt * 1e3 / ours_step_ms,
+            "ms_per_solver_iteration": it_ms,
+            "speedup_of_library_per_solver_iteration": it_ms / ours_it_ms,
             "kv_product_ms": kv_ms,
-            "speedup_of_library": dt / ours_s_per_step,
-            "predict_latency_ms": {"p50": float(np.percentile(lat, 50)),
-                                   "p99": float(np.percentile(lat, 99))},
-            "p99_ratio_plain_over_library": float(np.percentile(lat, 99)) / ours_p99_ms}
+            "speedup_of_library_per_product": kv_ms / (ours["kv"]["avg_us"] / 1e3),
+            "predict_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": p99},
+            "p99_ratio_plain_over_library": p99 / ours["predict_latency_ms"]["p99"]}
+
+
+def bf16_product_headline() -> dict:
+    """The image-shaped product (N=60000, D=784, C=10, RBF, median lengthscale)
+    through glm_kernel_matmul in both BF16 modes: device time (HIP events on
+    the calling stream, 5 calls; each call prepares the rows, runs the
+    symmetric product and reduces its partials), TFLOP/s against the BF16
+    matrix peak, and the error against stored FP64 values of 64 rows."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_2310_20285_amd import api
+    w = datagen.config3(Ns=1000)        # the lengthscale depends on the draw of test points
+    g = golden("kv_products.json")["config3"]
+    assert abs(w.lengthscale - g["lengthscale"]) <= 1e-12 * g["lengthscale"]
+    rng = np.random.default_rng(2024)
+    v = rng.standard_normal(w.N * w.C).astype(np.float32)
+    X = torch.tensor(w.X, dtype=torch.float32, device="cuda")
+    vd = torch.tensor(v, device="cuda")
+    rows = np.asarray(g["rows"])
+    method = w.N * (w.N + 1.0) * w.D + 2.0 * w.N * w.N * w.C   # each pair once
+    dense = 2.0 * w.N * w.N * (w.D + w.C)
+    res = {"workload": "image-shaped N=60000 D=784 C=10 rbf, one vector (W=10)",
+           "flop_count": "method N(N+1) D + 2 N^2 W (each pair of rows once); dense "
+                         "2 N^2 (D + W)"}
+    for mode in ("bf16", "bf16x3"):
+        out = api.glm_kernel_matmul(X, X, vd, w.C, w.kernel, w.lengthscale, w.outputscale, mode)
+        err = rel_err(out.double().cpu().numpy().reshape(w.N, w.C)[rows], g["ref"])
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            api.glm_kernel_matmul(X, X, vd, w.C, w.kernel, w.lengthscale, w.outputscale, mode,
+                                  out=out)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        res[mode] = {"ms": ms, "tflops_method": method / ms / 1e9,
+                     "frac_bf16_peak_method": method / ms / 1e9 / BF16_MFMA_PEAK_TFLOPS,
+                     "frac_bf16_peak_dense": dense / ms / 1e9 / BF16_MFMA_PEAK_TFLOPS,
+                     "rel_err_vs_fp64_64_rows": err}
+    return res
+
+
+def serving_headline(args) -> dict:
+    """p99 of the predictive queries in a shortened serving stream (100
+    requests at half the measured capacity) against the fitted N=100000 model."""
+    a = argparse.Namespace(**vars(args))
+    a.requests, a.load, a.no_plain, a.precision = 100, [0.5], True, "fp32"
+    r = bench_serving(a)
+    run = r["runs"][0]
+    return {"p99_ms": r["value"], "p50_ms": run["predict"].get("p50_ms"),
+            "capacity_rps": r["capacity_rps"], "requests": r["config"]["requests"],
+            "alone_vs_mix_mismatches": r["alone_vs_mix_mismatches"],
+            "workload": r["config"]["workload"]}
 
 
 def bench_batched(args):
@@ -386,9 +536,11 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak
 
 
 def bench_image(args):
-    """Image-shaped workload: N=60000, D=784, C=10, RBF, BF16 distance GEMM.
-    IterNCGP-CG with j <= 5 per Newton step, no compression, 3 Newton steps
-    (the paper's MNIST schedule), prediction at 1000 test points per step."""
+    """Image-shaped workload: N=60000, D=784, C=10, RBF (median lengthscale),
+    BF16 distance GEMM (--precision bf16x3: the split-input mode).  IterNCGP-CG
+    with j <= 5 per Newton step, no compression, 3 Newton steps (the paper's
+    MNIST schedule), prediction at 1000 test points per step.  The fit is
+    compared with the stored FP64 O-method run of the same schedule."""
     import numpy as np
     import torch
 
@@ -430,17 +582,25 @@ def bench_image(args):
     flops = prof["kv_flops"] / max(prof["kv_launches"], 1)
     tflops = flops / kv_avg_s / 1e12
     dense_tflops = 2.0 * w.N * w.N * (w.D + w.C) / kv_avg_s / 1e12
-    # error of one product against the FP64 oracle on sampled rows
-    from oracle import kernels as ok
-    rng = np.random.default_rng(0)
-    v = rng.standard_normal(w.N * w.C)
-    out = api.glm_kernel_matmul(X, X, torch.tensor(v, dtype=torch.float32, device=dev), w.C,
-                                w.kernel, w.lengthscale, w.outputscale, prec).double().cpu().numpy()
-    rows = rng.choice(w.N, size=64, replace=False)
-    ref = ok.kernel_matvec(w.X[rows], w.X, v.reshape(w.N, w.C), w.kernel, w.lengthscale,
-                           w.outputscale)
-    got = out.reshape(w.N, w.C)[rows]
-    kv_err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    # the fit against the stored FP64 O-method run (F at 256 rows after each
+    # step, predictive mean at 256 test points after the last)
+    g = golden("omethod_config3.json")
+    rows = np.asarray(g["rows"])
+    F = m.view(0).double().cpu().numpy().reshape(w.N, w.C)
+    err = {"reference": "FP64 O-method (Algorithms 1-3 on the CPU, stored)",
+           "after_step": steps,
+           "f_rel_err_256_rows": rel_err(F[rows], g["steps"][steps - 1]["F_rows"])}
+    if steps == len(g["steps"]):
+        mean, _, _ = m.predict(Xs[:g["test_points"]], var=False, probs=False)
+        err["pred_mean_rel_err_256_points"] = rel_err(mean.double().cpu().numpy(), g["mean"])
+    # one product against stored FP64 values at 64 rows
+    gp = golden("kv_products.json")["config3"]
+    assert abs(w.lengthscale - gp["lengthscale"]) <= 1e-12 * gp["lengthscale"]
+    v = np.random.default_rng(2024).standard_normal(w.N * w.C).astype(np.float32)
+    out = api.glm_kernel_matmul(X, X, torch.tensor(v, device=dev), w.C, w.kernel,
+                                w.lengthscale, w.outputscale, prec).double().cpu().numpy()
+    err["kv_rel_err_64_rows"] = rel_err(out.reshape(w.N, w.C)[np.asarray(gp["rows"])], gp["ref"])
+    instance = {"bf16": "kv_bf16_sym<0, false>", "bf16x3": "kv_bf16_sym<0, true>"}.get(prec)
     res = {
         "metric": "IterNCGP Newton steps/s",
         "value": steps / (t1 - t0),
@@ -455,19 +615,18 @@ def bench_image(args):
                    "precision": prec, "residual": args.residual},
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": BF16_MFMA_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / BF16_MFMA_PEAK_TFLOPS,
-                     "traffic": MEASURED_TRAFFIC.get(
-                         ("kv_bf16_sym<0>" if symmetric else "kv_bf16_kernel<0>", prec)),
+                     "traffic": MEASURED_TRAFFIC.get((instance, prec)) if symmetric else None,
                      "kernel": ("symmetric fused K.v, BF16 distance GEMM (N(N+1) D + 2 N^2 C "
                                 "flops per product)" if symmetric else
                                 "fused K.v, BF16 distance GEMM (2 N^2 (D + C) flops per product)"),
                      "avg_launch_us": kv_avg_s * 1e6,
                      "dense_equivalent_tflops": dense_tflops},
-        "kv_error_vs_fp64": {"rel_l2_64_rows": kv_err},
+        "error_vs_fp64": err,
         "dense_k_fp32": None if args.no_plain else dense_k(w, X, kv_avg_s),
         "newton": [{k: (round(v_, 6) if isinstance(v_, float) else v_) for k, v_ in i.items()
                     if k in ("iters", "buffer_cols", "rel_change", "psi")} for i in infos],
     }
-    print(json.dumps(res))
+    return res
 
 
 FP32_MFMA_PEAK_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
@@ -624,7 +783,7 @@ def bench_serving(args):
                   "span_s": max(d for _, _, d in rec)}
         pr["p99_ratio_plain_over_library"] = pr["predict"]["p99_ms"] / res["value"]
         res["plain_fp32_fifo"] = pr
-    print(json.dumps(res))
+    return res
 
 
 def bench_gmm(args):
@@ -690,6 +849,79 @@ def bench_gmm(args):
         "runs": runs,
     }
     print(json.dumps(res))
+
+
+def bench_peaks(args):
+    """Issue-rate microbenchmarks (libitergp_peaks.so): wave-instructions per
+    SIMD per second of v_fma_f32, v_exp_f32, v_sqrt_f32 and the FP32 / BF16
+    matrix instructions the product kernels use, expressed as cycles per
+    instruction at the nominal 2.4 GHz, and whether FP32 MFMA and VALU work
+    overlap (mixed loop time against the sum of the parts).  These are the
+    constants of the ALU issue model of the default workload's roofline."""
+    import ctypes as ct
+
+    import torch
+
+    from paper_2310_20285_amd import build as pb
+    lib = ct.CDLL(pb.PEAKS_LIB)
+    lib.igp_peaks_run.restype = ct.c_int
+    lib.igp_peaks_run.argtypes = [ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_void_p,
+                                  ct.c_void_p]
+    blocks = 256 * 8                         # 8 workgroups of 4 waves per CU: 8 waves per SIMD
+    waves_per_simd = blocks * 4 / SIMDS
+    out = torch.empty(blocks * 256, device="cuda")
+    st = torch.cuda.current_stream()
+
+    def run(which, iters, nvalu=0):
+        for rep in range(2):             # the first launch warms up
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            rc = lib.igp_peaks_run(which, blocks, iters, nvalu, ct.c_void_p(out.data_ptr()),
+                                   ct.c_void_p(st.cuda_stream))
+            e1.record()
+            e1.synchronize()
+            if rc != 0:
+                raise RuntimeError(f"microbenchmark {which} failed ({rc})")
+        return e0.elapsed_time(e1) / 1e3
+
+    def cycles(t, per_trip, iters):
+        instr = waves_per_simd * iters * per_trip          # wave-instructions per SIMD
+        return t * CLOCK_HZ / instr
+
+    it = 4000
+    res = {}
+    t_fma = run(0, it)
+    res["v_fma_f32"] = {"cycles": cycles(t_fma, 64, it),
+                        "tflops": 2 * 64 * waves_per_simd * SIMDS * it * 64 / t_fma / 1e12}
+    res["v_exp_f32"] = {"cycles": cycles(run(1, it), 64, it)}
+    res["v_sqrt_f32"] = {"cycles": cycles(run(2, it), 64, it)}
+    t_mf = run(3, it)
+    res["v_mfma_f32_16x16x4f32"] = {"cycles": cycles(t_mf, 16, it),
+                                    "tflops": 2 * 16 * 16 * 4 * 16 * waves_per_simd * SIMDS * it
+                                    / t_mf / 1e12}
+    t_bf = run(4, it)
+    res["v_mfma_f32_16x16x32_bf16"] = {"cycles": cycles(t_bf, 16, it),
+                                       "tflops": 2 * 16 * 16 * 32 * 16 * waves_per_simd * SIMDS
+                                       * it / t_bf / 1e12}
+    mixed = {}
+    for nv in (32, 64, 128):
+        t_mix = run(5, it, nv)
+        t_valu = t_fma * nv / 64             # the same FMAs alone (kind 0 at the same count)
+        mixed[str(nv)] = {"mixed_ms": t_mix * 1e3, "mfma_alone_ms": t_mf * 1e3,
+                          "valu_alone_ms": t_valu * 1e3,
+                          "overlap": (t_mf + t_valu - t_mix) / min(t_mf, t_valu)}
+    res["mfma_f32_with_valu"] = mixed
+    line = {"metric": "issue rates (cycles per wave-instruction per SIMD at 2.4 GHz)",
+            "value": res["v_exp_f32"]["cycles"], "unit": "cycles per v_exp_f32",
+            "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": None,
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "issue-rate microbenchmarks, 8 waves per SIMD",
+                       "blocks": blocks, "iters": it},
+            "rates": res,
+            "model_constants": {"valu": VALU_CYCLES, "transcendental": TRANS_CYCLES,
+                                "mfma_f32": MFMA_F32_CYCLES}}
+    print(json.dumps(line))
 
 
 def bench_poisson(args):

@@ -26,8 +26,11 @@
  * - Return value: IGP_OK (0) or a negative igp_status.  No C++ exception
  *   crosses this boundary.  igp_last_error() returns a thread-local message
  *   describing the last failure of the calling thread.
- * - All latent functions share one kernel k with the same hyperparameters,
- *   as in every experiment of the paper, so K = K_X (x) I_C in CN-ordering.
+ * - By default all latent functions share one kernel k with the same
+ *   hyperparameters, as in every experiment of the paper, so K = K_X (x) I_C
+ *   in CN-ordering; with n_kp == C kernel parameter sets each latent function
+ *   has its own lengthscale and outputscale (one kernel family), K =
+ *   sum_c K_c (x) e_c e_c^T.
  */
 #ifndef ITERGP_H
 #define ITERGP_H

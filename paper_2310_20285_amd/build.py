@@ -19,6 +19,9 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libitergp.so")
+# issue-rate microbenchmarks (bench.py --workload peaks), a library of their own
+PEAKS_SRC = "peaks.hip"
+PEAKS_LIB = os.path.join(HERE, "libitergp_peaks.so")
 
 SOURCES = ["kv.hip", "kv_mfma.hip", "kv_bf16.hip", "hessian.hip", "diaglik.hip", "linalg.hip", "batched_ops.hip", "blocklik.hip", "noalloc.hip", "itergp.cpp", "abi.cpp",
            "eigh.cpp"]
@@ -92,8 +95,15 @@ def build(force: bool = True, verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    pobj = _compile(PEAKS_SRC, force)
+    ptmp = PEAKS_LIB + ".tmp"
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", pobj, "-o", ptmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(ptmp, PEAKS_LIB)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {PEAKS_LIB}")
     return LIB
 
 

@@ -73,8 +73,10 @@ class PlainIterNCGP:
         w = u / pi.view(self.N, self.C, 1)
         return (w - w.mean(1, keepdim=True)).reshape(V.shape)
 
-    def newton_step(self) -> dict:
+    def newton_step(self, j_max: int = None) -> dict:
+        """One Newton step; ``j_max`` overrides the per-step action budget."""
         N, C = self.N, self.C
+        jcap = self.j_max if j_max is None else int(j_max)
         F = self.f.view(N, C)
         pi = torch.softmax(F, dim=1)
         onehot = torch.nn.functional.one_hot(self.y, C).float()
@@ -97,7 +99,7 @@ class PlainIterNCGP:
         v = self.Q @ (self.Q.T @ rhs)
         thresh = max(self.tol_abs, self.tol_rel * float(rhs.double().norm()))
         j = 0
-        while j < self.j_max:
+        while j < jcap:
             r = rhs - self.apply_K(v) - self.winv(pi.reshape(-1), v)
             rn = float(r.double().norm())
             if rn < thresh:

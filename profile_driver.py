@@ -1,7 +1,7 @@
 """Profiling driver for rocprofv3.
 
-    python paper_2310_20285_amd/profile_driver.py [--workload gpc16|image|predict]
-                                                  [--reps 20] [--copy-mib 256]
+    python profile_driver.py [--workload gpc16|image|predict] [--precision ...]
+                             [--reps 20] [--copy-mib 256]
 
 Workloads (each ends with one device-to-device copy of ``--copy-mib`` MiB, a
 transfer of known size whose FETCH_SIZE / WRITE_SIZE readings give the factor
@@ -11,7 +11,8 @@ that converts the counters of the other kernels to bytes):
           in FP32 (the product each solver iteration issues), ``--reps`` times
           via glm_kernel_matmul;
 * image   the fused K.v product of the image-shaped N=60000, D=784, C=10 RBF
-          workload with the BF16 distance GEMM, ``--reps`` times;
+          workload with the BF16 distance GEMM (``--precision bf16x3``: the
+          split-input mode), ``--reps`` times;
 * predict prediction (mean, variance, probit) at 4096 test points against a
           fitted N=100000, D=32, C=10 RBF model compressed to 100 directions
           (the serving workload's model), ``--reps`` times.
@@ -22,7 +23,7 @@ import argparse
 import os
 import sys
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
@@ -32,7 +33,7 @@ def main():
     ap.add_argument("--workload", default="gpc16", choices=["gpc16", "image", "predict"])
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--copy-mib", type=int, default=256)
-    ap.add_argument("--precision", default=None, choices=["fp32", "bf16"])
+    ap.add_argument("--precision", default=None, choices=["fp32", "bf16", "bf16x3"])
     args = ap.parse_args()
 
     import numpy as np

@@ -2,6 +2,7 @@
 
     python tests/golden/make_fullsize_golden.py config2   # N=20000: ~10 min, ~8 GB RAM
     python tests/golden/make_fullsize_golden.py config3   # N=60000: ~15 min, ~36 GB RAM
+    python tests/golden/make_fullsize_golden.py products  # sampled rows of single products
 
 Calls only ``oracle/`` (the FP64 CPU reference) and ``datagen/`` (the seeded
 inputs).  The inputs are the arrays the GPU receives: X and the test points
@@ -15,6 +16,10 @@ config2: X ~ N(0, I_16), N = 20000, C = 5, Matern-5/2 (l = 2, os = 1);
          from f_0 = 0 (outer stop off).
 config3: image-shaped N = 60000, D = 784, C = 10, RBF (median lengthscale);
          CG actions, j <= 5, R = infinity, 3 Newton steps.
+
+products: one product K(X, X) v at each benchmark size (the N=20000 and the
+         image-shaped N=60000 inputs), v ~ N(0, 1) seeded and rounded to FP32,
+         FP64 values at 64 seeded rows (the last row included).
 
 Stored (JSON): per Newton step the iteration count, the last residual norm,
 the number of recycled columns, ||F||, the relative change and Psi; F at 256
@@ -117,6 +122,31 @@ def run(name: str) -> str:
     return path
 
 
+def run_products() -> str:
+    out = {}
+    for name, make, gram in (("config2", lambda: datagen.config2(), False),
+                             ("config3", lambda: datagen.config3(Ns=1000), True)):
+        w = make()
+        X = as_fp32(w.X)
+        rng = np.random.default_rng(2024)
+        v = as_fp32(rng.standard_normal(w.N * w.C))
+        rows = np.sort(rng.choice(w.N, size=64, replace=False))
+        rows[-1] = w.N - 1
+        kmat = ok.kernel_matrix_gram if gram else ok.kernel_matrix
+        K = kmat(X[rows], X, w.kernel, w.lengthscale, w.outputscale)
+        ref = K @ v.reshape(w.N, w.C)
+        out[name] = {"N": w.N, "D": w.D, "C": w.C, "kernel": w.kernel,
+                     "lengthscale": w.lengthscale, "outputscale": w.outputscale,
+                     "v": "numpy default_rng(2024).standard_normal(N*C) rounded to FP32; "
+                          "rows drawn next from the same generator (64, last row forced)",
+                     "rows": rows.tolist(), "ref": ref.tolist()}
+        print(f"products {name}: done", flush=True)
+    path = os.path.join(HERE, "kv_products.json")
+    with open(path, "w") as f:
+        json.dump(out, f, separators=(",", ":"))
+    return path
+
+
 if __name__ == "__main__":
     for nm in sys.argv[1:] or ["config2"]:
-        run(nm)
+        run_products() if nm == "products" else run(nm)
