@@ -18,6 +18,7 @@
 #include "ops.hpp"
 
 namespace igp {
+size_t state_bytes(int64_t N, int64_t D, int64_t C, const igp_solver_config* cfg);
 
 namespace {
 
@@ -1310,6 +1311,16 @@ __global__ void k_check_labels(const int32_t* y, int64_t N, int C, int* bad) {
     if (y[i] < 0 || y[i] >= C) atomicAdd(bad, 1);
 }
 
+// counts the entries of X that are NaN or infinite
+template <typename T>
+__global__ void k_count_nonfinite(const T* X, int64_t n, int* bad) {
+  int cnt = 0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    cnt += isfinite(X[i]) ? 0 : 1;
+  if (cnt) atomicAdd(bad, cnt);
+}
+
 int validate_common(const igp_kernel_params* kp, int n_kp, const igp_solver_config* cfg,
                     int64_t N, int64_t D, int64_t C) {
   IGP_REQUIRE(kp && cfg, "NULL kernel params or config");
@@ -1363,7 +1374,10 @@ template <typename T>
 int init_t(igp_model** out, const igp_kernel_params* kp, int n_kp, const igp_solver_config* cfg,
            const void* X, const void* y, int64_t N, int64_t D, int64_t C, void* arena,
            size_t arena_bytes, hipStream_t stream) {
-  const size_t need = state_bytes_t<T>(N, D, C, *cfg, kp->kind, n_kp);
+  // the arena must hold what itergp_state_bytes reports (the query does not
+  // know the kernel and sizes for the larger layout), whatever this kernel needs
+  const size_t need = std::max(::igp::state_bytes(N, D, C, cfg),
+                               state_bytes_t<T>(N, D, C, *cfg, kp->kind, n_kp));
   if (arena_bytes < need) {
     set_error("arena too small: need %zu bytes, have %zu", need, arena_bytes);
     return IGP_ENOMEM;
@@ -1401,9 +1415,17 @@ int init_t(igp_model** out, const igp_kernel_params* kp, int n_kp, const igp_sol
   } else if (cfg->likelihood != IGP_LIK_BLOCK) {
     IGP_TRY(diag_check_targets<T>(cfg->likelihood, y, m->n, m->L.flags, stream));
   }
-  int bad = 0;
-  IGP_CHECK_HIP(hipMemcpyAsync(&bad, m->L.flags, sizeof(int), hipMemcpyDeviceToHost, stream));
+  k_count_nonfinite<T><<<256, 256, 0, stream>>>(static_cast<const T*>(m->L.X), N * D,
+                                                 m->L.flags + 1);
+  IGP_CHECK_LAUNCH();
+  int bad2[2] = {0, 0};
+  IGP_CHECK_HIP(hipMemcpyAsync(bad2, m->L.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
   IGP_CHECK_HIP(hipStreamSynchronize(stream));
+  const int bad = bad2[0];
+  if (bad2[1]) {
+    set_error("%d non-finite entries in X", bad2[1]);
+    return IGP_EINVAL;
+  }
   if (bad) {
     set_error(cfg->likelihood == IGP_LIK_SOFTMAX ? "%d labels outside [0, C)"
               : cfg->likelihood == IGP_LIK_POISSON ? "%d negative counts"
