@@ -144,6 +144,13 @@ def main():
                          "C=10); poisson: the paper's Poisson budget-split schedules; "
                          "peaks: issue-rate microbenchmarks behind the ALU roofline")
     ap.add_argument("--requests", type=int, default=160, help="serving: stream length")
+    ap.add_argument("--tuning-file", default=os.path.join(ROOT, "paper_2310_20285_amd",
+                                                          "batched_tuning_gfx950.json"),
+                    help="batched: launch-shape table to seed the tuner from (if present)")
+    ap.add_argument("--retune", action="store_true",
+                    help="batched: ignore the table file and time every shape")
+    ap.add_argument("--save-tuning", action="store_true",
+                    help="batched: write the table (loaded and newly timed entries) to the file")
     ap.add_argument("--load", type=float, nargs="+", default=[0.5],
                     help="serving: arrival rates as fractions of the measured capacity")
     args = ap.parse_args()
@@ -462,6 +469,9 @@ def bench_batched(args):
     import datagen
     from paper_2310_20285_amd import api
 
+    prec = args.precision or "fp32"
+    if prec not in ("fp32", "bf16"):
+        raise SystemExit("the batched form takes FP32 or BF16 models")
     ws_ = datagen.config4()
     dev = torch.device("cuda:0")
     data = [(torch.tensor(w.X, dtype=torch.float32, device=dev),
@@ -470,11 +480,16 @@ def bench_batched(args):
 
     def models():
         return [api.IterNCGP(X, y, w.C, w.kernel, w.lengthscale, w.outputscale, policy="cg",
-                             j_max=200, rank_limit=100, recycle=True, precision="fp32",
+                             j_max=200, rank_limit=100, recycle=True, precision=prec,
                              residual_mode="recurrence", max_buffer=300)
                 for w, (X, y) in zip(ws_, data)]
 
-    # warm-up (also runs the launch-shape tuning of the batched product)
+    # the launch-shape table: seeded from the saved file (shapes it covers skip
+    # the timing), or timed afresh and saved with --retune
+    seeded = 0
+    if not args.retune and os.path.exists(args.tuning_file):
+        seeded = api.load_batched_tuning_file(args.tuning_file)
+    # warm-up (also runs the launch-shape tuning of shapes the table lacks)
     wm = models()
     buf = None
     _, buf = api.newton_step_batched(wm, buf)
@@ -506,15 +521,20 @@ def bench_batched(args):
         "n_gpus": 1, "steps": steps, "warmup": 1,
         "ms_per_step": t_batch / steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": {"fp32": "f32", "bf16": "bf16"}[prec], "data": "synthetic",
         "config": {"workload": "64 problems N~U{1000..16000} D=8 C~U{2..8} matern32; "
                                "IterNCGP-CG j<=200 R=100; batched Newton steps",
+                   "precision": prec,
                    "problems": len(ws_), "sum_N": int(sum(w.N for w in ws_))},
         "solver_iterations_per_batched_step": iters,
         "sequential_library": {"value": len(ws_) * steps / t_seq, "unit": "Newton steps/s",
                                "speedup_of_batched": t_seq / t_batch},
-        "tuning": api.batched_tuning(),
+        "tuning": json.loads(api.batched_tuning()),
+        "tuning_seeded_from_file": seeded,
     }
+    if args.save_tuning:
+        api.save_batched_tuning_file(args.tuning_file)
+        res["tuning_saved_to"] = os.path.relpath(args.tuning_file, ROOT)
     if not args.no_plain:
         from plain_fp32 import PlainIterNCGP
         pms = [PlainIterNCGP(X, y, w.C, w.kernel, w.lengthscale, w.outputscale, j_max=200,

@@ -356,17 +356,28 @@ int itergp_get_profile(const igp_model* m, igp_profile* out);
  * solver runs run in parallel host threads.  Results match itergp_newton_step
  * on each model up to the summation order of the products (the batched launch
  * may split the X2 rows differently).
- * Requirements: FP32 models on one stream, recurrence residual, RBF or
- * Matern-3/2 or -5/2, D <= 32, C <= 8, each model at most once.  The launch
+ * Requirements: FP32 models, or BF16 models (all of one precision; their
+ * products run a BF16 tile of the same launch), on one stream, recurrence
+ * residual, RBF or Matern-3/2 or -5/2, D <= 32, C <= 8, each model at most
+ * once.  The launch
  * shape (rows per wave, X2 rows per split) is chosen by timing candidates on
- * the first batch of each (kernel, feature class, size class) and cached for
- * the process; itergp_batched_tuning returns the table as JSON.
+ * the first batch of each (precision, kernel, feature class, size class) and
+ * cached for the process; itergp_batched_tuning returns the table as JSON.
  *   ws  device workspace of >= itergp_batched_ws_bytes(models, n) bytes.
  *   infos  n entries (nullable).  Synchronises the models' stream. */
 size_t itergp_batched_ws_bytes(igp_model* const* models, int32_t n);
 int itergp_newton_step_batched(igp_model* const* models, int32_t n, igp_step_info* infos,
                                void* ws, size_t ws_bytes);
 int itergp_batched_tuning(char* buf, size_t len);
+/* Seeds the launch-shape table from JSON in the format itergp_batched_tuning
+ * writes (an array of objects with kind, feature_chunks, log2_rows, strips,
+ * split_rows; us and precision optional, precision "fp32"), e.g. a table
+ * saved by an earlier process on the same kind of GPU, so that batches of
+ * those shapes skip the timing.  Entries already in the table are kept.
+ * loaded (nullable) receives the number of entries added.  Host only.
+ * Errors: IGP_EINVAL (NULL text, a malformed entry, values outside the
+ * candidate set: strips 1 or 2, split_rows 1024 or 4096). */
+int itergp_batched_tuning_load(const char* json, int32_t* loaded);
 
 /* Release the host-side handle (the arena stays the caller's). */
 int itergp_destroy(igp_model* m);

@@ -104,6 +104,7 @@ SIGNATURES = {
     "itergp_newton_step_batched": (ct.c_int, [ct.POINTER(_P), _I32, ct.POINTER(StepInfo), _P,
                                               _SZ]),
     "itergp_batched_tuning": (ct.c_int, [ct.c_char_p, _SZ]),
+    "itergp_batched_tuning_load": (ct.c_int, [ct.c_char_p, ct.POINTER(_I32)]),
 }
 
 _LIB = None

@@ -329,3 +329,23 @@ def batched_tuning() -> str:
     buf = ct.create_string_buffer(1 << 16)
     L.check(lib.itergp_batched_tuning(buf, len(buf)))
     return buf.value.decode()
+
+
+def batched_tuning_load(text: str) -> int:
+    """itergp_batched_tuning_load: seed the batched launch-shape table from JSON
+    (as batched_tuning() returns it); returns the number of entries added."""
+    n = ct.c_int32()
+    L.check(L.load().itergp_batched_tuning_load(text.encode(), ct.byref(n)))
+    return n.value
+
+
+def load_batched_tuning_file(path: str) -> int:
+    """Seed the table from a JSON file written by save_batched_tuning_file."""
+    with open(path) as f:
+        return batched_tuning_load(f.read())
+
+
+def save_batched_tuning_file(path: str) -> None:
+    """Write the current launch-shape table as JSON."""
+    with open(path, "w") as f:
+        f.write(batched_tuning() + "\n")

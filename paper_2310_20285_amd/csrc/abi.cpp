@@ -12,6 +12,7 @@ size_t batched_ws_bytes(igp_model* const* models, int n);
 int newton_step_batched(igp_model* const* models, int n, igp_step_info* infos, void* ws,
                         size_t ws_bytes);
 std::string batched_tuning_json();
+int batched_tuning_load(const char* json, int* loaded);
 size_t state_bytes(int64_t N, int64_t D, int64_t C, const igp_solver_config* cfg);
 int model_init(igp_model** out, const igp_kernel_params* kp, int n_kp,
                const igp_solver_config* cfg, const void* X, const void* y, int64_t N, int64_t D,
@@ -279,6 +280,16 @@ int itergp_batched_tuning(char* buf, size_t len) {
     IGP_REQUIRE(buf && len > js.size(), "buffer of %zu bytes too small (need %zu)", len,
                 js.size() + 1);
     memcpy(buf, js.c_str(), js.size() + 1);
+    return IGP_OK;
+  });
+}
+
+int itergp_batched_tuning_load(const char* json, int32_t* loaded) {
+  return guarded([&]() -> int {
+    clear_error();
+    int n = 0;
+    IGP_TRY(batched_tuning_load(json, &n));
+    if (loaded) *loaded = n;
     return IGP_OK;
   });
 }

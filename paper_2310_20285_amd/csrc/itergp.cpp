@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -987,9 +988,9 @@ __global__ void k_gather_scalars(const double* const* __restrict__ src, int n,
 }
 
 struct TuneKey {
-  int kind, dch, nbucket;
+  int kind, dch, nbucket, bf16;
   bool operator<(const TuneKey& o) const {
-    return std::tie(kind, dch, nbucket) < std::tie(o.kind, o.dch, o.nbucket);
+    return std::tie(bf16, kind, dch, nbucket) < std::tie(o.bf16, o.kind, o.dch, o.nbucket);
   }
 };
 struct TuneVal {
@@ -1006,6 +1007,7 @@ struct Batch {
   std::vector<Model<float>*> ms;
   hipStream_t stream = nullptr;
   int kind = 0, dch = 1;
+  bool bf16 = false;        // BF16 models (the narrow BF16 tile)
   // workspace
   BatchProblem* dtab = nullptr;
   int* counter = nullptr;
@@ -1118,9 +1120,9 @@ struct Batch {
       Model<float>* m = ms[i];
       const KVProblem kp = update ? m->product_update() : m->product_action();
       BatchProblem bp{};
-      bp.X1p = static_cast<const float*>(kp.X1p);
+      bp.X1p = kp.X1p;
       bp.nrm1 = kp.norm1;
-      bp.X2p = static_cast<const float*>(kp.X2p);
+      bp.X2p = kp.X2p;
       bp.nrm2 = kp.norm2;
       bp.n1 = kp.n1;
       bp.n2 = kp.n2;
@@ -1151,15 +1153,16 @@ struct Batch {
     if (htab.empty()) return IGP_OK;
     IGP_CHECK_HIP(hipMemcpyAsync(dtab, htab.data(), htab.size() * sizeof(BatchProblem),
                                  hipMemcpyHostToDevice, stream));
-    return kv_batched_run(kind, dch, ns, dtab, static_cast<int>(htab.size()), tiles, outs, counter,
-                          stream);
+    return kv_batched_run(kind, dch, ns, bf16, dtab, static_cast<int>(htab.size()), tiles, outs,
+                          counter, stream);
   }
 
   // the tuned launch shape for this batch (timed on first use, then cached)
   int products(const std::vector<int>& idx, bool update) {
     int64_t total = 0;
     for (int i : idx) total += ms[i]->N;
-    const TuneKey key{kind, dch, static_cast<int>(std::log2(std::max<int64_t>(total, 1)))};
+    const TuneKey key{kind, dch, static_cast<int>(std::log2(std::max<int64_t>(total, 1))),
+                      bf16 ? 1 : 0};
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
       auto it = g_tune.find(key);
@@ -1211,14 +1214,14 @@ int parallel_for(int n, F&& f) {
 }
 
 int batch_models(igp_model* const* models, int n, std::vector<Model<float>*>* out, int* kind,
-                 int* dch, hipStream_t* stream) {
+                 int* dch, hipStream_t* stream, bool* bf16) {
   IGP_REQUIRE(models && n >= 1, "no models");
   out->clear();
   for (int i = 0; i < n; ++i) {
     auto* m = dynamic_cast<Model<float>*>(models[i]);
-    IGP_REQUIRE(m, "batched steps need FP32 models (model %d is not)", i);
-    IGP_REQUIRE(m->prepared && m->cfg.precision == IGP_FP32,
-                "model %d: batched steps need the FP32 matrix-core path", i);
+    IGP_REQUIRE(m, "batched steps need FP32 or BF16 models (model %d is FP64)", i);
+    IGP_REQUIRE(m->prepared && (m->cfg.precision == IGP_FP32 || m->cfg.precision == IGP_BF16),
+                "model %d: batched steps need the FP32 or BF16 matrix-core path", i);
     IGP_REQUIRE(m->recurrence(), "model %d: batched steps need the recurrence residual", i);
     IGP_REQUIRE(!m->block(), "model %d: batched steps do not take the block likelihood", i);
     IGP_REQUIRE(batched_supported(m->kp.kind, m->D, m->C), "model %d: kernel, D <= 32 and C <= 8 "
@@ -1227,10 +1230,12 @@ int batch_models(igp_model* const* models, int n, std::vector<Model<float>*>* ou
       *kind = m->kp.kind;
       *dch = static_cast<int>(ceil_div(m->D, 16));
       *stream = m->stream;
+      *bf16 = m->cfg.precision == IGP_BF16;
     }
-    IGP_REQUIRE(m->kp.kind == *kind && ceil_div(m->D, 16) == *dch && m->stream == *stream,
-                "model %d: all models of a batch share kernel family, feature count class and "
-                "stream", i);
+    IGP_REQUIRE(m->kp.kind == *kind && ceil_div(m->D, 16) == *dch && m->stream == *stream &&
+                    (m->cfg.precision == IGP_BF16) == *bf16,
+                "model %d: all models of a batch share kernel family, feature count class, "
+                "precision and stream", i);
     for (auto* o : *out) IGP_REQUIRE(o != m, "model %d appears twice", i);
     IGP_REQUIRE(!m->in_step, "model %d is in the middle of a Newton step", i);
     out->push_back(m);
@@ -1244,14 +1249,15 @@ size_t batched_ws_bytes(igp_model* const* models, int n) {
   std::vector<Model<float>*> ms;
   int kind, dch;
   hipStream_t st;
-  if (batch_models(models, n, &ms, &kind, &dch, &st) != IGP_OK) return 0;
+  bool bf;
+  if (batch_models(models, n, &ms, &kind, &dch, &st, &bf) != IGP_OK) return 0;
   return Batch::ws_bytes(ms);
 }
 
 int newton_step_batched(igp_model* const* models, int n, igp_step_info* infos, void* ws,
                         size_t ws_bytes) {
   Batch b;
-  IGP_TRY(batch_models(models, n, &b.ms, &b.kind, &b.dch, &b.stream));
+  IGP_TRY(batch_models(models, n, &b.ms, &b.kind, &b.dch, &b.stream, &b.bf16));
   IGP_TRY(b.carve_ws(ws, ws_bytes));
   auto& ms = b.ms;
   for (auto* m : ms) IGP_TRY(m->phase_begin());
@@ -1293,13 +1299,77 @@ std::string batched_tuning_json() {
   for (auto& kv : g_tune) {
     char buf[256];
     snprintf(buf, sizeof(buf),
-             "%s{\"kind\": %d, \"feature_chunks\": %d, \"log2_rows\": %d, \"strips\": %d, "
-             "\"split_rows\": %lld, \"us\": %.2f}",
-             s.size() > 1 ? ", " : "", kv.first.kind, kv.first.dch, kv.first.nbucket,
+             "%s{\"precision\": \"%s\", \"kind\": %d, \"feature_chunks\": %d, "
+             "\"log2_rows\": %d, \"strips\": %d, \"split_rows\": %lld, \"us\": %.2f}",
+             s.size() > 1 ? ", " : "", kv.first.bf16 ? "bf16" : "fp32", kv.first.kind,
+             kv.first.dch, kv.first.nbucket,
              kv.second.ns, (long long)kv.second.split_rows, kv.second.us);
     s += buf;
   }
   return s + "]";
+}
+
+namespace {
+// the number after "key": inside the object text [b, e); false if absent
+bool json_number(const std::string& js, size_t b, size_t e, const char* key, double* out) {
+  const std::string pat = std::string("\"") + key + "\"";
+  size_t k = js.find(pat, b);
+  if (k == std::string::npos || k >= e) return false;
+  k = js.find(':', k + pat.size());
+  if (k == std::string::npos || k >= e) return false;
+  const char* start = js.c_str() + k + 1;
+  char* end = nullptr;
+  const double v = std::strtod(start, &end);
+  if (end == start || static_cast<size_t>(end - js.c_str()) > e) return false;
+  *out = v;
+  return true;
+}
+}  // namespace
+
+// Seeds the tuner's table from the JSON that batched_tuning_json writes (an
+// array of flat objects); entries already in the table are kept.
+int batched_tuning_load(const char* json, int* loaded) {
+  IGP_REQUIRE(json, "NULL tuning text");
+  const std::string js(json);
+  std::vector<std::pair<TuneKey, TuneVal>> entries;
+  size_t pos = 0;
+  while ((pos = js.find('{', pos)) != std::string::npos) {
+    const size_t end = js.find('}', pos);
+    IGP_REQUIRE(end != std::string::npos, "tuning text: unterminated object");
+    double kind, dch, nb, ns, sr, us = 0.0;
+    IGP_REQUIRE(json_number(js, pos, end, "kind", &kind) &&
+                    json_number(js, pos, end, "feature_chunks", &dch) &&
+                    json_number(js, pos, end, "log2_rows", &nb) &&
+                    json_number(js, pos, end, "strips", &ns) &&
+                    json_number(js, pos, end, "split_rows", &sr),
+                "tuning text: an entry lacks kind, feature_chunks, log2_rows, strips or "
+                "split_rows");
+    json_number(js, pos, end, "us", &us);
+    // precision: "fp32" (the default when absent) or "bf16"
+    const size_t pk = js.find("\"precision\"", pos);
+    int bf = 0;
+    if (pk != std::string::npos && pk < end) {
+      const bool is32 = js.find("\"fp32\"", pk) < end, is16 = js.find("\"bf16\"", pk) < end;
+      IGP_REQUIRE(is32 || is16, "tuning text: precision must be \"fp32\" or \"bf16\"");
+      bf = is16 && !is32 ? 1 : 0;
+    }
+    bool ns_ok = false, sr_ok = false;
+    for (int c : TUNE_NS) ns_ok |= ns == c;
+    for (int64_t c : TUNE_SPLITS) sr_ok |= sr == static_cast<double>(c);
+    IGP_REQUIRE(ns_ok && sr_ok && kind >= IGP_RBF && kind <= IGP_MATERN52 && dch >= 1 &&
+                    nb >= 0 && nb < 64,
+                "tuning text: entry out of range (strips %g, split_rows %g, kind %g)", ns, sr,
+                kind);
+    entries.push_back({TuneKey{static_cast<int>(kind), static_cast<int>(dch),
+                               static_cast<int>(nb), bf},
+                       TuneVal{static_cast<int>(ns), static_cast<int64_t>(sr), us}});
+    pos = end + 1;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  int added = 0;
+  for (auto& e : entries) added += g_tune.insert(e).second ? 1 : 0;
+  if (loaded) *loaded = added;
+  return IGP_OK;
 }
 
 namespace {

@@ -26,6 +26,8 @@
 namespace igp {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8x __attribute__((ext_vector_type(8)));
+typedef unsigned int u4x __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -391,6 +393,159 @@ __device__ inline void narrow_tile(NarrowSmem<DCH, WX>& sm, const float* __restr
   }
 }
 
+// BF16 form of the narrow tile (inputs of at most 32 features): the X rows are
+// the model's centred rows rounded to BF16 and zero-padded to 32 features, so
+// one v_mfma_f32_16x16x32_bf16 forms a 16 x 16 block of distances where the
+// FP32 tile issues four (D <= 16) or eight 16x16x4 instructions; norms, kernel
+// transform and the VALU contraction are those of the FP32 tile.
+template <int WX>
+struct NarrowSmemB {
+  static constexpr int XS = 40;    // bf16 per LDS row: 32 features + 16 bytes of padding
+  static constexpr int VE = (TN * WX + 255) / 256;
+  __bf16 sX[2][TN * XS];
+  float sN[2][TN];
+  float sV[2][VE * 256];
+};
+
+template <int KIND, int WX, int NS>
+__device__ inline void narrow_tile_bf16(NarrowSmemB<WX>& sm, const __bf16* __restrict__ X1p,
+                                        const float* __restrict__ nrm1,
+                                        const __bf16* __restrict__ X2p,
+                                        const float* __restrict__ nrm2, int64_t n1,
+                                        int64_t row_base, int64_t m_begin, int64_t m_end,
+                                        const float* __restrict__ V, int C, int64_t ldv,
+                                        float* __restrict__ P, float cnorm, float cdot) {
+  constexpr int DPB = 32;
+  constexpr int XS = NarrowSmemB<WX>::XS;
+  constexpr int XQT = TN * DPB / 8 / 256;  // 16-byte pieces of X2 per thread per tile
+  static_assert(XQT >= 1, "one X2 tile covers at least one piece per thread");
+  constexpr int VT = TN * WX;
+  constexpr int VE = (VT + 255) / 256;
+  auto& sX = sm.sX;
+  auto& sN = sm.sN;
+  auto& sV = sm.sV;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  const int64_t row0 = row_base + wave * (16 * NS);
+  bf8x xb[NS];
+  float n1v[NS];
+#pragma unroll
+  for (int st = 0; st < NS; ++st) {
+    const int64_t nrow = row0 + st * 16 + r;
+    const bool ok = nrow < n1;
+    const u4x q = ok ? *reinterpret_cast<const u4x*>(X1p + nrow * DPB + 8 * g) : u4x{0, 0, 0, 0};
+    xb[st] = *reinterpret_cast<const bf8x*>(&q);
+    n1v[st] = ok ? nrm1[nrow] * cnorm : 0.0f;
+  }
+  float acc[NS][WX];
+#pragma unroll
+  for (int st = 0; st < NS; ++st)
+#pragma unroll
+    for (int w = 0; w < WX; ++w) acc[st][w] = 0.0f;
+  int vm[VE];
+  int64_t voff[VE];
+#pragma unroll
+  for (int q = 0; q < VE; ++q) {
+    const int e = tid + q * 256;
+    const int w = e % WX;
+    vm[q] = e < VT ? e / WX : TN;
+    voff[q] = static_cast<int64_t>(w / C) * ldv + (w % C);
+  }
+  u4x px[XQT];
+  float pv[VE];
+  float pn = 0.0f;
+  auto fetch = [&](int64_t m0) {
+#pragma unroll
+    for (int q = 0; q < XQT; ++q) {
+      const int e = tid + q * 256;
+      const int row = e / (DPB / 8), col = e % (DPB / 8);
+      const int64_t m = m0 + row;
+      px[q] = m < m_end ? *reinterpret_cast<const u4x*>(X2p + m * DPB + col * 8)
+                        : u4x{0, 0, 0, 0};
+    }
+    if (tid < TN) {
+      const int64_t m = m0 + tid;
+      pn = m < m_end ? nrm2[m] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < VE; ++q) {
+      const int64_t gm = m0 + vm[q];
+      pv[q] = (vm[q] < TN && gm < m_end) ? V[voff[q] + gm * C] : 0.0f;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < XQT; ++q) {
+      const int e = tid + q * 256;
+      const int row = e / (DPB / 8), col = e % (DPB / 8);
+      *reinterpret_cast<u4x*>(&sX[buf][row * XS + col * 8]) = px[q];
+    }
+    if (tid < TN) sN[buf][tid] = pn * cnorm;
+#pragma unroll
+    for (int q = 0; q < VE; ++q) sV[buf][tid + q * 256] = pv[q];
+  };
+
+  if (m_begin < m_end) {
+    fetch(m_begin);
+    stash(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t m0 = m_begin; m0 < m_end; m0 += TN) {
+    const bool more = m0 + TN < m_end;
+    if (more) fetch(m0 + TN);
+#pragma unroll 2
+    for (int mb = 0; mb < TN / 16; ++mb) {
+      const bf8x a = *reinterpret_cast<const bf8x*>(&sX[buf][(mb * 16 + r) * XS + 8 * g]);
+      f4 dd[NS];
+#pragma unroll
+      for (int st = 0; st < NS; ++st)
+        dd[st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, xb[st], f4{0, 0, 0, 0}, 0, 0, 0);
+      const f4 n2v = *reinterpret_cast<const f4*>(&sN[buf][mb * 16 + 4 * g]);
+      f4 vv[WX];
+      const f4* vsrc = reinterpret_cast<const f4*>(&sV[buf][(mb * 16 + 4 * g) * WX]);
+#pragma unroll
+      for (int q = 0; q < WX; ++q) vv[q] = vsrc[q];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+          const float kk = ktransform<KIND>(__builtin_fmaf(dd[st][v], cdot, n1v[st] + n2v[v]));
+#pragma unroll
+          for (int w = 0; w < WX; ++w) {
+            const int idx = v * WX + w;
+            acc[st][w] = __builtin_fmaf(kk, vv[idx / 4][idx % 4], acc[st][w]);
+          }
+        }
+      }
+    }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int st = 0; st < NS; ++st)
+#pragma unroll
+    for (int w = 0; w < WX; ++w) {
+      float x = acc[st][w];
+      x += __shfl_xor(x, 16, 64);
+      x += __shfl_xor(x, 32, 64);
+      acc[st][w] = x;
+    }
+  if (g == 0) {
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+      const int64_t n = row0 + st * 16 + r;
+      if (n < n1) {
+        float* dst = P + n * WX;
+#pragma unroll
+        for (int w = 0; w < WX; ++w) dst[w] = acc[st][w];
+      }
+    }
+  }
+}
+
 template <int KIND, int DCH, int WX, int NS>
 __global__ void __launch_bounds__(256)
 kv_mfma_f32_narrow(const float* __restrict__ X1p, const float* __restrict__ nrm1,
@@ -690,11 +845,12 @@ kv_mfma_f32_sym(const float* __restrict__ Xp, const float* __restrict__ nrm, int
 // workgroups takes tiles from an atomic counter until none are left, so one
 // launch covers all problems x classes and keeps every CU busy while small
 // problems finish.  The counter is cleared by a kernel before each launch.
-template <int KIND, int DCH, int NS>
+template <int KIND, int DCH, int NS, bool BF>
 __global__ void __launch_bounds__(256)
 kv_batched_persistent(const BatchProblem* __restrict__ probs, int np, int64_t ntiles,
                       int* __restrict__ counter) {
-  __shared__ __align__(16) unsigned char smem_raw[sizeof(NarrowSmem<DCH, WV>)];
+  constexpr size_t SMEM = BF ? sizeof(NarrowSmemB<WV>) : sizeof(NarrowSmem<DCH, WV>);
+  __shared__ __align__(16) unsigned char smem_raw[SMEM];
   __shared__ int64_t s_tile;
   for (;;) {
     if (threadIdx.x == 0) s_tile = atomicAdd(reinterpret_cast<unsigned long long*>(counter), 1ull);
@@ -717,9 +873,18 @@ kv_batched_persistent(const BatchProblem* __restrict__ probs, int np, int64_t nt
     switch (pb.W) {
 #define IGP_BW(K)                                                                              \
   case K:                                                                                      \
-    narrow_tile<KIND, DCH, K, NS>(*reinterpret_cast<NarrowSmem<DCH, K>*>(smem_raw), pb.X1p,    \
-                                  pb.nrm1, pb.X2p, pb.nrm2, pb.n1, rb * (64 * NS), m_begin,      \
-                                  m_end, pb.V, pb.C, pb.ldv, P, pb.cnorm, pb.cdot);            \
+    if constexpr (BF)                                                                          \
+      narrow_tile_bf16<KIND, K, NS>(*reinterpret_cast<NarrowSmemB<K>*>(smem_raw),              \
+                                    static_cast<const __bf16*>(pb.X1p), pb.nrm1,               \
+                                    static_cast<const __bf16*>(pb.X2p), pb.nrm2, pb.n1,        \
+                                    rb * (64 * NS), m_begin, m_end, pb.V, pb.C, pb.ldv, P,     \
+                                    pb.cnorm, pb.cdot);                                        \
+    else                                                                                       \
+      narrow_tile<KIND, DCH, K, NS>(*reinterpret_cast<NarrowSmem<DCH, K>*>(smem_raw),          \
+                                    static_cast<const float*>(pb.X1p), pb.nrm1,                \
+                                    static_cast<const float*>(pb.X2p), pb.nrm2, pb.n1,         \
+                                    rb * (64 * NS), m_begin, m_end, pb.V, pb.C, pb.ldv, P,     \
+                                    pb.cnorm, pb.cdot);                                        \
     break;
       IGP_BW(1) IGP_BW(2) IGP_BW(3) IGP_BW(4) IGP_BW(5) IGP_BW(6) IGP_BW(7) IGP_BW(8)
 #undef IGP_BW
@@ -1061,11 +1226,15 @@ int kv_mfma_f32_launch(const KVProblem& p, const float* X1p, const float* n1p,
 
 namespace {
 template <int KIND, int NS>
-void launch_batched_kind(int dch, const BatchProblem* dprobs, int np, int64_t ntiles, int* counter,
-                         int grid, hipStream_t s) {
+void launch_batched_kind(int dch, bool bf, const BatchProblem* dprobs, int np, int64_t ntiles,
+                         int* counter, int grid, hipStream_t s) {
+  if (bf) {
+    kv_batched_persistent<KIND, 1, NS, true><<<grid, 256, 0, s>>>(dprobs, np, ntiles, counter);
+    return;
+  }
   switch (dch) {
-    case 1: kv_batched_persistent<KIND, 1, NS><<<grid, 256, 0, s>>>(dprobs, np, ntiles, counter); break;
-    default: kv_batched_persistent<KIND, 2, NS><<<grid, 256, 0, s>>>(dprobs, np, ntiles, counter); break;
+    case 1: kv_batched_persistent<KIND, 1, NS, false><<<grid, 256, 0, s>>>(dprobs, np, ntiles, counter); break;
+    default: kv_batched_persistent<KIND, 2, NS, false><<<grid, 256, 0, s>>>(dprobs, np, ntiles, counter); break;
   }
 }
 }  // namespace
@@ -1085,22 +1254,22 @@ void batched_plan(int64_t n1, int64_t n2, int64_t W, int ns, int64_t split_rows,
   (void)W;
 }
 
-int kv_batched_run(int kind, int dch, int ns, const BatchProblem* dprobs, int np, int64_t ntiles,
-                   int64_t total_out, int* counter, hipStream_t s) {
+int kv_batched_run(int kind, int dch, int ns, bool bf16, const BatchProblem* dprobs, int np,
+                   int64_t ntiles, int64_t total_out, int* counter, hipStream_t s) {
   k_zero_counter<<<1, 64, 0, s>>>(counter);
   if (ntiles > 0) {
     const int grid = static_cast<int>(std::min<int64_t>(ntiles, 256 * 4));
     if (ns == 1) {
       switch (kind) {
-        case IGP_RBF: launch_batched_kind<IGP_RBF, 1>(dch, dprobs, np, ntiles, counter, grid, s); break;
-        case IGP_MATERN32: launch_batched_kind<IGP_MATERN32, 1>(dch, dprobs, np, ntiles, counter, grid, s); break;
-        default: launch_batched_kind<IGP_MATERN52, 1>(dch, dprobs, np, ntiles, counter, grid, s); break;
+        case IGP_RBF: launch_batched_kind<IGP_RBF, 1>(dch, bf16, dprobs, np, ntiles, counter, grid, s); break;
+        case IGP_MATERN32: launch_batched_kind<IGP_MATERN32, 1>(dch, bf16, dprobs, np, ntiles, counter, grid, s); break;
+        default: launch_batched_kind<IGP_MATERN52, 1>(dch, bf16, dprobs, np, ntiles, counter, grid, s); break;
       }
     } else {
       switch (kind) {
-        case IGP_RBF: launch_batched_kind<IGP_RBF, 2>(dch, dprobs, np, ntiles, counter, grid, s); break;
-        case IGP_MATERN32: launch_batched_kind<IGP_MATERN32, 2>(dch, dprobs, np, ntiles, counter, grid, s); break;
-        default: launch_batched_kind<IGP_MATERN52, 2>(dch, dprobs, np, ntiles, counter, grid, s); break;
+        case IGP_RBF: launch_batched_kind<IGP_RBF, 2>(dch, bf16, dprobs, np, ntiles, counter, grid, s); break;
+        case IGP_MATERN32: launch_batched_kind<IGP_MATERN32, 2>(dch, bf16, dprobs, np, ntiles, counter, grid, s); break;
+        default: launch_batched_kind<IGP_MATERN52, 2>(dch, bf16, dprobs, np, ntiles, counter, grid, s); break;
       }
     }
   }

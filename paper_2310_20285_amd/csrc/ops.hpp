@@ -87,9 +87,9 @@ int kv_mfma_f32_launch(const KVProblem& p, const float* X1p, const float* n1p,
 // Batched persistent product (kv_mfma.hip): one launch covers the narrow
 // products (W <= 8) of many independent problems.
 struct BatchProblem {
-  const float* X1p;
+  const void* X1p;          // prepared rows: float (FP32 models) or __bf16 (BF16 models)
   const float* nrm1;
-  const float* X2p;
+  const void* X2p;
   const float* nrm2;
   int64_t n1, n2;
   const float* V;
@@ -130,8 +130,8 @@ int biter_launch(int op, const BIter* tab, const int64_t* pre, int nm, int64_t t
                  hipStream_t s);
 bool batched_supported(int kind, int64_t d, int64_t W);
 void batched_plan(int64_t n1, int64_t n2, int64_t W, int ns, int64_t split_rows, BatchProblem* bp);
-int kv_batched_run(int kind, int dch, int ns, const BatchProblem* dprobs, int np, int64_t ntiles,
-                   int64_t total_out, int* counter, hipStream_t s);
+int kv_batched_run(int kind, int dch, int ns, bool bf16, const BatchProblem* dprobs, int np,
+                   int64_t ntiles, int64_t total_out, int* counter, hipStream_t s);
 float kv_kappa(int kind);
 
 // BF16 matrix-core kernel product (kv_bf16.hip): rows rounded to BF16, padded

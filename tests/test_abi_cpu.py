@@ -125,3 +125,45 @@ def test_host_eigh_degenerate_spectrum():
     np.testing.assert_allclose(w, lam, atol=1e-12)
     U = Z.T
     np.testing.assert_allclose(U @ np.diag(w) @ U.T, A, atol=1e-12)
+
+
+def test_batched_tuning_table_round_trip():
+    """The launch-shape table loads from the JSON itergp_batched_tuning
+    writes (FP32 and BF16 entries are separate keys), keeps entries it already
+    has, and refuses malformed or out-of-range entries (host only, no device
+    work)."""
+    import json
+
+    from paper_2310_20285_amd import api
+    entries = [{"precision": "fp32", "kind": 2, "feature_chunks": 1, "log2_rows": 13,
+                "strips": 2, "split_rows": 1024, "us": 812.5},
+               {"kind": 3, "feature_chunks": 2, "log2_rows": 17, "strips": 1,
+                "split_rows": 4096}]
+    added = api.batched_tuning_load(json.dumps(entries))
+    assert added == 2
+    table = json.loads(api.batched_tuning())
+    keys = {(e["precision"], e["kind"], e["feature_chunks"], e["log2_rows"]):
+            (e["strips"], e["split_rows"]) for e in table}
+    assert keys[("fp32", 2, 1, 13)] == (2, 1024) and keys[("fp32", 3, 2, 17)] == (1, 4096)
+    # a BF16 entry of the same shape is a different key
+    bf = dict(entries[0], precision="bf16", strips=1)
+    assert api.batched_tuning_load(json.dumps([bf])) == 1
+    keys = {(e["precision"], e["kind"], e["feature_chunks"], e["log2_rows"]):
+            (e["strips"], e["split_rows"]) for e in json.loads(api.batched_tuning())}
+    assert keys[("bf16", 2, 1, 13)] == (1, 1024) and keys[("fp32", 2, 1, 13)] == (2, 1024)
+    # the same entries again add nothing; a different value for a known key
+    # does not replace it
+    assert api.batched_tuning_load(json.dumps(entries)) == 0
+    other = dict(entries[1], strips=2)
+    assert api.batched_tuning_load(json.dumps([other])) == 0
+    table = json.loads(api.batched_tuning())
+    assert [e["strips"] for e in table if (e["kind"], e["log2_rows"]) == (3, 17)] == [1]
+    for bad in ('[{"kind": 2, "feature_chunks": 1, "log2_rows": 13, "strips": 3, '
+                '"split_rows": 1024}]',
+                '[{"kind": 2, "feature_chunks": 1, "log2_rows": 13, "strips": 1}]',
+                '[{"precision": "fp64", "kind": 2, "feature_chunks": 1, "log2_rows": 13, '
+                '"strips": 1, "split_rows": 1024}]',
+                '[{"kind": 2, "feature_chunks": 1'):
+        with pytest.raises(L.IterGPError) as e:
+            api.batched_tuning_load(bad)
+        assert e.value.code == L.IGP_EINVAL
