@@ -354,6 +354,27 @@ constexpr int TS = TNW + 8;               // row stride (bf16) of the transpose 
 constexpr int TWAVE = 2 * 32 * TS;        // scratch per wave: hi and lo of 32 m rows
 constexpr int TSF = TNW + 4;              // row stride of the FP32 scratch of the X3 mode
 static_assert(32 * TSF * 2 <= TWAVE, "the FP32 transpose scratch fits in a wave's share");
+// plain mode: the scratch holds K as [n][m] (64 n rows of 32 m + 4 padding),
+// written 4 consecutive m at a time and read back transposed
+constexpr int TRS = 36;
+static_assert(TNW * TRS == 32 * TS, "the [n][m] scratch takes the hi part's share");
+typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
+typedef short s4v __attribute__((ext_vector_type(4)));
+
+// B operand of a 16x16x32 MFMA from a [n][m] BF16 scratch: lane (g, r) gets
+// S[n0 + 8g + k][m0 + r] for k < 8.  ds_read_b64_tr_b16 hands output lane j of
+// each 16-lane group element (j mod 4) of the 8-byte piece that lane
+// 4k + j/4 addressed, for k < 4; so lane i of the group addresses
+// S[nbase + i/4][m0 + 4 (i mod 4)], nbase = n0 + 8g (then + 4).
+__device__ inline bf8 read_tr_b(const __bf16* S, int n0, int m0, int g, int r) {
+  const __bf16* p0 = S + (n0 + 8 * g + (r >> 2)) * TRS + m0 + 4 * (r & 3);
+  const s4v lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+      (__attribute__((address_space(3))) s4v*)(p0));
+  const s4v hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+      (__attribute__((address_space(3))) s4v*)(p0 + 4 * TRS));
+  const bf4v blo = __builtin_bit_cast(bf4v, lo), bhi = __builtin_bit_cast(bf4v, hi);
+  return bf8{blo[0], blo[1], blo[2], blo[3], bhi[0], bhi[1], bhi[2], bhi[3]};
+}
 static_assert(WM == 2, "the direct reduction adds the second wave row to the first");
 static_assert(WM * WN * TWAVE <= 2 * (BM + BN) * RS, "transpose scratch fits in the chunk buffers");
 static_assert(WM * WN * MB * 64 * 16 + WN * NB * 64 * 16 <= 2 * (BM + BN) * RS * 2,
@@ -480,16 +501,21 @@ kv_bf16_sym(const __bf16* __restrict__ Xb, const float* __restrict__ nrm,
       }
       out[nb] = contract<X3>(kh, km, kl, vh, vm, vl, out[nb]);
       if (!diag) {
-        // K[n = nb*16 + r][m = sub*16 + 4g + t] -> scratch row m, column n
+        if constexpr (X3) {
+          // K[n = nb*16 + r][m = sub*16 + 4g + t] -> FP32 scratch row m, column n
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int row = (t >> 2) * 16 + 4 * g + (t & 3);
-          if constexpr (X3) {
+          for (int t = 0; t < 8; ++t) {
+            const int row = (t >> 2) * 16 + 4 * g + (t & 3);
             Tf[row * TSF + nb * 16 + r] = kf[t];
-          } else {
-            Th[row * TS + nb * 16 + r] = kh[t];
-            Tl[row * TS + nb * 16 + r] = kl[t];
           }
+        } else {
+          // row n = nb*16 + r of the [n][m] scratch, m = 4g..4g+3 and 16+4g..16+4g+3
+          __bf16* rh = Th + (nb * 16 + r) * TRS + 4 * g;
+          __bf16* rl = Tl + (nb * 16 + r) * TRS + 4 * g;
+          *reinterpret_cast<bf4v*>(rh) = bf4v{kh[0], kh[1], kh[2], kh[3]};
+          *reinterpret_cast<bf4v*>(rh + 16) = bf4v{kh[4], kh[5], kh[6], kh[7]};
+          *reinterpret_cast<bf4v*>(rl) = bf4v{kl[0], kl[1], kl[2], kl[3]};
+          *reinterpret_cast<bf4v*>(rl + 16) = bf4v{kl[4], kl[5], kl[6], kl[7]};
         }
       }
     }
@@ -514,8 +540,8 @@ kv_bf16_sym(const __bf16* __restrict__ Xb, const float* __restrict__ nrm,
             }
             o = contract<true>(ah, am, al, bh, bm, bl, o);
           } else {
-            const bf8 bh = *reinterpret_cast<const bf8*>(&Th[(sub * 16 + r) * TS + col]);
-            const bf8 bl = *reinterpret_cast<const bf8*>(&Tl[(sub * 16 + r) * TS + col]);
+            const bf8 bh = read_tr_b(Th, ks * 32, sub * 16, g, r);
+            const bf8 bl = read_tr_b(Tl, ks * 32, sub * 16, g, r);
             o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, o, 0, 0, 0);
             o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, o, 0, 0, 0);
             o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, o, 0, 0, 0);
