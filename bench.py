@@ -210,21 +210,30 @@ def main():
     prof = {}
     check = None            # the first fit's model, kept for the error check
     done = 0
+    # prediction outputs are allocated once; the workspace grows with the fit's
+    # buffer columns and is reallocated (doubled) only when the query exceeds it
+    n_s = Xs.shape[0]
+    pout = torch.empty((3, n_s * w.C), dtype=dt, device=dev)
+    pws = None
+    st = torch.cuda.current_stream()
     while done < args.steps:
         m = make_model()
         m.set_profiling(True, every=KV_SAMPLE)
         n_here = min(FIT_STEPS, args.steps - done)
+        events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(n_here)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         its = []
-        for _ in range(n_here):
+        for a, b in events:
             info = m.newton_step()
             infos.append(info)
             its.append(info["iters"])
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
+            need = m.predict_ws_bytes(n_s)
+            if pws is None or pws.numel() < need:
+                pws = torch.empty(2 * need, dtype=torch.uint8, device=dev)
             a.record()
-            m.predict(Xs)
+            m.predict_into(Xs, pout[0], pout[1], pout[2], pws, st)
             b.record()
             pred_ev.append((a, b))   # read after the loop: the next step queues behind it
         torch.cuda.synchronize()
