@@ -58,7 +58,11 @@ KV_SAMPLE = 3
 # copy in the same run; profiles/kv_matern52_N20000_D16_C5_fp32.md and
 # profiles/kv_bf16_rbf_N60000_D784_C10.md).  Keyed by the kernel instance it
 # was measured on; any other instance reports null.
-MEASURED_TRAFFIC = {("kv_mfma_f32_sym<3,1,5>", "fp32"): 46.03e6}
+MEASURED_TRAFFIC = {("kv_mfma_f32_sym<3,1,5>", "fp32"): 46.03e6,
+                    # one prediction at 4096 points on the served model (variance
+                    # pass kv_mfma_f32<0,2,4> 5.81 GB + mean pass 0.17 GB;
+                    # profiles/predict_rbf_N100000_D32_C10_B100_fp32.md)
+                    ("predict_4096_rbf_N100000_D32_C10_B100", "fp32"): 5.98e9}
 
 
 def block_cycles(kind: str, W: int, D: int, symmetric: bool) -> float:
@@ -790,7 +794,9 @@ def bench_serving(args):
         "runs": runs,
         "alone_vs_mix_mismatches": mism,
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": peak, "unit": "TFLOP/s",
-                     "frac": tflops / peak, "traffic": None,
+                     "frac": tflops / peak,
+                     "traffic": MEASURED_TRAFFIC.get(
+                         ("predict_4096_rbf_N100000_D32_C10_B100", prec)) if kept == 100 else None,
                      "kernel": "prediction at 4096 points: K(X*,X) v and K(X*,X) Q "
                                "(2 N* N (2D + C(1+B)) flops)",
                      "avg_call_ms": pred_ms},
