@@ -668,6 +668,8 @@ size_t bf16_partial_bytes(int64_t n1, int64_t n2, int64_t W, bool fixed) {
   size_t b = static_cast<size_t>(pl.nsplit) * n1 * W * sizeof(float);
   if (!fixed && n1 == n2)
     b = std::max(b, static_cast<size_t>(sym_blocks(n1, W)) * n1 * W * sizeof(float));
+  // the narrow tile's plan (taken for few features; sized whatever the kernel)
+  if (W <= 8) b = std::max(b, bf16_narrow_partial_bytes(n1, n2, W, fixed));
   return b;
 }
 
@@ -685,6 +687,11 @@ int prep_rows_bf16(int precision, const float* X, int64_t n, int64_t d, const fl
 int kv_bf16_launch(const KVProblem& p, const void* X1b, const float* n1p, const void* X2b,
                    const float* n2p, float* P, size_t P_bytes, hipStream_t s, int* nsplit_out) {
   const int64_t W = p.C * p.nb;
+  // few features and a narrow output: the narrow BF16 tile (one 16x16x32 MFMA
+  // per block of distances, the contraction on VALU); the 256 x 256 tiles
+  // below are built for hundreds of features
+  if (p.precision == IGP_BF16 && bf16_narrow_supported(p.kp.kind, p.d, W))
+    return kv_bf16_narrow_launch(p, X1b, n1p, X2b, n2p, P, P_bytes, s, nsplit_out);
   // the same prepared rows on both sides: each pair of 256-row blocks once
   const int64_t Q = (X1b == X2b && n1p == n2p && p.n1 == p.n2 && !p.fixed_split)
                         ? sym_blocks(p.n1, W) : 0;

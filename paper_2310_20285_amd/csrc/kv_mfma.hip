@@ -845,6 +845,25 @@ kv_mfma_f32_sym(const float* __restrict__ Xp, const float* __restrict__ nrm, int
 // workgroups takes tiles from an atomic counter until none are left, so one
 // launch covers all problems x classes and keeps every CU busy while small
 // problems finish.  The counter is cleared by a kernel before each launch.
+// One product of a BF16 model with at most 32 features on the narrow BF16 tile
+// (grid: X1 row blocks x X2 splits), partial sums per split.
+template <int KIND, int WX, int NS>
+__global__ void __launch_bounds__(256)
+kv_bf16_narrow(const __bf16* __restrict__ X1p, const float* __restrict__ nrm1,
+               const __bf16* __restrict__ X2p, const float* __restrict__ nrm2, int64_t n1,
+               int64_t n2, const float* __restrict__ V, int C, int64_t ldv,
+               float* __restrict__ P, int64_t cols_per_split, float cnorm, float cdot,
+               const int* skip) {
+  if (gate_closed(skip)) return;
+  __shared__ __align__(16) NarrowSmemB<WX> sm;
+  const int64_t m_begin = static_cast<int64_t>(blockIdx.y) * cols_per_split;
+  const int64_t m_end = m_begin + cols_per_split < n2 ? m_begin + cols_per_split : n2;
+  narrow_tile_bf16<KIND, WX, NS>(sm, X1p, nrm1, X2p, nrm2, n1,
+                                 static_cast<int64_t>(blockIdx.x) * (64 * NS), m_begin, m_end,
+                                 V, C, ldv, P + static_cast<int64_t>(blockIdx.y) * n1 * WX,
+                                 cnorm, cdot);
+}
+
 template <int KIND, int DCH, int NS, bool BF>
 __global__ void __launch_bounds__(256)
 kv_batched_persistent(const BatchProblem* __restrict__ probs, int np, int64_t ntiles,
@@ -1113,6 +1132,75 @@ float kv_kappa(int kind) {
     case IGP_MATERN32: return kappa<IGP_MATERN32>();
     default: return kappa<IGP_MATERN52>();
   }
+}
+
+bool bf16_narrow_supported(int kind, int64_t d, int64_t W) {
+  return kind != IGP_MATERN12 && d >= 1 && d <= 32 && W >= 1 && W <= WV;
+}
+
+size_t bf16_narrow_partial_bytes(int64_t n1, int64_t n2, int64_t W, bool fixed) {
+  const Plan pl = plan_mfma(n1, n2, 32, W, fixed);
+  return static_cast<size_t>(pl.nsplit) * n1 * W * sizeof(float);
+}
+
+namespace {
+template <int KIND>
+void launch_bf16_narrow_kind(const Plan& pl, const __bf16* X1, const float* n1p,
+                             const __bf16* X2, const float* n2p, int64_t n1, int64_t n2,
+                             const float* V, int C, int W, int64_t ldv, float* P, float cnorm,
+                             float cdot, const int* skip, hipStream_t s) {
+  const dim3 grid(pl.gx, pl.nsplit);
+  switch (W) {
+#define IGP_BNW(K)                                                                             \
+  case K:                                                                                      \
+    kv_bf16_narrow<KIND, K, NSTRIP><<<grid, 256, 0, s>>>(X1, n1p, X2, n2p, n1, n2, V, C, ldv,   \
+                                                         P, pl.cols_per_split, cnorm, cdot,    \
+                                                         skip);                                \
+    break;
+    IGP_BNW(1) IGP_BNW(2) IGP_BNW(3) IGP_BNW(4) IGP_BNW(5) IGP_BNW(6) IGP_BNW(7) IGP_BNW(8)
+#undef IGP_BNW
+    default: break;
+  }
+}
+}  // namespace
+
+// Out partials of a BF16 product with at most 32 features and 8 output columns
+// on the narrow BF16 tile (rows prepared as for the wide BF16 kernel).
+int kv_bf16_narrow_launch(const KVProblem& p, const void* X1b, const float* n1p,
+                          const void* X2b, const float* n2p, float* P, size_t P_bytes,
+                          hipStream_t s, int* nsplit_out) {
+  const int64_t W = p.C * p.nb;
+  const Plan pl = plan_mfma(p.n1, p.n2, 32, W, p.fixed_split);
+  *nsplit_out = pl.nsplit;
+  if (p.symmetric_out) *p.symmetric_out = 0;
+  if (static_cast<size_t>(pl.nsplit) * p.n1 * W * sizeof(float) > P_bytes) {
+    set_error("kernel-product workspace too small for the split partials");
+    return IGP_ENOMEM;
+  }
+  if (pl.nsplit == 0 || pl.gx == 0) return IGP_OK;
+  const double inv_l2 = 1.0 / (p.kp.lengthscale * p.kp.lengthscale);
+  const float k = kv_kappa(p.kp.kind);
+  const float cnorm = static_cast<float>(k * inv_l2), cdot = static_cast<float>(-2.0 * k * inv_l2);
+  const __bf16* A1 = static_cast<const __bf16*>(X1b);
+  const __bf16* A2 = static_cast<const __bf16*>(X2b);
+  const float* V = static_cast<const float*>(p.V);
+  const int C = static_cast<int>(p.C), Wi = static_cast<int>(W);
+  switch (p.kp.kind) {
+    case IGP_RBF:
+      launch_bf16_narrow_kind<IGP_RBF>(pl, A1, n1p, A2, n2p, p.n1, p.n2, V, C, Wi, p.ldv, P,
+                                       cnorm, cdot, p.skip, s);
+      break;
+    case IGP_MATERN32:
+      launch_bf16_narrow_kind<IGP_MATERN32>(pl, A1, n1p, A2, n2p, p.n1, p.n2, V, C, Wi, p.ldv,
+                                            P, cnorm, cdot, p.skip, s);
+      break;
+    default:
+      launch_bf16_narrow_kind<IGP_MATERN52>(pl, A1, n1p, A2, n2p, p.n1, p.n2, V, C, Wi, p.ldv,
+                                            P, cnorm, cdot, p.skip, s);
+      break;
+  }
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
 }
 
 bool mfma_f32_supported(int kind, int64_t d) {

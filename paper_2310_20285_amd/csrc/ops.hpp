@@ -133,6 +133,12 @@ void batched_plan(int64_t n1, int64_t n2, int64_t W, int ns, int64_t split_rows,
 int kv_batched_run(int kind, int dch, int ns, bool bf16, const BatchProblem* dprobs, int np,
                    int64_t ntiles, int64_t total_out, int* counter, hipStream_t s);
 float kv_kappa(int kind);
+// BF16 products with few features on the narrow BF16 tile (kv_mfma.hip)
+bool bf16_narrow_supported(int kind, int64_t d, int64_t W);
+size_t bf16_narrow_partial_bytes(int64_t n1, int64_t n2, int64_t W, bool fixed);
+int kv_bf16_narrow_launch(const KVProblem& p, const void* X1b, const float* n1p,
+                          const void* X2b, const float* n2p, float* P, size_t P_bytes,
+                          hipStream_t s, int* nsplit_out);
 
 // BF16 matrix-core kernel product (kv_bf16.hip): rows rounded to BF16, padded
 // to a multiple of 32 features, norms of the rounded rows.
