@@ -616,9 +616,21 @@ struct Model final : igp_model {
     }
   }
 
+  // K v of the final iterate is on the device already when the solver carried it
+  // (recurrence residual) or formed it for its last residual (explicit residual:
+  // every iteration but iteration j_max forms one, and r_0 is formed when
+  // j_max > 0); a breakdown leaves v, hence that K v, as they were
+  bool kv_current() const { return recurrence() || (cfg.j_max > 0 && st.j < cfg.j_max); }
+
+  // f_{i+1} = K v into fnew: that K v when it is current, else a product
+  int phase_update() {
+    if (kv_current()) return copy_vec<T>(L.kv, L.fnew, n, stream);
+    ++st.kprod;
+    return apply_K(L.v, L.fnew);
+  }
+
   // after f_{i+1} = K v + m has been enqueued into fnew
   int phase_stats() {
-    ++st.kprod;
     if (softmax())
       IGP_TRY(newton_stats<T>(L.fnew, L.f, L.v, static_cast<const int32_t*>(y), N, C, L.part,
                               L.scal, stream));
@@ -832,7 +844,7 @@ struct Model final : igp_model {
     IGP_TRY(phase_can_act());
     IGP_REQUIRE(!st.active, "the solver has not finished: iterate until done");
     in_step = false;
-    IGP_TRY(apply_K(L.v, L.fnew));
+    IGP_TRY(phase_update());
     IGP_TRY(phase_stats());
     IGP_TRY(read_scalars(sc));
     return phase_finish(info_out);
@@ -1284,9 +1296,18 @@ int newton_step_batched(igp_model* const* models, int n, igp_step_info* infos, v
     IGP_TRY(b.read_all());
     for (int i : act) ms[i]->phase_consume();
   }
-  std::vector<int> all(n);
-  for (int i = 0; i < n; ++i) all[i] = i;
-  IGP_TRY(b.products(all, true));                       // f_{i+1} = K v for every model
+  // f_{i+1} = K v: the carried K v, or one launch for the models without it
+  std::vector<int> need;
+  for (int i = 0; i < n; ++i) {
+    if (ms[i]->kv_current())
+      IGP_TRY(ms[i]->phase_update());
+    else
+      need.push_back(i);
+  }
+  if (!need.empty()) {
+    IGP_TRY(b.products(need, true));
+    for (int i : need) ++ms[i]->st.kprod;
+  }
   for (auto* m : ms) IGP_TRY(m->phase_stats());
   IGP_TRY(b.read_all());
   for (int i = 0; i < n; ++i) IGP_TRY(ms[i]->phase_finish(infos ? &infos[i] : nullptr));
