@@ -62,7 +62,10 @@ MEASURED_TRAFFIC = {("kv_mfma_f32_sym<3,1,5>", "fp32"): 46.03e6,
                     # one prediction at 4096 points on the served model (variance
                     # pass kv_mfma_f32<0,2,4> 5.81 GB + mean pass 0.17 GB;
                     # profiles/predict_rbf_N100000_D32_C10_B100_fp32.md)
-                    ("predict_4096_rbf_N100000_D32_C10_B100", "fp32"): 5.98e9}
+                    ("predict_4096_rbf_N100000_D32_C10_B100", "fp32"): 5.98e9,
+                    # the symmetric BF16 product at N=60000 D=784 C=10, pairs in bands
+                    # of 16 blocks (profiles/kv_bf16_rbf_N60000_D784_C10.md)
+                    ("kv_bf16_sym<0, false>", "bf16"): 7.52e9}
 
 
 def block_cycles(kind: str, W: int, D: int, symmetric: bool) -> float:
@@ -453,6 +456,8 @@ def bf16_product_headline() -> dict:
         res[mode] = {"ms": ms, "tflops_method": method / ms / 1e9,
                      "frac_bf16_peak_method": method / ms / 1e9 / BF16_MFMA_PEAK_TFLOPS,
                      "frac_bf16_peak_dense": dense / ms / 1e9 / BF16_MFMA_PEAK_TFLOPS,
+                     "frac_measured_random_operand_rate_method":
+                         method / ms / 1e9 / BF16_MFMA_RANDOM_TFLOPS,
                      "rel_err_vs_fp64_64_rows": err}
     return res
 
@@ -566,6 +571,10 @@ def bench_batched(args):
 
 
 BF16_MFMA_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak
+# v_mfma_f32_16x16x32_bf16 on random operands, measured by --workload peaks
+# (19.7 cycles per instruction at 2.4 GHz): the matrix rate on data like the
+# product's, which draws more power than the constant operands a peak assumes
+BF16_MFMA_RANDOM_TFLOPS = 2041.0
 
 
 def bench_image(args):
@@ -653,7 +662,8 @@ def bench_image(args):
                                 "flops per product)" if symmetric else
                                 "fused K.v, BF16 distance GEMM (2 N^2 (D + C) flops per product)"),
                      "avg_launch_us": kv_avg_s * 1e6,
-                     "dense_equivalent_tflops": dense_tflops},
+                     "dense_equivalent_tflops": dense_tflops,
+                     "frac_measured_random_operand_rate": tflops / BF16_MFMA_RANDOM_TFLOPS},
         "error_vs_fp64": err,
         "dense_k_fp32": None if args.no_plain else dense_k(w, X, kv_avg_s),
         "newton": [{k: (round(v_, 6) if isinstance(v_, float) else v_) for k, v_ in i.items()
@@ -892,7 +902,10 @@ def bench_peaks(args):
     matrix instructions the product kernels use, expressed as cycles per
     instruction at the nominal 2.4 GHz, and whether FP32 MFMA and VALU work
     overlap (mixed loop time against the sum of the parts).  These are the
-    constants of the ALU issue model of the default workload's roofline."""
+    constants of the ALU issue model of the default workload's roofline.
+    Also the LDS read and write bandwidth (bytes per clock per CU, 16-byte
+    accesses) and whether LDS reads overlap BF16 MFMAs, which bound the BF16
+    product's feature loop."""
     import ctypes as ct
 
     import torch
@@ -938,6 +951,10 @@ def bench_peaks(args):
     res["v_mfma_f32_16x16x32_bf16"] = {"cycles": cycles(t_bf, 16, it),
                                        "tflops": 2 * 16 * 16 * 32 * 16 * waves_per_simd * SIMDS
                                        * it / t_bf / 1e12}
+    t_bfr = run(8, it)
+    res["v_mfma_f32_16x16x32_bf16_random_operands"] = {
+        "cycles": cycles(t_bfr, 16, it),
+        "tflops": 2 * 16 * 16 * 32 * 16 * waves_per_simd * SIMDS * it / t_bfr / 1e12}
     mixed = {}
     for nv in (32, 64, 128):
         t_mix = run(5, it, nv)
@@ -946,6 +963,22 @@ def bench_peaks(args):
                           "valu_alone_ms": t_valu * 1e3,
                           "overlap": (t_mf + t_valu - t_mix) / min(t_mf, t_valu)}
     res["mfma_f32_with_valu"] = mixed
+    # LDS: 8 ds_read_b128 per trip per wave (1 KB each), two 64 KB workgroups per CU
+    lds_bytes = blocks * 4 * it * 8 * 1024
+
+    def per_clk(t):                       # bytes per clock per CU
+        return lds_bytes / (t * CLOCK_HZ * (SIMDS // 4))
+
+    t_rd = {nm: run(6, it, nm) for nm in (4, 12, 24)}
+    t_bf_one = t_bf / 16                  # time of one BF16 MFMA per wave at this launch
+    lds = {"read_bytes_per_clk_per_cu": per_clk(t_rd[4]),
+           "write_bytes_per_clk_per_cu": per_clk(run(7, it))}
+    for nm in (12, 24):
+        t_m = t_bf_one * nm
+        lds[f"read_with_{nm}_bf16_mfma"] = {
+            "mixed_ms": t_rd[nm] * 1e3, "lds_alone_ms": t_rd[4] * 1e3, "mfma_alone_ms": t_m * 1e3,
+            "overlap": (t_rd[4] + t_m - t_rd[nm]) / min(t_rd[4], t_m)}
+    res["lds"] = lds
     line = {"metric": "issue rates (cycles per wave-instruction per SIMD at 2.4 GHz)",
             "value": res["v_exp_f32"]["cycles"], "unit": "cycles per v_exp_f32",
             "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": None,

@@ -36,7 +36,10 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 # per-source device flags: the FP32 matrix-core kernels keep their MFMA
 # accumulators in ordinary VGPRs (no accumulator-register copies before the
 # kernel transform reads the distances)
-SOURCE_FLAGS = {"kv_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+SOURCE_FLAGS = {"kv_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+                # accumulators in VGPRs: loop-carried AGPR accumulators get rotated
+                # through extra moves, which would be timed with the matrix unit
+                "peaks.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 # host-only sources (no HIP kernels), built with the host C++ compiler against
 # the HIP host headers

@@ -375,6 +375,38 @@ __device__ inline bf8 read_tr_b(const __bf16* S, int n0, int m0, int g, int r) {
   const bf4v blo = __builtin_bit_cast(bf4v, lo), bhi = __builtin_bit_cast(bf4v, hi);
   return bf8{blo[0], blo[1], blo[2], blo[3], bhi[0], bhi[1], bhi[2], bhi[3]};
 }
+// Pair index -> block pair (s <= u) in bands of SYM_BAND s-blocks: inside a
+// band the triangle u < s0 + SYM_BAND first, then u ascending with s the
+// fastest index.  The ~32 workgroups an XCD runs at once then share a few s
+// and u blocks in its L2 (in row order they would share one s block and each
+// bring its own u block).  A bijection onto the pairs s <= u.
+constexpr int SYM_BAND = 16;
+__device__ inline void band_pair(int Q, int lin, int* sb, int* ub) {
+  int s0 = 0, Sb = 1;
+  for (;;) {
+    Sb = SYM_BAND < Q - s0 ? SYM_BAND : Q - s0;
+    if (Sb <= 0) {   // lin beyond the Q (Q + 1) / 2 pairs: no pair
+      *sb = *ub = -1;
+      return;
+    }
+    const int cnt = Sb * (Q - s0) - Sb * (Sb - 1) / 2;
+    if (lin < cnt) break;
+    lin -= cnt;
+    s0 += Sb;
+  }
+  const int tri = Sb * (Sb + 1) / 2;
+  if (lin < tri) {
+    int k = 0;
+    while ((k + 1) * (k + 2) / 2 <= lin) ++k;
+    *sb = s0 + lin - k * (k + 1) / 2;
+    *ub = s0 + k;
+  } else {
+    const int t = lin - tri;
+    *sb = s0 + t % Sb;
+    *ub = s0 + Sb + t / Sb;
+  }
+}
+
 static_assert(WM == 2, "the direct reduction adds the second wave row to the first");
 static_assert(WM * WN * TWAVE <= 2 * (BM + BN) * RS, "transpose scratch fits in the chunk buffers");
 static_assert(WM * WN * MB * 64 * 16 + WN * NB * 64 * 16 <= 2 * (BM + BN) * RS * 2,
@@ -402,15 +434,9 @@ kv_bf16_sym(const __bf16* __restrict__ Xb, const float* __restrict__ nrm,
   const int per = (nwg + 7) >> 3, rem = nwg & 7;
   const int lin = (rem == 0 || xcd < rem) ? xcd * per + loc
                                           : rem * per + (xcd - rem) * (per - 1) + loc;
-  // pair index -> (s, u): the pairs of blocks before s number s Q - s (s - 1) / 2
-  int lo = 0, hi = Q - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (mid * Q - mid * (mid - 1) / 2 <= lin) lo = mid;
-    else hi = mid - 1;
-  }
-  const int sb = lo;
-  const int ub = sb + (lin - (sb * Q - sb * (sb - 1) / 2));
+  int sb, ub;
+  band_pair(Q, lin, &sb, &ub);
+  if (sb < 0) return;
   const bool diag = ub == sb;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
