@@ -68,6 +68,20 @@ __device__ inline float kt_bf(float t) {
 __device__ inline __bf16 to_bf(float x) { return static_cast<__bf16>(x); }
 __device__ inline float from_bf(__bf16 x) { return static_cast<float>(x); }
 
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+typedef unsigned u4w __attribute__((ext_vector_type(4)));
+// BF16 high and low parts of two values, each pair packed in one 32-bit word
+// (element 0 in the low half): hi = RNE(x), lo = RNE(x - hi), where x - hi is
+// exact (hi lies within a factor of two of x).  One packed conversion per pair
+// for each part; the high parts are widened back by shift and mask.
+__device__ inline void split2_pk(float a, float b, unsigned& hi, unsigned& lo) {
+  hi = __builtin_bit_cast(unsigned, __builtin_convertvector(f2v{a, b}, b2v));
+  const float ha = __builtin_bit_cast(float, hi << 16);
+  const float hb = __builtin_bit_cast(float, hi & 0xffff0000u);
+  lo = __builtin_bit_cast(unsigned, __builtin_convertvector(f2v{a - ha, b - hb}, b2v));
+}
+
 // x = h + m + l to about 2^-24 |x| (three BF16 parts)
 __device__ inline void split3(float x, __bf16& h, __bf16& m, __bf16& l) {
   h = to_bf(x);
@@ -113,6 +127,8 @@ constexpr int NT = 64 * WM * WN;       // threads per workgroup (512)
 constexpr int MB = TMW / 16, NB = TNW / 16;
 constexpr int VS = BM + 8;             // LDS row stride of the transposed V tile (bf16)
 constexpr int QA = BM * 4 / NT, QB = BN * 4 / NT;   // 16-byte pieces staged per thread
+static_assert(NT % VT == 0 && BM % (NT / VT) == 0 && NT >= BM,
+              "each thread stages one fixed column of the V^T tiles and one X2 norm");
 
 // D^T of one (X2 tile, X1 block) pair for this wave: acc[mb][nb][v] =
 // sum_k X2[m0 + wm TMW + mb 16 + 4g + v][k] X1[n0 + wn TNW + nb 16 + r][k].
@@ -240,14 +256,16 @@ kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) out[nb] = f4{0, 0, 0, 0};
 
+  // this thread stages column wl = tid % VT of V^T at every step (NT is a
+  // multiple of VT): its offset in V, (w / C) ldv + w % C, is computed once
+  const int wl = tid % VT, w = w0 + wl;
+  const int64_t voff = w < W ? static_cast<int64_t>(w / C) * ldv + (w % C) : -1;
   for (int64_t m0 = m_begin; m0 < m_end; m0 += BM) {
     // V^T tile (hi / lo) and X2 norms of this m tile; V = 0 past the end
-    for (int e = tid; e < BM * VT; e += NT) {
-      const int m = e / VT, wl = e % VT;
+    for (int m = tid / VT; m < BM; m += NT / VT) {
       const int64_t gm = m0 + m;
-      const int w = w0 + wl;
       float v = 0.0f;
-      if (gm < m_end && w < W) v = V[static_cast<int64_t>(w / C) * ldv + gm * C + (w % C)];
+      if (gm < m_end && voff >= 0) v = V[voff + gm * C];
       if constexpr (X3) {
         split3(v, sVh[wl * VS + m], sVm[wl * VS + m], sVl[wl * VS + m]);
       } else {
@@ -285,20 +303,24 @@ kv_bf16_kernel(const __bf16* __restrict__ X1b, const float* __restrict__ nrm1,
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         bf8 kh, kl, km;
+        float ka[4], kb[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          const float ka = kt_bf<KIND>(__builtin_fmaf(acc[mba][nb][t], cdot, n1v[nb] + na[t]));
-          const float kb = kt_bf<KIND>(__builtin_fmaf(acc[mbb][nb][t], cdot, n1v[nb] + nbv[t]));
+          ka[t] = kt_bf<KIND>(__builtin_fmaf(acc[mba][nb][t], cdot, n1v[nb] + na[t]));
+          kb[t] = kt_bf<KIND>(__builtin_fmaf(acc[mbb][nb][t], cdot, n1v[nb] + nbv[t]));
           if constexpr (X3) {
-            split3_at(ka, kh, km, kl, t);
-            split3_at(kb, kh, km, kl, 4 + t);
-          } else {
-            const __bf16 ha = to_bf(ka), hb = to_bf(kb);
-            kh[t] = ha;
-            kh[4 + t] = hb;
-            kl[t] = to_bf(ka - from_bf(ha));
-            kl[4 + t] = to_bf(kb - from_bf(hb));
+            split3_at(ka[t], kh, km, kl, t);
+            split3_at(kb[t], kh, km, kl, 4 + t);
           }
+        }
+        if constexpr (!X3) {
+          unsigned h[4], l[4];
+          split2_pk(ka[0], ka[1], h[0], l[0]);
+          split2_pk(ka[2], ka[3], h[1], l[1]);
+          split2_pk(kb[0], kb[1], h[2], l[2]);
+          split2_pk(kb[2], kb[3], h[3], l[3]);
+          kh = __builtin_bit_cast(bf8, u4w{h[0], h[1], h[2], h[3]});
+          kl = __builtin_bit_cast(bf8, u4w{l[0], l[1], l[2], l[3]});
         }
         out[nb] = contract<X3>(kh, km, kl, vh, vm, vl, out[nb]);
       }
@@ -452,14 +474,31 @@ kv_bf16_sym(const __bf16* __restrict__ Xb, const float* __restrict__ nrm,
     const int64_t row = n0 + wn * TNW + nb * 16 + r;
     n1v[nb] = row < n ? nrm[row] * cnorm : 0.0f;
   }
-  // V^T tiles (hi / lo) of the u rows and, off the diagonal, of the s rows;
-  // the X2 norms of the u rows; V = 0 past the end
-  for (int e = tid; e < BM * VT; e += NT) {
-    const int m = e / VT, w = e % VT;
-    float v = 0.0f, x = 0.0f;
-    if (m0 + m < n && w < W) v = V[static_cast<int64_t>(w / C) * ldv + (m0 + m) * C + (w % C)];
-    if (!diag && n0 + m < n && w < W)
-      x = V[static_cast<int64_t>(w / C) * ldv + (n0 + m) * C + (w % C)];
+  // V of the u rows and, off the diagonal, of the s rows (V = 0 past the end),
+  // and the X2 norms of the u rows: loaded before the feature loop, so that
+  // their latency overlaps its first chunks, and split into the V^T tiles
+  // (hi / lo, or three parts) in LDS after it.  This thread stages column
+  // w = tid % VT at every step (NT is a multiple of VT): its offset in V is
+  // computed once.
+  constexpr int VROWS = BM / (NT / VT);   // V rows per thread
+  const int w = tid % VT;
+  const int64_t voff = w < W ? static_cast<int64_t>(w / C) * ldv + (w % C) : -1;
+  float vreg[VROWS], xreg[VROWS];
+#pragma unroll
+  for (int k = 0; k < VROWS; ++k) {
+    const int m = tid / VT + k * (NT / VT);
+    vreg[k] = (m0 + m < n && voff >= 0) ? V[voff + (m0 + m) * C] : 0.0f;
+    xreg[k] = (!diag && n0 + m < n && voff >= 0) ? V[voff + (n0 + m) * C] : 0.0f;
+  }
+  const float nreg = (tid < BM && m0 + tid < n) ? nrm[m0 + tid] * cnorm : 0.0f;
+
+  f4 acc[MB][NB];
+  dist_tile(acc, sAB, sAB + 2 * BM * RS, Xb, Xb, Xl, Xl, nph, n0, n, m0, m_end, DPB, tid, wm,
+            wn, g, r);
+#pragma unroll
+  for (int k = 0; k < VROWS; ++k) {
+    const int m = tid / VT + k * (NT / VT);
+    const float v = vreg[k], x = xreg[k];
     if constexpr (X3) {
       split3(v, sVh[w * VS + m], sVm[w * VS + m], sVl[w * VS + m]);
       split3(x, sUh[w * VS + m], sUm[w * VS + m], sUl[w * VS + m]);
@@ -471,11 +510,8 @@ kv_bf16_sym(const __bf16* __restrict__ Xb, const float* __restrict__ nrm,
       sUl[w * VS + m] = to_bf(x - from_bf(xh));
     }
   }
-  for (int e = tid; e < BM; e += NT) sN2[e] = m0 + e < n ? nrm[m0 + e] * cnorm : 0.0f;
-
-  f4 acc[MB][NB];
-  dist_tile(acc, sAB, sAB + 2 * BM * RS, Xb, Xb, Xl, Xl, nph, n0, n, m0, m_end, DPB, tid, wm,
-            wn, g, r);
+  if (tid < BM) sN2[tid] = nreg;
+  __syncthreads();
 
   __bf16* Th = sAB + wave * TWAVE;     // this wave's transpose scratch, [32 m][TS]
   __bf16* Tl = Th + 32 * TS;
@@ -517,13 +553,16 @@ kv_bf16_sym(const __bf16* __restrict__ Xb, const float* __restrict__ nrm,
         if constexpr (X3) {
           split3_at(ka, kh, km, kl, t);
           split3_at(kb, kh, km, kl, 4 + t);
-        } else {
-          const __bf16 ha = to_bf(ka), hb = to_bf(kb);
-          kh[t] = ha;
-          kh[4 + t] = hb;
-          kl[t] = to_bf(ka - from_bf(ha));
-          kl[4 + t] = to_bf(kb - from_bf(hb));
         }
+      }
+      if constexpr (!X3) {
+        unsigned h[4], l[4];
+        split2_pk(kf[0], kf[1], h[0], l[0]);
+        split2_pk(kf[2], kf[3], h[1], l[1]);
+        split2_pk(kf[4], kf[5], h[2], l[2]);
+        split2_pk(kf[6], kf[7], h[3], l[3]);
+        kh = __builtin_bit_cast(bf8, u4w{h[0], h[1], h[2], h[3]});
+        kl = __builtin_bit_cast(bf8, u4w{l[0], l[1], l[2], l[3]});
       }
       out[nb] = contract<X3>(kh, km, kl, vh, vm, vl, out[nb]);
       if (!diag) {
