@@ -963,6 +963,17 @@ def bench_peaks(args):
                           "valu_alone_ms": t_valu * 1e3,
                           "overlap": (t_mf + t_valu - t_mix) / min(t_mf, t_valu)}
     res["mfma_f32_with_valu"] = mixed
+    # the same two kinds in different waves of one SIMD (waves 0-3 MFMA, 4-7 FMA)
+    split = {}
+    t_sm = run(9, it, -1)                   # MFMA waves alone
+    t_sv = run(9, it, -2)                   # FMA waves alone (64 FMAs per trip)
+    for nv in (32, 64, 128):
+        t_mix = run(9, it, nv)
+        t_valu = t_sv * nv / 64
+        split[str(nv)] = {"mixed_ms": t_mix * 1e3, "mfma_waves_alone_ms": t_sm * 1e3,
+                          "fma_waves_alone_ms": t_valu * 1e3,
+                          "overlap": (t_sm + t_valu - t_mix) / min(t_sm, t_valu)}
+    res["mfma_f32_and_valu_in_different_waves"] = split
     # LDS: 8 ds_read_b128 per trip per wave (1 KB each), two 64 KB workgroups per CU
     lds_bytes = blocks * 4 * it * 8 * 1024
 

@@ -17,6 +17,10 @@
 //                                mantissas, 8 operand registers cycled): the
 //                                matrix rate on data like the product's, which
 //                                draws more power than the constant operands of 4
+//   9  FP32 MFMA and FMA in different waves of one SIMD: 512-thread workgroups,
+//      waves 0-3 run kind 3's MFMA loop and waves 4-7 an FMA loop of nvalu FMAs
+//      per trip (one wave of each kind per SIMD); nvalu = -1: only the MFMA
+//      waves run, -2: only the FMA waves (64 FMAs per trip)
 // The LDS kinds use 64 KB of LDS per workgroup (two workgroups per CU); every
 // lane reads or writes its own 16 bytes, lanes contiguous (no bank conflicts).
 // Every chain's result is stored, so nothing is dead code.
@@ -159,6 +163,44 @@ __global__ void __launch_bounds__(NT) k_mfma_rand(float* out, int iters) {
   out[t] = s;
 }
 
+// kind 9: waves 0-3 MFMA, waves 4-7 FMA (wave w runs on SIMD w mod 4)
+template <int NV>
+__global__ void __launch_bounds__(512) k_split_waves(float* out, int iters, int which, float b,
+                                                     float c) {
+  const int wave = threadIdx.x >> 6;
+  float s = 0.0f;
+  if (wave < 4) {
+    if (which == 2) return;
+    f4 acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = f4{0, 0, 0, 0};
+    const float x = 1e-3f * (threadIdx.x & 63), y = 1e-3f;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, acc[i], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s += acc[i][0] + acc[i][1] + acc[i][2] + acc[i][3];
+  } else {
+    if (which == 1) return;
+    float a[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = threadIdx.x * 1e-3f + i;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int u = 0; u < NV / 8; ++u)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i] = __builtin_fmaf(a[i], b, c);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s += a[i];
+  }
+  out[blockIdx.x * 512 + threadIdx.x] = s;
+}
+
 constexpr int LDS_Q = 4096;   // 16-byte pieces per workgroup (64 KB)
 
 // 8 ds_read_b128 per trip feed NMF BF16 MFMAs (4: each pair of reads once, as
@@ -215,7 +257,8 @@ extern "C" {
 
 // Launch microbenchmark `which` (see above) with `blocks` workgroups of 256
 // threads; out holds blocks * 256 floats (device).  nvalu (kind 5): FMAs
-// per trip, one of 32, 64, 128; kind 6: MFMAs per trip, one of 4, 12, 24.
+// per trip, one of 32, 64, 128; kind 6: MFMAs per trip, one of 4, 12, 24;
+// kind 9: FMAs per trip of the FMA waves (32, 64, 128), or -1 / -2 (see above).
 // Returns 0, or -1 for an unknown kind.
 int igp_peaks_run(int which, int blocks, int iters, int nvalu, float* out, hipStream_t s) {
   const dim3 g(static_cast<unsigned>(blocks)), b(NT);
@@ -239,6 +282,18 @@ int igp_peaks_run(int which, int blocks, int iters, int nvalu, float* out, hipSt
       break;
     case 7: k_lds_write<<<g, b, 0, s>>>(out, iters); break;
     case 8: k_mfma_rand<<<g, b, 0, s>>>(out, iters); break;
+    case 9: {
+      // blocks counts 256-thread units of out: half as many 512-thread workgroups
+      const dim3 g2(static_cast<unsigned>(blocks / 2)), b2(512);
+      const float bb = 0.999f, cc = 1e-4f;
+      if (nvalu == -1) k_split_waves<64><<<g2, b2, 0, s>>>(out, iters, 1, bb, cc);
+      else if (nvalu == -2) k_split_waves<64><<<g2, b2, 0, s>>>(out, iters, 2, bb, cc);
+      else if (nvalu == 32) k_split_waves<32><<<g2, b2, 0, s>>>(out, iters, 0, bb, cc);
+      else if (nvalu == 64) k_split_waves<64><<<g2, b2, 0, s>>>(out, iters, 0, bb, cc);
+      else if (nvalu == 128) k_split_waves<128><<<g2, b2, 0, s>>>(out, iters, 0, bb, cc);
+      else return -1;
+      break;
+    }
     default: return -1;
   }
   return hipGetLastError() == hipSuccess ? 0 : -3;
