@@ -143,7 +143,8 @@ def main():
                     help="default workload: skip the BF16 image product and the serving p99")
     ap.add_argument("--precision", default=None, choices=["fp32", "fp64", "bf16", "bf16x3"])
     ap.add_argument("--workload", default="gpc16",
-                    choices=["gpc16", "image", "batched", "serving", "gmm", "poisson", "peaks"],
+                    choices=["gpc16", "image", "batched", "serving", "gmm", "poisson", "peaks",
+                             "perclass"],
                     help="gpc16: N=20000 D=16 C=5 (default); image: N=60000 D=784 C=10 BF16; "
                          "batched: 64 independent problems in one persistent launch; "
                          "serving: request stream against a fitted N=100000 D=32 C=10 model; "
@@ -186,6 +187,8 @@ def main():
         return bench_poisson(args)
     if args.workload == "peaks":
         return bench_peaks(args)
+    if args.workload == "perclass":
+        return bench_perclass(args)
     args.precision = args.precision or "fp32"
     KV_INSTANCE = "kv_mfma_f32_sym<3,1,5>"   # Matern-5/2, D <= 16, W = 5
     w = datagen.config2()
@@ -1001,6 +1004,97 @@ def bench_peaks(args):
             "model_constants": {"valu": VALU_CYCLES, "transcendental": TRANS_CYCLES,
                                 "mfma_f32": MFMA_F32_CYCLES}}
     print(json.dumps(line))
+
+
+def bench_perclass(args):
+    """Per-class kernels (one lengthscale and outputscale per latent function,
+    the n_kp = C form of the product): at the default workload's shape (N =
+    20000, D = 16, C = 5, Matern-5/2, lengthscales 1.5-2.5, outputscales
+    0.8-1.2), the FP32 product K_c(X, X) v_c against the shared-kernel product
+    of the same shape, its error against FP64 on 64 sampled rows, and a fresh
+    5-step IterNCGP fit with per-class kernels (j <= 200, R = 100, tolerance
+    1e-5).  value = Newton steps/s of that fit."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from oracle import kernels as ok
+    from paper_2310_20285_amd import api
+
+    dev = torch.device("cuda:0")
+    w = datagen.config2()
+    C = w.C
+    ls = [1.5 + 0.25 * c for c in range(C)]
+    os_ = [0.8 + 0.1 * c for c in range(C)]
+    X = torch.tensor(w.X, dtype=torch.float32, device=dev)
+    y = torch.tensor(w.y, dtype=torch.int32, device=dev)
+    rng = np.random.default_rng(5)
+    v = torch.tensor(rng.standard_normal(w.N * C), dtype=torch.float32, device=dev)
+
+    def timed(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out_pc = torch.empty_like(v)
+    out_sh = torch.empty_like(v)
+    ms_pc = timed(lambda: api.glm_kernel_matmul(X, X, v, C, w.kernel, ls, os_, "fp32",
+                                                out=out_pc))
+    ms_sh = timed(lambda: api.glm_kernel_matmul(X, X, v, C, w.kernel, w.lengthscale,
+                                                w.outputscale, "fp32", out=out_sh))
+    # error against FP64 on 64 sampled rows
+    Xh = X.double().cpu().numpy()
+    vh = v.double().cpu().numpy().reshape(w.N, C)
+    rows = np.sort(rng.choice(w.N, size=64, replace=False))
+    ref = np.empty((64, C))
+    for c in range(C):
+        Kc = ok.kernel_matrix(Xh[rows], Xh, w.kernel, ls[c], os_[c])
+        ref[:, c] = Kc @ vh[:, c]
+    got = out_pc.double().cpu().numpy().reshape(w.N, C)[rows]
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    # a fresh 5-step fit with per-class kernels
+    def make():
+        return api.IterNCGP(X, y, C, w.kernel, ls, os_, policy="cg", j_max=200, rank_limit=100,
+                            recycle=True, tol_abs=1e-5, tol_rel=1e-5, precision="fp32",
+                            residual_mode="recurrence", max_buffer=300)
+    mw = make()
+    mw.newton_step()
+    torch.cuda.synchronize()
+    del mw
+    m = make()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [m.newton_step() for _ in range(FIT_STEPS)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    evals = w.N * w.N * C               # one kernel evaluation per pair and class
+    res = {
+        "metric": "IterNCGP Newton steps/s",
+        "value": FIT_STEPS / el,
+        "unit": "Newton steps/s",
+        "n_gpus": 1, "steps": FIT_STEPS, "warmup": 1,
+        "ms_per_step": el / FIT_STEPS * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "per-class kernels: gpc N=20000 D=16 C=5 matern52, lengthscales "
+                               f"{ls}, outputscales {os_}; IterNCGP-CG j<=200 R=100 tol 1e-5, "
+                               f"one fresh fit of {FIT_STEPS} Newton steps"},
+        "product": {"per_class_ms": ms_pc, "shared_kernel_ms": ms_sh,
+                    "per_class_over_shared": ms_pc / ms_sh,
+                    "per_class_geval_s": evals / ms_pc / 1e6,
+                    "rel_err_vs_fp64_64_rows": err,
+                    "kernel": "direct-difference VALU kernel, one transform per class "
+                              "(the shared form evaluates one transform for all classes "
+                              "on the symmetric matrix-core kernel)"},
+        "iters_per_step": [i["iters"] for i in infos],
+    }
+    print(json.dumps(res))
 
 
 def bench_poisson(args):
