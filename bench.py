@@ -1089,9 +1089,10 @@ def bench_perclass(args):
                     "per_class_over_shared": ms_pc / ms_sh,
                     "per_class_geval_s": evals / ms_pc / 1e6,
                     "rel_err_vs_fp64_64_rows": err,
-                    "kernel": "direct-difference VALU kernel, one transform per class "
-                              "(the shared form evaluates one transform for all classes "
-                              "on the symmetric matrix-core kernel)"},
+                    "kernel": "symmetric matrix-core kernel, per-class form: the "
+                              "distance once per pair, one transform per class, the "
+                              "transposed sums on VALU (the shared form: one transform "
+                              "per pair, the transposed sums on MFMA)"},
         "iters_per_step": [i["iters"] for i in infos],
     }
     print(json.dumps(res))

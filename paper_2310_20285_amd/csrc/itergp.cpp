@@ -1234,6 +1234,8 @@ int batch_models(igp_model* const* models, int n, std::vector<Model<float>*>* ou
     IGP_REQUIRE(m, "batched steps need FP32 or BF16 models (model %d is FP64)", i);
     IGP_REQUIRE(m->prepared && (m->cfg.precision == IGP_FP32 || m->cfg.precision == IGP_BF16),
                 "model %d: batched steps need the FP32 or BF16 matrix-core path", i);
+    IGP_REQUIRE(m->n_kp == 1, "model %d: batched steps need one kernel shared by the classes",
+                i);
     IGP_REQUIRE(m->recurrence(), "model %d: batched steps need the recurrence residual", i);
     IGP_REQUIRE(!m->block(), "model %d: batched steps do not take the block likelihood", i);
     IGP_REQUIRE(batched_supported(m->kp.kind, m->D, m->C), "model %d: kernel, D <= 32 and C <= 8 "
@@ -1449,8 +1451,12 @@ int validate_common(const igp_kernel_params* kp, int n_kp, const igp_solver_conf
 
 // prepared (centred, padded) rows feed the matrix-core products; one kernel per
 // class runs on the direct-difference kernel instead
+// centred rows prepared once per model for the matrix-core products (also
+// with one kernel per class: K(X, X) v then takes the symmetric kernel's
+// per-class form)
 bool model_prepared(int precision, int kind, int64_t D, int n_kp) {
-  return n_kp == 1 && kv_uses_prepared(precision, kind, D);
+  (void)n_kp;
+  return kv_uses_prepared(precision, kind, D);
 }
 
 template <typename T>

@@ -340,10 +340,11 @@ int launch_mfma_path(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t 
                                static_cast<const float*>(X2p), n2p, P, pbytes, s, &nsplit));
   const int64_t total = p.n1 * W;
   int blocks = static_cast<int>(std::min<int64_t>(std::max<int64_t>(ceil_div(total, 256), 1), 4096));
+  // with one kernel per class the outputscales are applied inside the product
+  const float os = p.n_kp > 1 ? 1.0f : static_cast<float>(p.kp.outputscale);
   kv_reduce<float><<<blocks, 256, 0, s>>>(P, nsplit, p.n1, static_cast<int>(W),
                                           static_cast<int>(p.C), static_cast<float*>(p.Out), p.ldo,
-                                          static_cast<float>(p.kp.outputscale),
-                                          static_cast<float>(p.beta), p.skip);
+                                          os, static_cast<float>(p.beta), p.skip);
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
@@ -352,8 +353,8 @@ int launch_mfma_path(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t 
 int kv_launch(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t s) {
   if (p.n1 == 0 || p.nb == 0) return IGP_OK;
   if (p.n_kp > 1) {
-    // one kernel per class: the direct-difference kernel evaluates each class's
-    // kernel on the shared distances (FP64 and FP32)
+    // one kernel per class: each class's kernel evaluated on the shared
+    // distances
     IGP_REQUIRE(p.kpc && p.n_kp == p.C && p.C <= 64,
                 "one kernel per class needs n_kp == C <= 64 parameter sets");
     for (int c = 0; c < p.n_kp; ++c)
@@ -363,6 +364,9 @@ int kv_launch(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t s) {
       return IGP_EUNSUPPORTED;
     }
     if (p.precision == IGP_FP64) return launch_valu<double>(p, ws, ws_bytes, s);
+    // FP32 K(X, X) v (one vector, at most 8 classes): the symmetric matrix-core
+    // kernel in its per-class form; otherwise the direct-difference kernel
+    if (mfma_f32_perclass_ok(p)) return launch_mfma_path(p, ws, ws_bytes, s);
     return launch_valu<float>(p, ws, ws_bytes, s);
   }
   if (p.precision == IGP_FP64) return launch_valu<double>(p, ws, ws_bytes, s);

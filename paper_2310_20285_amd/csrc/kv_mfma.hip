@@ -613,11 +613,24 @@ struct SymLayout {
   static constexpr int SW = WX <= 4 ? 4 : 8;   // slab row: the output columns, padded
 };
 
-template <int KIND, int DCH, int WX>
+// One kernel per class (PC): the products of the solver (one vector, W = C
+// columns, column w of class w) with per-class lengthscales and outputscales.
+// The distance is formed once with the kernel constant alone (cnorm = kappa,
+// cdot = -2 kappa) and column w takes os_w k(t il2_w); the transposed sums
+// run on VALU FMAs per lane (one MFMA cannot serve columns with different
+// kernel values) and are added over the four lane rows of a 16-row tile
+// before they go to the slab.
+struct ClassScale {
+  float il2[8];   // 1 / lengthscale^2 of class w
+  float os[8];    // outputscale of class w
+};
+
+template <int KIND, int DCH, int WX, bool PC = false>
 __global__ void __launch_bounds__(256)
 kv_mfma_f32_sym(const float* __restrict__ Xp, const float* __restrict__ nrm, int64_t n,
                 const float* __restrict__ V, int C, int64_t ldv, float* __restrict__ P, int G,
-                int Q, float cnorm, float cdot, const int* skip) {
+                int Q, float cnorm, float cdot, ClassScale cs, const int* skip) {
+  static_assert(!PC || WX <= 8, "per-class columns are at most 8");
   if (gate_closed(skip)) return;
   using L = SymLayout<DCH, WX>;
   constexpr int NS = SYM_NS;
@@ -716,6 +729,8 @@ kv_mfma_f32_sym(const float* __restrict__ Xp, const float* __restrict__ nrm, int
     f4 xa[NS][DCH];
     float n1v[NS][4];
     float a1[NS][4];   // V[16 st + 4g + v][w = r]: A operand of the transposed MFMA
+    // PC: V[16 st + 4g + v][w] for every column w (the transposed sums on VALU)
+    float a1w[PC ? NS : 1][4][PC ? WX : 1];
 #pragma unroll
     for (int st = 0; st < NS; ++st) {
       const int64_t na = row0 + st * 16 + r;
@@ -728,7 +743,15 @@ kv_mfma_f32_sym(const float* __restrict__ Xp, const float* __restrict__ nrm, int
         const int64_t nb = row0 + st * 16 + 4 * g + v;
         const bool ok = nb < n;
         n1v[st][v] = ok ? nrm[nb] * cnorm : 0.0f;
-        a1[st][v] = (ok && r < WX) ? V[static_cast<int64_t>(r / C) * ldv + (r % C) + nb * C] : 0.0f;
+        if constexpr (PC) {
+          a1[st][v] = 0.0f;
+#pragma unroll
+          for (int w = 0; w < WX; ++w)
+            a1w[st][v][w] = ok ? V[static_cast<int64_t>(w / C) * ldv + (w % C) + nb * C] : 0.0f;
+        } else {
+          a1[st][v] = (ok && r < WX) ? V[static_cast<int64_t>(r / C) * ldv + (r % C) + nb * C]
+                                     : 0.0f;
+        }
       }
     }
     float acc[NS][4][WX];
@@ -771,6 +794,48 @@ kv_mfma_f32_sym(const float* __restrict__ Xp, const float* __restrict__ nrm, int
         float vm2[WX];
 #pragma unroll
         for (int w = 0; w < WX; ++w) vm2[w] = bV[w * VS + mb * 16 + r];
+        if constexpr (PC) {
+          // column w: os_w k(t il2_w), t = kappa |x_n - x_m|^2; tr2[w] = this
+          // lane's part of the transposed sum for m = mb 16 + r
+          float tr2[WX];
+#pragma unroll
+          for (int w = 0; w < WX; ++w) tr2[w] = 0.0f;
+#pragma unroll
+          for (int st = 0; st < NS; ++st)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const float t = __builtin_fmaf(dd[st][v], cdot, n1v[st][v] + n2v);
+#pragma unroll
+              for (int w = 0; w < WX; ++w) {
+                const float kw = cs.os[w] * ktransform<KIND>(t * cs.il2[w]);
+                acc[st][v][w] = __builtin_fmaf(kw, vm2[w], acc[st][v][w]);
+                tr2[w] = __builtin_fmaf(kw, a1w[st][v][w], tr2[w]);
+              }
+            }
+          if (both) {
+            // add over the lane rows g (the same m), then lane (r, g) adds
+            // columns 4g .. 4g + 3 to the slab row m
+#pragma unroll
+            for (int w = 0; w < WX; ++w) {
+              tr2[w] += __shfl_xor(tr2[w], 16, 64);
+              tr2[w] += __shfl_xor(tr2[w], 32, 64);
+            }
+            f4* dst = reinterpret_cast<f4*>(myslab + ((m0 - j_lo) + mb * 16 + r) * SW + 4 * g);
+            if (4 * g < SW) {
+              f4 add = {0, 0, 0, 0};
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                float x = 0.0f;
+#pragma unroll
+                for (int q = 0; q < SW / 4; ++q)
+                  if (4 * q + j < WX && g == q) x = tr2[4 * q + j];
+                add[j] = x;
+              }
+              *dst = *dst + add;
+            }
+          }
+          continue;
+        }
         f4 kk[NS];
 #pragma unroll
         for (int st = 0; st < NS; ++st)
@@ -1051,16 +1116,17 @@ SymPlan plan_sym(int64_t n, int64_t d, int64_t W) {
   return sp;
 }
 
-template <int KIND, int DCH>
+template <int KIND, int DCH, bool PC>
 int launch_sym_dch(const SymPlan& sp, const float* Xp, const float* np_, int64_t n,
                    const float* V, int C, int W, int64_t ldv, float* P, float cnorm, float cdot,
-                   const int* skip, hipStream_t s) {
+                   const ClassScale& cs, const int* skip, hipStream_t s) {
   const unsigned items = static_cast<unsigned>(sp.Q * (sp.Q + 1) / 2);
   switch (W) {
 #define IGP_SW(K)                                                                              \
   case K:                                                                                      \
-    kv_mfma_f32_sym<KIND, DCH, K><<<items, 256, sp.lds, s>>>(Xp, np_, n, V, C, ldv, P, sp.G,   \
-                                                             sp.Q, cnorm, cdot, skip);         \
+    kv_mfma_f32_sym<KIND, DCH, K, PC><<<items, 256, sp.lds, s>>>(Xp, np_, n, V, C, ldv, P,     \
+                                                                 sp.G, sp.Q, cnorm, cdot, cs,  \
+                                                                 skip);                        \
     break;
     IGP_SW(1) IGP_SW(2) IGP_SW(3) IGP_SW(4) IGP_SW(5) IGP_SW(6) IGP_SW(7) IGP_SW(8)
 #undef IGP_SW
@@ -1070,13 +1136,13 @@ int launch_sym_dch(const SymPlan& sp, const float* Xp, const float* np_, int64_t
   return IGP_OK;
 }
 
-template <int KIND>
+template <int KIND, bool PC = false>
 int launch_sym(const SymPlan& sp, int dch, const float* Xp, const float* np_, int64_t n,
                const float* V, int C, int W, int64_t ldv, float* P, float cnorm, float cdot,
-               const int* skip, hipStream_t s) {
+               const int* skip, hipStream_t s, const ClassScale& cs = ClassScale{}) {
   if (dch == 1)
-    return launch_sym_dch<KIND, 1>(sp, Xp, np_, n, V, C, W, ldv, P, cnorm, cdot, skip, s);
-  return launch_sym_dch<KIND, 2>(sp, Xp, np_, n, V, C, W, ldv, P, cnorm, cdot, skip, s);
+    return launch_sym_dch<KIND, 1, PC>(sp, Xp, np_, n, V, C, W, ldv, P, cnorm, cdot, cs, skip, s);
+  return launch_sym_dch<KIND, 2, PC>(sp, Xp, np_, n, V, C, W, ldv, P, cnorm, cdot, cs, skip, s);
 }
 
 template <int KIND, int DCH>
@@ -1247,6 +1313,18 @@ int prep_rows_f32(const float* X, int64_t n, int64_t d, const float* centre, flo
 }
 
 // Out = os * K(X1, X2) V from prepared (centred, padded) rows; partials in ws.
+// whether a per-class FP32 product (n_kp == C) can take the symmetric
+// matrix-core kernel: one vector (W = C <= 8), the same point set on both
+// sides, a symmetric plan, and a kernel family that path supports
+bool mfma_f32_perclass_ok(const KVProblem& p) {
+  const int64_t W = p.C * p.nb;
+  const bool same = p.X1p ? (p.X1p == p.X2p && p.norm1 == p.norm2) : (p.X1 == p.X2);
+  return p.precision == IGP_FP32 && p.n_kp > 1 && p.n_kp == p.C && p.nb == 1 && W <= 8 &&
+         same && p.n1 == p.n2 && !p.fixed_split && mfma_f32_supported(p.kp.kind, p.d) &&
+         (p.kp.kind == IGP_RBF || p.kp.kind == IGP_MATERN32 || p.kp.kind == IGP_MATERN52) &&
+         plan_sym(p.n1, p.d, W).ok;
+}
+
 int kv_mfma_f32_launch(const KVProblem& p, const float* X1p, const float* n1p,
                        const float* X2p, const float* n2p, float* P, size_t P_bytes,
                        hipStream_t s, int* nsplit_out) {
@@ -1265,6 +1343,39 @@ int kv_mfma_f32_launch(const KVProblem& p, const float* X1p, const float* n1p,
   const SymPlan sp = (X1p == X2p && n1p == n2p && p.n1 == p.n2 && !p.fixed_split)
                          ? plan_sym(p.n1, p.d, W) : SymPlan{};
   if (p.symmetric_out) *p.symmetric_out = sp.ok ? 1 : 0;
+  if (p.n_kp > 1) {
+    // one kernel per class: the symmetric kernel's per-class form only
+    if (!(sp.ok && p.nb == 1 && p.n_kp == p.C && W <= 8)) {
+      set_error("per-class product not supported on the matrix-core path");
+      return IGP_EUNSUPPORTED;
+    }
+    if (static_cast<size_t>(sp.Q) * p.n1 * W * sizeof(float) > P_bytes) {
+      set_error("kernel-product workspace too small for the symmetric partials");
+      return IGP_ENOMEM;
+    }
+    *nsplit_out = sp.Q;
+    ClassScale cs{};
+    for (int w = 0; w < Wi; ++w) {
+      cs.il2[w] = static_cast<float>(1.0 / (p.kpc[w].lengthscale * p.kpc[w].lengthscale));
+      cs.os[w] = static_cast<float>(p.kpc[w].outputscale);
+    }
+    const int dch = static_cast<int>(ceil_div(p.d, 16));
+    const float k = kv_kappa(p.kp.kind);
+    switch (p.kp.kind) {
+      case IGP_RBF:
+        return launch_sym<IGP_RBF, true>(sp, dch, X1p, n1p, p.n1, V, C, Wi, p.ldv, P, k, -2.0f * k,
+                                         p.skip, s, cs);
+      case IGP_MATERN32:
+        return launch_sym<IGP_MATERN32, true>(sp, dch, X1p, n1p, p.n1, V, C, Wi, p.ldv, P, k,
+                                              -2.0f * k, p.skip, s, cs);
+      case IGP_MATERN52:
+        return launch_sym<IGP_MATERN52, true>(sp, dch, X1p, n1p, p.n1, V, C, Wi, p.ldv, P, k,
+                                              -2.0f * k, p.skip, s, cs);
+      default:
+        set_error("per-class product not supported on the matrix-core path");
+        return IGP_EUNSUPPORTED;
+    }
+  }
   if (sp.ok) {
     if (static_cast<size_t>(sp.Q) * p.n1 * W * sizeof(float) > P_bytes) {
       set_error("kernel-product workspace too small for the symmetric partials");

@@ -80,6 +80,8 @@ int column_mean_f32(const float* X, int64_t n, int64_t d, float* mean, double* p
                     int64_t part_cap, hipStream_t s);
 int prep_rows_f32(const float* X, int64_t n, int64_t d, const float* centre, float* Xp,
                   float* norms, hipStream_t s);
+// a per-class FP32 product that the symmetric matrix-core kernel can take
+bool mfma_f32_perclass_ok(const KVProblem& p);
 int kv_mfma_f32_launch(const KVProblem& p, const float* X1p, const float* n1p,
                        const float* X2p, const float* n2p, float* P, size_t P_bytes,
                        hipStream_t s, int* nsplit_out);

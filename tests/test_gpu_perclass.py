@@ -8,8 +8,17 @@ outputscale) on the GPU path, against the FP64 oracle:
   within 1e-10 (FP64) / 1e-4 (FP32) of the oracle; prediction (mean and
   variance with the class-specific prior variances) within 1e-10 of the
   oracle's formulas on the GPU's own state;
+* K(X, X) v with n_kp = C in FP32 (one vector, C <= 8): the symmetric
+  matrix-core kernel's per-class form, element by element, over several
+  super-blocks and ragged tails, within the first-order bound of the FP32
+  norm expansion (the BF16 tests' bound with exact inputs):
+    |got - ref| <= (os_c Lk / l_c^2) sum_m dr2_nm |v_m| + 8 eps32 (8 + sqrt n) (K_c|v|)
+    dr2_nm = 4 sqrt(D) eps32 (|a_n|^2 + |a_m|^2)   (a: rows centred on the mean)
+  Lk = max |dk/d(r^2)| / os: 1/2 (RBF), 3/2 (Matern-3/2), 5/6 (Matern-5/2).  Near
+  r = 0 the expansion's absolute error in r^2 grows as 1/l^2, so the second
+  term alone does not hold at short lengthscales (here down to 0.6);
 * n_kp = C with equal parameters reproduces the shared-kernel result;
-  BF16 with n_kp > 1 is refused.
+  BF16 with n_kp > 1 is refused, and so is a per-class model in a batched step.
 """
 import math
 
@@ -59,6 +68,47 @@ def test_per_class_kernel_matmul(gpu_lib, prec, kind, shape):
         scale = ok.apply_kernel_per_class(Ks, np.abs(Vh[b]))
         err = np.abs(out[b] - ref)
         assert np.all(err <= tol * scale + 1e-300), (err / scale).max()
+
+
+@pytest.mark.parametrize("kind", KERNEL_KINDS)
+@pytest.mark.parametrize("n,d,C", [(1, 3, 2), (300, 16, 5), (1000, 8, 8), (2777, 16, 3),
+                                   (4100, 32, 1)])
+def test_per_class_symmetric_product(gpu_lib, kind, n, d, C):
+    """The same point set on both sides and one vector: the symmetric
+    matrix-core kernel's per-class form (Matern-1/2 keeps the direct-difference
+    kernel)."""
+    rng = np.random.default_rng(n + 31 * d + C)
+    ells, oss = _params(C, n + d)
+    X = torch.tensor(rng.standard_normal((n, d)), dtype=torch.float32, device="cuda")
+    V = torch.tensor(rng.standard_normal(n * C), dtype=torch.float32, device="cuda")
+    out = api.glm_kernel_matmul(X, X, V, C, kind, ells, oss, "fp32").double().cpu().numpy()
+    Xh, Vh = X.double().cpu().numpy(), V.double().cpu().numpy()
+    Ks = ok.kernel_matrices_per_class(Xh, Xh, kind, ells, oss)
+    ref = ok.apply_kernel_per_class(Ks, Vh)
+    scale = ok.apply_kernel_per_class(Ks, np.abs(Vh))
+    A = Xh - Xh.mean(axis=0)
+    na = (A * A).sum(1)
+    va = np.abs(Vh).reshape(n, C)
+    # sum_m dr2_nm |v_m| per class, with dr2_nm = 4 sqrt(D) eps32 (|a_n|^2 + |a_m|^2)
+    ne = 4 * math.sqrt(d) * EPS32 * (na[:, None] * va.sum(0)[None, :] + (na @ va)[None, :])
+    lk = {"rbf": 0.5, "matern32": 1.5, "matern52": 5.0 / 6.0}.get(kind, 0.0)
+    ne *= np.array([o * lk / l ** 2 for l, o in zip(ells, oss)])[None, :]
+    if kind == "matern12":      # the direct-difference kernel: no expansion term
+        ne[:] = 0.0
+    bound = ne.reshape(-1) + 8 * EPS32 * (8 + math.sqrt(n)) * scale
+    err = np.abs(out - ref)
+    assert np.all(err <= bound + 1e-300), (err / bound).max()
+
+
+def test_per_class_model_refused_in_batched_step(gpu_lib):
+    w = datagen.config4(seed=2, n_problems=1, n_lo=200, n_hi=300)[0]
+    X = torch.tensor(w.X, dtype=torch.float32, device="cuda")
+    y = torch.tensor(w.y, dtype=torch.int32, device="cuda")
+    ells, oss = _params(w.C, 3)
+    m = api.IterNCGP(X, y, w.C, w.kernel, ells, oss, policy="cg", j_max=5, precision="fp32",
+                     residual_mode="recurrence", max_buffer=10)
+    with pytest.raises(IterGPError, match="one kernel shared"):
+        api.newton_step_batched([m])
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
