@@ -368,6 +368,23 @@ int itergp_get_profile(const igp_model* m, igp_profile* out);
 size_t itergp_batched_ws_bytes(igp_model* const* models, int32_t n);
 int itergp_newton_step_batched(igp_model* const* models, int32_t n, igp_step_info* infos,
                                void* ws, size_t ws_bytes);
+/* The batched step with flags (itergp_newton_step_batched is flags = 0).
+ * IGP_BATCH_DEVICE_CONTROL moves the solver's control flow onto the device:
+ * the host enqueues windows of up to 8 solver iterations (Algorithm 2) for
+ * every model still iterating, as if each took all of them (bounded by its
+ * j_max, its buffer and its user actions), and reads the models' iteration
+ * records once per window instead of their scalars once per iteration.  On
+ * the device each model's end of iteration (breakdown eta <= 0, or
+ * ||r|| < tolerance, as in the single-model step) closes that model's gate,
+ * and every later operation and product tile of the model returns at once.
+ * The arithmetic is that of flags = 0, so results, iteration counts and
+ * flags are the same.  A window whose launch shape (see above) has not been
+ * timed yet runs one iteration under host control first.  Same requirements,
+ * workspace and errors as itergp_newton_step_batched, and IGP_EINVAL for an
+ * unknown flag. */
+enum { IGP_BATCH_DEVICE_CONTROL = 1 };
+int itergp_newton_step_batched_ex(igp_model* const* models, int32_t n, igp_step_info* infos,
+                                  void* ws, size_t ws_bytes, int32_t flags);
 int itergp_batched_tuning(char* buf, size_t len);
 /* Seeds the launch-shape table from JSON in the format itergp_batched_tuning
  * writes (an array of objects with kind, feature_chunks, log2_rows, strips,

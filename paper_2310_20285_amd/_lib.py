@@ -103,11 +103,16 @@ SIGNATURES = {
     "itergp_batched_ws_bytes": (_SZ, [ct.POINTER(_P), _I32]),
     "itergp_newton_step_batched": (ct.c_int, [ct.POINTER(_P), _I32, ct.POINTER(StepInfo), _P,
                                               _SZ]),
+    "itergp_newton_step_batched_ex": (ct.c_int, [ct.POINTER(_P), _I32, ct.POINTER(StepInfo),
+                                                 _P, _SZ, _I32]),
     "itergp_batched_tuning": (ct.c_int, [ct.c_char_p, _SZ]),
     "itergp_batched_tuning_load": (ct.c_int, [ct.c_char_p, ct.POINTER(_I32)]),
 }
 
 _LIB = None
+
+
+IGP_BATCH_DEVICE_CONTROL = 1
 
 
 class IterGPError(RuntimeError):

@@ -309,8 +309,10 @@ class IterNCGP:
                                         ct.c_void_p(stream.cuda_stream)))
 
 
-def newton_step_batched(models, ws: Optional[torch.Tensor] = None):
-    """itergp_newton_step_batched over a list of IterNCGP models."""
+def newton_step_batched(models, ws: Optional[torch.Tensor] = None, device_control: bool = False):
+    """itergp_newton_step_batched over a list of IterNCGP models; with
+    device_control the solver's control flow runs on the device
+    (IGP_BATCH_DEVICE_CONTROL: windows of iterations, one host read each)."""
     lib = L.load()
     n = len(models)
     arr = (ct.c_void_p * n)(*[m.handle.value for m in models])
@@ -320,7 +322,8 @@ def newton_step_batched(models, ws: Optional[torch.Tensor] = None):
     if ws is None or ws.numel() < wsb:
         ws = torch.empty(int(wsb), dtype=torch.uint8, device="cuda")
     infos = (L.StepInfo * n)()
-    L.check(lib.itergp_newton_step_batched(arr, n, infos, _ptr(ws), wsb))
+    flags = L.IGP_BATCH_DEVICE_CONTROL if device_control else 0
+    L.check(lib.itergp_newton_step_batched_ex(arr, n, infos, _ptr(ws), wsb, flags))
     return [i.as_dict() for i in infos], ws
 
 

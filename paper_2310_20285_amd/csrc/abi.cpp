@@ -10,7 +10,7 @@
 namespace igp {
 size_t batched_ws_bytes(igp_model* const* models, int n);
 int newton_step_batched(igp_model* const* models, int n, igp_step_info* infos, void* ws,
-                        size_t ws_bytes);
+                        size_t ws_bytes, int flags);
 std::string batched_tuning_json();
 int batched_tuning_load(const char* json, int* loaded);
 size_t state_bytes(int64_t N, int64_t D, int64_t C, const igp_solver_config* cfg);
@@ -269,7 +269,15 @@ int itergp_newton_step_batched(igp_model* const* models, int32_t n, igp_step_inf
                                void* ws, size_t ws_bytes) {
   return guarded([&]() -> int {
     clear_error();
-    return newton_step_batched(models, n, infos, ws, ws_bytes);
+    return newton_step_batched(models, n, infos, ws, ws_bytes, 0);
+  });
+}
+
+int itergp_newton_step_batched_ex(igp_model* const* models, int32_t n, igp_step_info* infos,
+                                  void* ws, size_t ws_bytes, int32_t flags) {
+  return guarded([&]() -> int {
+    clear_error();
+    return newton_step_batched(models, n, infos, ws, ws_bytes, flags);
   });
 }
 

@@ -25,6 +25,7 @@ __global__ void __launch_bounds__(NT)
 kb_iter(const BIter* __restrict__ tab, const int64_t* __restrict__ pre, int nm) {
   const int m = find_model(pre, nm, blockIdx.x);
   const BIter& t = tab[m];
+  if (t.gate && gate_closed(t.gate)) return;
   const int64_t bid = blockIdx.x - pre[m];
   const int64_t nblk = pre[m + 1] - pre[m];
   if constexpr (OP == BOP_ACTION) {
@@ -42,7 +43,12 @@ kb_iter(const BIter* __restrict__ tab, const int64_t* __restrict__ pre, int nm) 
     const int slot = OP == BOP_FIN_ALPHA ? SC_ALPHA : OP == BOP_FIN_ETA ? SC_ETA : SC_RR;
     const int np = OP == BOP_FIN_ETA ? static_cast<int>(iter::cdiv(t.n, NT))
                                      : iter::grid_for(t.n);
-    iter::finish_sum(t.part, np, t.scal + slot, red);
+    if (OP != BOP_FIN_RR || t.next_r) iter::finish_sum(t.part, np, t.scal + slot, red);
+    if constexpr (OP == BOP_FIN_RR) {
+      // device control: the end of the iteration (finish_sum wrote rr from thread 0)
+      if (t.gate && threadIdx.x == 0)
+        iter::consume_iteration(t.scal, t.thresh, t.next_r, t.gate, t.rec);
+    }
   } else if constexpr (OP == BOP_WINV_Z || OP == BOP_WINV_V) {
     // z = t + W^+ s, or wv = W^+ v
     const float* V = OP == BOP_WINV_Z ? t.s : t.v;
@@ -88,7 +94,7 @@ int64_t biter_blocks(int op, const BIter& t, bool residual) {
     case BOP_DIR: return ceil_div(t.n, NT);
     case BOP_WINV_V: return residual ? ceil_div(t.lik == IGP_LIK_SOFTMAX ? t.N : t.n, NT) : 0;
     case BOP_RESID: return residual ? iter::grid_for(t.n) : 0;
-    case BOP_FIN_RR: return residual ? 1 : 0;
+    case BOP_FIN_RR: return residual || t.gate ? 1 : 0;   // device control: always the end
     default: return 0;
   }
 }

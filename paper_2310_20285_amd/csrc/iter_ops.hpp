@@ -34,6 +34,30 @@ __device__ inline void finish_sum(const double* __restrict__ part, int nblk, dou
   if (threadIdx.x == 0) *out = s;
 }
 
+// end of a solver iteration (one thread): unless the gate is closed, count it,
+// close the gate on a breakdown (eta <= 0) or convergence, keep min eta and rr
+__device__ inline void consume_iteration(const double* __restrict__ scal, double thresh,
+                                         int next_r, int* gate, double* rec) {
+  if (gate_closed(gate)) return;
+  rec[REC_EXEC] = coherent_load(rec + REC_EXEC) + 1.0;
+  const double eta = coherent_load(scal + SC_ETA);
+  if (!(eta > 0.0)) {   // breakdown: the iteration's column was not appended
+    rec[REC_BREAK] = 1.0;
+    __hip_atomic_store(gate, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  rec[REC_APPEND] = coherent_load(rec + REC_APPEND) + 1.0;
+  rec[REC_ETAMIN] = fmin(coherent_load(rec + REC_ETAMIN), eta);
+  if (next_r) {
+    const double rr = coherent_load(scal + SC_RR);
+    rec[REC_RR] = rr;
+    if (!(sqrt(rr) >= thresh)) {
+      rec[REC_CONV] = 1.0;
+      __hip_atomic_store(gate, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 // r = rhs - kv - wv ; part[bid] = sum of r^2 over this block's rows
 template <typename T>
 __device__ inline void residual(const T* __restrict__ rhs, const T* __restrict__ kv,

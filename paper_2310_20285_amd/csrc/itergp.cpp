@@ -593,7 +593,67 @@ struct Model final : igp_model {
     t.n = n; t.N = N; t.ld = ld; t.unit_idx = st.j - 1;
     t.C = static_cast<int>(C); t.ncols = ncols; t.lik = cfg.likelihood; t.policy = cfg.policy;
     t.nchunks = static_cast<int>(ceil_div(n, QTZ_ROWS));
+    t.next_r = st.next_r ? 1 : 0;
     return t;
+  }
+
+  // device-controlled batched window: iteration jj (1-based) with its action in
+  // buffer column col, as biter() would describe it after jj - 1 appended
+  // iterations; the gate and record end the iteration on the device
+  BIter biter_at(int64_t jj, int col) const {
+    BIter t = biter();
+    const int64_t off = static_cast<int64_t>(col) * ld;
+    t.s = L.S + off;
+    t.t = L.Tb + off;
+    t.qcol = L.Q + off;
+    t.kqcol = L.KQ + off;
+    t.user = cfg.policy == IGP_POLICY_USER && user ? user + (jj - 1) * user_ld : nullptr;
+    t.unit_idx = jj - 1;
+    t.ncols = col;
+    t.next_r = jj < cfg.j_max ? 1 : 0;
+    t.gate = L.gate;
+    t.rec = L.rec;
+    t.thresh = st.thresh;
+    return t;
+  }
+  KVProblem product_action_at(int col) const {
+    const int64_t off = static_cast<int64_t>(col) * ld;
+    return kv_problem(L.X, N, L.S + off, 1, n, L.Tb + off, n);
+  }
+  // rounds a device-controlled window may give this model (iteration cap,
+  // buffer, user actions); 0 when it cannot act
+  int window_cap(int wmax) const {
+    if (!st.active) return 0;
+    int64_t c = std::min<int64_t>(wmax, cfg.j_max - st.j);
+    c = std::min<int64_t>(c, cfg.max_buffer - ncols);
+    if (cfg.policy == IGP_POLICY_USER) c = std::min<int64_t>(c, user ? user_cols - st.j : 0);
+    return static_cast<int>(std::max<int64_t>(c, 0));
+  }
+  // after a device-controlled window of `cap` rounds: fold the device record
+  // (rec, this model's REC_COUNT values) into the host state
+  int consume_dc(const double* rec, int cap) {
+    const int ran = static_cast<int>(rec[REC_EXEC] - rec_h[REC_EXEC]);
+    const int appended = static_cast<int>(rec[REC_APPEND] - rec_h[REC_APPEND]);
+    const bool stopped = rec[REC_BREAK] != 0.0 || rec[REC_CONV] != 0.0;
+    IGP_REQUIRE(ran >= 0 && ran <= cap && appended <= ran && appended >= ran - 1 &&
+                    (ran == cap || stopped) && (appended == ran || rec[REC_BREAK] != 0.0),
+                "batched iteration record out of step with the host");
+    const int64_t j0 = st.j;
+    st.kprod += ran;
+    st.j += appended;
+    ncols += appended;
+    st.next_r = st.j < cfg.j_max;
+    if (ran > 0) st.info.eta_min = std::min(st.info.eta_min, rec[REC_ETAMIN]);
+    if (appended > 0 && j0 + 1 < cfg.j_max) st.info.res_norm = std::sqrt(rec[REC_RR]);
+    if (rec[REC_BREAK] != 0.0) {
+      st.info.breakdown = 1;
+      st.active = false;
+    } else if (rec[REC_CONV] != 0.0) {
+      st.info.converged = 1;
+      st.active = false;
+    }
+    std::copy(rec, rec + REC_COUNT, rec_h);
+    return IGP_OK;
   }
 
   // after the iteration's scalars are on the host (batched driver)
@@ -999,6 +1059,14 @@ __global__ void k_gather_scalars(const double* const* __restrict__ src, int n,
   dst[i] = src[i / SC_COUNT][i % SC_COUNT];
 }
 
+// the iteration records of the models (REC_COUNT doubles each), gathered
+__global__ void k_gather_records(const double* const* __restrict__ src, int n,
+                                 double* __restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * REC_COUNT) return;
+  dst[i] = src[i / REC_COUNT][i % REC_COUNT];
+}
+
 struct TuneKey {
   int kind, dch, nbucket, bf16;
   bool operator<(const TuneKey& o) const {
@@ -1031,6 +1099,18 @@ struct Batch {
   BIter* dit = nullptr;            // iteration descriptors (device)
   int64_t* dpre = nullptr;         // per-operation block prefixes (device)
   std::vector<unsigned char> hitbuf;
+  // device control: the tables of every round of a window, in slots of their
+  // own ([DC_WINDOW][models] descriptors, [DC_WINDOW][BOP_COUNT][models + 1]
+  // prefixes, [DC_WINDOW][models] product problems), uploaded in one copy
+  static constexpr int DC_WINDOW = 8;
+  BIter* dit_w = nullptr;
+  int64_t* dpre_w = nullptr;
+  BatchProblem* dtab_w = nullptr;
+  char* dwin_end = nullptr;
+  const double** drec = nullptr;   // record pointers of the models
+  double* grec = nullptr;          // gathered records
+  std::vector<double> hrec;
+  std::vector<unsigned char> hwin;
 
   static size_t partial_floats(const Model<float>* m) {
     return static_cast<size_t>(ceil_div(m->N, TUNE_SPLITS[0]) + 1) * m->N * m->C;
@@ -1044,6 +1124,11 @@ struct Batch {
     cv.take<int64_t>(1);
     cv.take<const double*>(ms.size());
     cv.take<double>(ms.size() * SC_COUNT);
+    cv.take<BIter>(DC_WINDOW * ms.size());
+    cv.take<int64_t>(static_cast<size_t>(DC_WINDOW) * BOP_COUNT * (ms.size() + 1));
+    cv.take<BatchProblem>(DC_WINDOW * ms.size());
+    cv.take<const double*>(ms.size());
+    cv.take<double>(ms.size() * REC_COUNT);
     size_t pf = 0;
     for (auto* m : ms) pf += align_up(partial_floats(m) * sizeof(float)) / sizeof(float);
     cv.take<float>(pf);
@@ -1058,6 +1143,12 @@ struct Batch {
     counter = reinterpret_cast<int*>(cv.take<int64_t>(1));
     dscal = cv.take<const double*>(ms.size());
     gathered = cv.take<double>(ms.size() * SC_COUNT);
+    dit_w = cv.take<BIter>(DC_WINDOW * ms.size());
+    dpre_w = cv.take<int64_t>(static_cast<size_t>(DC_WINDOW) * BOP_COUNT * (ms.size() + 1));
+    dtab_w = cv.take<BatchProblem>(DC_WINDOW * ms.size());
+    dwin_end = reinterpret_cast<char*>(dtab_w + DC_WINDOW * ms.size());
+    drec = cv.take<const double*>(ms.size());
+    grec = cv.take<double>(ms.size() * REC_COUNT);
     size_t pf = 0;
     for (auto* m : ms) pf += align_up(partial_floats(m) * sizeof(float)) / sizeof(float);
     partials = cv.take<float>(pf);
@@ -1065,14 +1156,120 @@ struct Batch {
       set_error("batched workspace too small: need %zu bytes", ws_bytes(ms));
       return IGP_ENOMEM;
     }
-    std::vector<const double*> hs(ms.size());
-    for (size_t i = 0; i < ms.size(); ++i) hs[i] = ms[i]->L.scal;
+    std::vector<const double*> hs(ms.size()), hr(ms.size());
+    for (size_t i = 0; i < ms.size(); ++i) {
+      hs[i] = ms[i]->L.scal;
+      hr[i] = ms[i]->L.rec;
+    }
     IGP_CHECK_HIP(hipMemcpyAsync(dscal, hs.data(), hs.size() * sizeof(double*),
+                                 hipMemcpyHostToDevice, stream));
+    IGP_CHECK_HIP(hipMemcpyAsync(drec, hr.data(), hr.size() * sizeof(double*),
                                  hipMemcpyHostToDevice, stream));
     IGP_CHECK_HIP(hipStreamSynchronize(stream));
     hgather.resize(ms.size() * SC_COUNT);
+    hrec.resize(ms.size() * REC_COUNT);
     return IGP_OK;
   }
+
+  int read_records() {
+    const int n = static_cast<int>(ms.size());
+    k_gather_records<<<static_cast<unsigned>(ceil_div(n * REC_COUNT, 256)), 256, 0, stream>>>(
+        drec, n, grec);
+    IGP_CHECK_LAUNCH();
+    IGP_CHECK_HIP(hipMemcpyAsync(hrec.data(), grec, hrec.size() * sizeof(double),
+                                 hipMemcpyDeviceToHost, stream));
+    IGP_CHECK_HIP(hipStreamSynchronize(stream));
+    return IGP_OK;
+  }
+
+  // The tuned launch shape for the product of the models in idx, if known.
+  bool tuned(const std::vector<int>& idx, TuneVal* out) const {
+    int64_t total = 0;
+    for (int i : idx) total += ms[i]->N;
+    const TuneKey key{kind, dch, static_cast<int>(std::log2(std::max<int64_t>(total, 1))),
+                      bf16 ? 1 : 0};
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    *out = it->second;
+    return true;
+  }
+
+  // One device-controlled window: round k < rounds.size() runs iteration
+  // jj = j + k + 1 at column ncols + k of every model listed for it (each
+  // model's rounds are a prefix).  All rounds' tables are built on the host
+  // and uploaded in one copy; every operation and product tile of a model
+  // whose gate has closed returns at once.  Returns IGP_EUNSUPPORTED (nothing
+  // enqueued) if a round's launch shape has not been tuned yet.
+  int dc_window(const std::vector<std::vector<int>>& rounds) {
+    const size_t nmod = ms.size(), pre_len = nmod + 1;
+    const size_t R = rounds.size();
+    std::vector<TuneVal> tv(R);
+    for (size_t k = 0; k < R; ++k)
+      if (!tuned(rounds[k], &tv[k])) return IGP_EUNSUPPORTED;
+    char* base = reinterpret_cast<char*>(dit_w);
+    const size_t bytes = static_cast<size_t>(dwin_end - base);
+    hwin.assign(bytes, 0);
+    auto hit = [&](size_t k) {
+      return reinterpret_cast<BIter*>(hwin.data() + (reinterpret_cast<char*>(dit_w + k * nmod) - base));
+    };
+    auto hpre = [&](size_t k, int op) {
+      return reinterpret_cast<int64_t*>(
+          hwin.data() + (reinterpret_cast<char*>(dpre_w + (k * BOP_COUNT + op) * pre_len) - base));
+    };
+    auto htb = [&](size_t k) {
+      return reinterpret_cast<BatchProblem*>(
+          hwin.data() + (reinterpret_cast<char*>(dtab_w + k * nmod) - base));
+    };
+    std::vector<std::vector<int64_t>> totals(R, std::vector<int64_t>(BOP_COUNT, 0));
+    std::vector<int64_t> ptiles(R, 0), pouts(R, 0);
+    for (size_t k = 0; k < R; ++k) {
+      const auto& idx = rounds[k];
+      BIter* ht = hit(k);
+      for (size_t q = 0; q < idx.size(); ++q) {
+        Model<float>* m = ms[idx[q]];
+        ht[q] = m->biter_at(m->st.j + static_cast<int64_t>(k) + 1, m->ncols + static_cast<int>(k));
+      }
+      for (int op = 0; op < BOP_COUNT; ++op) {
+        int64_t* pre = hpre(k, op);
+        pre[0] = 0;
+        for (size_t q = 0; q < idx.size(); ++q)
+          pre[q + 1] = pre[q] + biter_blocks(op, ht[q], ht[q].next_r != 0);
+        totals[k][op] = pre[idx.size()];
+      }
+      BatchProblem* tb = htb(k);
+      size_t poff = 0;
+      for (size_t q = 0; q < idx.size(); ++q) {
+        Model<float>* m = ms[idx[q]];
+        const KVProblem kp = m->product_action_at(m->ncols + static_cast<int>(k));
+        BatchProblem& bp = tb[q];
+        bp = problem_of(kp, tv[k].ns, tv[k].split_rows);
+        bp.P = partials + poff;
+        poff += align_up(partial_floats(m) * sizeof(float)) / sizeof(float);
+        bp.gate = m->L.gate;
+        bp.tile_begin = ptiles[k];
+        bp.out_begin = pouts[k];
+        ptiles[k] += static_cast<int64_t>(bp.gx) * bp.nsplit;
+        pouts[k] += bp.n1 * bp.W;
+      }
+    }
+    IGP_CHECK_HIP(hipMemcpyAsync(base, hwin.data(), bytes, hipMemcpyHostToDevice, stream));
+    for (size_t k = 0; k < R; ++k) {
+      const int nm = static_cast<int>(rounds[k].size());
+      if (nm == 0) continue;
+      BIter* dt = dit_w + k * nmod;
+      for (int op = BOP_ACTION; op <= BOP_FIN_ALPHA; ++op)
+        IGP_TRY(biter_launch(op, dt, dpre_w + (k * BOP_COUNT + op) * pre_len, nm, totals[k][op],
+                             stream));
+      IGP_TRY(kv_batched_run(kind, dch, tv[k].ns, bf16, dtab_w + k * nmod, nm, ptiles[k],
+                             pouts[k], counter, stream));
+      for (int op = BOP_WINV_Z; op < BOP_COUNT; ++op)
+        IGP_TRY(biter_launch(op, dt, dpre_w + (k * BOP_COUNT + op) * pre_len, nm, totals[k][op],
+                             stream));
+    }
+    return IGP_OK;
+  }
+
 
   // copy every model's scalar block to its host array (one transfer)
   int read_all() {
@@ -1123,6 +1320,31 @@ struct Batch {
     return IGP_OK;
   }
 
+  // one model's product in the batched launch (partials, tile and output
+  // offsets and gate are set by the caller)
+  static BatchProblem problem_of(const KVProblem& kp, int ns, int64_t split_rows) {
+    BatchProblem bp{};
+    bp.X1p = kp.X1p;
+    bp.nrm1 = kp.norm1;
+    bp.X2p = kp.X2p;
+    bp.nrm2 = kp.norm2;
+    bp.n1 = kp.n1;
+    bp.n2 = kp.n2;
+    bp.V = static_cast<const float*>(kp.V);
+    bp.ldv = kp.ldv;
+    bp.C = static_cast<int>(kp.C);
+    bp.W = static_cast<int>(kp.C * kp.nb);
+    batched_plan(bp.n1, bp.n2, bp.W, ns, split_rows, &bp);
+    const double inv_l2 = 1.0 / (kp.kp.lengthscale * kp.kp.lengthscale);
+    const float kap = kv_kappa(kp.kp.kind);
+    bp.cnorm = static_cast<float>(kap * inv_l2);
+    bp.cdot = static_cast<float>(-2.0 * kap * inv_l2);
+    bp.os = static_cast<float>(kp.kp.outputscale);
+    bp.Out = static_cast<float*>(kp.Out);
+    bp.ldo = kp.ldo;
+    return bp;
+  }
+
   // one persistent launch for the products of the selected models
   int run_products(const std::vector<int>& idx, bool update, int ns, int64_t split_rows) {
     htab.clear();
@@ -1131,27 +1353,9 @@ struct Batch {
     for (int i : idx) {
       Model<float>* m = ms[i];
       const KVProblem kp = update ? m->product_update() : m->product_action();
-      BatchProblem bp{};
-      bp.X1p = kp.X1p;
-      bp.nrm1 = kp.norm1;
-      bp.X2p = kp.X2p;
-      bp.nrm2 = kp.norm2;
-      bp.n1 = kp.n1;
-      bp.n2 = kp.n2;
-      bp.V = static_cast<const float*>(kp.V);
-      bp.ldv = kp.ldv;
-      bp.C = static_cast<int>(kp.C);
-      bp.W = static_cast<int>(kp.C * kp.nb);
-      batched_plan(bp.n1, bp.n2, bp.W, ns, split_rows, &bp);
+      BatchProblem bp = problem_of(kp, ns, split_rows);
       bp.P = partials + poff;
       poff += align_up(partial_floats(m) * sizeof(float)) / sizeof(float);
-      const double inv_l2 = 1.0 / (kp.kp.lengthscale * kp.kp.lengthscale);
-      const float kap = kv_kappa(kp.kp.kind);
-      bp.cnorm = static_cast<float>(kap * inv_l2);
-      bp.cdot = static_cast<float>(-2.0 * kap * inv_l2);
-      bp.os = static_cast<float>(kp.kp.outputscale);
-      bp.Out = static_cast<float*>(kp.Out);
-      bp.ldo = kp.ldo;
       bp.tile_begin = tiles;
       bp.out_begin = outs;
       tiles += static_cast<int64_t>(bp.gx) * bp.nsplit;
@@ -1269,7 +1473,9 @@ size_t batched_ws_bytes(igp_model* const* models, int n) {
 }
 
 int newton_step_batched(igp_model* const* models, int n, igp_step_info* infos, void* ws,
-                        size_t ws_bytes) {
+                        size_t ws_bytes, int flags) {
+  IGP_REQUIRE((flags & ~IGP_BATCH_DEVICE_CONTROL) == 0, "unknown batched-step flags %d", flags);
+  const bool dc = (flags & IGP_BATCH_DEVICE_CONTROL) != 0;
   Batch b;
   IGP_TRY(batch_models(models, n, &b.ms, &b.kind, &b.dch, &b.stream, &b.bf16));
   IGP_TRY(b.carve_ws(ws, ws_bytes));
@@ -1282,6 +1488,12 @@ int newton_step_batched(igp_model* const* models, int n, igp_step_info* infos, v
   for (auto* m : ms) IGP_TRY(m->phase_v0());
   IGP_TRY(b.read_all());
   for (auto* m : ms) m->phase_start_iterations();
+  if (dc) {
+    for (auto* m : ms) {
+      IGP_TRY(iter_gate_init(m->L.gate, m->L.rec, b.stream));
+      for (double& x : m->rec_h) x = 0.0;
+    }
+  }
   std::vector<int> act;
   for (;;) {
     act.clear();
@@ -1290,6 +1502,30 @@ int newton_step_batched(igp_model* const* models, int n, igp_step_info* infos, v
       if (ms[i]->st.active) act.push_back(i);
     }
     if (act.empty()) break;
+    if (dc) {
+      // a window of up to DC_WINDOW rounds, the host reading the records once:
+      // model i takes rounds 0 .. cap_i - 1, its gate skips those after it stops
+      std::vector<int> cap(n, 0);
+      int R = 0;
+      for (int i : act) {
+        cap[i] = ms[i]->window_cap(Batch::DC_WINDOW);
+        R = std::max(R, cap[i]);
+      }
+      std::vector<std::vector<int>> rounds(R);
+      for (int k = 0; k < R; ++k)
+        for (int i : act)
+          if (k < cap[i]) rounds[k].push_back(i);
+      const int rc = R > 0 ? b.dc_window(rounds) : IGP_EUNSUPPORTED;
+      if (rc == IGP_OK) {
+        IGP_TRY(b.read_records());
+        for (int i : act)
+          IGP_TRY(ms[i]->consume_dc(&b.hrec[static_cast<size_t>(i) * REC_COUNT], cap[i]));
+        continue;
+      }
+      if (rc != IGP_EUNSUPPORTED) return rc;
+      clear_error();
+      // a launch shape not timed yet: one round under host control times it
+    }
     for (int i : act) ms[i]->host_action();
     IGP_TRY(b.iter_group(act, BOP_ACTION, BOP_FIN_ALPHA + 1));   // s_j, alpha_j
     IGP_TRY(b.products(act, false));                    // t_j = K s_j for every active model

@@ -949,6 +949,7 @@ kv_batched_persistent(const BatchProblem* __restrict__ probs, int np, int64_t nt
       else hi = mid - 1;
     }
     const BatchProblem& pb = probs[lo];
+    if (pb.gate && gate_closed(pb.gate)) continue;   // the problem's solver has stopped
     const int64_t local = t - pb.tile_begin;
     const int64_t rb = local % pb.gx, sp = local / pb.gx;
     const int64_t m_begin = sp * pb.cols_per_split;
@@ -993,6 +994,7 @@ __global__ void kv_reduce_batched(const BatchProblem* __restrict__ probs, int np
       else hi = mid - 1;
     }
     const BatchProblem& pb = probs[lo];
+    if (pb.gate && gate_closed(pb.gate)) continue;
     const int64_t e = idx - pb.out_begin;
     const int64_t n = e / pb.W;
     const int w = static_cast<int>(e % pb.W);

@@ -23,30 +23,6 @@ __global__ void k_finish_sum(const double* __restrict__ part, int nblk, double* 
   iter::finish_sum(part, nblk, out, red);
 }
 
-// end of a solver iteration (one thread): unless the gate is closed, count it,
-// close the gate on a breakdown (eta <= 0) or convergence, keep min eta and rr
-__device__ inline void consume_iteration(const double* __restrict__ scal, double thresh,
-                                         int next_r, int* gate, double* rec) {
-  if (gate_closed(gate)) return;
-  rec[REC_EXEC] = coherent_load(rec + REC_EXEC) + 1.0;
-  const double eta = coherent_load(scal + SC_ETA);
-  if (!(eta > 0.0)) {   // breakdown: the iteration's column was not appended
-    rec[REC_BREAK] = 1.0;
-    __hip_atomic_store(gate, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return;
-  }
-  rec[REC_APPEND] = coherent_load(rec + REC_APPEND) + 1.0;
-  rec[REC_ETAMIN] = fmin(coherent_load(rec + REC_ETAMIN), eta);
-  if (next_r) {
-    const double rr = coherent_load(scal + SC_RR);
-    rec[REC_RR] = rr;
-    if (!(sqrt(rr) >= thresh)) {
-      rec[REC_CONV] = 1.0;
-      __hip_atomic_store(gate, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
-}
-
 template <typename T>
 __global__ void __launch_bounds__(NT)
 k_residual(const T* __restrict__ rhs, const T* __restrict__ kv, const T* __restrict__ wv,
@@ -63,7 +39,7 @@ __global__ void k_finish_rr_consume(const double* __restrict__ part, int nblk,
   if (gate_closed(gate)) return;
   __shared__ double red[NT / 64];
   iter::finish_sum(part, nblk, scal + SC_RR, red);
-  if (threadIdx.x == 0) consume_iteration(scal, thresh, 1, gate, rec);
+  if (threadIdx.x == 0) iter::consume_iteration(scal, thresh, 1, gate, rec);
 }
 
 template <typename T>
@@ -363,7 +339,7 @@ __global__ void k_iter_gate_init(int* gate, double* rec) {
 
 __global__ void k_iter_consume(const double* __restrict__ scal, double thresh, int next_r,
                                int* gate, double* rec) {
-  if (threadIdx.x == 0) consume_iteration(scal, thresh, next_r, gate, rec);
+  if (threadIdx.x == 0) iter::consume_iteration(scal, thresh, next_r, gate, rec);
 }
 
 }  // namespace

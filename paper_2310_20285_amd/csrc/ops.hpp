@@ -105,6 +105,7 @@ struct BatchProblem {
   int64_t ldo;
   int64_t tile_begin;       // prefix over problems of gx * nsplit
   int64_t out_begin;        // prefix over problems of n1 * W
+  const int* gate;          // device control: the problem's iteration gate (or null)
 };
 // One model's part of a batched solver iteration (recurrence residual, FP32):
 // the vectors and scalars the per-iteration operations touch.
@@ -115,6 +116,13 @@ struct BIter {
   double *scal, *part, *yb;
   int64_t n, N, ld, unit_idx;
   int C, ncols, lik, policy, nchunks, pad;
+  // device control (null gate: the host decides after every round): every
+  // operation of a closed gate returns at once; BOP_FIN_RR ends the iteration
+  // (iter::consume_iteration with thresh and next_r) even without a residual
+  int* gate;
+  double* rec;
+  double thresh;
+  int next_r, pad2;
 };
 // operations of a batched iteration, in launch order
 enum BIterOp {

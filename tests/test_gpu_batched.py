@@ -8,6 +8,11 @@ different N and C.
   match the FP64 oracle within 1e-4.
 * Free-running CG in the batch matches the oracle's iteration counts within
   one and its iterates within 1e-3 (the CG iterate's own rounding sensitivity).
+* Device control (IGP_BATCH_DEVICE_CONTROL: windows of iterations decided on
+  the device, one host read per window) against host control on identical
+  models: the same iteration counts, flags and product counts, and bitwise
+  the same iterates (FP32 and BF16, free-running CG, models stopping at
+  different iterations inside a window).
 * BF16 models (distance on the BF16 matrix cores, inputs rounded to BF16):
   the batched step (narrow BF16 tile) and the single-model step (the wide
   BF16 kernel, whose contraction takes BF16 hi/lo parts of K and V) agree to
@@ -127,3 +132,23 @@ def test_batched_rejects_mixed_precision(gpu_lib):
     w = datagen.config4(seed=1, n_problems=1, n_lo=200, n_hi=300)[0]
     with pytest.raises(Exception):
         api.newton_step_batched([_model(w, "cg", "fp32"), _model(w, "cg", "bf16")])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_device_control_matches_host_control(gpu_lib, precision):
+    probs = _problems(k=6, seed=19)
+    host = [_model(w, "cg", precision) for w, _ in probs]
+    dev = [_model(w, "cg", precision) for w, _ in probs]
+    wsh = wsd = None
+    keys = ("iters", "breakdown", "converged", "buffer_cols", "recycled_cols", "k_products")
+    for step in range(3):
+        ih, wsh = api.newton_step_batched(host, wsh)
+        idv, wsd = api.newton_step_batched(dev, wsd, device_control=True)
+        print(f"{precision} step {step + 1}: iterations "
+              f"{[i['iters'] for i in ih]} (host) {[i['iters'] for i in idv]} (device)",
+              flush=True)
+        for (w, _), mh, md, a, b in zip(probs, host, dev, ih, idv):
+            for k in keys:
+                assert a[k] == b[k], (step, w.name, k, a[k], b[k])
+            assert torch.equal(mh.view(0), md.view(0)), (step, w.name)
+            assert torch.equal(mh.view(1), md.view(1)), (step, w.name)

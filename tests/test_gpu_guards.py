@@ -93,10 +93,12 @@ def test_breakdown_zero_action_matches_oracle(gpu_lib, small, residual, zero_at)
         assert _rel(Q @ Q.T, rec.Q @ rec.Q.T) <= 1e-10
 
 
-def test_breakdown_in_batched_step_matches_single(gpu_lib, small):
+@pytest.mark.parametrize("device_control", [False, True])
+def test_breakdown_in_batched_step_matches_single(gpu_lib, small, device_control):
     """FP32, recurrence residual: a batch of three models, one with a zero
     action at the 3rd position, one at the 5th, one without, against the same
-    models stepped one at a time with the same actions."""
+    models stepped one at a time with the same actions; with device control
+    the breakdowns fall inside a window of iterations."""
     w, _ = small
     n = w.N * w.C
     zeros = [2, 4, None]
@@ -111,7 +113,7 @@ def test_breakdown_in_batched_step_matches_single(gpu_lib, small):
             for m in (mb, ms):
                 m.set_user_actions(torch.tensor(a[step].T.copy(), dtype=torch.float32,
                                                 device="cuda"))
-        infos, buf = api.newton_step_batched(batch, buf)
+        infos, buf = api.newton_step_batched(batch, buf, device_control=device_control)
         for k, (mb, ms) in enumerate(zip(batch, single)):
             si = ms.newton_step()
             bi = infos[k]
