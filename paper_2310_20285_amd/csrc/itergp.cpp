@@ -1112,8 +1112,51 @@ struct Batch {
   std::vector<double> hrec;
   std::vector<unsigned char> hwin;
 
+  // partial slots of a model's product: the one-sided tiles' splits, or the
+  // symmetric plan's super-blocks (FP32)
   static size_t partial_floats(const Model<float>* m) {
-    return static_cast<size_t>(ceil_div(m->N, TUNE_SPLITS[0]) + 1) * m->N * m->C;
+    size_t f = static_cast<size_t>(ceil_div(m->N, TUNE_SPLITS[0]) + 1) * m->N * m->C;
+    BatchProblem bp{};
+    if (m->cfg.precision == IGP_FP32 && batched_sym_plan(m->N, m->D, m->C, &bp))
+      f = std::max(f, static_cast<size_t>(bp.sym_q) * m->N * m->C);
+    return f;
+  }
+
+  // a product's partial slots must fit the model's partial area
+  static int check_partials(const BatchProblem& bp, const Model<float>* m) {
+    IGP_REQUIRE(static_cast<size_t>(bp.nsplit) * bp.n1 * bp.W <= partial_floats(m),
+                "batched product partials exceed the model's partial area");
+    return IGP_OK;
+  }
+
+  // the launch layout of one round's products: symmetric problems first,
+  // sorted by output width (one group and launch per width)
+  struct Layout {
+    std::vector<SymGroup> groups;
+    int64_t tiles = 0, outs = 0;
+  };
+  Layout lay_out(BatchProblem* tb, size_t n) const {
+    auto* mid = std::stable_partition(tb, tb + n, [](const BatchProblem& b) { return b.sym_q > 0; });
+    std::stable_sort(tb, mid, [](const BatchProblem& a, const BatchProblem& b) { return a.W < b.W; });
+    Layout L;
+    for (size_t q = 0; q < n; ++q) {
+      BatchProblem& bp = tb[q];
+      if (bp.sym_q > 0) {
+        if (L.groups.empty() || L.groups.back().W != bp.W)
+          L.groups.push_back(SymGroup{static_cast<int>(q), 0, bp.W, 0, 0});
+        SymGroup& g = L.groups.back();
+        bp.tile_begin = g.tiles;
+        g.tiles += batched_tiles(bp);
+        ++g.count;
+        g.lds = std::max(g.lds, batched_sym_lds(bp, dch));
+      } else {
+        bp.tile_begin = L.tiles;
+        L.tiles += batched_tiles(bp);
+      }
+      bp.out_begin = L.outs;
+      L.outs += bp.n1 * bp.W;
+    }
+    return L;
   }
 
   static size_t ws_bytes(const std::vector<Model<float>*>& ms) {
@@ -1121,7 +1164,7 @@ struct Batch {
     cv.take<BIter>(ms.size());
     cv.take<int64_t>(static_cast<size_t>(BOP_COUNT) * (ms.size() + 1));
     cv.take<BatchProblem>(ms.size());
-    cv.take<int64_t>(1);
+    cv.take<int64_t>(BATCH_COUNTERS);
     cv.take<const double*>(ms.size());
     cv.take<double>(ms.size() * SC_COUNT);
     cv.take<BIter>(DC_WINDOW * ms.size());
@@ -1140,7 +1183,7 @@ struct Batch {
     dit = cv.take<BIter>(ms.size());
     dpre = cv.take<int64_t>(static_cast<size_t>(BOP_COUNT) * (ms.size() + 1));
     dtab = cv.take<BatchProblem>(ms.size());
-    counter = reinterpret_cast<int*>(cv.take<int64_t>(1));
+    counter = reinterpret_cast<int*>(cv.take<int64_t>(BATCH_COUNTERS));
     dscal = cv.take<const double*>(ms.size());
     gathered = cv.take<double>(ms.size() * SC_COUNT);
     dit_w = cv.take<BIter>(DC_WINDOW * ms.size());
@@ -1222,7 +1265,7 @@ struct Batch {
           hwin.data() + (reinterpret_cast<char*>(dtab_w + k * nmod) - base));
     };
     std::vector<std::vector<int64_t>> totals(R, std::vector<int64_t>(BOP_COUNT, 0));
-    std::vector<int64_t> ptiles(R, 0), pouts(R, 0);
+    std::vector<Layout> lay(R);
     for (size_t k = 0; k < R; ++k) {
       const auto& idx = rounds[k];
       BIter* ht = hit(k);
@@ -1243,15 +1286,13 @@ struct Batch {
         Model<float>* m = ms[idx[q]];
         const KVProblem kp = m->product_action_at(m->ncols + static_cast<int>(k));
         BatchProblem& bp = tb[q];
-        bp = problem_of(kp, tv[k].ns, tv[k].split_rows);
+        bp = problem_of(kp, tv[k].ns, tv[k].split_rows, !bf16);
+        IGP_TRY(check_partials(bp, m));
         bp.P = partials + poff;
         poff += align_up(partial_floats(m) * sizeof(float)) / sizeof(float);
         bp.gate = m->L.gate;
-        bp.tile_begin = ptiles[k];
-        bp.out_begin = pouts[k];
-        ptiles[k] += static_cast<int64_t>(bp.gx) * bp.nsplit;
-        pouts[k] += bp.n1 * bp.W;
       }
+      lay[k] = lay_out(tb, idx.size());
     }
     IGP_CHECK_HIP(hipMemcpyAsync(base, hwin.data(), bytes, hipMemcpyHostToDevice, stream));
     for (size_t k = 0; k < R; ++k) {
@@ -1261,8 +1302,9 @@ struct Batch {
       for (int op = BOP_ACTION; op <= BOP_FIN_ALPHA; ++op)
         IGP_TRY(biter_launch(op, dt, dpre_w + (k * BOP_COUNT + op) * pre_len, nm, totals[k][op],
                              stream));
-      IGP_TRY(kv_batched_run(kind, dch, tv[k].ns, bf16, dtab_w + k * nmod, nm, ptiles[k],
-                             pouts[k], counter, stream));
+      IGP_TRY(kv_batched_run(kind, dch, tv[k].ns, bf16, dtab_w + k * nmod, nm,
+                             lay[k].groups.data(), static_cast<int>(lay[k].groups.size()),
+                             lay[k].tiles, lay[k].outs, counter, stream));
       for (int op = BOP_WINV_Z; op < BOP_COUNT; ++op)
         IGP_TRY(biter_launch(op, dt, dpre_w + (k * BOP_COUNT + op) * pre_len, nm, totals[k][op],
                              stream));
@@ -1322,7 +1364,8 @@ struct Batch {
 
   // one model's product in the batched launch (partials, tile and output
   // offsets and gate are set by the caller)
-  static BatchProblem problem_of(const KVProblem& kp, int ns, int64_t split_rows) {
+  // (sym: FP32, where the symmetric plan applies to K(X, X) V)
+  static BatchProblem problem_of(const KVProblem& kp, int ns, int64_t split_rows, bool sym) {
     BatchProblem bp{};
     bp.X1p = kp.X1p;
     bp.nrm1 = kp.norm1;
@@ -1335,6 +1378,8 @@ struct Batch {
     bp.C = static_cast<int>(kp.C);
     bp.W = static_cast<int>(kp.C * kp.nb);
     batched_plan(bp.n1, bp.n2, bp.W, ns, split_rows, &bp);
+    if (sym && kp.X1p == kp.X2p && kp.norm1 == kp.norm2 && kp.n1 == kp.n2)
+      batched_sym_plan(bp.n1, kp.d, bp.W, &bp);
     const double inv_l2 = 1.0 / (kp.kp.lengthscale * kp.kp.lengthscale);
     const float kap = kv_kappa(kp.kp.kind);
     bp.cnorm = static_cast<float>(kap * inv_l2);
@@ -1348,18 +1393,14 @@ struct Batch {
   // one persistent launch for the products of the selected models
   int run_products(const std::vector<int>& idx, bool update, int ns, int64_t split_rows) {
     htab.clear();
-    int64_t tiles = 0, outs = 0;
     size_t poff = 0;
     for (int i : idx) {
       Model<float>* m = ms[i];
       const KVProblem kp = update ? m->product_update() : m->product_action();
-      BatchProblem bp = problem_of(kp, ns, split_rows);
+      BatchProblem bp = problem_of(kp, ns, split_rows, !bf16);
+      IGP_TRY(check_partials(bp, m));
       bp.P = partials + poff;
       poff += align_up(partial_floats(m) * sizeof(float)) / sizeof(float);
-      bp.tile_begin = tiles;
-      bp.out_begin = outs;
-      tiles += static_cast<int64_t>(bp.gx) * bp.nsplit;
-      outs += bp.n1 * bp.W;
       htab.push_back(bp);
       if (m->prof) {
         m->pending_evals += static_cast<double>(bp.n1) * bp.n2;
@@ -1367,9 +1408,11 @@ struct Batch {
       }
     }
     if (htab.empty()) return IGP_OK;
+    const Layout L = lay_out(htab.data(), htab.size());
     IGP_CHECK_HIP(hipMemcpyAsync(dtab, htab.data(), htab.size() * sizeof(BatchProblem),
                                  hipMemcpyHostToDevice, stream));
-    return kv_batched_run(kind, dch, ns, bf16, dtab, static_cast<int>(htab.size()), tiles, outs,
+    return kv_batched_run(kind, dch, ns, bf16, dtab, static_cast<int>(htab.size()),
+                          L.groups.data(), static_cast<int>(L.groups.size()), L.tiles, L.outs,
                           counter, stream);
   }
 

@@ -625,13 +625,36 @@ struct ClassScale {
   float os[8];    // outputscale of class w
 };
 
-template <int KIND, int DCH, int WX, bool PC = false>
-__global__ void __launch_bounds__(256)
-kv_mfma_f32_sym(const float* __restrict__ Xp, const float* __restrict__ nrm, int64_t n,
-                const float* __restrict__ V, int C, int64_t ldv, float* __restrict__ P, int G,
-                int Q, float cnorm, float cdot, ClassScale cs, const int* skip) {
+// Item t of a symmetric plan with Q super-blocks -> pair (s, u): the
+// Q (Q - 1) / 2 pairs u > s first (those of super-blocks before s number
+// s (Q - 1) - s (s - 1) / 2), then the Q diagonal pairs, which take about half
+// the work, at the end.
+__device__ inline void sym_pair(int t, int Q, int& s, int& u) {
+  const int noff = Q * (Q - 1) / 2;
+  if (t >= noff) {
+    s = u = t - noff;
+    return;
+  }
+  int lo = 0, hi = Q - 2;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (mid * (Q - 1) - mid * (mid - 1) / 2 <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  s = lo;
+  u = s + 1 + (t - (s * (Q - 1) - s * (s - 1) / 2));
+}
+
+// One item (super-block pair (s, u)) of the symmetric product on a workgroup of
+// 256 threads; smem holds sym_lds_bytes(DCH, WX, G) bytes of LDS.  Every
+// thread takes the same path (the barriers inside are workgroup-uniform).
+template <int KIND, int DCH, int WX, bool PC>
+__device__ __forceinline__ void sym_item(float* smem, const float* __restrict__ Xp,
+                                         const float* __restrict__ nrm, int64_t n,
+                                         const float* __restrict__ V, int C, int64_t ldv,
+                                         float* __restrict__ P, int G, int s, int u,
+                                         float cnorm, float cdot, const ClassScale& cs) {
   static_assert(!PC || WX <= 8, "per-class columns are at most 8");
-  if (gate_closed(skip)) return;
   using L = SymLayout<DCH, WX>;
   constexpr int NS = SYM_NS;
   constexpr int DP = L::DP, XS = L::XS, VS = L::VS;
@@ -639,7 +662,6 @@ kv_mfma_f32_sym(const float* __restrict__ Xp, const float* __restrict__ nrm, int
   constexpr int VT = TN * WX;
   constexpr int VE = (VT + 255) / 256;
   constexpr int IB = 64 * NS;
-  extern __shared__ __align__(16) float smem[];
   float* sX = smem;                        // [2][TN * XS]
   float* sN = sX + 2 * TN * XS;            // [2][TN]
   float* sV = sN + 2 * TN;                 // [2][WX * VS]
@@ -651,24 +673,6 @@ kv_mfma_f32_sym(const float* __restrict__ Xp, const float* __restrict__ nrm, int
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, r = lane & 15;
 
-  // workgroup -> pair (s, u): the Q (Q - 1) / 2 pairs u > s first (those of
-  // super-blocks before s number s (Q - 1) - s (s - 1) / 2), then the Q
-  // diagonal pairs, which take about half the work, at the end of the grid
-  const int t = static_cast<int>(blockIdx.x);
-  const int noff = Q * (Q - 1) / 2;
-  int s, u;
-  if (t >= noff) {
-    s = u = t - noff;
-  } else {
-    int lo = 0, hi = Q - 2;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (mid * (Q - 1) - mid * (mid - 1) / 2 <= t) lo = mid;
-      else hi = mid - 1;
-    }
-    s = lo;
-    u = s + 1 + (t - (s * (Q - 1) - s * (s - 1) / 2));
-  }
   const bool diag_item = u == s;
   const int64_t j_lo = u * ST;
   const int64_t j_hi = (u + 1) * ST < n ? (u + 1) * ST : n;
@@ -903,6 +907,18 @@ kv_mfma_f32_sym(const float* __restrict__ Xp, const float* __restrict__ nrm, int
   }
 }
 
+template <int KIND, int DCH, int WX, bool PC = false>
+__global__ void __launch_bounds__(256)
+kv_mfma_f32_sym(const float* __restrict__ Xp, const float* __restrict__ nrm, int64_t n,
+                const float* __restrict__ V, int C, int64_t ldv, float* __restrict__ P, int G,
+                int Q, float cnorm, float cdot, ClassScale cs, const int* skip) {
+  if (gate_closed(skip)) return;
+  extern __shared__ __align__(16) float smem[];
+  int s, u;
+  sym_pair(static_cast<int>(blockIdx.x), Q, s, u);
+  sym_item<KIND, DCH, WX, PC>(smem, Xp, nrm, n, V, C, ldv, P, G, s, u, cnorm, cdot, cs);
+}
+
 // ---- persistent batched launch -------------------------------------------------
 // Every product of a batch (independent problems of different sizes, output
 // widths and hyperparameters; same kernel family and feature count) is cut
@@ -980,7 +996,9 @@ kv_batched_persistent(const BatchProblem* __restrict__ probs, int np, int64_t nt
 }
 
 __global__ void k_zero_counter(int* c) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) reinterpret_cast<unsigned long long*>(c)[0] = 0ull;
+  // the queue counters of a batched launch
+  if (threadIdx.x < BATCH_COUNTERS && blockIdx.x == 0)
+    reinterpret_cast<unsigned long long*>(c)[threadIdx.x] = 0ull;
 }
 
 __global__ void kv_reduce_batched(const BatchProblem* __restrict__ probs, int np,
@@ -1010,6 +1028,41 @@ __global__ void kv_reduce_batched(const BatchProblem* __restrict__ probs, int np
     }
     for (; sp < pb.nsplit; ++sp) s0 += q[sp * stride];
     pb.Out[(w / pb.C) * pb.ldo + n * pb.C + (w % pb.C)] = pb.os * ((s0 + s1) + (s2 + s3));
+  }
+}
+
+// The symmetric FP32 products of a batch with W output columns (problems whose
+// plan admits the symmetric kernel): items (problem, super-block pair) from
+// one queue, each run by sym_item with the problem's own plan (G, Q), so the
+// partial slots -- and after kv_reduce_batched the product -- are those of the
+// single-problem launch, bit for bit.  One instantiation per W keeps the
+// single kernel's register budget.  Dynamic LDS: the largest plan's bytes.
+template <int KIND, int DCH, int WX>
+__global__ void __launch_bounds__(256)
+kv_batched_sym(const BatchProblem* __restrict__ probs, int np, int64_t ntiles,
+               int* __restrict__ counter) {
+  extern __shared__ __align__(16) float smem[];
+  __shared__ int64_t s_tile;
+  const ClassScale none{};
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(reinterpret_cast<unsigned long long*>(counter), 1ull);
+    __syncthreads();
+    const int64_t t = s_tile;
+    __syncthreads();
+    if (t >= ntiles) break;
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (probs[mid].tile_begin <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const BatchProblem& pb = probs[lo];
+    if (pb.gate && gate_closed(pb.gate)) continue;   // the problem's solver has stopped
+    int su, uu;
+    sym_pair(static_cast<int>(t - pb.tile_begin), pb.sym_q, su, uu);
+    sym_item<KIND, DCH, WX, false>(smem, static_cast<const float*>(pb.X1p), pb.nrm1, pb.n1, pb.V,
+                                   pb.C, pb.ldv, pb.P, pb.sym_g, su, uu, pb.cnorm, pb.cdot,
+                                   none);
   }
 }
 
@@ -1455,22 +1508,99 @@ void batched_plan(int64_t n1, int64_t n2, int64_t W, int ns, int64_t split_rows,
   (void)W;
 }
 
+bool batched_sym_plan(int64_t n, int64_t d, int64_t W, BatchProblem* bp) {
+  const SymPlan sp = plan_sym(n, d, W);
+  if (!sp.ok) return false;
+  bp->sym_g = sp.G;
+  bp->sym_q = sp.Q;
+  bp->nsplit = sp.Q;
+  bp->gx = 0;
+  bp->cols_per_split = 0;
+  return true;
+}
+
+size_t batched_sym_lds(const BatchProblem& bp, int dch) {
+  return sym_lds_bytes(dch, bp.W, bp.sym_g);
+}
+
+int64_t batched_tiles(const BatchProblem& bp) {
+  if (bp.sym_q > 0) return static_cast<int64_t>(bp.sym_q) * (bp.sym_q + 1) / 2;
+  return static_cast<int64_t>(bp.gx) * bp.nsplit;
+}
+
+namespace {
+template <int KIND, int DCH>
+void launch_batched_sym(const SymGroup& g, const BatchProblem* dprobs, int* counter,
+                        hipStream_t s) {
+  const int grid = static_cast<int>(std::min<int64_t>(g.tiles, 256 * 4));
+  const BatchProblem* pr = dprobs + g.first;
+  switch (g.W) {
+#define IGP_BS(K)                                                                              \
+  case K: kv_batched_sym<KIND, DCH, K><<<grid, 256, g.lds, s>>>(pr, g.count, g.tiles, counter); break;
+    IGP_BS(1) IGP_BS(2) IGP_BS(3) IGP_BS(4) IGP_BS(5) IGP_BS(6) IGP_BS(7) IGP_BS(8)
+#undef IGP_BS
+    default: break;
+  }
+}
+}  // namespace
+
 int kv_batched_run(int kind, int dch, int ns, bool bf16, const BatchProblem* dprobs, int np,
-                   int64_t ntiles, int64_t total_out, int* counter, hipStream_t s) {
+                   const SymGroup* groups, int ngroups, int64_t ntiles, int64_t total_out,
+                   int* counter, hipStream_t s) {
+  // validate the symmetric groups against the table (contiguous from 0)
+  int nsym = 0;
+  if (ngroups < 0 || ngroups > BATCH_COUNTERS - 1 || (ngroups > 0 && (bf16 || dch > 2))) {
+    set_error("batched launch: bad symmetric groups");
+    return IGP_EINVAL;
+  }
+  for (int k = 0; k < ngroups; ++k) {
+    const SymGroup& g = groups[k];
+    if (g.first != nsym || g.count < 1 || g.W < 1 || g.W > 8 || g.tiles < 1 ||
+        g.lds > SYM_MAX_LDS) {
+      set_error("batched launch: bad symmetric groups");
+      return IGP_EINVAL;
+    }
+    nsym += g.count;
+  }
+  if (nsym > np) {
+    set_error("batched launch: bad symmetric groups");
+    return IGP_EINVAL;
+  }
   k_zero_counter<<<1, 64, 0, s>>>(counter);
-  if (ntiles > 0) {
+  for (int k = 0; k < ngroups; ++k) {
+    int* ck = counter + 2 * k;
+    switch (kind) {
+      case IGP_RBF:
+        if (dch == 1) launch_batched_sym<IGP_RBF, 1>(groups[k], dprobs, ck, s);
+        else launch_batched_sym<IGP_RBF, 2>(groups[k], dprobs, ck, s);
+        break;
+      case IGP_MATERN32:
+        if (dch == 1) launch_batched_sym<IGP_MATERN32, 1>(groups[k], dprobs, ck, s);
+        else launch_batched_sym<IGP_MATERN32, 2>(groups[k], dprobs, ck, s);
+        break;
+      default:
+        if (dch == 1) launch_batched_sym<IGP_MATERN52, 1>(groups[k], dprobs, ck, s);
+        else launch_batched_sym<IGP_MATERN52, 2>(groups[k], dprobs, ck, s);
+        break;
+    }
+  }
+  // the one-sided problems: their own queue counter (the last) and tile prefixes
+  const BatchProblem* oprobs = dprobs + nsym;
+  const int onp = np - nsym;
+  int* c1 = counter + 2 * (BATCH_COUNTERS - 1);
+  if (ntiles > 0 && onp > 0) {
     const int grid = static_cast<int>(std::min<int64_t>(ntiles, 256 * 4));
     if (ns == 1) {
       switch (kind) {
-        case IGP_RBF: launch_batched_kind<IGP_RBF, 1>(dch, bf16, dprobs, np, ntiles, counter, grid, s); break;
-        case IGP_MATERN32: launch_batched_kind<IGP_MATERN32, 1>(dch, bf16, dprobs, np, ntiles, counter, grid, s); break;
-        default: launch_batched_kind<IGP_MATERN52, 1>(dch, bf16, dprobs, np, ntiles, counter, grid, s); break;
+        case IGP_RBF: launch_batched_kind<IGP_RBF, 1>(dch, bf16, oprobs, onp, ntiles, c1, grid, s); break;
+        case IGP_MATERN32: launch_batched_kind<IGP_MATERN32, 1>(dch, bf16, oprobs, onp, ntiles, c1, grid, s); break;
+        default: launch_batched_kind<IGP_MATERN52, 1>(dch, bf16, oprobs, onp, ntiles, c1, grid, s); break;
       }
     } else {
       switch (kind) {
-        case IGP_RBF: launch_batched_kind<IGP_RBF, 2>(dch, bf16, dprobs, np, ntiles, counter, grid, s); break;
-        case IGP_MATERN32: launch_batched_kind<IGP_MATERN32, 2>(dch, bf16, dprobs, np, ntiles, counter, grid, s); break;
-        default: launch_batched_kind<IGP_MATERN52, 2>(dch, bf16, dprobs, np, ntiles, counter, grid, s); break;
+        case IGP_RBF: launch_batched_kind<IGP_RBF, 2>(dch, bf16, oprobs, onp, ntiles, c1, grid, s); break;
+        case IGP_MATERN32: launch_batched_kind<IGP_MATERN32, 2>(dch, bf16, oprobs, onp, ntiles, c1, grid, s); break;
+        default: launch_batched_kind<IGP_MATERN52, 2>(dch, bf16, oprobs, onp, ntiles, c1, grid, s); break;
       }
     }
   }

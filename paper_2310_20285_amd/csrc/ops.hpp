@@ -106,6 +106,9 @@ struct BatchProblem {
   int64_t tile_begin;       // prefix over problems of gx * nsplit
   int64_t out_begin;        // prefix over problems of n1 * W
   const int* gate;          // device control: the problem's iteration gate (or null)
+  // symmetric plan (FP32, K(X, X) V): sym_q super-blocks of sym_g row blocks,
+  // sym_q (sym_q + 1) / 2 items, nsplit = sym_q partial slots; 0: one-sided tiles
+  int sym_g, sym_q;
 };
 // One model's part of a batched solver iteration (recurrence residual, FP32):
 // the vectors and scalars the per-iteration operations touch.
@@ -140,8 +143,30 @@ int biter_launch(int op, const BIter* tab, const int64_t* pre, int nm, int64_t t
                  hipStream_t s);
 bool batched_supported(int kind, int64_t d, int64_t W);
 void batched_plan(int64_t n1, int64_t n2, int64_t W, int ns, int64_t split_rows, BatchProblem* bp);
+// The symmetric plan of an FP32 product K(X, X) V (n rows, d features, W
+// columns) in the batched launch: sets sym_g, sym_q and nsplit and returns
+// true, or returns false (the problem takes one-sided tiles).  The plan is the
+// single-problem launch's, so the product equals that launch's bit for bit.
+bool batched_sym_plan(int64_t n, int64_t d, int64_t W, BatchProblem* bp);
+// LDS bytes of a symmetric problem's items; workgroup tiles of a problem
+size_t batched_sym_lds(const BatchProblem& bp, int dch);
+int64_t batched_tiles(const BatchProblem& bp);
+// The symmetric problems of one output width W: dprobs[first, first + count),
+// tile prefixes over them from 0, `tiles` items, `lds` the largest plan's LDS.
+struct SymGroup {
+  int first, count, W;
+  int64_t tiles;
+  size_t lds;
+};
+// 64-bit queue counters a batched launch needs (one per symmetric group, one
+// for the one-sided problems)
+constexpr int BATCH_COUNTERS = 16;
+// The products of a batch: the symmetric groups (problems sorted by W, first
+// in the table), then dprobs[nsym, np) one-sided (tile prefixes from 0, ntiles
+// tiles), then one reduction over all np (out_begin prefixes over all).
 int kv_batched_run(int kind, int dch, int ns, bool bf16, const BatchProblem* dprobs, int np,
-                   int64_t ntiles, int64_t total_out, int* counter, hipStream_t s);
+                   const SymGroup* groups, int ngroups, int64_t ntiles, int64_t total_out,
+                   int* counter, hipStream_t s);
 float kv_kappa(int kind);
 // BF16 products with few features on the narrow BF16 tile (kv_mfma.hip)
 bool bf16_narrow_supported(int kind, int64_t d, int64_t W);

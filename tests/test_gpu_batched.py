@@ -3,9 +3,13 @@ solver iteration covering the products of many independent problems of
 different N and C.
 
 * With each problem's actions fixed (policy USER, the FP64 oracle's CG
-  actions), the batched step and the single-model step agree to FP32 rounding
-  (they differ only in how the products' split partials are summed), and both
-  match the FP64 oracle within 1e-4.
+  actions), the batched step and the single-model step agree (asserted to
+  1e-5), and both match the FP64 oracle within 1e-4.
+* FP32 products K(X, X) V take the symmetric plan in the batch (one launch per
+  output width, each problem's own super-block plan), which is the
+  single-model launch's: batched and single-model steps agree bit for bit,
+  free-running CG.  A problem too large for that plan (N = 16500, C = 5) runs
+  on one-sided tiles in the same batch and agrees to FP32 rounding.
 * Free-running CG in the batch matches the oracle's iteration counts within
   one and its iterates within 1e-3 (the CG iterate's own rounding sensitivity).
 * Device control (IGP_BATCH_DEVICE_CONTROL: windows of iterations decided on
@@ -152,3 +156,37 @@ def test_device_control_matches_host_control(gpu_lib, precision):
                 assert a[k] == b[k], (step, w.name, k, a[k], b[k])
             assert torch.equal(mh.view(0), md.view(0)), (step, w.name)
             assert torch.equal(mh.view(1), md.view(1)), (step, w.name)
+
+
+def test_batched_fp32_symmetric_equals_single_bitwise(gpu_lib):
+    ws_ = datagen.config4(seed=11, n_problems=6, n_lo=200, n_hi=3000)
+    batch = [_model(w, "cg") for w in ws_]
+    single = [_model(w, "cg") for w in ws_]
+    buf = None
+    for step in range(2):
+        infos, buf = api.newton_step_batched(batch, buf)
+        for w, mb, ms, ib in zip(ws_, batch, single, infos):
+            isg = ms.newton_step()
+            assert ib["iters"] == isg["iters"], (step, w.name, ib["iters"], isg["iters"])
+            assert torch.equal(mb.view(0), ms.view(0)), (step, w.name)
+            assert torch.equal(mb.view(1), ms.view(1)), (step, w.name)
+
+
+def test_batched_mixed_symmetric_and_one_sided(gpu_lib):
+    small = datagen.config4(seed=12, n_problems=4, n_lo=300, n_hi=1500)
+    big = datagen.gp_classification(13, 16500, 8, 5, "matern32", 1.0, 1.0, F=512, name="big")
+    ws_ = small[:2] + [big] + small[2:]
+    batch = [_model(w, "cg") for w in ws_]
+    single = [_model(w, "cg") for w in ws_]
+    infos, _ = api.newton_step_batched(batch)
+    for w, mb, ms, ib in zip(ws_, batch, single, infos):
+        isg = ms.newton_step()
+        if w is big:
+            assert abs(ib["iters"] - isg["iters"]) <= 1, (ib["iters"], isg["iters"])
+            Fb = mb.view(0).double().cpu().numpy()
+            Fs = ms.view(0).double().cpu().numpy()
+            assert _rel(Fb, Fs) <= 1e-4, _rel(Fb, Fs)
+        else:
+            assert ib["iters"] == isg["iters"], (w.name, ib["iters"], isg["iters"])
+            assert torch.equal(mb.view(0), ms.view(0)), w.name
+            assert torch.equal(mb.view(1), ms.view(1)), w.name
