@@ -58,7 +58,7 @@ KV_SAMPLE = 3
 # copy in the same run; profiles/kv_matern52_N20000_D16_C5_fp32.md and
 # profiles/kv_bf16_rbf_N60000_D784_C10.md).  Keyed by the kernel instance it
 # was measured on; any other instance reports null.
-MEASURED_TRAFFIC = {("kv_mfma_f32_sym<3,1,5>", "fp32"): 46.03e6,
+MEASURED_TRAFFIC = {("kv_mfma_f32_sym<3,1,5,false>", "fp32"): 46.03e6,
                     # one prediction at 4096 points on the served model (variance
                     # pass kv_mfma_f32<0,2,4> 5.81 GB + mean pass 0.17 GB;
                     # profiles/predict_rbf_N100000_D32_C10_B100_fp32.md)
@@ -190,7 +190,7 @@ def main():
     if args.workload == "perclass":
         return bench_perclass(args)
     args.precision = args.precision or "fp32"
-    KV_INSTANCE = "kv_mfma_f32_sym<3,1,5>"   # Matern-5/2, D <= 16, W = 5
+    KV_INSTANCE = "kv_mfma_f32_sym<3,1,5,false>"   # Matern-5/2, D <= 16, W = 5, shared kernel
     w = datagen.config2()
     dt = torch.float64 if args.precision == "fp64" else torch.float32
     X = torch.tensor(w.X, dtype=dt, device=dev)

@@ -11,6 +11,13 @@ namespace {
 
 using iter::NT;
 
+// a model whose append step and residual run as one pass over its points
+// (softmax likelihood, residual after the iteration): the single-model
+// k_append_winv_residual, with alpha and eta from the finished scalars
+__device__ __host__ inline bool fused_resid(const BIter& t, bool residual) {
+  return residual && t.lik == IGP_LIK_SOFTMAX;
+}
+
 __device__ inline int find_model(const int64_t* __restrict__ pre, int nm, int64_t bid) {
   int lo = 0, hi = nm;            // pre[lo] <= bid < pre[hi]
   while (hi - lo > 1) {
@@ -42,8 +49,10 @@ kb_iter(const BIter* __restrict__ tab, const int64_t* __restrict__ pre, int nm) 
     __shared__ double red[NT / 64];
     const int slot = OP == BOP_FIN_ALPHA ? SC_ALPHA : OP == BOP_FIN_ETA ? SC_ETA : SC_RR;
     const int np = OP == BOP_FIN_ETA ? static_cast<int>(iter::cdiv(t.n, NT))
-                                     : iter::grid_for(t.n);
-    if (OP != BOP_FIN_RR || t.next_r) iter::finish_sum(t.part, np, t.scal + slot, red);
+                   : OP == BOP_FIN_RR && fused_resid(t, t.next_r) ? static_cast<int>(iter::cdiv(t.N, NT))
+                                                                   : iter::grid_for(t.n);
+    const double* part = OP == BOP_FIN_ETA ? t.epart : t.part;
+    if (OP != BOP_FIN_RR || t.next_r) iter::finish_sum(part, np, t.scal + slot, red);
     if constexpr (OP == BOP_FIN_RR) {
       // device control: the end of the iteration (finish_sum wrote rr from thread 0)
       if (t.gate && threadIdx.x == 0)
@@ -69,10 +78,27 @@ kb_iter(const BIter* __restrict__ tab, const int64_t* __restrict__ pre, int nm) 
   } else if constexpr (OP == BOP_DIR) {
     __shared__ double sy[iter::MAXCOLS_LDS];
     __shared__ double red[NT / 64];
-    iter::dir_update<float, true>(t.s, t.Q, t.ld, t.n, t.ncols, t.yb, t.z, t.d, t.part, t.t,
+    iter::dir_update<float, true>(t.s, t.Q, t.ld, t.n, t.ncols, t.yb, t.z, t.d, t.epart, t.t,
                                   t.KQ, t.kd, bid, sy, red);
   } else if constexpr (OP == BOP_APPEND) {
-    iter::append_step<float, true>(t.d, t.scal, t.qcol, t.v, t.n, t.kd, t.kqcol, t.kv, bid, nblk);
+    if (fused_resid(t, t.next_r)) {
+      // append and residual per point; the r^T r partials go to part (the eta
+      // partials there were finished by BOP_FIN_ETA)
+      __shared__ double red[NT / 64];
+      const int64_t i = bid * NT + threadIdx.x;
+      double acc = 0.0;
+      if (i < t.N) {
+        iter::AppendPoint<float, 8> pt;
+        pt.load_point(t.d, t.v, t.kd, t.kv, t.pi, t.rhs, i, t.C);
+        acc = pt.append_residual(coherent_load(t.scal + SC_ALPHA), coherent_load(t.scal + SC_ETA),
+                                 t.qcol, t.v, t.kqcol, t.kv, t.wv, t.r, i, t.C);
+      }
+      acc = block_sum(acc, red);
+      if (threadIdx.x == 0) t.part[bid] = acc;
+    } else {
+      iter::append_step<float, true>(t.d, t.scal, t.qcol, t.v, t.n, t.kd, t.kqcol, t.kv, bid,
+                                     nblk);
+    }
   } else if constexpr (OP == BOP_RESID) {
     __shared__ double red[NT / 64];
     iter::residual<float>(t.rhs, t.kv, t.wv, t.r, t.n, t.part, bid, nblk, red);
@@ -84,16 +110,18 @@ kb_iter(const BIter* __restrict__ tab, const int64_t* __restrict__ pre, int nm) 
 int64_t biter_blocks(int op, const BIter& t, bool residual) {
   switch (op) {
     case BOP_ACTION:
-    case BOP_DOT_ALPHA:
-    case BOP_APPEND: return iter::grid_for(t.n);
+    case BOP_DOT_ALPHA: return iter::grid_for(t.n);
+    case BOP_APPEND: return fused_resid(t, residual) ? ceil_div(t.N, NT) : iter::grid_for(t.n);
     case BOP_FIN_ALPHA:
     case BOP_FIN_ETA: return 1;
     case BOP_WINV_Z: return ceil_div(t.lik == IGP_LIK_SOFTMAX ? t.N : t.n, NT);
     case BOP_GEMV: return t.ncols == 0 ? 0 : ceil_div(static_cast<int64_t>(t.nchunks) * t.ncols, NT / 64);
     case BOP_FIN_COLS: return t.ncols == 0 ? 0 : ceil_div(t.ncols, NT / 64);
     case BOP_DIR: return ceil_div(t.n, NT);
-    case BOP_WINV_V: return residual ? ceil_div(t.lik == IGP_LIK_SOFTMAX ? t.N : t.n, NT) : 0;
-    case BOP_RESID: return residual ? iter::grid_for(t.n) : 0;
+    case BOP_WINV_V:
+      return residual && !fused_resid(t, residual)
+                 ? ceil_div(t.lik == IGP_LIK_SOFTMAX ? t.N : t.n, NT) : 0;
+    case BOP_RESID: return residual && !fused_resid(t, residual) ? iter::grid_for(t.n) : 0;
     case BOP_FIN_RR: return residual || t.gate ? 1 : 0;   // device control: always the end
     default: return 0;
   }

@@ -93,6 +93,40 @@ k_winv_residual(const T* __restrict__ pi, int64_t N, int C, const T* __restrict_
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
+// The append step and the residual of a solver iteration in one pass, one
+// thread per point (softmax likelihood, recurrence residual): every block
+// finishes alpha and eta from their partials (the fixed-order sum, so all
+// blocks hold the same values; block 0 stores them), then each point takes
+// its append and residual, and the block partials of r^T r are those of
+// k_winv_residual.
+template <typename T, int CMAX>
+__global__ void __launch_bounds__(256)
+k_append_winv_residual(const T* __restrict__ d, const double* __restrict__ apart, int anblk,
+                       const double* __restrict__ epart, int enblk, double* __restrict__ scal,
+                       T* __restrict__ qcol, T* __restrict__ v, const T* __restrict__ kd,
+                       T* __restrict__ kqcol, T* __restrict__ kv, const T* __restrict__ pi,
+                       int64_t N, int C, const T* __restrict__ rhs, T* __restrict__ wv,
+                       T* __restrict__ r, double* __restrict__ part, const int* gate) {
+  if (gate_closed(gate)) return;
+  __shared__ double red[4];
+  const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  iter::AppendPoint<T, CMAX> pt;
+  if (n < N) pt.load_point(d, v, kd, kv, pi, rhs, n, C);   // in flight over the sums below
+  double a = 0.0, e = 0.0;
+  for (int i = threadIdx.x; i < anblk; i += 256) a += apart[i];
+  a = block_sum(a, red);
+  for (int i = threadIdx.x; i < enblk; i += 256) e += epart[i];
+  e = block_sum(e, red);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal[SC_ALPHA] = a;
+    scal[SC_ETA] = e;
+  }
+  double acc = 0.0;
+  if (n < N) acc = pt.append_residual(a, e, qcol, v, kqcol, kv, wv, r, n, C);
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
 }  // namespace
 
 #define IGP_DISPATCH_C(C, BODY)                    \
@@ -157,6 +191,33 @@ int winv_residual(const T* pi, int64_t N, int64_t C, const T* v, const T* rhs, c
   return IGP_OK;
 }
 
+template <typename T>
+int append_winv_residual(const T* d, const double* apart, const double* epart, double* scal,
+                         T* qcol, T* v, const T* kd, T* kqcol, T* kv, const T* pi, int64_t N,
+                         int64_t C, const T* rhs, T* wv, T* r, double* part, int* nblk_out,
+                         hipStream_t s, const int* gate) {
+  if (C > 64) {
+    set_error("C = %lld classes exceeds the supported maximum of 64", (long long)C);
+    return IGP_EUNSUPPORTED;
+  }
+  const int blocks = static_cast<int>(ceil_div(N, 256));
+  *nblk_out = blocks;
+  if (blocks == 0) return IGP_OK;
+  const int anblk = iter::grid_for(N * C), enblk = static_cast<int>(ceil_div(N * C, iter::NT));
+  IGP_DISPATCH_C(C, (k_append_winv_residual<T, CM><<<blocks, 256, 0, s>>>(d, apart, anblk, epart, enblk, scal, qcol, v, kd, kqcol, kv, pi, N, (int)C, rhs, wv, r, part, gate)));
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
+template int append_winv_residual<float>(const float*, const double*, const double*, double*,
+                                         float*, float*, const float*, float*, float*,
+                                         const float*, int64_t, int64_t, const float*, float*,
+                                         float*, double*, int*, hipStream_t, const int*);
+template int append_winv_residual<double>(const double*, const double*, const double*, double*,
+                                          double*, double*, const double*, double*, double*,
+                                          const double*, int64_t, int64_t, const double*,
+                                          double*, double*, double*, int*, hipStream_t,
+                                          const int*);
 template int winv_residual<float>(const float*, int64_t, int64_t, const float*, const float*,
                                   const float*, float*, float*, double*, int*, hipStream_t,
                                   const int*);

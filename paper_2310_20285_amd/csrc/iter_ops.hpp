@@ -143,13 +143,13 @@ __device__ inline void finish_col(const double* __restrict__ part, int nchunks, 
   if (lane == 0) y[b] = s;
 }
 
-// d = s - Q y (and kd = t - KQ y) ; part[bid] = z^T d over this block's rows.
+// d = s - Q y (and kd = t - KQ y) ; epart[bid] = z^T d over this block's rows.
 // sy: LDS staging of y (MAXCOLS_LDS doubles)
 template <typename T, bool KQ>
 __device__ inline void dir_update(const T* __restrict__ sv, const T* __restrict__ Q, int64_t ldq,
                                   int64_t n, int ncols, const double* __restrict__ y,
                                   const T* __restrict__ z, T* __restrict__ d,
-                                  double* __restrict__ part, const T* __restrict__ tv,
+                                  double* __restrict__ epart, const T* __restrict__ tv,
                                   const T* __restrict__ KQm, T* __restrict__ kd, int64_t bid,
                                   double* sy, double* red) {
   for (int b = threadIdx.x; b < ncols; b += NT) sy[b] = y[b];
@@ -183,7 +183,7 @@ __device__ inline void dir_update(const T* __restrict__ sv, const T* __restrict_
     e = static_cast<double>(z[i]) * static_cast<double>(di);
   }
   e = block_sum(e, red);
-  if (threadIdx.x == 0) part[bid] = e;
+  if (threadIdx.x == 0) epart[bid] = e;
 }
 
 // eta > 0: Q column = d / sqrt(eta), v += (alpha / eta) d (and the K Q / K v twins)
@@ -308,6 +308,74 @@ __device__ inline void winv_diag(const T* __restrict__ winv, int64_t i, const T*
   if (Add) o += Add[b * lda + i];
   Out[b * ldo + i] = o;
 }
+
+// The append step of a solver iteration followed by its residual, for data
+// point n (softmax likelihood, recurrence residual), in two parts so that a
+// kernel can issue the point's loads before it finishes alpha and eta:
+// load_point takes the point's d, v, K d, K v, pi and rhs; append_residual
+// then, with eta > 0, sets the point's Q and K Q entries and advances v, K v
+// (the values of append_step_vals), and forms wv = W^+ v and
+// r = rhs - K v - wv.  Returns the point's part of r^T r.
+template <typename T, int CMAX>
+struct AppendPoint {
+  T d[CMAX], v[CMAX], kd[CMAX], kv[CMAX], p[CMAX], rhs[CMAX];
+
+  __device__ inline void load_point(const T* __restrict__ dg, const T* __restrict__ vg,
+                                    const T* __restrict__ kdg, const T* __restrict__ kvg,
+                                    const T* __restrict__ pi, const T* __restrict__ rhsg,
+                                    int64_t n, int C) {
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c)
+      if (c < C) {
+        const int64_t i = n * C + c;
+        d[c] = dg[i];
+        v[c] = vg[i];
+        kd[c] = kdg[i];
+        kv[c] = kvg[i];
+        p[c] = pi[i];
+        rhs[c] = rhsg[i];
+      }
+  }
+
+  __device__ inline double append_residual(double alpha, double eta, T* __restrict__ qcol,
+                                           T* __restrict__ vg, T* __restrict__ kqcol,
+                                           T* __restrict__ kvg, T* __restrict__ wv,
+                                           T* __restrict__ r, int64_t n, int C) {
+    const bool app = eta > 0.0;
+    const double qs = app ? 1.0 / sqrt(eta) : 0.0;
+    const double step = app ? alpha / eta : 0.0;
+    if (app) {
+#pragma unroll
+      for (int c = 0; c < CMAX; ++c)
+        if (c < C) {
+          const int64_t i = n * C + c;
+          const double di = static_cast<double>(d[c]);
+          qcol[i] = static_cast<T>(di * qs);
+          v[c] = static_cast<T>(static_cast<double>(v[c]) + step * di);
+          vg[i] = v[c];
+          const double kdi = static_cast<double>(kd[c]);
+          kqcol[i] = static_cast<T>(kdi * qs);
+          kv[c] = static_cast<T>(static_cast<double>(kv[c]) + step * kdi);
+          kvg[i] = kv[c];
+        }
+    }
+    T u[CMAX];
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c) u[c] = c < C ? v[c] : T(0);
+    apply_block<T, CMAX>(IGP_W_PINV, C, p, u);
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c)
+      if (c < C) {
+        const int64_t i = n * C + c;
+        wv[i] = u[c];
+        const T ri = rhs[c] - kv[c] - u[c];
+        r[i] = ri;
+        acc += static_cast<double>(ri) * static_cast<double>(ri);
+      }
+    return acc;
+  }
+};
 
 }  // namespace iter
 }  // namespace igp

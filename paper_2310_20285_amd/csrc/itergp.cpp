@@ -33,6 +33,7 @@ struct Layout {
   T* wblk;      // block likelihood: the inverted C x C blocks W_n^{-1}
   double *part, *scal, *yb, *M, *U, *lamscale, *gram_part;
   double* apart;  // partials of a solver iteration's alpha (finished by the append step)
+  double* epart;  // partials of a solver iteration's eta (the direction update's blocks)
   size_t gram_cap;
   void* kvws;
   size_t kvws_bytes;
@@ -97,6 +98,7 @@ Layout<T> carve(Carver& cv, int64_t N, int64_t D, int64_t C, const igp_solver_co
   L.gate = cv.take<int>(1);
   L.rec = cv.take<double>(REC_COUNT);
   L.apart = cv.take<double>(RED_BLOCKS);
+  L.epart = cv.take<double>(ceil_div(n, 256) + 1);
   if (prepared) {
     L.centre = cv.take<float>(D);
     L.Xp = is_bf16(cfg.precision)
@@ -589,7 +591,7 @@ struct Model final : igp_model {
     t.pi = L.pi;
     t.user = cfg.policy == IGP_POLICY_USER && user
                  ? user + static_cast<int64_t>(st.j - 1) * user_ld : nullptr;
-    t.scal = L.scal; t.part = L.part; t.yb = L.yb;
+    t.scal = L.scal; t.part = L.part; t.epart = L.epart; t.yb = L.yb;
     t.n = n; t.N = N; t.ld = ld; t.unit_idx = st.j - 1;
     t.C = static_cast<int>(C); t.ncols = ncols; t.lik = cfg.likelihood; t.policy = cfg.policy;
     t.nchunks = static_cast<int>(ceil_div(n, QTZ_ROWS));
@@ -740,9 +742,18 @@ struct Model final : igp_model {
     IGP_TRY(apply_K(sv, tv, gate, jj));
     IGP_TRY(apply_winv(sv, 1, n, tv, n, L.z, n, gate));
     IGP_TRY(gemv_t<T>(L.Q, ld, n, col, L.z, L.part, L.yb, stream, gate));
-    IGP_TRY(dir_update<T>(sv, L.Q, ld, n, col, L.yb, L.z, L.d, L.part, nullptr, stream, tv,
+    IGP_TRY(dir_update<T>(sv, L.Q, ld, n, col, L.yb, L.z, L.d, L.epart, nullptr, stream, tv,
                           recurrence() ? L.KQ : nullptr, L.kd, gate));
-    IGP_TRY(append_and_step<T>(L.d, L.apart, L.part, L.scal,
+    if (next_r && recurrence() && softmax()) {
+      // the append and the next residual in one pass over the points
+      int g = 0;
+      IGP_TRY(append_winv_residual<T>(L.d, L.apart, L.epart, L.scal,
+                                      L.Q + static_cast<int64_t>(col) * ld, L.v, L.kd,
+                                      L.KQ + static_cast<int64_t>(col) * ld, L.kv, L.pi, N, C,
+                                      L.rhs, L.wv, L.r, L.part, &g, stream, gate));
+      return rr_consume(L.part, g, L.scal, st.thresh, gate, L.rec, stream);
+    }
+    IGP_TRY(append_and_step<T>(L.d, L.apart, L.epart, L.scal,
                                L.Q + static_cast<int64_t>(col) * ld, L.v, n,
                                stream, recurrence() ? L.kd : nullptr,
                                recurrence() ? L.KQ + static_cast<int64_t>(col) * ld : nullptr,

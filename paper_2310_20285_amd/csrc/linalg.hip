@@ -124,12 +124,13 @@ template <typename T, bool KQ>
 __global__ void __launch_bounds__(NT)
 k_dir_update(const T* __restrict__ sv, const T* __restrict__ Q, int64_t ldq, int64_t n,
              int ncols, const double* __restrict__ y, const T* __restrict__ z,
-             T* __restrict__ d, double* __restrict__ part, const T* __restrict__ tv,
+             T* __restrict__ d, double* __restrict__ epart, const T* __restrict__ tv,
              const T* __restrict__ KQm, T* __restrict__ kd, const int* gate) {
   if (gate_closed(gate)) return;
   __shared__ double sy[MAXCOLS_LDS];
   __shared__ double red[NT / 64];
-  iter::dir_update<T, KQ>(sv, Q, ldq, n, ncols, y, z, d, part, tv, KQm, kd, blockIdx.x, sy, red);
+  iter::dir_update<T, KQ>(sv, Q, ldq, n, ncols, y, z, d, epart, tv, KQm, kd, blockIdx.x, sy,
+                          red);
 }
 
 template <typename T>

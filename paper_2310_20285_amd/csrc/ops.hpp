@@ -116,7 +116,7 @@ struct BIter {
   float *r, *s, *t, *z, *d, *v, *kv, *kd, *rhs, *wv, *Q, *KQ, *qcol, *kqcol;
   const float* pi;          // softmax probabilities, or the diagonal of W^{-1}
   const float* user;        // this iteration's user action (policy USER)
-  double *scal, *part, *yb;
+  double *scal, *part, *epart, *yb;
   int64_t n, N, ld, unit_idx;
   int C, ncols, lik, policy, nchunks, pad;
   // device control (null gate: the host decides after every round): every
@@ -235,6 +235,16 @@ int rr_consume(const double* partials, int nblk, double* scal, double thresh, in
                double* rec, hipStream_t s);
 // softmax: wv = W^+ v, r = rhs - kv - wv and ceil(N / 256) partials of r^T r
 // (one thread per point), *nblk_out = their count
+// The append step (Q and K Q columns, v, K v; alpha and eta finished from
+// their partials and stored to scal) and the residual r = rhs - K v - W^+ v
+// with wv = W^+ v in one pass over the N points (softmax likelihood,
+// recurrence residual); part: the ceil(N / 256) block partials of r^T r
+// (must not alias epart).
+template <typename T>
+int append_winv_residual(const T* d, const double* apart, const double* epart, double* scal,
+                         T* qcol, T* v, const T* kd, T* kqcol, T* kv, const T* pi, int64_t N,
+                         int64_t C, const T* rhs, T* wv, T* r, double* part, int* nblk_out,
+                         hipStream_t s, const int* gate);
 template <typename T>
 int winv_residual(const T* pi, int64_t N, int64_t C, const T* v, const T* rhs, const T* kv,
                   T* wv, T* r, double* partials, int* nblk_out, hipStream_t s,
