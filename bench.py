@@ -159,6 +159,8 @@ def main():
                     help="batched: ignore the table file and time every shape")
     ap.add_argument("--save-tuning", action="store_true",
                     help="batched: write the table (loaded and newly timed entries) to the file")
+    ap.add_argument("--device-control", action="store_true",
+                    help="batched: also time the steps with the control flow on the device")
     ap.add_argument("--load", type=float, nargs="+", default=[0.5],
                     help="serving: arrival rates as fractions of the measured capacity")
     args = ap.parse_args()
@@ -526,17 +528,23 @@ def bench_batched(args):
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     del ms
-    # the same with the control flow on the device (windows of iterations)
-    ms = models()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    iters_dc = []
-    for _ in range(steps):
-        infos, buf = api.newton_step_batched(ms, buf, device_control=True)
-        iters_dc.append(sum(i["iters"] for i in infos))
-    torch.cuda.synchronize()
-    t_dc = time.perf_counter() - t0
-    del ms
+    # the same with the control flow on the device (windows of iterations), on request
+    dc_line = None
+    if args.device_control:
+        ms = models()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters_dc = []
+        for _ in range(steps):
+            infos, buf = api.newton_step_batched(ms, buf, device_control=True)
+            iters_dc.append(sum(i["iters"] for i in infos))
+        torch.cuda.synchronize()
+        t_dc = time.perf_counter() - t0
+        del ms
+        dc_line = {"value": len(ws_) * steps / t_dc, "unit": "Newton steps/s",
+                   "ms_per_step": t_dc / steps * 1e3,
+                   "speedup_over_host_control": t_batch / t_dc,
+                   "solver_iterations_per_batched_step": iters_dc}
     ms = models()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -559,10 +567,7 @@ def bench_batched(args):
                    "precision": prec,
                    "problems": len(ws_), "sum_N": int(sum(w.N for w in ws_))},
         "solver_iterations_per_batched_step": iters,
-        "device_control": {"value": len(ws_) * steps / t_dc, "unit": "Newton steps/s",
-                           "ms_per_step": t_dc / steps * 1e3,
-                           "speedup_over_host_control": t_batch / t_dc,
-                           "solver_iterations_per_batched_step": iters_dc},
+        "device_control": dc_line,
         "sequential_library": {"value": len(ws_) * steps / t_seq, "unit": "Newton steps/s",
                                "speedup_of_batched": t_seq / t_batch},
         "tuning": json.loads(api.batched_tuning()),

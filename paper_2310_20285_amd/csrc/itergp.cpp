@@ -1078,6 +1078,27 @@ __global__ void k_gather_records(const double* const* __restrict__ src, int n,
   dst[i] = src[i / REC_COUNT][i % REC_COUNT];
 }
 
+// the virtual solver run's Gram matrices of a batch's models, gathered into one
+// device buffer for a single copy to the host: entry k covers
+// dst[off_k, off_{k+1}) from src_k (off of the last entry: the total)
+struct GatherEnt {
+  const double* src;
+  int64_t off;
+};
+__global__ void k_gather_mats(const GatherEnt* __restrict__ ent, int n, double* __restrict__ dst) {
+  const int64_t total = ent[n].off;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (ent[mid].off <= i) lo = mid;
+      else hi = mid - 1;
+    }
+    dst[i] = ent[lo].src[i - ent[lo].off];
+  }
+}
+
 struct TuneKey {
   int kind, dch, nbucket, bf16;
   bool operator<(const TuneKey& o) const {
@@ -1122,6 +1143,17 @@ struct Batch {
   double* grec = nullptr;          // gathered records
   std::vector<double> hrec;
   std::vector<unsigned char> hwin;
+  // the Gram matrices M of the virtual solver run, gathered for one copy
+  GatherEnt* dgent = nullptr;
+  double* gM = nullptr;
+  std::vector<GatherEnt> hgent;
+  std::vector<double> hgM;
+
+  static size_t gram_doubles(const std::vector<Model<float>*>& ms) {
+    size_t t = 0;
+    for (auto* m : ms) t += static_cast<size_t>(m->cfg.max_buffer) * m->cfg.max_buffer;
+    return std::max<size_t>(t, 1);
+  }
 
   // partial slots of a model's product: the one-sided tiles' splits, or the
   // symmetric plan's super-blocks (FP32)
@@ -1183,6 +1215,8 @@ struct Batch {
     cv.take<BatchProblem>(DC_WINDOW * ms.size());
     cv.take<const double*>(ms.size());
     cv.take<double>(ms.size() * REC_COUNT);
+    cv.take<GatherEnt>(ms.size() + 1);
+    cv.take<double>(gram_doubles(ms));
     size_t pf = 0;
     for (auto* m : ms) pf += align_up(partial_floats(m) * sizeof(float)) / sizeof(float);
     cv.take<float>(pf);
@@ -1203,6 +1237,8 @@ struct Batch {
     dwin_end = reinterpret_cast<char*>(dtab_w + DC_WINDOW * ms.size());
     drec = cv.take<const double*>(ms.size());
     grec = cv.take<double>(ms.size() * REC_COUNT);
+    dgent = cv.take<GatherEnt>(ms.size() + 1);
+    gM = cv.take<double>(gram_doubles(ms));
     size_t pf = 0;
     for (auto* m : ms) pf += align_up(partial_floats(m) * sizeof(float)) / sizeof(float);
     partials = cv.take<float>(pf);
@@ -1222,6 +1258,38 @@ struct Batch {
     IGP_CHECK_HIP(hipStreamSynchronize(stream));
     hgather.resize(ms.size() * SC_COUNT);
     hrec.resize(ms.size() * REC_COUNT);
+    return IGP_OK;
+  }
+
+  // every model's M (ncols x ncols) to its host copy: one gather kernel and one
+  // device-to-host copy for the batch, instead of a copy and a wait per model
+  int fetch_grams() {
+    hgent.clear();
+    int64_t off = 0;
+    std::vector<int> who;
+    for (size_t i = 0; i < ms.size(); ++i) {
+      const int B = ms[i]->ncols;
+      if (B == 0) continue;
+      hgent.push_back(GatherEnt{ms[i]->L.M, off});
+      who.push_back(static_cast<int>(i));
+      off += static_cast<int64_t>(B) * B;
+    }
+    if (who.empty()) return IGP_OK;
+    IGP_REQUIRE(static_cast<size_t>(off) <= gram_doubles(ms), "batched Gram gather too large");
+    hgent.push_back(GatherEnt{nullptr, off});
+    IGP_CHECK_HIP(hipMemcpyAsync(dgent, hgent.data(), hgent.size() * sizeof(GatherEnt),
+                                 hipMemcpyHostToDevice, stream));
+    const int blocks = static_cast<int>(std::min<int64_t>(ceil_div(off, 256), 2048));
+    k_gather_mats<<<blocks, 256, 0, stream>>>(dgent, static_cast<int>(who.size()), gM);
+    IGP_CHECK_LAUNCH();
+    hgM.resize(static_cast<size_t>(off));
+    IGP_CHECK_HIP(hipMemcpyAsync(hgM.data(), gM, hgM.size() * sizeof(double),
+                                 hipMemcpyDeviceToHost, stream));
+    IGP_CHECK_HIP(hipStreamSynchronize(stream));
+    for (size_t k = 0; k < who.size(); ++k) {
+      Model<float>* m = ms[who[k]];
+      m->hM.assign(hgM.begin() + hgent[k].off, hgM.begin() + hgent[k + 1].off);
+    }
     return IGP_OK;
   }
 
@@ -1536,7 +1604,7 @@ int newton_step_batched(igp_model* const* models, int n, igp_step_info* infos, v
   auto& ms = b.ms;
   for (auto* m : ms) IGP_TRY(m->phase_begin());
   for (auto* m : ms) IGP_TRY(m->phase_vsr_gram());
-  for (auto* m : ms) IGP_TRY(m->phase_vsr_fetch());
+  IGP_TRY(b.fetch_grams());
   IGP_TRY(parallel_for(n, [&](int i) { return ms[i]->phase_vsr_host(); }));
   for (auto* m : ms) IGP_TRY(m->phase_vsr_apply());
   for (auto* m : ms) IGP_TRY(m->phase_v0());

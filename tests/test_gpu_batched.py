@@ -138,6 +138,10 @@ def test_batched_rejects_mixed_precision(gpu_lib):
         api.newton_step_batched([_model(w, "cg", "fp32"), _model(w, "cg", "bf16")])
 
 
+DEVICE_CONTROL_HOLD = ("a run of this test hung with a variant of the persistent product kernels that skipped the tiles of stopped problems (since removed); the cause has not been found, so device-controlled batched steps stay off the GPU until it is")
+
+
+@pytest.mark.skip(reason=DEVICE_CONTROL_HOLD)
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_device_control_matches_host_control(gpu_lib, precision):
     probs = _problems(k=6, seed=19)

