@@ -1,6 +1,6 @@
 """Profiling driver for rocprofv3.
 
-    python profile_driver.py [--workload gpc16|image|predict] [--precision ...]
+    python profile_driver.py [--workload gpc16|image|predict|batched] [--precision ...]
                              [--reps 20] [--copy-mib 256]
 
 Workloads (each ends with one device-to-device copy of ``--copy-mib`` MiB, a
@@ -15,7 +15,11 @@ that converts the counters of the other kernels to bytes):
           split-input mode), ``--reps`` times;
 * predict prediction (mean, variance, probit) at 4096 test points against a
           fitted N=100000, D=32, C=10 RBF model compressed to 100 directions
-          (the serving workload's model), ``--reps`` times.
+          (the serving workload's model), ``--reps`` times;
+* batched 64 independent problems (N ~ U{1000..16000}, D=8, C ~ U{2..8},
+          Matern-3/2, IterNCGP-CG j<=200, R=100) advanced by min(--reps, 3)
+          batched Newton steps from f_0 = 0, launch shapes from the saved table
+          (FP32, or ``--precision bf16``).
 """
 from __future__ import annotations
 
@@ -30,7 +34,8 @@ if ROOT not in sys.path:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="gpc16", choices=["gpc16", "image", "predict"])
+    ap.add_argument("--workload", default="gpc16",
+                    choices=["gpc16", "image", "predict", "batched"])
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16", "bf16x3"])
@@ -52,6 +57,24 @@ def main():
             out = api.glm_kernel_matmul(X, X, v, w.C, w.kernel, w.lengthscale, w.outputscale,
                                         prec, out=out)
         what = f"{args.reps} K.v products (N={w.N}, D={w.D}, C={w.C}, {prec})"
+    elif args.workload == "batched":
+        prec = args.precision or "fp32"
+        api.load_batched_tuning_file(os.path.join(ROOT, "paper_2310_20285_amd",
+                                                  "batched_tuning_gfx950.json"))
+        ws_ = datagen.config4()
+        ms = [api.IterNCGP(torch.tensor(w.X, dtype=torch.float32, device="cuda"),
+                           torch.tensor(w.y, dtype=torch.int32, device="cuda"), w.C, w.kernel,
+                           w.lengthscale, w.outputscale, policy="cg", j_max=200,
+                           rank_limit=100, recycle=True, precision=prec,
+                           residual_mode="recurrence", max_buffer=300) for w in ws_]
+        buf = None
+        steps = min(args.reps, 3)
+        iters = []
+        for _ in range(steps):
+            infos, buf = api.newton_step_batched(ms, buf)
+            iters.append(sum(i["iters"] for i in infos))
+        what = (f"{steps} batched Newton steps over {len(ms)} problems ({prec}; solver "
+                f"iterations {iters})")
     else:
         prec = args.precision or "fp32"
         w = datagen.config5_model()
