@@ -84,7 +84,9 @@ Layout<T> carve(Carver& cv, int64_t N, int64_t D, int64_t C, const igp_solver_co
   npart = std::max(npart, gemv_need);
   npart = std::max(npart, 4 * ceil_div(N, 256) + 64);
   L.part = cv.take<double>(npart);
-  L.scal = cv.take<double>(SC_COUNT);
+  // the scalars and, right after them, the iteration record: one copy to the
+  // host per window of iterations
+  L.scal = cv.take<double>(SC_COUNT + REC_COUNT);
   L.yb = cv.take<double>(std::max<int64_t>(B, 1));
   L.M = cv.take<double>(std::max<int64_t>(B * B, 1));
   L.U = cv.take<double>(std::max<int64_t>(B * B, 1));
@@ -96,7 +98,7 @@ Layout<T> carve(Carver& cv, int64_t N, int64_t D, int64_t C, const igp_solver_co
   L.kvws = cv.take<char>(L.kvws_bytes);
   L.flags = cv.take<int>(64);
   L.gate = cv.take<int>(1);
-  L.rec = cv.take<double>(REC_COUNT);
+  L.rec = L.scal + SC_COUNT;
   L.apart = cv.take<double>(RED_BLOCKS);
   L.epart = cv.take<double>(ceil_div(n, 256) + 1);
   if (prepared) {
@@ -800,9 +802,8 @@ struct Model final : igp_model {
       IGP_TRY(enqueue_iteration(jj, win.col0 + i, jj < cfg.j_max));
     }
     double* h = win_host + win.slot * (SC_COUNT + REC_COUNT);
-    IGP_CHECK_HIP(hipMemcpyAsync(h, L.scal, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost,
-                                 stream));
-    IGP_CHECK_HIP(hipMemcpyAsync(h + SC_COUNT, L.rec, REC_COUNT * sizeof(double),
+    // scalars and record (adjacent in the arena) in one copy
+    IGP_CHECK_HIP(hipMemcpyAsync(h, L.scal, (SC_COUNT + REC_COUNT) * sizeof(double),
                                  hipMemcpyDeviceToHost, stream));
     IGP_CHECK_HIP(hipEventRecord(win_ev[win.slot], stream));
     return IGP_OK;
