@@ -723,16 +723,34 @@ struct Model final : igp_model {
   KVProblem product_action() const { return kv_problem(L.X, N, s_col(), 1, n, t_col(), n); }
   KVProblem product_update() const { return kv_problem(L.X, N, L.v, 1, n, L.fnew, n); }
 
+  // An iteration's end (the norm of its residual and iter_consume) left to
+  // the next iteration's action kernel: the residual partials to finish.
+  struct PendingEnd {
+    const double* part = nullptr;
+    int nblk = 0;
+  };
+  // whether an iteration's end may be left to the next iteration's action
+  bool can_defer_end() const {
+    return cfg.policy == IGP_POLICY_CG && recurrence() && softmax();
+  }
+
   // Solver iteration jj (1-based) with its action in buffer column col, behind
   // the gate: the action, alpha, t = K s, z, Q^T z, d and eta, the guarded
   // append, the next residual when next_r, and iter_consume (Algorithm 2).
-  int enqueue_iteration(int jj, int col, bool next_r) {
+  // pend: the previous iteration's end when it was left to this action (then
+  // cleared); defer_end: leave this iteration's end to the next one, which
+  // the caller enqueues right after it.
+  int enqueue_iteration(int jj, int col, bool next_r, PendingEnd* pend, bool defer_end) {
     int* gate = L.gate;
     T* sv = L.S + static_cast<int64_t>(col) * ld;
     T* tv = L.Tb + static_cast<int64_t>(col) * ld;
     // alpha and eta stay as partials (L.apart, L.part) until the append step
     // finishes them
-    if (cfg.policy == IGP_POLICY_CG) {
+    if (cfg.policy == IGP_POLICY_CG && pend->part) {
+      IGP_TRY(consume_action_cg_dot<T>(L.r, pend->part, pend->nblk, L.scal, st.thresh, gate,
+                                       L.rec, sv, n, L.apart, stream));
+      *pend = PendingEnd{};
+    } else if (cfg.policy == IGP_POLICY_CG) {
       IGP_TRY(action_cg_dot<T>(L.r, L.scal + SC_RR, sv, n, L.apart, nullptr, gate, stream));
     } else {
       if (cfg.policy == IGP_POLICY_UNIT)
@@ -753,6 +771,10 @@ struct Model final : igp_model {
                                       L.Q + static_cast<int64_t>(col) * ld, L.v, L.kd,
                                       L.KQ + static_cast<int64_t>(col) * ld, L.kv, L.pi, N, C,
                                       L.rhs, L.wv, L.r, L.part, &g, stream, gate));
+      if (defer_end) {   // L.part is next written after the next action has read it
+        *pend = PendingEnd{L.part, g};
+        return IGP_OK;
+      }
       return rr_consume(L.part, g, L.scal, st.thresh, gate, L.rec, stream);
     }
     IGP_TRY(append_and_step<T>(L.d, L.apart, L.epart, L.scal,
@@ -797,10 +819,16 @@ struct Model final : igp_model {
   }
 
   int enqueue_window(const Window& win) {
+    // within the window each iteration's end goes into the next iteration's
+    // action where that is possible; the last iteration ends on its own
+    PendingEnd pend;
     for (int i = 0; i < win.w; ++i) {
       const int jj = win.j0 + i + 1;
-      IGP_TRY(enqueue_iteration(jj, win.col0 + i, jj < cfg.j_max));
+      const bool next_r = jj < cfg.j_max;
+      IGP_TRY(enqueue_iteration(jj, win.col0 + i, next_r, &pend,
+                                next_r && i + 1 < win.w && can_defer_end()));
     }
+    IGP_REQUIRE(!pend.part, "a solver iteration's end was left without a next iteration");
     double* h = win_host + win.slot * (SC_COUNT + REC_COUNT);
     // scalars and record (adjacent in the arena) in one copy
     IGP_CHECK_HIP(hipMemcpyAsync(h, L.scal, (SC_COUNT + REC_COUNT) * sizeof(double),

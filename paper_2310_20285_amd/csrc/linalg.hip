@@ -72,6 +72,39 @@ k_action_cg_dot(const T* __restrict__ r, const double* __restrict__ rr, T* __res
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
+// the previous iteration's end (k_finish_rr_consume) and this iteration's CG
+// action (k_action_cg_dot) in one launch
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_consume_action_cg_dot(const T* __restrict__ r, const double* __restrict__ rpart, int rnblk,
+                        double* __restrict__ scal, double thresh, int* gate, double* rec,
+                        T* __restrict__ s, int64_t n, double* __restrict__ part) {
+  if (gate_closed(gate)) return;
+  __shared__ double red[NT / 64];
+  // rr in the order of iter::finish_sum: the same value in every block
+  double rr = 0.0;
+  for (int i = threadIdx.x; i < rnblk; i += NT) rr += rpart[i];
+  rr = block_sum(rr, red);
+  const double eta = coherent_load(scal + SC_ETA);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal[SC_RR] = rr;
+    iter::consume_iteration(scal, thresh, 1, gate, rec);
+  }
+  // the decision consume_iteration takes, in every block
+  if (!(eta > 0.0) || !(sqrt(rr) >= thresh)) return;
+  const double inv = 1.0 / sqrt(rr);
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(NT) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * NT) {
+    const T ri = r[i];
+    const T si = static_cast<T>(static_cast<double>(ri) * inv);
+    s[i] = si;
+    acc += static_cast<double>(si) * static_cast<double>(ri);
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(NT) k_fill_unit(T* __restrict__ s, int64_t n, int64_t idx,
                                                   const int* gate) {
@@ -390,6 +423,16 @@ int action_cg_dot(const T* r, const double* rr, T* sv, int64_t n, double* part, 
   return IGP_OK;
 }
 
+template <typename T>
+int consume_action_cg_dot(const T* r, const double* rpart, int rnblk, double* scal,
+                          double thresh, int* gate, double* rec, T* sv, int64_t n,
+                          double* apart, hipStream_t s) {
+  k_consume_action_cg_dot<T><<<grid_for(n), NT, 0, s>>>(r, rpart, rnblk, scal, thresh, gate, rec,
+                                                        sv, n, apart);
+  IGP_CHECK_LAUNCH();
+  return IGP_OK;
+}
+
 int rr_consume(const double* part, int nblk, double* scal, double thresh, int* gate, double* rec,
                hipStream_t s) {
   k_finish_rr_consume<<<1, NT, 0, s>>>(part, nblk, scal, thresh, gate, rec);
@@ -575,6 +618,8 @@ int predict_epilogue(const T* A, int64_t lda, int64_t nrows, int ncols, const do
   template int action_cg_dot<T>(const T*, const double*, T*, int64_t, double*, double*,        \
                                 const int*,                                                    \
                                 hipStream_t);                                                  \
+  template int consume_action_cg_dot<T>(const T*, const double*, int, double*, double, int*,   \
+                                        double*, T*, int64_t, double*, hipStream_t);           \
   template int fill_unit<T>(T*, int64_t, int64_t, hipStream_t, const int*);                    \
   template int copy_vec<T>(const T*, T*, int64_t, hipStream_t, const int*);                    \
   template int fill_zero<T>(T*, int64_t, hipStream_t);                                         \

@@ -233,8 +233,6 @@ int residual(const T* rhs, const T* kv, const T* wv, T* r, int64_t n, double* pa
 // the end of the solver iteration as in residual_consume
 int rr_consume(const double* partials, int nblk, double* scal, double thresh, int* gate,
                double* rec, hipStream_t s);
-// softmax: wv = W^+ v, r = rhs - kv - wv and ceil(N / 256) partials of r^T r
-// (one thread per point), *nblk_out = their count
 // The append step (Q and K Q columns, v, K v; alpha and eta finished from
 // their partials and stored to scal) and the residual r = rhs - K v - W^+ v
 // with wv = W^+ v in one pass over the N points (softmax likelihood,
@@ -245,6 +243,8 @@ int append_winv_residual(const T* d, const double* apart, const double* epart, d
                          T* qcol, T* v, const T* kd, T* kqcol, T* kv, const T* pi, int64_t N,
                          int64_t C, const T* rhs, T* wv, T* r, double* part, int* nblk_out,
                          hipStream_t s, const int* gate);
+// softmax: wv = W^+ v, r = rhs - kv - wv and ceil(N / 256) partials of r^T r
+// (one thread per point), *nblk_out = their count
 template <typename T>
 int winv_residual(const T* pi, int64_t N, int64_t C, const T* v, const T* rhs, const T* kv,
                   T* wv, T* r, double* partials, int* nblk_out, hipStream_t s,
@@ -262,6 +262,16 @@ int dot_into(const T* a, const T* b, int64_t n, double* partials, double* out_sc
 template <typename T>
 int action_cg_dot(const T* r, const double* rr, T* s_out, int64_t n, double* partials,
                   double* alpha, const int* gate, hipStream_t s);
+// The end of the previous solver iteration and the CG action of this one in
+// one launch: rr = the fixed-order sum of the previous residual's rnblk
+// partials (rpart), stored to scal[SC_RR] with that iteration's end
+// (iter_consume with next_r = 1) by one thread; every block takes the same
+// stop decision (breakdown or rr below thresh^2) and, when it goes on, forms
+// s = r / sqrt(rr) and the grid_for(n) partials of alpha = s^T r (apart)
+template <typename T>
+int consume_action_cg_dot(const T* r, const double* rpart, int rnblk, double* scal,
+                          double thresh, int* gate, double* rec, T* s_out, int64_t n,
+                          double* apart, hipStream_t s);
 template <typename T>
 int fill_unit(T* s_out, int64_t n, int64_t idx, hipStream_t s, const int* gate = nullptr);
 template <typename T>
