@@ -246,7 +246,12 @@ struct Model final : igp_model {
   bool recurrence() const { return cfg.residual_mode == IGP_RESIDUAL_RECURRENCE; }
 
   // Out = K V; with a gate, part of solver iteration `iter`, skipped once the gate closes
-  int apply_K(const T* V, T* Out, const int* gate = nullptr, int iter = 0) {
+  // Out = K V (one vector); with zout (softmax): also zout = Out + W^+ V in the
+  // product's reduction when its launch path takes that epilogue (*zdone = 1).
+  // A product timed for the profile leaves z to the caller, so that the timed
+  // unit is the product alone (kernel and reduction).
+  int apply_K(const T* V, T* Out, const int* gate = nullptr, int iter = 0, T* zout = nullptr,
+              int* zdone = nullptr) {
     hipEvent_t a = nullptr, b = nullptr;
     const bool timed = prof && (prof_seq++ % prof_every == 0);
     if (timed) {
@@ -257,6 +262,12 @@ struct Model final : igp_model {
     KVProblem p = kv_problem(L.X, N, V, 1, n, Out, n);
     p.symmetric_out = &sym;
     p.skip = gate;
+    if (zout && softmax() && !timed) {
+      p.epi_pi = L.pi;
+      p.epi_s = V;
+      p.epi_z = zout;
+      p.epi_applied = zdone;
+    }
     IGP_TRY(kv_launch(p, L.kvws, L.kvws_bytes, stream));
     if (timed) {
       IGP_CHECK_HIP(hipEventRecord(b, stream));
@@ -759,8 +770,10 @@ struct Model final : igp_model {
         IGP_TRY(copy_vec<T>(user + static_cast<int64_t>(jj - 1) * user_ld, sv, n, stream, gate));
       IGP_TRY(dot_into<T>(sv, L.r, n, L.apart, nullptr, stream, gate));
     }
-    IGP_TRY(apply_K(sv, tv, gate, jj));
-    IGP_TRY(apply_winv(sv, 1, n, tv, n, L.z, n, gate));
+    // t = K s, with z = t + W^+ s in the product's reduction where it can be
+    int zdone = 0;
+    IGP_TRY(apply_K(sv, tv, gate, jj, L.z, &zdone));
+    if (!zdone) IGP_TRY(apply_winv(sv, 1, n, tv, n, L.z, n, gate));
     IGP_TRY(gemv_t<T>(L.Q, ld, n, col, L.z, L.part, L.yb, stream, gate));
     IGP_TRY(dir_update<T>(sv, L.Q, ld, n, col, L.yb, L.z, L.d, L.epart, nullptr, stream, tv,
                           recurrence() ? L.KQ : nullptr, L.kd, gate));

@@ -121,9 +121,13 @@ kv_valu(const T* __restrict__ X1, const T* __restrict__ X2, int64_t n1, int64_t 
   }
 }
 
+// With epi_z (one vector, W == C, beta == 0): z = Out + W^+ s at point n,
+// W^+ s in the order of iter::apply_block (class means summed in class order).
 template <typename T>
 __global__ void kv_reduce(const T* __restrict__ P, int nsplit, int64_t n1, int W, int C,
-                          T* __restrict__ Out, int64_t ldo, T os, T beta, const int* skip) {
+                          T* __restrict__ Out, int64_t ldo, T os, T beta, const int* skip,
+                          const T* __restrict__ epi_pi, const T* __restrict__ epi_s,
+                          T* __restrict__ epi_z) {
   if (gate_closed(skip)) return;
   const int64_t total = n1 * W;
   for (int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; idx < total;
@@ -146,8 +150,29 @@ __global__ void kv_reduce(const T* __restrict__ P, int nsplit, int64_t n1, int W
     for (; sp < nsplit; ++sp) s0 += p[sp * stride];
     const T s = (s0 + s1) + (s2 + s3);
     T* o = Out + (w / C) * ldo + n * C + (w % C);
-    *o = (beta != T(0)) ? os * s + beta * *o : os * s;
+    const T val = (beta != T(0)) ? os * s + beta * *o : os * s;
+    *o = val;
+    if (epi_z) {
+      const T* sn = epi_s + n * C;
+      const T* pn = epi_pi + n * C;
+      T m = T(0);
+      for (int c = 0; c < C; ++c) m += sn[c];
+      m /= T(C);
+      T m2 = T(0), uw = T(0);
+      for (int c = 0; c < C; ++c) {
+        const T u = (sn[c] - m) / pn[c];
+        m2 += u;
+        if (c == w) uw = u;
+      }
+      m2 /= T(C);
+      epi_z[n * C + w] = (uw - m2) + val;
+    }
   }
+}
+
+// whether the product's reduction can take the z = Out + W^+ s epilogue
+bool epilogue_ok(const KVProblem& p) {
+  return p.epi_z && p.epi_s && p.epi_pi && p.nb == 1 && p.beta == 0.0;
 }
 
 struct SplitPlan {
@@ -230,9 +255,14 @@ int launch_valu(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t s) {
   if (blocks < 1) blocks = 1;
   // with one kernel per class the outputscales are applied inside the product
   const T os = p.n_kp > 1 ? T(1) : static_cast<T>(p.kp.outputscale);
+  const bool epi = epilogue_ok(p);
   kv_reduce<T><<<blocks, 256, 0, s>>>(P, sp.nsplit, p.n1, static_cast<int>(W),
                                       static_cast<int>(p.C), static_cast<T*>(p.Out), p.ldo, os,
-                                      static_cast<T>(p.beta), p.skip);
+                                      static_cast<T>(p.beta), p.skip,
+                                      epi ? static_cast<const T*>(p.epi_pi) : nullptr,
+                                      epi ? static_cast<const T*>(p.epi_s) : nullptr,
+                                      epi ? static_cast<T*>(p.epi_z) : nullptr);
+  if (epi && p.epi_applied) *p.epi_applied = 1;
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }
@@ -342,9 +372,14 @@ int launch_mfma_path(const KVProblem& p, void* ws, size_t ws_bytes, hipStream_t 
   int blocks = static_cast<int>(std::min<int64_t>(std::max<int64_t>(ceil_div(total, 256), 1), 4096));
   // with one kernel per class the outputscales are applied inside the product
   const float os = p.n_kp > 1 ? 1.0f : static_cast<float>(p.kp.outputscale);
+  const bool epi = epilogue_ok(p);
   kv_reduce<float><<<blocks, 256, 0, s>>>(P, nsplit, p.n1, static_cast<int>(W),
                                           static_cast<int>(p.C), static_cast<float*>(p.Out), p.ldo,
-                                          os, static_cast<float>(p.beta), p.skip);
+                                          os, static_cast<float>(p.beta), p.skip,
+                                          epi ? static_cast<const float*>(p.epi_pi) : nullptr,
+                                          epi ? static_cast<const float*>(p.epi_s) : nullptr,
+                                          epi ? static_cast<float*>(p.epi_z) : nullptr);
+  if (epi && p.epi_applied) *p.epi_applied = 1;
   IGP_CHECK_LAUNCH();
   return IGP_OK;
 }

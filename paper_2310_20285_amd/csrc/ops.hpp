@@ -57,6 +57,15 @@ struct KVProblem {
   // rows, at least 1024, for outputs at most 512 wide), so that each output
   // row is summed in the same order whatever rows share the launch
   bool fixed_split = false;
+  // optional epilogue of the final reduction (one vector, nb == 1, beta == 0):
+  // z = Out + W^+ s at every point, W^+ the pseudo-inverse of the softmax
+  // Hessian block from the probabilities epi_pi (N x C), s = epi_s (N x C),
+  // into epi_z (N x C); the launcher sets *epi_applied to 1 when it took it
+  // (else the caller forms z itself)
+  const void* epi_pi = nullptr;
+  const void* epi_s = nullptr;
+  void* epi_z = nullptr;
+  int* epi_applied = nullptr;
 };
 constexpr int64_t FIXED_SPLIT_ROWS = 4096;
 constexpr int64_t FIXED_SPLIT_ROWS_NARROW = 512;
