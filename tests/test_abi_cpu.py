@@ -96,6 +96,20 @@ def test_argument_errors_without_device_work():
         assert msg in lib.igp_last_error()
 
 
+def test_batched_step_argument_errors_without_device_work():
+    """The batched step refuses unknown flags and an empty batch before it
+    touches a model or the device."""
+    lib = L.load()
+    rc = lib.itergp_newton_step_batched_ex(None, 1, None, None, 0,
+                                           L.IGP_BATCH_DEVICE_CONTROL << 1)
+    assert rc == L.IGP_EINVAL
+    assert b"flags" in lib.igp_last_error()
+    assert lib.itergp_newton_step_batched_ex(None, 0, None, None, 0,
+                                             L.IGP_BATCH_DEVICE_CONTROL) == L.IGP_EINVAL
+    assert b"no models" in lib.igp_last_error()
+    assert lib.itergp_newton_step_batched(None, 0, None, None, 0) == L.IGP_EINVAL
+
+
 @pytest.mark.parametrize("n", [1, 2, 7, 40, 150])
 def test_host_eigh_matches_numpy(n):
     lib = L.load()
