@@ -82,8 +82,8 @@ kb_iter(const BIter* __restrict__ tab, const int64_t* __restrict__ pre, int nm) 
                                   t.KQ, t.kd, bid, sy, red);
   } else if constexpr (OP == BOP_APPEND) {
     if (fused_resid(t, t.next_r)) {
-      // append and residual per point; the r^T r partials go to part (the eta
-      // partials there were finished by BOP_FIN_ETA)
+      // append and residual per point; the r^T r partials go to part (the
+      // Q^T z partials there were summed by BOP_FIN_COLS; eta's are in epart)
       __shared__ double red[NT / 64];
       const int64_t i = bid * NT + threadIdx.x;
       double acc = 0.0;
