@@ -67,13 +67,18 @@ __device__ inline float ktransform(float t) {
 
 constexpr int TN = 64;   // X2 rows per LDS tile
 
-template <int KIND, int DCH, int WCH>
+// D4: at most 4 features.  The prepared rows keep their 16 padded floats, but
+// features 0..3 form the one k-block of a single distance MFMA per 16 x 16
+// block (lane group g takes feature g) instead of four MFMAs over 16 mostly
+// zero features.
+template <int KIND, int DCH, int WCH, bool D4 = false>
 __global__ void __launch_bounds__(256)
 kv_mfma_f32(const float* __restrict__ X1p, const float* __restrict__ nrm1,
             const float* __restrict__ X2p, const float* __restrict__ nrm2, int64_t n1,
             int64_t n2, const float* __restrict__ V, int C, int W, int64_t ldv,
             float* __restrict__ P, int64_t cols_per_split, float cnorm, float cdot,
             const int* skip) {
+  static_assert(!D4 || DCH == 1, "the 4-feature form pads to one chunk");
   if (gate_closed(skip)) return;
   constexpr int DP = DCH * 16;        // padded feature count
   constexpr int XS = DP + 4;          // LDS row stride of the X2 tile (floats)
@@ -100,6 +105,7 @@ kv_mfma_f32(const float* __restrict__ X1p, const float* __restrict__ nrm1,
 #pragma unroll
   for (int c = 0; c < DCH; ++c)
     xb[c] = nvalid ? *reinterpret_cast<const f4*>(X1p + nrow * DP + 16 * c + 4 * g) : f4{0, 0, 0, 0};
+  const float xg = nvalid ? X1p[nrow * DP + g] : 0.0f;   // D4: feature g of the row
   const float n1v = nvalid ? nrm1[nrow] * cnorm : 0.0f;
 
   f4 out[WCH];
@@ -171,13 +177,18 @@ kv_mfma_f32(const float* __restrict__ X1p, const float* __restrict__ nrm1,
 #pragma unroll
     for (int mb = 0; mb < TN / 16; ++mb) {
       f4 acc = {0, 0, 0, 0};
+      if constexpr (D4) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(sX[buf][(mb * 16 + r) * XS + g], xg, acc, 0,
+                                                   0, 0);
+      } else {
 #pragma unroll
-      for (int c = 0; c < DCH; ++c) {
-        const f4 a = *reinterpret_cast<const f4*>(&sX[buf][(mb * 16 + r) * XS + 16 * c + 4 * g]);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], xb[c][0], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], xb[c][1], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], xb[c][2], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], xb[c][3], acc, 0, 0, 0);
+        for (int c = 0; c < DCH; ++c) {
+          const f4 a = *reinterpret_cast<const f4*>(&sX[buf][(mb * 16 + r) * XS + 16 * c + 4 * g]);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], xb[c][0], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], xb[c][1], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], xb[c][2], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], xb[c][3], acc, 0, 0, 0);
+        }
       }
       const f4 n2v = *reinterpret_cast<const f4*>(&sN[buf][mb * 16 + 4 * g]);
       // this block's V fragments, read before the transform so that their
@@ -1108,12 +1119,14 @@ k_col_finish(const double* __restrict__ part, int nblk, int d, int64_t n,
 struct Plan {
   int dch, wch, gx, gz, nsplit;
   bool narrow;
+  bool d4;          // at most 4 features (the wide kernel's one-MFMA distance)
   int64_t cols_per_split;
 };
 
 Plan plan_mfma(int64_t n1, int64_t n2, int64_t d, int64_t W, bool fixed = false) {
   Plan p{};
   p.dch = static_cast<int>(ceil_div(d, 16));
+  p.d4 = d <= 4;
   p.narrow = W <= WV && p.dch <= 2;
   p.wch = W <= 16 ? 1 : (W <= 32 ? 2 : 4);
   p.gx = static_cast<int>(ceil_div(n1, p.narrow ? 64 * NSTRIP : 64));
@@ -1215,6 +1228,21 @@ int launch_kind_dch(const Plan& pl, const float* X1p, const float* n1p, const fl
 #undef IGP_NW
         default: break;
       }
+    }
+  } else if (DCH == 1 && pl.d4) {
+    if constexpr (DCH == 1) {
+      if (pl.wch == 1)
+        kv_mfma_f32<KIND, 1, 1, true><<<grid, 256, 0, s>>>(X1p, n1p, X2p, n2p, n1, n2, V, C, W,
+                                                           ldv, P, pl.cols_per_split, cnorm,
+                                                           cdot, skip);
+      else if (pl.wch == 2)
+        kv_mfma_f32<KIND, 1, 2, true><<<grid, 256, 0, s>>>(X1p, n1p, X2p, n2p, n1, n2, V, C, W,
+                                                           ldv, P, pl.cols_per_split, cnorm,
+                                                           cdot, skip);
+      else
+        kv_mfma_f32<KIND, 1, 4, true><<<grid, 256, 0, s>>>(X1p, n1p, X2p, n2p, n1, n2, V, C, W,
+                                                           ldv, P, pl.cols_per_split, cnorm,
+                                                           cdot, skip);
     }
   } else if (pl.wch == 1)
     kv_mfma_f32<KIND, DCH, 1><<<grid, 256, 0, s>>>(X1p, n1p, X2p, n2p, n1, n2, V, C, W, ldv, P,

@@ -39,6 +39,9 @@ SHAPES = [  # n1, n2, d, C, nb  -- several tiles plus ragged tails
     (1000, 2311, 16, 5, 1),     # solver product shape (matrix-core path in FP32)
     (129, 700, 32, 5, 40),      # predict shape: W = C * nb = 200 output columns
     (70, 90, 128, 3, 2),        # widest feature count of the FP32 matrix-core path
+    (150, 333, 3, 10, 1),       # at most 4 features, wide outputs (one-MFMA distance)
+    (90, 260, 4, 5, 4),         # ... 20 output columns
+    (70, 200, 1, 3, 17),        # ... 51 output columns
 ]
 
 
