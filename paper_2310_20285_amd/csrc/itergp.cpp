@@ -1215,20 +1215,22 @@ struct Batch {
   }
 
   // the launch layout of one round's products: symmetric problems first,
-  // sorted by output width (one group and launch per width)
+  // sorted by output width and distance k-blocks (one group and launch each)
   struct Layout {
     std::vector<SymGroup> groups;
     int64_t tiles = 0, outs = 0;
   };
   Layout lay_out(BatchProblem* tb, size_t n) const {
     auto* mid = std::stable_partition(tb, tb + n, [](const BatchProblem& b) { return b.sym_q > 0; });
-    std::stable_sort(tb, mid, [](const BatchProblem& a, const BatchProblem& b) { return a.W < b.W; });
+    std::stable_sort(tb, mid, [](const BatchProblem& a, const BatchProblem& b) {
+      return a.W < b.W || (a.W == b.W && a.sym_kb < b.sym_kb);
+    });
     Layout L;
     for (size_t q = 0; q < n; ++q) {
       BatchProblem& bp = tb[q];
       if (bp.sym_q > 0) {
-        if (L.groups.empty() || L.groups.back().W != bp.W)
-          L.groups.push_back(SymGroup{static_cast<int>(q), 0, bp.W, 0, 0});
+        if (L.groups.empty() || L.groups.back().W != bp.W || L.groups.back().kb != bp.sym_kb)
+          L.groups.push_back(SymGroup{static_cast<int>(q), 0, bp.W, bp.sym_kb, 0, 0});
         SymGroup& g = L.groups.back();
         bp.tile_begin = g.tiles;
         g.tiles += batched_tiles(bp);

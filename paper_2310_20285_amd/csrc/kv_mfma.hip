@@ -659,13 +659,17 @@ __device__ inline void sym_pair(int t, int Q, int& s, int& u) {
 // One item (super-block pair (s, u)) of the symmetric product on a workgroup of
 // 256 threads; smem holds sym_lds_bytes(DCH, WX, G) bytes of LDS.  Every
 // thread takes the same path (the barriers inside are workgroup-uniform).
-template <int KIND, int DCH, int WX, bool PC>
+// KB < 4 (at most 4 KB features, one padded chunk): the distance takes the
+// features in KB k-blocks of four, lane group g holding feature 4 kb + g, so
+// KB MFMAs per strip instead of four over mostly zero features.
+template <int KIND, int DCH, int WX, bool PC, int KB = 4>
 __device__ __forceinline__ void sym_item(float* smem, const float* __restrict__ Xp,
                                          const float* __restrict__ nrm, int64_t n,
                                          const float* __restrict__ V, int C, int64_t ldv,
                                          float* __restrict__ P, int G, int s, int u,
                                          float cnorm, float cdot, const ClassScale& cs) {
   static_assert(!PC || WX <= 8, "per-class columns are at most 8");
+  static_assert(KB == 4 || (DCH == 1 && KB >= 1 && KB <= 3), "k-blocks of one feature chunk");
   using L = SymLayout<DCH, WX>;
   constexpr int NS = SYM_NS;
   constexpr int DP = L::DP, XS = L::XS, VS = L::VS;
@@ -742,6 +746,7 @@ __device__ __forceinline__ void sym_item(float* smem, const float* __restrict__ 
     const int64_t row0 = ib0 + wave * (16 * NS);
     // this wave's rows: A operand (row 16 st + r), norms and V of rows 16 st + 4g + v
     f4 xa[NS][DCH];
+    float xk[NS][KB < 4 ? KB : 1];   // KB < 4: feature 4 kb + g of row 16 st + r
     float n1v[NS][4];
     float a1[NS][4];   // V[16 st + 4g + v][w = r]: A operand of the transposed MFMA
     // PC: V[16 st + 4g + v][w] for every column w (the transposed sums on VALU)
@@ -749,10 +754,15 @@ __device__ __forceinline__ void sym_item(float* smem, const float* __restrict__ 
 #pragma unroll
     for (int st = 0; st < NS; ++st) {
       const int64_t na = row0 + st * 16 + r;
+      if constexpr (KB < 4) {
 #pragma unroll
-      for (int c = 0; c < DCH; ++c)
-        xa[st][c] = na < n ? *reinterpret_cast<const f4*>(Xp + na * DP + 16 * c + 4 * g)
-                           : f4{0, 0, 0, 0};
+        for (int kb = 0; kb < KB; ++kb) xk[st][kb] = na < n ? Xp[na * DP + 4 * kb + g] : 0.0f;
+      } else {
+#pragma unroll
+        for (int c = 0; c < DCH; ++c)
+          xa[st][c] = na < n ? *reinterpret_cast<const f4*>(Xp + na * DP + 16 * c + 4 * g)
+                             : f4{0, 0, 0, 0};
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t nb = row0 + st * 16 + 4 * g + v;
@@ -796,14 +806,25 @@ __device__ __forceinline__ void sym_item(float* smem, const float* __restrict__ 
         f4 dd[NS];
 #pragma unroll
         for (int st = 0; st < NS; ++st) dd[st] = f4{0, 0, 0, 0};
+        if constexpr (KB < 4) {
 #pragma unroll
-        for (int c = 0; c < DCH; ++c) {
-          const f4 b = *reinterpret_cast<const f4*>(&bX[(mb * 16 + r) * XS + 16 * c + 4 * g]);
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk)
+          for (int kb = 0; kb < KB; ++kb) {
+            const float b = bX[(mb * 16 + r) * XS + 4 * kb + g];
 #pragma unroll
             for (int st = 0; st < NS; ++st)
-              dd[st] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[st][c][kk], b[kk], dd[st], 0, 0, 0);
+              dd[st] = __builtin_amdgcn_mfma_f32_16x16x4f32(xk[st][kb], b, dd[st], 0, 0, 0);
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < DCH; ++c) {
+            const f4 b = *reinterpret_cast<const f4*>(&bX[(mb * 16 + r) * XS + 16 * c + 4 * g]);
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+              for (int st = 0; st < NS; ++st)
+                dd[st] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[st][c][kk], b[kk], dd[st], 0, 0,
+                                                              0);
+          }
         }
         const float n2v = bN[mb * 16 + r];
         float vm2[WX];
@@ -918,7 +939,7 @@ __device__ __forceinline__ void sym_item(float* smem, const float* __restrict__ 
   }
 }
 
-template <int KIND, int DCH, int WX, bool PC = false>
+template <int KIND, int DCH, int WX, bool PC = false, int KB = 4>
 __global__ void __launch_bounds__(256)
 kv_mfma_f32_sym(const float* __restrict__ Xp, const float* __restrict__ nrm, int64_t n,
                 const float* __restrict__ V, int C, int64_t ldv, float* __restrict__ P, int G,
@@ -927,7 +948,7 @@ kv_mfma_f32_sym(const float* __restrict__ Xp, const float* __restrict__ nrm, int
   extern __shared__ __align__(16) float smem[];
   int s, u;
   sym_pair(static_cast<int>(blockIdx.x), Q, s, u);
-  sym_item<KIND, DCH, WX, PC>(smem, Xp, nrm, n, V, C, ldv, P, G, s, u, cnorm, cdot, cs);
+  sym_item<KIND, DCH, WX, PC, KB>(smem, Xp, nrm, n, V, C, ldv, P, G, s, u, cnorm, cdot, cs);
 }
 
 // ---- persistent batched launch -------------------------------------------------
@@ -1048,7 +1069,7 @@ __global__ void kv_reduce_batched(const BatchProblem* __restrict__ probs, int np
 // partial slots -- and after kv_reduce_batched the product -- are those of the
 // single-problem launch, bit for bit.  One instantiation per W keeps the
 // single kernel's register budget.  Dynamic LDS: the largest plan's bytes.
-template <int KIND, int DCH, int WX>
+template <int KIND, int DCH, int WX, int KB>
 __global__ void __launch_bounds__(256)
 kv_batched_sym(const BatchProblem* __restrict__ probs, int np, int64_t ntiles,
                int* __restrict__ counter) {
@@ -1071,7 +1092,7 @@ kv_batched_sym(const BatchProblem* __restrict__ probs, int np, int64_t ntiles,
     if (pb.gate && gate_closed(pb.gate)) continue;   // the problem's solver has stopped
     int su, uu;
     sym_pair(static_cast<int>(t - pb.tile_begin), pb.sym_q, su, uu);
-    sym_item<KIND, DCH, WX, false>(smem, static_cast<const float*>(pb.X1p), pb.nrm1, pb.n1, pb.V,
+    sym_item<KIND, DCH, WX, false, KB>(smem, static_cast<const float*>(pb.X1p), pb.nrm1, pb.n1, pb.V,
                                    pb.C, pb.ldv, pb.P, pb.sym_g, su, uu, pb.cnorm, pb.cdot,
                                    none);
   }
@@ -1160,8 +1181,12 @@ Plan plan_mfma(int64_t n1, int64_t n2, int64_t d, int64_t W, bool fixed = false)
 struct SymPlan {
   bool ok;
   int G, Q;
+  int kb;           // feature k-blocks of the distance (sym_item's KB)
   size_t lds;
 };
+
+// sym_item's KB for d features: 1 or 2 k-blocks of four within one padded chunk
+int sym_kblocks(int64_t d) { return d <= 4 ? 1 : (d <= 8 ? 2 : 4); }
 
 size_t sym_lds_bytes(int dch, int64_t W, int G) {
   const int64_t fixed = 2 * TN * (dch * 16 + 4) + 2 * TN + 2 * W * (TN + 1);
@@ -1178,23 +1203,24 @@ SymPlan plan_sym(int64_t n, int64_t d, int64_t W) {
   int G = static_cast<int>(std::min<int64_t>(std::max<int64_t>(ceil_div(n, IB * 90), 1), 4));
   while (G > 1 && sym_lds_bytes(dch, W, G) > SYM_MAX_LDS) --G;
   sp.G = G;
+  sp.kb = sym_kblocks(d);
   sp.Q = static_cast<int>(ceil_div(n, G * IB));
   sp.lds = sym_lds_bytes(dch, W, G);
   sp.ok = sp.Q <= SYM_MAX_Q && sp.lds <= SYM_MAX_LDS;
   return sp;
 }
 
-template <int KIND, int DCH, bool PC>
-int launch_sym_dch(const SymPlan& sp, const float* Xp, const float* np_, int64_t n,
-                   const float* V, int C, int W, int64_t ldv, float* P, float cnorm, float cdot,
-                   const ClassScale& cs, const int* skip, hipStream_t s) {
+template <int KIND, int DCH, bool PC, int KB>
+int launch_sym_kb(const SymPlan& sp, const float* Xp, const float* np_, int64_t n,
+                  const float* V, int C, int W, int64_t ldv, float* P, float cnorm, float cdot,
+                  const ClassScale& cs, const int* skip, hipStream_t s) {
   const unsigned items = static_cast<unsigned>(sp.Q * (sp.Q + 1) / 2);
   switch (W) {
 #define IGP_SW(K)                                                                              \
   case K:                                                                                      \
-    kv_mfma_f32_sym<KIND, DCH, K, PC><<<items, 256, sp.lds, s>>>(Xp, np_, n, V, C, ldv, P,     \
-                                                                 sp.G, sp.Q, cnorm, cdot, cs,  \
-                                                                 skip);                        \
+    kv_mfma_f32_sym<KIND, DCH, K, PC, KB><<<items, 256, sp.lds, s>>>(Xp, np_, n, V, C, ldv, P, \
+                                                                     sp.G, sp.Q, cnorm, cdot,  \
+                                                                     cs, skip);                \
     break;
     IGP_SW(1) IGP_SW(2) IGP_SW(3) IGP_SW(4) IGP_SW(5) IGP_SW(6) IGP_SW(7) IGP_SW(8)
 #undef IGP_SW
@@ -1202,6 +1228,23 @@ int launch_sym_dch(const SymPlan& sp, const float* Xp, const float* np_, int64_t
   }
   IGP_CHECK_LAUNCH();
   return IGP_OK;
+}
+
+// the per-class form keeps four k-blocks (its registers are spent on the classes)
+template <int KIND, int DCH, bool PC>
+int launch_sym_dch(const SymPlan& sp, const float* Xp, const float* np_, int64_t n,
+                   const float* V, int C, int W, int64_t ldv, float* P, float cnorm, float cdot,
+                   const ClassScale& cs, const int* skip, hipStream_t s) {
+  if constexpr (DCH == 1 && !PC) {
+    if (sp.kb == 1)
+      return launch_sym_kb<KIND, 1, false, 1>(sp, Xp, np_, n, V, C, W, ldv, P, cnorm, cdot, cs,
+                                              skip, s);
+    if (sp.kb == 2)
+      return launch_sym_kb<KIND, 1, false, 2>(sp, Xp, np_, n, V, C, W, ldv, P, cnorm, cdot, cs,
+                                              skip, s);
+  }
+  return launch_sym_kb<KIND, DCH, PC, 4>(sp, Xp, np_, n, V, C, W, ldv, P, cnorm, cdot, cs, skip,
+                                         s);
 }
 
 template <int KIND, bool PC = false>
@@ -1541,6 +1584,7 @@ bool batched_sym_plan(int64_t n, int64_t d, int64_t W, BatchProblem* bp) {
   if (!sp.ok) return false;
   bp->sym_g = sp.G;
   bp->sym_q = sp.Q;
+  bp->sym_kb = sp.kb;
   bp->nsplit = sp.Q;
   bp->gx = 0;
   bp->cols_per_split = 0;
@@ -1557,18 +1601,30 @@ int64_t batched_tiles(const BatchProblem& bp) {
 }
 
 namespace {
-template <int KIND, int DCH>
-void launch_batched_sym(const SymGroup& g, const BatchProblem* dprobs, int* counter,
-                        hipStream_t s) {
+template <int KIND, int DCH, int KB>
+void launch_batched_sym_kb(const SymGroup& g, const BatchProblem* dprobs, int* counter,
+                           hipStream_t s) {
   const int grid = static_cast<int>(std::min<int64_t>(g.tiles, 256 * 4));
   const BatchProblem* pr = dprobs + g.first;
   switch (g.W) {
 #define IGP_BS(K)                                                                              \
-  case K: kv_batched_sym<KIND, DCH, K><<<grid, 256, g.lds, s>>>(pr, g.count, g.tiles, counter); break;
+  case K:                                                                                      \
+    kv_batched_sym<KIND, DCH, K, KB><<<grid, 256, g.lds, s>>>(pr, g.count, g.tiles, counter);  \
+    break;
     IGP_BS(1) IGP_BS(2) IGP_BS(3) IGP_BS(4) IGP_BS(5) IGP_BS(6) IGP_BS(7) IGP_BS(8)
 #undef IGP_BS
     default: break;
   }
+}
+
+template <int KIND, int DCH>
+void launch_batched_sym(const SymGroup& g, const BatchProblem* dprobs, int* counter,
+                        hipStream_t s) {
+  if constexpr (DCH == 1) {
+    if (g.kb == 1) return launch_batched_sym_kb<KIND, 1, 1>(g, dprobs, counter, s);
+    if (g.kb == 2) return launch_batched_sym_kb<KIND, 1, 2>(g, dprobs, counter, s);
+  }
+  launch_batched_sym_kb<KIND, DCH, 4>(g, dprobs, counter, s);
 }
 }  // namespace
 
@@ -1584,7 +1640,7 @@ int kv_batched_run(int kind, int dch, int ns, bool bf16, const BatchProblem* dpr
   for (int k = 0; k < ngroups; ++k) {
     const SymGroup& g = groups[k];
     if (g.first != nsym || g.count < 1 || g.W < 1 || g.W > 8 || g.tiles < 1 ||
-        g.lds > SYM_MAX_LDS) {
+        g.lds > SYM_MAX_LDS || !(g.kb == 4 || (dch == 1 && (g.kb == 1 || g.kb == 2)))) {
       set_error("batched launch: bad symmetric groups");
       return IGP_EINVAL;
     }

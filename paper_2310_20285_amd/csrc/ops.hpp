@@ -116,8 +116,9 @@ struct BatchProblem {
   int64_t out_begin;        // prefix over problems of n1 * W
   const int* gate;          // device control: the problem's iteration gate (or null)
   // symmetric plan (FP32, K(X, X) V): sym_q super-blocks of sym_g row blocks,
-  // sym_q (sym_q + 1) / 2 items, nsplit = sym_q partial slots; 0: one-sided tiles
-  int sym_g, sym_q;
+  // sym_q (sym_q + 1) / 2 items, nsplit = sym_q partial slots, sym_kb feature
+  // k-blocks of the distance; sym_q = 0: one-sided tiles
+  int sym_g, sym_q, sym_kb;
 };
 // One model's part of a batched solver iteration (recurrence residual, FP32):
 // the vectors and scalars the per-iteration operations touch.
@@ -160,17 +161,18 @@ bool batched_sym_plan(int64_t n, int64_t d, int64_t W, BatchProblem* bp);
 // LDS bytes of a symmetric problem's items; workgroup tiles of a problem
 size_t batched_sym_lds(const BatchProblem& bp, int dch);
 int64_t batched_tiles(const BatchProblem& bp);
-// The symmetric problems of one output width W: dprobs[first, first + count),
-// tile prefixes over them from 0, `tiles` items, `lds` the largest plan's LDS.
+// The symmetric problems of one output width W and distance k-block count kb:
+// dprobs[first, first + count), tile prefixes over them from 0, `tiles` items,
+// `lds` the largest plan's LDS.
 struct SymGroup {
-  int first, count, W;
+  int first, count, W, kb;
   int64_t tiles;
   size_t lds;
 };
 // 64-bit queue counters a batched launch needs (one per symmetric group, one
 // for the one-sided problems)
-constexpr int BATCH_COUNTERS = 16;
-// The products of a batch: the symmetric groups (problems sorted by W, first
+constexpr int BATCH_COUNTERS = 32;
+// The products of a batch: the symmetric groups (problems sorted by (W, kb), first
 // in the table), then dprobs[nsym, np) one-sided (tile prefixes from 0, ntiles
 // tiles), then one reduction over all np (out_begin prefixes over all).
 int kv_batched_run(int kind, int dch, int ns, bool bf16, const BatchProblem* dprobs, int np,

@@ -48,7 +48,8 @@ def _check_rows(out, X, V, rows, C, kind, ell, os_):
 
 @pytest.mark.parametrize("kind", ["rbf", "matern32", "matern52"])
 @pytest.mark.parametrize("n,d,C,nb", [(1, 3, 2, 1), (130, 3, 5, 1), (257, 20, 1, 1), (1000, 16, 8, 1),
-                                      (3001, 7, 3, 2), (2049, 32, 4, 2)])
+                                      (3001, 7, 3, 2), (2049, 32, 4, 2), (600, 8, 7, 1),
+                                      (400, 4, 8, 1)])
 def test_symmetric_product_all_entries(gpu_lib, kind, n, d, C, nb):
     X, V = _case(n, d, C, nb, zlib.crc32(f"{kind}{n}{d}{C}{nb}".encode()))
     out = api.glm_kernel_matmul(X, X, V, C, kind, 1.7, 1.2, "fp32")
