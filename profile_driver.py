@@ -1,6 +1,6 @@
 """Profiling driver for rocprofv3.
 
-    python profile_driver.py [--workload gpc16|image|predict|batched] [--precision ...]
+    python profile_driver.py [--workload gpc16|image|predict|batched|gmm] [--precision ...]
                              [--reps 20] [--copy-mib 256]
 
 Workloads (each ends with one device-to-device copy of ``--copy-mib`` MiB, a
@@ -19,7 +19,9 @@ that converts the counters of the other kernels to bytes):
 * batched 64 independent problems (N ~ U{1000..16000}, D=8, C ~ U{2..8},
           Matern-3/2, IterNCGP-CG j<=200, R=100) advanced by min(--reps, 3)
           batched Newton steps from f_0 = 0, launch shapes from the saved table
-          (FP32, or ``--precision bf16``).
+          (FP32, or ``--precision bf16``);
+* gmm     the fused K.v product of the Gaussian-mixture workload (N=100000,
+          D=3, C=10, Matern-3/2, lengthscale 0.05) in FP32, ``--reps`` times.
 """
 from __future__ import annotations
 
@@ -35,7 +37,7 @@ if ROOT not in sys.path:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="gpc16",
-                    choices=["gpc16", "image", "predict", "batched"])
+                    choices=["gpc16", "image", "predict", "batched", "gmm"])
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16", "bf16x3"])
@@ -47,9 +49,10 @@ def main():
     import datagen
     from paper_2310_20285_amd import api
 
-    if args.workload in ("gpc16", "image"):
-        w = datagen.config2() if args.workload == "gpc16" else datagen.config3(Ns=1000)
-        prec = args.precision or ("fp32" if args.workload == "gpc16" else "bf16")
+    if args.workload in ("gpc16", "image", "gmm"):
+        w = {"gpc16": datagen.config2, "image": lambda: datagen.config3(Ns=1000),
+             "gmm": datagen.gmm}[args.workload]()
+        prec = args.precision or ("bf16" if args.workload == "image" else "fp32")
         X = torch.tensor(w.X, dtype=torch.float32, device="cuda")
         v = torch.randn(w.N * w.C, dtype=torch.float32, device="cuda")
         out = None
